@@ -1,0 +1,346 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself -- hand-derived closed forms, LAPACK through numpy, identities, invariances
+and convergence theory.  CPU only."""
+import json
+import pathlib
+
+import numpy as np
+import pytest
+
+from oracle import wssr_oracle as orc
+
+GOLDEN = pathlib.Path(__file__).parent / "golden"
+rng0 = np.random.default_rng
+
+
+def _problem(n, m, seed, spectrum=None, noise=1e-3, mean_shift=0.3):
+    """Small random problem with a decaying spectrum (plain numpy, test-local)."""
+    rng = rng0(seed)
+    k = min(n, m)
+    u = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    w = np.linalg.qr(rng.standard_normal((m, k)))[0]
+    s = spectrum if spectrum is not None else np.arange(1, k + 1) ** -1.2
+    o = np.sqrt(n) * (u * s) @ w.T + noise * rng.standard_normal((n, m))
+    o += mean_shift * rng.standard_normal(m)[None, :]
+    e_l = -1.0 + 0.1 * rng.standard_normal(n)
+    return o, e_l
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b)
+
+
+# --------------------------------------------------------------- golden examples
+
+def test_golden_hand_examples():
+    cases = json.loads((GOLDEN / "hand_examples.json").read_text())["cases"]
+    c1, c2 = cases
+    o, e = np.array(c1["O"], float), np.array(c1["E_L"], float)
+    np.testing.assert_allclose(orc.gradient(o, e), c1["g"], atol=1e-15)
+    np.testing.assert_allclose(orc.sr_direct(o, e, c1["lam"]), c1["delta_full"], atol=1e-14)
+    res = orc.wssr_step(o, e, np.array(c1["V_in"]), c1["lam"], c1["r"], 1)
+    np.testing.assert_allclose(res["delta"], c1["delta_damped"], atol=1e-14)
+    np.testing.assert_allclose(res["sigma"], c1["sigma"], atol=1e-14)
+    np.testing.assert_allclose(res["v"], c1["V"], atol=1e-14)
+
+    o, e = np.array(c2["O"], float), np.array(c2["E_L"], float)
+    lam = c2["lam"]
+    np.testing.assert_allclose(orc.gradient(o, e), c2["g"], atol=1e-15)
+    np.testing.assert_allclose(orc.sr_direct(o, e, lam), c2["delta_full"], atol=1e-14)
+    np.testing.assert_allclose(orc.sr_pushthrough(o, e, lam), c2["delta_full"], atol=1e-14)
+    for key, r, q in (("r1", 1, 80), ("r2", 2, 1)):
+        sub = c2[key]
+        vin = np.array(sub["V_in"], float)
+        for pre in ("damped", "floor"):
+            res = orc.wssr_step(o, e, vin, lam, r, q, precond=pre)
+            np.testing.assert_allclose(res["delta"], sub["delta_" + pre], atol=1e-13)
+        np.testing.assert_allclose(res["sigma"], c2["sigma"][:r], atol=1e-13)
+        np.testing.assert_allclose(res["v"], sub["V"], atol=1e-12)
+
+
+# --------------------------------------------------------------- building blocks
+
+@pytest.mark.parametrize("n", [1, 2, 7, 30])
+def test_cholesky_and_triangular_vs_lapack(n):
+    rng = rng0(n)
+    x = rng.standard_normal((n + 3, n))
+    g = x.T @ x + 0.1 * np.eye(n)
+    low = orc.cholesky_lower(g)
+    np.testing.assert_allclose(low, np.linalg.cholesky(g), rtol=1e-12, atol=1e-13)
+    b = rng.standard_normal((n, 3))
+    np.testing.assert_allclose(orc.spd_solve(g, b), np.linalg.solve(g, b), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(orc.solve_upper(low.T, b), np.linalg.solve(low.T, b), rtol=1e-10,
+                               atol=1e-12)
+
+
+def test_cholesky_rejects_indefinite():
+    with pytest.raises(np.linalg.LinAlgError):
+        orc.cholesky_lower(np.array([[1.0, 2.0], [2.0, 1.0]]))
+
+
+@pytest.mark.parametrize("shape", [(12, 5), (40, 40), (9, 1), (64, 33)])
+def test_qr_positive(shape):
+    x = rng0(3).standard_normal(shape)
+    q, r = orc.qr_positive(x)
+    np.testing.assert_allclose(q @ r, x, atol=1e-13)
+    np.testing.assert_allclose(q.T @ q, np.eye(shape[1]), atol=1e-13)
+    assert np.all(np.diag(r) > 0) and np.allclose(np.tril(r, -1), 0)
+
+
+@pytest.mark.parametrize("kind", ["random", "graded", "rank_deficient", "odd", "wide", "diag"])
+def test_jacobi_svd_vs_lapack(kind):
+    rng = rng0(11)
+    if kind == "random":
+        c = rng.standard_normal((24, 24))
+    elif kind == "graded":   # singular values spanning 12 decades (Demmel-Veselic test class)
+        qa = np.linalg.qr(rng.standard_normal((20, 20)))[0]
+        qb = np.linalg.qr(rng.standard_normal((20, 20)))[0]
+        c = (qa * np.logspace(0, -12, 20)) @ qb.T
+    elif kind == "rank_deficient":
+        c = rng.standard_normal((16, 5)) @ rng.standard_normal((5, 16))
+    elif kind == "odd":
+        c = rng.standard_normal((13, 13))
+    elif kind == "wide":
+        c = rng.standard_normal((6, 15))
+    else:
+        c = np.diag([3.0, -1.0, 2.0, 0.0, 5.0])
+    u, s, p = orc.jacobi_svd(c)
+    ref = np.linalg.svd(c, compute_uv=False)
+    k = min(c.shape)
+    np.testing.assert_allclose(s[:k], ref, rtol=1e-12, atol=1e-13 * ref[0])
+    assert np.all(s[k:] <= 1e-13 * ref[0])
+    np.testing.assert_allclose(p.T @ p, np.eye(c.shape[1]), atol=1e-13)
+    np.testing.assert_allclose((u * s) @ p.T, c, atol=1e-13 * ref[0])
+    assert np.all(np.diff(s) <= 0)
+    # singular subspaces where the gap is clear: compare projectors with LAPACK
+    _, _, vt = np.linalg.svd(c)
+    for j in range(k - 1):
+        if ref[j] - ref[j + 1] > 1e-3 * ref[0] and (j == 0 or ref[j - 1] - ref[j] > 1e-3 * ref[0]):
+            assert abs(abs(p[:, j] @ vt[j]) - 1) < 1e-10
+
+
+# --------------------------------------------------------------- P1, P2: direct solves
+
+@pytest.mark.parametrize("n,m", [(8, 20), (40, 30), (64, 200)])
+def test_p1_direct_solve_vs_numpy(n, m):
+    o, e = _problem(n, m, seed=n + m)
+    lam = 1e-3
+    a = (o - o.mean(0)) / np.sqrt(n)
+    g_ref = a.T @ (e - e.mean()) / np.sqrt(n)
+    ref = np.linalg.solve(a.T @ a + lam * np.eye(m), g_ref)
+    assert _rel(orc.sr_direct(o, e, lam), ref) < 1e-10
+
+
+@pytest.mark.parametrize("n,m", [(8, 20), (40, 30), (64, 200), (100, 60)])
+def test_p2_pushthrough_equals_direct(n, m):
+    o, e = _problem(n, m, seed=3 * n + m)
+    for lam in (1e-2, 1e-4):
+        assert _rel(orc.sr_pushthrough(o, e, lam), orc.sr_direct(o, e, lam)) < 1e-9
+
+
+def test_gradient_definition_by_loop():
+    """g_m = (1/N) sum_n (O[n,m] - mu_m)(E_L[n] - mean E_L): per-entry brute force."""
+    o, e = _problem(9, 5, seed=4)
+    g = orc.gradient(o, e)
+    for m in range(5):
+        mu = sum(o[n, m] for n in range(9)) / 9
+        el = sum(e) / 9
+        ref = sum((o[n, m] - mu) * (e[n] - el) for n in range(9)) / 9
+        assert abs(g[m] - ref) < 1e-14
+
+
+# --------------------------------------------------------------- P3: exactness at full rank
+
+@pytest.mark.parametrize("n,m,q", [(10, 30, 1), (24, 50, 2), (17, 17, 3)])
+def test_p3_exact_at_full_rank(n, m, q):
+    o, e = _problem(n, m, seed=n * m)
+    r = n - 1            # rank of the centred matrix
+    vin = rng0(1).standard_normal((m, r))
+    lam = 1e-3
+    res = orc.wssr_step(o, e, vin, lam, r, q)
+    assert _rel(res["delta"], orc.sr_direct(o, e, lam)) < 1e-9
+    ref_s = np.linalg.svd((o - o.mean(0)) / np.sqrt(n), compute_uv=False)[:r]
+    np.testing.assert_allclose(res["sigma"], ref_s, rtol=1e-9)
+
+
+# --------------------------------------------------------------- P4, P5: fixed point, orthonormality
+
+@pytest.mark.parametrize("q", [1, 3])
+def test_p4_fixed_point(q):
+    n, m, r = 40, 70, 6
+    o, e = _problem(n, m, seed=5)
+    v_ex, s_ex = orc.exact_topr(o, r)
+    res = orc.wssr_step(o, e, v_ex, 1e-3, r, q)
+    np.testing.assert_allclose(res["v"], v_ex, atol=1e-11)
+    np.testing.assert_allclose(res["sigma"], s_ex, rtol=1e-12)
+    assert _rel(res["delta"], orc.delta_exact_r(o, e, 1e-3, r)) < 1e-11
+    # the exact vectors themselves agree with LAPACK's SVD of A
+    _, s_l, vt = np.linalg.svd((o - o.mean(0)) / np.sqrt(n))
+    np.testing.assert_allclose(s_ex, s_l[:r], rtol=1e-12)
+    np.testing.assert_allclose(np.abs(np.sum(v_ex * vt[:r].T, axis=0)), 1, atol=1e-10)
+
+
+def test_p5_orthonormal_output():
+    o, e = _problem(50, 120, seed=6)
+    res = orc.wssr_step(o, e, rng0(2).standard_normal((120, 9)), 1e-3, 9, 2)
+    assert np.abs(res["v"].T @ res["v"] - np.eye(9)).max() < 1e-13
+
+
+# --------------------------------------------------------------- P7: convergence rate
+
+def test_p7_convergence_rate():
+    n, m, r = 60, 90, 5
+    spec = np.concatenate([[1.0, 0.9, 0.8, 0.7, 0.6], 0.3 * 0.9 ** np.arange(n - 5)])
+    o, e = _problem(n, m, seed=7, spectrum=spec, noise=0.0, mean_shift=0.0)
+    lam = 1e-2
+    ref = orc.delta_exact_r(o, e, lam, r)
+    vin = rng0(3).standard_normal((m, r))
+    errs = [_rel(orc.wssr_step(o, e, vin, lam, r, q)["delta"], ref) for q in range(1, 8)]
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    s = np.linalg.svd((o - o.mean(0)) / np.sqrt(n), compute_uv=False)
+    rate = (s[r] / s[r - 1]) ** 2
+    fitted = np.exp(np.polyfit(np.arange(3, 8), np.log(errs[2:]), 1)[0])
+    assert 0.5 * rate < fitted < 1.5 * rate
+
+
+# --------------------------------------------------------------- P8: closed form
+
+def test_p8_closed_form_noise_free():
+    n, m, k = 30, 50, 8
+    rng = rng0(8)
+    u = np.linalg.qr(np.concatenate([np.ones((n, 1)), rng.standard_normal((n, k))], 1))[0][:, 1:]
+    w = np.linalg.qr(rng.standard_normal((m, k)))[0]
+    s = np.array([2.0, 1.5, 1.0, 0.5, 0.2, 0.1, 0.05, 0.01])
+    o = np.sqrt(n) * (u * s) @ w.T + rng.standard_normal(m)[None, :]   # constant row shift
+    e = rng.standard_normal(n)
+    lam = 1e-2
+    g = orc.gradient(o, e)
+    closed = w @ ((w.T @ g) / (s ** 2 + lam)) + (g - w @ (w.T @ g)) / lam
+    assert _rel(orc.sr_direct(o, e, lam), closed) < 1e-10
+    res = orc.wssr_step(o, e, rng.standard_normal((m, k)), lam, k, 2)
+    np.testing.assert_allclose(res["sigma"], s, rtol=1e-10)
+    np.testing.assert_allclose(np.abs(np.sum(res["v"] * w, 0)), 1, atol=1e-10)
+    assert _rel(res["delta"], closed) < 1e-10
+
+
+# --------------------------------------------------------------- P9: invariances
+
+def test_p9_invariances():
+    n, m, r, q, lam = 25, 40, 4, 2, 1e-3
+    o, e = _problem(n, m, seed=9)
+    rng = rng0(9)
+    vin = rng.standard_normal((m, r))
+    base = orc.wssr_step(o, e, vin, lam, r, q)
+    perm = rng.permutation(n)
+    r1 = orc.wssr_step(o[perm], e[perm], vin, lam, r, q)
+    assert _rel(r1["delta"], base["delta"]) < 1e-11
+    r2 = orc.wssr_step(o + rng.standard_normal(m)[None, :], e + 7.0, vin, lam, r, q)
+    assert _rel(r2["delta"], base["delta"]) < 1e-10
+    c = 3.0
+    r3 = orc.wssr_step(c * o, e, vin, c * c * lam, r, q)
+    assert _rel(r3["delta"], base["delta"] / c) < 1e-11
+    np.testing.assert_allclose(r3["sigma"], c * base["sigma"], rtol=1e-12)
+    pm = rng.permutation(m)
+    dsg = np.where(rng.random(m) < 0.5, -1.0, 1.0)
+    # O -> O Pi D  (column j of the new O is d_j * O[:, pm[j]])
+    r4 = orc.wssr_step(o[:, pm] * dsg, e, vin[pm] * dsg[:, None], lam, r, q)
+    assert _rel(r4["delta"], base["delta"][pm] * dsg) < 1e-11
+    r5 = orc.wssr_step(o, np.full(n, -2.5), vin, lam, r, q)
+    assert np.abs(r5["delta"]).max() == 0.0
+
+
+# --------------------------------------------------------------- P10: limits
+
+def test_p10_large_damping_limit():
+    o, e = _problem(20, 30, seed=10)
+    g = orc.gradient(o, e)
+    for lam in (1e6, 1e9):
+        res = orc.wssr_step(o, e, rng0(0).standard_normal((30, 3)), lam, 3, 2)
+        s1 = res["sigma"][0] ** 2
+        assert _rel(lam * res["delta"], g) < 2 * s1 / lam
+
+
+# --------------------------------------------------------------- P11: the two forms of C
+
+def test_p11_projection_identity():
+    """Q_Y^T A Q_Z = (R_Z R_Y^{-1})^T when Z = A^T Y and Y has full rank."""
+    o, e = _problem(30, 45, seed=11)
+    a = (o - o.mean(0)) / np.sqrt(30)
+    v = orc.qr_positive(rng0(4).standard_normal((45, 6)))[0]
+    y = a @ v
+    z = a.T @ y
+    qy, ry = orc.qr_positive(y)
+    qz, rz = orc.qr_positive(z)
+    c1 = qy.T @ (a @ qz)
+    c2 = (rz @ np.linalg.inv(ry)).T
+    np.testing.assert_allclose(c1, c2, atol=1e-12 * np.abs(c1).max())
+
+
+def test_woodbury_general_core_equals_dense_inverse():
+    """Woodbury apply for a non-orthonormal V equals the dense (V S^2 V^T + lam I)^{-1} g."""
+    rng = rng0(12)
+    v = rng.standard_normal((25, 4))
+    s = np.array([1.0, 0.5, 0.1, 0.0])
+    g = rng.standard_normal(25)
+    lam = 0.05
+    dense = np.linalg.solve((v * s**2) @ v.T + lam * np.eye(25), g)
+    assert _rel(orc.woodbury_apply(v, s, g, lam), dense) < 1e-12
+
+
+def test_sign_rule():
+    v = np.array([[1.0, 0.0], [0.0, -1.0], [0.0, 0.0]])
+    ref = np.array([[-1.0, 0.0], [0.0, 0.0], [0.0, 1.0]])
+    out = orc.fix_signs(v, ref)
+    np.testing.assert_allclose(out, [[-1.0, 0.0], [0.0, 1.0], [0.0, 0.0]])
+
+
+def test_step_rejects_bad_arguments():
+    o, e = _problem(10, 12, seed=13)
+    vin = np.ones((12, 3))
+    with pytest.raises(ValueError):
+        orc.wssr_step(o, e, vin, 1e-3, 10, 1)      # r > N - 1
+    with pytest.raises(ValueError):
+        orc.wssr_step(o, e, vin, 0.0, 3, 1)
+    with pytest.raises(ValueError):
+        orc.wssr_step(o, e, vin, 1e-3, 3, 0)
+    o2 = o.copy()
+    o2[3, 4] = np.nan
+    with pytest.raises(FloatingPointError):
+        orc.wssr_step(o2, e, vin, 1e-3, 3, 1)
+
+
+# --------------------------------------------------------------- planted mistakes
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    """A plausible slip in the oracle (factor 2 in g, no centring of O, a transposed
+    projection) must fail at least one pin; run the pins against each slip."""
+    cases = json.loads((GOLDEN / "hand_examples.json").read_text())["cases"]
+    c2 = cases[1]
+    o, e = np.array(c2["O"], float), np.array(c2["E_L"], float)
+
+    def pins_pass():
+        try:
+            np.testing.assert_allclose(orc.gradient(o, e), c2["g"], atol=1e-14)
+            np.testing.assert_allclose(orc.sr_direct(o, e, 1.0), c2["delta_full"], atol=1e-13)
+            res = orc.wssr_step(o, e, np.eye(2), 1.0, 2, 1)
+            np.testing.assert_allclose(res["delta"], c2["r2"]["delta_damped"], atol=1e-13)
+            test_p11_projection_identity()
+            test_p3_exact_at_full_rank(10, 30, 1)
+        except AssertionError:
+            return False
+        return True
+
+    assert pins_pass()
+    real_center = orc.center_columns
+    real_grad = orc.gradient
+    real_scaled = orc.scaled_centered
+    monkeypatch.setattr(orc, "gradient", lambda o_, e_: 2 * real_grad(o_, e_))
+    assert not pins_pass()
+    monkeypatch.setattr(orc, "gradient", real_grad)
+    monkeypatch.setattr(orc, "center_columns", lambda o_: np.asarray(o_, float))
+    assert not pins_pass()
+    monkeypatch.setattr(orc, "center_columns", real_center)
+    monkeypatch.setattr(orc, "scaled_centered", lambda o_: real_scaled(o_) * np.sqrt(o_.shape[0]))
+    assert not pins_pass()
+    monkeypatch.setattr(orc, "scaled_centered", real_scaled)
+    assert pins_pass()

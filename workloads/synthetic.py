@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs for one warm-started SR step.
+
+This module draws the inputs only; it contains none of the step's arithmetic
+and is shared by the oracle-side tests and by the HIP-side tests and benchmark.
+
+Recipe (stand-in for the per-sample log-derivatives of the paper's atomic and
+molecular wave functions, which are not available):
+
+    O_t = sqrt(N) * U_t diag(s) W_t^T + eta * G_t          (N x M, rows = samples)
+    s_k = k^(-alpha), k = 1..K
+    U_0 (N x K), W_0 (M x K): orthonormal, Q factors (positive diagonal) of
+        Gaussian matrices
+    U_t = R(t*theta) U_0,  W_t = R(t*theta) W_0: R rotates disjoint pairs of
+        ambient coordinates (pi(2i), pi(2i+1)) of a seeded permutation pi by
+        the same angle, so consecutive top-r subspaces drift by about theta
+        (the slow drift the warm start exploits, Sec. 4.2 Table 1)
+    G_t: i.i.d. N(0,1), fresh for each step
+    E_L,t: i.i.d. N(el_mean, el_std^2), fresh for each step
+    V_0: Q factor of an M x r Gaussian (the cold-start basis)
+
+``s_k`` are the singular values of the clean part of O/sqrt(N).  Every
+component has its own generator seeded from (seed, component, step), so any
+step can be drawn alone.  Generation runs in torch on the requested device;
+values differ between devices but are deterministic on each.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import torch
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    name: str
+    n: int            # samples (walkers)
+    m: int            # parameters
+    r: int            # rank
+    q: int            # subspace-iteration passes per step
+    lam: float        # damping
+    steps: int
+    alpha: float      # spectrum exponent
+    theta: float      # rotation per step
+    eta: float        # noise level
+    el_mean: float
+    el_std: float
+    seed: int
+    k: int = 0        # number of spectral components (0 -> n)
+    dtype: str = "f32"
+
+    @property
+    def ncomp(self):
+        return self.k if self.k else self.n
+
+
+# The workloads: a small exactly checkable one, the FP32 benchmark one, the
+# precision-form instance, and the large single instance.
+CONFIGS = {
+    "c1": Config("c1", n=1024, m=2000, r=32, q=2, lam=1e-3, steps=10, alpha=1.5,
+                 theta=0.02, eta=1e-3, el_mean=-1.0, el_std=0.1, seed=1),
+    "c2": Config("c2", n=8192, m=100_000, r=256, q=2, lam=1e-3, steps=20, alpha=1.2,
+                 theta=0.01, eta=1e-3, el_mean=-10.0, el_std=0.5, seed=2),
+    "c3": Config("c3", n=16384, m=1_000_000, r=512, q=2, lam=1e-3, steps=20, alpha=1.0,
+                 theta=0.01, eta=1e-4, el_mean=-10.0, el_std=0.5, seed=3, k=4096,
+                 dtype="bf16"),
+    "c5": Config("c5", n=16384, m=4_000_000, r=512, q=3, lam=1e-3, steps=10, alpha=1.3,
+                 theta=0.005, eta=1e-4, el_mean=-10.0, el_std=0.5, seed=5, k=4096,
+                 dtype="bf16"),
+}
+
+_COMPONENT = {"u": 1, "w": 2, "perm_n": 3, "perm_m": 4, "v0": 5, "noise": 6, "el": 7}
+
+
+def _gen(device, seed, component, step=0):
+    g = torch.Generator(device=device)
+    g.manual_seed((seed * 1_000_003 + _COMPONENT[component] * 10_007 + step) & 0x7FFF_FFFF_FFFF)
+    return g
+
+
+def _orthonormal(x):
+    """Q factor with a positive diagonal of R (Haar-distributed for Gaussian x)."""
+    q, r = torch.linalg.qr(x)
+    d = torch.sign(torch.diagonal(r))
+    d[d == 0] = 1
+    return q * d
+
+
+def _rotate_pairs(x, perm, angle):
+    """Rotate rows (perm[2i], perm[2i+1]) of x by angle."""
+    npair = perm.numel() // 2
+    a, b = perm[0:2 * npair:2], perm[1:2 * npair:2]
+    c, s = math.cos(angle), math.sin(angle)
+    xa, xb = x[a], x[b]
+    y = x.clone()
+    y[a] = c * xa - s * xb
+    y[b] = s * xa + c * xb
+    return y
+
+
+class Workload:
+    """Holds the fixed factors of one configuration and draws step inputs."""
+
+    def __init__(self, cfg: Config, device="cpu", gen_dtype=torch.float64, n=None, m=None):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.n = n or cfg.n
+        self.m = m or cfg.m
+        k = min(cfg.ncomp, self.n, self.m)
+        self.k = k
+        dev, sd = self.device, cfg.seed
+        self.gen_dtype = gen_dtype
+        gu = torch.randn(self.n, k, generator=_gen(dev, sd, "u"), device=dev, dtype=gen_dtype)
+        gw = torch.randn(self.m, k, generator=_gen(dev, sd, "w"), device=dev, dtype=gen_dtype)
+        self.u0 = _orthonormal(gu)
+        self.w0 = _orthonormal(gw)
+        del gu, gw
+        self.perm_n = torch.randperm(self.n, generator=_gen(dev, sd, "perm_n"), device=dev)
+        self.perm_m = torch.randperm(self.m, generator=_gen(dev, sd, "perm_m"), device=dev)
+        self.spectrum = torch.arange(1, k + 1, device=dev, dtype=gen_dtype) ** (-cfg.alpha)
+
+    def o(self, t, dtype=torch.float32):
+        """O_t (N x M) in the storage dtype."""
+        cfg, dev = self.cfg, self.device
+        ut = _rotate_pairs(self.u0, self.perm_n, t * cfg.theta)
+        wt = _rotate_pairs(self.w0, self.perm_m, t * cfg.theta)
+        o = (math.sqrt(self.n) * ut * self.spectrum[None, :]) @ wt.T
+        del ut, wt
+        noise = torch.randn(self.n, self.m, generator=_gen(dev, cfg.seed, "noise", t),
+                            device=dev, dtype=self.gen_dtype)
+        o.add_(noise, alpha=cfg.eta)
+        del noise
+        return o.to(dtype)
+
+    def e_l(self, t):
+        cfg = self.cfg
+        z = torch.randn(self.n, generator=_gen(self.device, cfg.seed, "el", t),
+                        device=self.device, dtype=torch.float64)
+        return cfg.el_mean + cfg.el_std * z
+
+    def v0(self, r=None, dtype=torch.float32):
+        r = r or self.cfg.r
+        g = torch.randn(self.m, r, generator=_gen(self.device, self.cfg.seed, "v0"),
+                        device=self.device, dtype=self.gen_dtype)
+        return _orthonormal(g).to(dtype)
+
+
+def random_problem(n, m, r, seed, alpha=1.2, eta=1e-3, el_mean=-1.0, el_std=0.1,
+                   device="cpu", dtype=torch.float32, theta=0.01, t=1):
+    """A single step's inputs (O, E_L, V_in) of arbitrary shape, drawn with the
+    same recipe; V_in is the exact-start-free cold basis V_0."""
+    cfg = Config("adhoc", n=n, m=m, r=r, q=2, lam=1e-3, steps=1, alpha=alpha, theta=theta,
+                 eta=eta, el_mean=el_mean, el_std=el_std, seed=seed)
+    wl = Workload(cfg, device=device)
+    return wl.o(t, dtype), wl.e_l(t), wl.v0(r, dtype)
