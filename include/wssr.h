@@ -1,0 +1,167 @@
+/*
+ * libwssr: one warm-started stochastic-reconfiguration (WSSR) step on an
+ * AMD Instinct MI355X (gfx950), as a plain C ABI.
+ *
+ * The step (paper: Sec. 3.1 eqs. Osr/Osrn/Lbarn for the centred matrices,
+ * Sec. 4.1 eq. barg for the gradient, Sec. 4.2 Alg. 1 for the warm-started
+ * subspace iteration, Sec. 4.1 eq. updated_sr_1 and Sec. 3.2 for the
+ * regularised low-rank preconditioner) computes, from the N x M matrix O of
+ * per-sample log-derivatives (rows = samples) and the local energies E_L:
+ *
+ *   eps   = E_L - mean(E_L)                       (eq. Lbarn)
+ *   A     = (O - 1 mu^T) / sqrt(N)                 (eqs. Osr, Osrn; mu = column means)
+ *   g     = A^T eps / sqrt(N) = O_bar^T eps / N    (eq. barg at averaging weight 0, no factor 2)
+ *   V, sigma <- q passes of subspace iteration on A^T A started from V_in,
+ *                closed by a Rayleigh-Ritz SVD      (Alg. 1)
+ *   delta = (V diag(sigma^2) V^T + lambda I)^{-1} g  (Woodbury)        [default]
+ *   delta = (V diag(sigma^-2) V^T + (I - V V^T)/lambda) g               [WSSR_FLOOR_PRECOND,
+ *                                                     eq. updated_sr_1 with floor lambda]
+ *
+ * sigma are the singular values of A (descending); sigma^2 are the
+ * eigenvalues of S = A^T A.  The caller applies theta <- theta - eta * delta.
+ *
+ * Memory.  Every data pointer passed to wssr_step and the wssr_dbg_* calls is
+ * DEVICE memory on the handle's device; the caller owns it.  The library owns
+ * only the workspace it allocates in wssr_create.  wssr_step never allocates.
+ * Layouts are row-major.  O is read-only; V is read, then overwritten.
+ *
+ * Streams.  All work is enqueued on the stream given at create time (a
+ * hipStream_t; NULL means the null stream); calls return without waiting.
+ * Results are valid once that stream has been synchronised.  A handle is not
+ * thread-safe; use one handle per stream.
+ *
+ * Errors.  Argument errors are detected on the host before anything is
+ * enqueued and returned as negative codes; nothing is enqueued then.
+ * Numerical errors (non-finite input, Cholesky breakdown) are recorded in a
+ * device status word and read with wssr_status_sync; after such an error the
+ * remaining kernels of the step leave V, delta and sigma untouched.
+ */
+#ifndef WSSR_H
+#define WSSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wssr_ctx* wssr_handle;
+
+typedef enum {
+  WSSR_OK = 0,
+  WSSR_WARN_NOT_CONVERGED = 2,   /* Rayleigh-Ritz Jacobi hit its sweep limit; results usable */
+  WSSR_ERR_INVALID_ARG = -1,
+  WSSR_ERR_NO_DEVICE = -2,
+  WSSR_ERR_OOM = -3,
+  WSSR_ERR_HIP = -4,
+  WSSR_ERR_NONFINITE = -5,       /* NaN/Inf in E_L, or reached the Gram matrices from O or V */
+  WSSR_ERR_BREAKDOWN = -6        /* a Cholesky pivot of a Gram matrix was not positive:
+                                    the iterated basis lost rank */
+} wssr_status;
+
+/* Storage and multiply precision of O. */
+typedef enum {
+  WSSR_F32 = 0
+} wssr_dtype;
+
+/* Flags (wssr_config.flags). */
+#define WSSR_FLOOR_PRECOND 0x1u  /* eq. updated_sr_1 weights w_j = 1 - lambda/sigma_j^2 instead of
+                                    the damped w_j = sigma_j^2/(sigma_j^2 + lambda) */
+
+typedef struct {
+  int64_t n_max;        /* largest N (samples) a step will be called with */
+  int64_t m_max;        /* largest M (parameters) */
+  int32_t r_max;        /* largest rank r, 1 <= r_max <= 512 */
+  int32_t q_max;        /* largest pass count q */
+  int32_t o_dtype;      /* wssr_dtype */
+  uint32_t flags;
+  void* stream;         /* hipStream_t */
+} wssr_config;
+
+/* Create a handle on the current HIP device and allocate its workspace
+ * (sized from n_max, m_max, r_max).  Returns WSSR_ERR_NO_DEVICE when no
+ * gfx950 device is visible, WSSR_ERR_OOM when the workspace does not fit,
+ * WSSR_ERR_INVALID_ARG for a bad config.  *out is NULL on failure. */
+wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out);
+
+/* Release the workspace.  Waits for the handle's stream first. */
+wssr_status wssr_destroy(wssr_handle h);
+
+/* One WSSR step (see the top of this file).
+ *   n, m     sample and parameter counts, 2 <= n <= n_max, 1 <= m <= m_max
+ *   O        device, n x m, row stride ld_o >= m elements (dtype as configured)
+ *   e_l      device, double[n]
+ *   V        device, float[m x r] row-major (row stride r): in: warm start whose
+ *            column span seeds the iteration (orthonormality not required);
+ *            out: right singular vectors of A, column j paired with sigma[j].
+ *            Column signs: <v_out_j, v_in_j> >= 0; where that inner product is
+ *            below 1e-8 in magnitude, the entry of largest magnitude (lowest row
+ *            on ties) is positive.
+ *   lambda   damping > 0 and finite
+ *   r        rank, 1 <= r <= min(n - 1, m, r_max)
+ *   q        passes, 1 <= q <= q_max
+ *   delta    device, double[m], out
+ *   sigma    device, double[r], out, descending
+ * Returns WSSR_OK or an argument error; numerical status via wssr_status_sync. */
+wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o,
+                      const double* e_l, float* V, double lambda, int32_t r, int32_t q,
+                      double* delta, double* sigma);
+
+/* Synchronise the handle's stream and read the numerical status of the last
+ * step (a wssr_status value) into *numeric_status.  If diag is non-NULL it
+ * receives 4 doubles: the smallest relative Cholesky pivot of the last step,
+ * the number of Rayleigh-Ritz Jacobi sweeps, the largest remaining column
+ * cosine after them, and the number of Cholesky factorisations performed. */
+wssr_status wssr_status_sync(wssr_handle h, int32_t* numeric_status, double* diag);
+
+/* Text of the last host-side error on this handle (never NULL). */
+const char* wssr_last_error(wssr_handle h);
+
+/* Stage timing for benchmarks.  wssr_profile(h, 1) clears the counters and
+ * starts recording a pair of HIP events on the handle's stream around every
+ * launch of the two data-matrix products (the sample-side product with its
+ * split-K reduction excluded, and the parameter-side product); 0 stops.
+ * wssr_profile_read synchronises the stream and returns, per slot, the summed
+ * milliseconds and the launch count: slot 0 = sample-side product kernel,
+ * slot 1 = parameter-side product kernel.  nslots <= 2. */
+wssr_status wssr_profile(wssr_handle h, int32_t enable);
+wssr_status wssr_profile_read(wssr_handle h, double* ms, int64_t* counts, int32_t nslots);
+
+/* Library version string, e.g. "libwssr 0.1 gfx950". */
+const char* wssr_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Single-kernel entry points, for checking each stage on its own.  Same
+ * conventions as wssr_step (device pointers, handle stream, host-side argument
+ * checks); sizes must fit the handle's capacities.
+ * ------------------------------------------------------------------------- */
+
+/* y = A V = (O - 1 mu^T) V / sqrt(n)   (Alg. 1, the product with the data
+ * matrix on the parameter-side block).  V float[m x r]; y double[n x r]. */
+wssr_status wssr_dbg_sample_side(wssr_handle h, int64_t n, int64_t m, const void* O,
+                                 int64_t ld_o, const float* V, int32_t r, double* y);
+
+/* z = O^T X / sqrt(n)   (Alg. 1, the product with the transposed data matrix).
+ * X float[n x r]; z float[m x r].  Equals A^T X when the columns of X sum to 0. */
+wssr_status wssr_dbg_param_side(wssr_handle h, int64_t n, int64_t m, const void* O,
+                                int64_t ld_o, const float* X, int32_t r, float* z);
+
+/* g = O_bar^T eps / n with eps = e_l - mean(e_l)  (eq. barg); g double[m]. */
+wssr_status wssr_dbg_gradient(wssr_handle h, int64_t n, int64_t m, const void* O,
+                              int64_t ld_o, const double* e_l, double* g);
+
+/* CholeskyQR2 of a tall matrix X (rows x r, float): X = Q R with Q^T Q = I,
+ * R upper triangular with positive diagonal (Alg. 1 "QR decomposition").
+ * Q float[rows x r]; R double[r x r] row-major.  rows <= max(n_max, m_max). */
+wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_t r,
+                             float* Q, double* R);
+
+/* SVD of a small square matrix C (r x r, double, row-major): C = G diag(s) P^T
+ * by block one-sided Jacobi.  s double[r] descending; P double[r x r] row-major. */
+wssr_status wssr_dbg_small_svd(wssr_handle h, const double* C, int32_t r, double* s, double* P);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSSR_H */

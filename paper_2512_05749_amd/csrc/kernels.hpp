@@ -1,0 +1,58 @@
+// Kernel declarations shared by the kernel sources and the host runtime.
+#pragma once
+#include "common.hpp"
+
+namespace wssr {
+
+__global__ void k_status_init(DevStatus* st);
+__global__ void k_center_energies(const double* e_l, int64_t n, double* eps, DevStatus* st);
+__global__ void k_gradient_partial(const float* O, int64_t ld, int64_t n, int64_t m, const double* eps,
+                                   int64_t rows_per_split, double* part, bool vec, const DevStatus* st);
+__global__ void k_gradient_reduce(const double* part, int nsplit, int64_t m, double inv_n, double* g,
+                                  const DevStatus* st);
+__global__ void k_ysum(const float* ypart, int nsplit, int64_t n, int r, double* y, double* colpart,
+                       const DevStatus* st);
+__global__ void k_ycenter(double* y, const double* colpart, int nrowblk, int64_t n, int r, double inv_sqrt_n,
+                          const DevStatus* st);
+__global__ void k_sign_partial(const float* vnew, const float* vin, int64_t m, int r, int64_t rows_per_chunk,
+                               double* dots, float* maxval, int64_t* maxrow, const DevStatus* st);
+__global__ void k_sign_final(const double* dots, const float* maxval, const int64_t* maxrow, int nchunk, int r,
+                             float* sgn, const DevStatus* st);
+__global__ void k_sign_apply(const float* vnew, const float* sgn, int64_t total, int r, float* v,
+                             const DevStatus* st);
+__global__ void k_vtg_partial(const float* v, const double* g, int64_t m, int r, int64_t rows_per_chunk,
+                              double* part, const DevStatus* st);
+__global__ void k_vtg_final(const double* part, int nchunk, int r, const double* sig_sorted, double lambda,
+                            int floor_form, double* cw, double* sigma_out, const DevStatus* st);
+__global__ void k_delta(const float* v, const double* g, const double* cw, int64_t m, int r, double inv_lambda,
+                        double* delta, const DevStatus* st);
+
+__global__ void k_gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* V, int r,
+                                   float* ypart, int64_t kchunk, bool vec_o, bool vec_v, const DevStatus* st);
+__global__ void k_gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
+                                  float scale, float* Z, bool vec_o, bool vec_q, const DevStatus* st);
+
+template <typename T>
+__global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,
+                               const DevStatus* st);
+__global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, double* G, const DevStatus* st);
+template <typename Tin, typename Tout>
+__global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
+                        Tout* Out, int ldo, bool upper, const DevStatus* st);
+
+__global__ void k_cholinv(double* G, int rp, double* R, double* Ri, DevStatus* st);
+__global__ void k_jacobi_prep(const double* Ct, int rp, int r, double* Bc, double* Pc, double* scal,
+                              DevStatus* st);
+__global__ void k_jacobi_round(double* Bc, double* Pc, int rp, int rd, double tol, const double* scal,
+                               double* cosbuf, DevStatus* st);
+__global__ void k_jacobi_check(const double* cosbuf, int n, double tol, DevStatus* st);
+__global__ void k_jacobi_final(const double* Bc, const double* Pc, int rp, int r, double* sig, double* Ps,
+                               DevStatus* st);
+
+__global__ void k_transpose_pad(const double* C, int r, int rp, double* Ct);
+
+// dynamic LDS sizes (bytes)
+constexpr size_t kCholinvLds = 4 * 64 * 65 * sizeof(double);
+constexpr size_t kJacobiLds = 3 * 64 * 65 * sizeof(double);
+
+}  // namespace wssr

@@ -1,0 +1,258 @@
+// Memory-bound kernels of the step: energy centring, gradient, the reduction
+// and centring of the sample-side product, the output-sign rule and the
+// Woodbury apply.  All reductions run in a fixed order (no float atomics), so
+// a step is bitwise reproducible.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace wssr {
+
+// ---------------------------------------------------------------------------
+// eps = E_L - mean(E_L)   (eq. Lbarn); one workgroup of 1024 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_center_energies(const double* __restrict__ e_l, int64_t n,
+                                                          double* __restrict__ eps, DevStatus* st) {
+  __shared__ double red[1024];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  double s = 0.0;
+  int nf = 0;
+  for (int64_t i = t; i < n; i += 1024) {
+    const double v = e_l[i];
+    s += v;
+    nf |= !isfinite(v);
+  }
+  red[t] = s;
+  __syncthreads();
+  if (nf) bad = 1;
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (bad) {
+    if (t == 0) raise_error(st, ST_NONFINITE);
+    return;
+  }
+  const double mean = red[0] / (double)n;
+  for (int64_t i = t; i < n; i += 1024) eps[i] = e_l[i] - mean;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient g = O^T eps / N (eq. barg; equals O_bar^T eps / N since sum eps = 0).
+// Stage 1: grid (column blocks of 1024 columns, row splits); each thread owns 4
+// consecutive columns and a contiguous range of rows; FP64 accumulation.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gradient_partial(const float* __restrict__ O, int64_t ld, int64_t n,
+                                                          int64_t m, const double* __restrict__ eps,
+                                                          int64_t rows_per_split, double* __restrict__ part,
+                                                          bool vec, const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (c0 >= m) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = min(n, r0 + rows_per_split);
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int64_t i = r0; i < r1; ++i) {
+    const f32x4 v = load4(O + i * ld, c0, m, vec);
+    const double e = eps[i];
+    a0 += (double)v[0] * e;
+    a1 += (double)v[1] * e;
+    a2 += (double)v[2] * e;
+    a3 += (double)v[3] * e;
+  }
+  double* p = part + (int64_t)blockIdx.y * m;
+  p[c0] = a0;
+  if (c0 + 1 < m) p[c0 + 1] = a1;
+  if (c0 + 2 < m) p[c0 + 2] = a2;
+  if (c0 + 3 < m) p[c0 + 3] = a3;
+}
+
+__global__ __launch_bounds__(256) void k_gradient_reduce(const double* __restrict__ part, int nsplit, int64_t m,
+                                                         double inv_n, double* __restrict__ g,
+                                                         const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= m) return;
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * m + c];
+  g[c] = s * inv_n;
+}
+
+// ---------------------------------------------------------------------------
+// Sample side: y = sum_s ypart[s] (split-K partial products), then centre the
+// columns and scale: y <- (y - 1 mean^T) / sqrt(N)   (implicit centring of O:
+// O_bar V = O V - 1 (mu^T V), and mu^T V is the column mean of O V).
+// grid (row blocks of 64, column blocks of 256).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ysum(const float* __restrict__ ypart, int nsplit, int64_t n, int r,
+                                              double* __restrict__ y, double* __restrict__ colpart,
+                                              const DevStatus* st) {
+  if (failed(st)) return;
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= r) return;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t i1 = min(n, i0 + 64);
+  const int64_t plane = n * r;
+  double cs = 0.0;
+  for (int64_t i = i0; i < i1; ++i) {
+    double v = 0.0;
+    for (int s = 0; s < nsplit; ++s) v += (double)ypart[s * plane + i * r + j];
+    y[i * r + j] = v;
+    cs += v;
+  }
+  colpart[(int64_t)blockIdx.x * r + j] = cs;
+}
+
+__global__ __launch_bounds__(256) void k_ycenter(double* __restrict__ y, const double* __restrict__ colpart,
+                                                 int nrowblk, int64_t n, int r, double inv_sqrt_n,
+                                                 const DevStatus* st) {
+  if (failed(st)) return;
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= r) return;
+  double cs = 0.0;
+  for (int b = 0; b < nrowblk; ++b) cs += colpart[(int64_t)b * r + j];
+  const double mean = cs / (double)n;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t i1 = min(n, i0 + 64);
+  for (int64_t i = i0; i < i1; ++i) y[i * r + j] = (y[i * r + j] - mean) * inv_sqrt_n;
+}
+
+// ---------------------------------------------------------------------------
+// Output signs.  Stage 1 (grid: row chunks x column blocks of 256): per column
+// the partial inner product <vnew_j, vin_j> and the entry of largest magnitude
+// (lowest row on ties) of vnew_j.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sign_partial(const float* __restrict__ vnew, const float* __restrict__ vin,
+                                                      int64_t m, int r, int64_t rows_per_chunk,
+                                                      double* __restrict__ dots, float* __restrict__ maxval,
+                                                      int64_t* __restrict__ maxrow, const DevStatus* st) {
+  if (failed(st)) return;
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= r) return;
+  const int64_t i0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t i1 = min(m, i0 + rows_per_chunk);
+  double d = 0.0;
+  float best = -1.0f, bestv = 0.0f;
+  int64_t bestrow = -1;
+  for (int64_t i = i0; i < i1; ++i) {
+    const float a = vnew[i * r + j];
+    d += (double)a * (double)vin[i * r + j];
+    if (fabsf(a) > best) {
+      best = fabsf(a);
+      bestv = a;
+      bestrow = i;
+    }
+  }
+  const int64_t o = (int64_t)blockIdx.x * r + j;
+  dots[o] = d;
+  maxval[o] = bestv;
+  maxrow[o] = bestrow;
+}
+
+// Stage 2 (one block): sign_j from the partials; also copies sigma out.
+__global__ __launch_bounds__(512) void k_sign_final(const double* __restrict__ dots, const float* __restrict__ maxval,
+                                                    const int64_t* __restrict__ maxrow, int nchunk, int r,
+                                                    float* __restrict__ sgn, const DevStatus* st) {
+  if (failed(st)) return;
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    double d = 0.0;
+    float bv = 0.0f, ba = -1.0f;
+    for (int c = 0; c < nchunk; ++c) {
+      d += dots[(int64_t)c * r + j];
+      const float v = maxval[(int64_t)c * r + j];
+      // chunks are in row order, so a strict > keeps the lowest row on ties
+      if (maxrow[(int64_t)c * r + j] >= 0 && fabsf(v) > ba) {
+        ba = fabsf(v);
+        bv = v;
+      }
+    }
+    float s;
+    if (fabs(d) >= 1e-8)
+      s = d >= 0.0 ? 1.0f : -1.0f;
+    else
+      s = bv >= 0.0f ? 1.0f : -1.0f;
+    sgn[j] = s;
+  }
+}
+
+// Stage 3: v[i][j] = sgn[j] * vnew[i][j] (elementwise over m x r).
+__global__ __launch_bounds__(256) void k_sign_apply(const float* __restrict__ vnew, const float* __restrict__ sgn,
+                                                    int64_t total, int r, float* __restrict__ v,
+                                                    const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  v[e] = sgn[e % r] * vnew[e];
+}
+
+// ---------------------------------------------------------------------------
+// Woodbury apply.  delta = (g - V diag(w) V^T g) / lambda, with
+//   damped: w_j = sigma_j^2 / (sigma_j^2 + lambda)     ((V S^2 V^T + lambda I)^{-1} g)
+//   floor:  w_j = 1 - lambda / sigma_j^2  (0 where sigma_j = 0)   (eq. updated_sr_1)
+// Stage 1: partial c = V^T g over row chunks (grid: chunks x column blocks).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vtg_partial(const float* __restrict__ v, const double* __restrict__ g,
+                                                     int64_t m, int r, int64_t rows_per_chunk,
+                                                     double* __restrict__ part, const DevStatus* st) {
+  if (failed(st)) return;
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= r) return;
+  const int64_t i0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t i1 = min(m, i0 + rows_per_chunk);
+  double d = 0.0;
+  for (int64_t i = i0; i < i1; ++i) d += (double)v[i * r + j] * g[i];
+  part[(int64_t)blockIdx.x * r + j] = d;
+}
+
+// Stage 2 (one block): cw_j = w_j * c_j; also writes sigma to the caller.
+__global__ __launch_bounds__(512) void k_vtg_final(const double* __restrict__ part, int nchunk, int r,
+                                                   const double* __restrict__ sig_sorted, double lambda, int floor_form,
+                                                   double* __restrict__ cw, double* __restrict__ sigma_out,
+                                                   const DevStatus* st) {
+  if (failed(st)) return;
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    double c = 0.0;
+    for (int k = 0; k < nchunk; ++k) c += part[(int64_t)k * r + j];
+    const double s = sig_sorted[j];
+    const double s2 = s * s;
+    double w;
+    if (floor_form)
+      w = s2 > 0.0 ? 1.0 - lambda / s2 : 0.0;
+    else
+      w = s2 / (s2 + lambda);
+    cw[j] = w * c;
+    sigma_out[j] = s;
+  }
+}
+
+// Stage 3: one wavefront per row: delta_i = (g_i - sum_j V[i][j] cw[j]) / lambda.
+__global__ __launch_bounds__(256) void k_delta(const float* __restrict__ v, const double* __restrict__ g,
+                                               const double* __restrict__ cw, int64_t m, int r, double inv_lambda,
+                                               double* __restrict__ delta, const DevStatus* st) {
+  if (failed(st)) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= m) return;
+  double d = 0.0;
+  for (int j = lane; j < r; j += 64) d += (double)v[i * r + j] * cw[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+  if (lane == 0) delta[i] = (g[i] - d) * inv_lambda;
+}
+
+}  // namespace wssr
+
+namespace wssr {
+__global__ void k_status_init(DevStatus* st) {
+  if (threadIdx.x == 0) {
+    st->code = 0;
+    st->chol_count = 0;
+    st->min_rel_pivot = 1.0;
+    st->jacobi_sweeps = 0.0;
+    st->jacobi_cosine = 0.0;
+    st->jacobi_done = 0;
+    st->pad = 0;
+  }
+}
+}  // namespace wssr

@@ -1,0 +1,489 @@
+// Host runtime of libwssr: handle, workspace, launch plans and the C ABI.
+#include "wssr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace wssr;
+
+namespace {
+
+constexpr int kS1Max = 16;      // split-K ranges of the sample-side product
+constexpr int kGSplitMax = 16;  // row splits of the gradient
+constexpr int kGramChunkMax = 64;
+constexpr int kVecChunkMax = 1024;
+constexpr int kJacobiSweeps = 15;
+constexpr double kJacobiTol = 1e-12;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+}  // namespace
+
+struct wssr_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  wssr_config cfg{};
+  std::string err;
+  int rp_max = 0;
+  int64_t rows_max = 0;
+  std::vector<void*> allocs;
+
+  DevStatus* st = nullptr;
+  double *eps = nullptr, *g = nullptr, *gpart = nullptr;
+  float* ypart = nullptr;
+  double *y64 = nullptr, *yq1 = nullptr, *colpart = nullptr;
+  float *qy = nullptr, *z = nullptr, *q1 = nullptr, *vw = nullptr;
+  double* gram_part = nullptr;
+  double *G = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *Rz = nullptr;
+  double *Bc = nullptr, *Pc = nullptr, *Ps = nullptr, *T = nullptr, *scal = nullptr, *sig = nullptr;
+  double *cosbuf = nullptr, *cw = nullptr, *vpart = nullptr, *dots = nullptr;
+  float *maxval = nullptr, *sgn = nullptr;
+  int64_t* maxrow = nullptr;
+
+  // stage timing (wssr_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
+
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  // record events around `launch` when profiling is on
+  template <typename F>
+  void timed(int slot, F&& launch) {
+    if (!prof) {
+      launch();
+      return;
+    }
+    hipEvent_t a = next_event(), b = next_event();
+    if (a) (void)hipEventRecord(a, stream);
+    launch();
+    if (b) (void)hipEventRecord(b, stream);
+    if (a && b) ev_marks.push_back({slot, {a, b}});
+  }
+
+  wssr_status fail(wssr_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+
+  template <typename T>
+  bool alloc(T*& p, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
+    allocs.push_back(q);
+    p = static_cast<T*>(q);
+    return true;
+  }
+
+  // ---------------------------------------------------------------- kernels
+  hipError_t last() { return hipGetLastError(); }
+
+  void gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* V, int r) {
+    const int64_t tn = cdiv(n, 128), tj = cdiv(r, 128);
+    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(2048, tn * tj)));
+    int64_t kchunk = rup(cdiv(m, s1), 32);
+    s1 = (int)cdiv(m, kchunk);
+    const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+    const bool vec_v = (r % 4 == 0) && ((uintptr_t)V % 16 == 0);
+    timed(0, [&] {
+      hipLaunchKernelGGL(k_gemm_sample_side, dim3(tn, tj, s1), dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
+                         vec_o, vec_v, (const DevStatus*)st);
+    });
+    const int nrb = (int)cdiv(n, 64);
+    hipLaunchKernelGGL(k_ysum, dim3(nrb, cdiv(r, 256)), dim3(256), 0, stream, (const float*)ypart, s1, n, r, y64,
+                       colpart, (const DevStatus*)st);
+    hipLaunchKernelGGL(k_ycenter, dim3(nrb, cdiv(r, 256)), dim3(256), 0, stream, y64, (const double*)colpart, nrb, n,
+                       r, 1.0 / std::sqrt((double)n), (const DevStatus*)st);
+  }
+
+  void gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r, float* Z) {
+    const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+    const bool vec_q = (r % 4 == 0) && ((uintptr_t)Q % 16 == 0);
+    timed(1, [&] {
+      hipLaunchKernelGGL(k_gemm_param_side, dim3(cdiv(m, 128), cdiv(r, 128)), dim3(256), 0, stream, O, ld, n, m, Q, r,
+                         (float)(1.0 / std::sqrt((double)n)), Z, vec_o, vec_q, (const DevStatus*)st);
+    });
+  }
+
+  void gradient(const float* O, int64_t ld, int64_t n, int64_t m, const double* e_l, double* gout) {
+    hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, eps, st);
+    const int64_t cb = cdiv(m, 1024);
+    const int gs = (int)std::min<int64_t>(kGSplitMax, std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, cb), n)));
+    const int64_t rows = cdiv(n, gs);
+    const bool vec = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+    hipLaunchKernelGGL(k_gradient_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n, m, (const double*)eps, rows,
+                       gpart, vec, (const DevStatus*)st);
+    hipLaunchKernelGGL(k_gradient_reduce, dim3(cdiv(m, 256)), dim3(256), 0, stream, (const double*)gpart, gs, m,
+                       1.0 / (double)n, gout, (const DevStatus*)st);
+  }
+
+  template <typename T>
+  void gram(const T* X, int64_t rows, int r) {
+    const int rp = (int)rup(r, 64), nt = rp / 64, npairs = nt * (nt + 1) / 2;
+    int nch = (int)std::min<int64_t>(std::min<int64_t>(kGramChunkMax, std::max(1, 2048 / npairs)),
+                                     std::max<int64_t>(1, cdiv(rows, 256)));
+    const int64_t rpc = rup(cdiv(rows, nch), 32);
+    nch = (int)std::max<int64_t>(1, cdiv(rows, rpc));
+    hipLaunchKernelGGL(k_gram_partial<T>, dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, nt, rpc, gram_part,
+                       (const DevStatus*)st);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(npairs), dim3(256), 0, stream, (const double*)gram_part, nch, nt, r, G,
+                       (const DevStatus*)st);
+  }
+
+  void cholinv(int rp, double* R, double* Ri) {
+    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(1024), kCholinvLds, stream, G, rp, R, Ri, st);
+  }
+
+  template <typename Tin, typename Tout>
+  void apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol, Tout* out, int ldo,
+             bool upper) {
+    hipLaunchKernelGGL((k_apply<Tin, Tout>), dim3(cdiv(rows, 64), cdiv(ncol, 64)), dim3(256), 0, stream, X, rows, ldx,
+                       kdim, Tm, rp, ncol, out, ldo, upper, (const DevStatus*)st);
+  }
+
+  // CholeskyQR2 of X (rows x r): Q (float) and, in R1/R1i/R2/R2i, both rounds'
+  // factors.  The first round's Q is kept in `mid` (type M).
+  template <typename Tin, typename Tmid>
+  void cholqr2(const Tin* X, int64_t rows, int r, Tmid* mid, float* Q, bool form_q) {
+    const int rp = (int)rup(r, 64);
+    gram(X, rows, r);
+    cholinv(rp, R1, R1i);
+    apply(X, rows, r, r, R1i, rp, r, mid, r, true);
+    gram((const Tmid*)mid, rows, r);
+    cholinv(rp, R2, R2i);
+    if (form_q) apply((const Tmid*)mid, rows, r, r, R2i, rp, r, Q, r, true);
+  }
+
+  // SVD of the r x r matrix whose transpose is Ct (rp x rp row-major): sorted
+  // singular values into sig[0..rp), right singular vectors into Ps (rp x rp).
+  void small_svd(const double* Ct, int r) {
+    const int rp = (int)rup(r, 64), nb = rp / 32;
+    hipLaunchKernelGGL(k_jacobi_prep, dim3(1), dim3(1024), 0, stream, Ct, rp, r, Bc, Pc, scal, st);
+    for (int sw = 0; sw < kJacobiSweeps; ++sw) {
+      for (int rd = 0; rd < nb - 1; ++rd)
+        hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2), dim3(1024), kJacobiLds, stream, Bc, Pc, rp, rd, kJacobiTol,
+                           (const double*)scal, cosbuf + (int64_t)rd * (nb / 2), st);
+      hipLaunchKernelGGL(k_jacobi_check, dim3(1), dim3(64), 0, stream, (const double*)cosbuf, (nb - 1) * (nb / 2),
+                         kJacobiTol, st);
+    }
+    hipLaunchKernelGGL(k_jacobi_final, dim3(1), dim3(1024), 0, stream, (const double*)Bc, (const double*)Pc, rp, r, sig,
+                       Ps, st);
+  }
+};
+
+namespace {
+
+bool device_ok(int* dev, std::string& why) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    why = "no HIP device visible";
+    return false;
+  }
+  if (hipGetDevice(dev) != hipSuccess) {
+    why = "hipGetDevice failed";
+    return false;
+  }
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, *dev) != hipSuccess) {
+    why = "hipGetDeviceProperties failed";
+    return false;
+  }
+  if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) {
+    why = std::string("device is ") + p.gcnArchName + ", libwssr is built for gfx950";
+    return false;
+  }
+  return true;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+extern "C" {
+
+const char* wssr_version(void) { return "libwssr 0.1 gfx950"; }
+
+wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
+  if (!out) return WSSR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!cfg || cfg->n_max < 2 || cfg->m_max < 1 || cfg->r_max < 1 || cfg->r_max > 512 || cfg->q_max < 1 ||
+      cfg->o_dtype != WSSR_F32) {
+    g_create_error = "invalid config";
+    return WSSR_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  std::string why;
+  if (!device_ok(&dev, why)) {
+    g_create_error = why;
+    return WSSR_ERR_NO_DEVICE;
+  }
+  auto* h = new wssr_ctx();
+  h->device = dev;
+  h->cfg = *cfg;
+  h->stream = static_cast<hipStream_t>(cfg->stream);
+  const int64_t n = cfg->n_max, m = cfg->m_max;
+  const int r = cfg->r_max;
+  const int rp = (int)rup(r, 64), nt = rp / 64, npairs = nt * (nt + 1) / 2;
+  h->rp_max = rp;
+  h->rows_max = std::max(n, m);
+  const int64_t rows = h->rows_max;
+  bool ok = h->alloc(h->st, 1) && h->alloc(h->eps, n) && h->alloc(h->g, m) &&
+            h->alloc(h->gpart, (size_t)kGSplitMax * m) && h->alloc(h->ypart, (size_t)kS1Max * n * r) &&
+            h->alloc(h->y64, (size_t)n * r) && h->alloc(h->yq1, (size_t)n * r) &&
+            h->alloc(h->colpart, (size_t)cdiv(n, 64) * r) && h->alloc(h->qy, (size_t)n * r) &&
+            h->alloc(h->z, (size_t)m * r) && h->alloc(h->q1, (size_t)rows * r) && h->alloc(h->vw, (size_t)m * r) &&
+            h->alloc(h->gram_part, (size_t)kGramChunkMax * npairs * 4096) && h->alloc(h->G, (size_t)rp * rp) &&
+            h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
+            h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
+            h->alloc(h->Pc, (size_t)rp * rp) && h->alloc(h->Ps, (size_t)rp * rp) && h->alloc(h->T, (size_t)rp * rp) &&
+            h->alloc(h->scal, 4) && h->alloc(h->sig, rp) && h->alloc(h->cosbuf, (size_t)rp * rp / 64) &&
+            h->alloc(h->cw, rp) && h->alloc(h->vpart, (size_t)kVecChunkMax * r) &&
+            h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
+            h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp);
+  if (!ok) {
+    (void)hipGetLastError();
+    for (void* p : h->allocs) (void)hipFree(p);
+    delete h;
+    g_create_error = "workspace allocation failed";
+    return WSSR_ERR_OOM;
+  }
+  if (hipFuncSetAttribute((const void*)k_cholinv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholinvLds) !=
+          hipSuccess ||
+      hipFuncSetAttribute((const void*)k_jacobi_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJacobiLds) !=
+          hipSuccess) {
+    for (void* p : h->allocs) (void)hipFree(p);
+    delete h;
+    g_create_error = "hipFuncSetAttribute failed";
+    return WSSR_ERR_HIP;
+  }
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  if (hipGetLastError() != hipSuccess) {
+    for (void* p : h->allocs) (void)hipFree(p);
+    delete h;
+    g_create_error = "kernel launch failed";
+    return WSSR_ERR_HIP;
+  }
+  *out = h;
+  return WSSR_OK;
+}
+
+wssr_status wssr_destroy(wssr_handle h) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : h->allocs) (void)hipFree(p);
+  delete h;
+  return WSSR_OK;
+}
+
+const char* wssr_last_error(wssr_handle h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+static wssr_status check_common(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, int32_t r) {
+  if (!O) return h->fail(WSSR_ERR_INVALID_ARG, "O is NULL");
+  if (n < 2 || n > h->cfg.n_max) return h->fail(WSSR_ERR_INVALID_ARG, "n=%lld outside [2, n_max]", (long long)n);
+  if (m < 1 || m > h->cfg.m_max) return h->fail(WSSR_ERR_INVALID_ARG, "m=%lld outside [1, m_max]", (long long)m);
+  if (ld_o < m) return h->fail(WSSR_ERR_INVALID_ARG, "ld_o < m");
+  if (r < 1 || r > h->cfg.r_max) return h->fail(WSSR_ERR_INVALID_ARG, "r=%d outside [1, r_max]", r);
+  return WSSR_OK;
+}
+
+wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, float* V,
+                      double lambda, int32_t r, int32_t q, double* delta, double* sigma) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  wssr_status s = check_common(h, n, m, O, ld_o, r);
+  if (s != WSSR_OK) return s;
+  if (!e_l || !V || !delta || !sigma) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (r > std::min<int64_t>(n - 1, m)) return h->fail(WSSR_ERR_INVALID_ARG, "r=%d exceeds min(n-1, m)", r);
+  if (q < 1 || q > h->cfg.q_max) return h->fail(WSSR_ERR_INVALID_ARG, "q=%d outside [1, q_max]", q);
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return h->fail(WSSR_ERR_INVALID_ARG, "lambda must be > 0 and finite");
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+
+  const float* Of = static_cast<const float*>(O);
+  const int rp = (int)rup(r, 64);
+  const DevStatus* cst = h->st;
+  hipStream_t stream = h->stream;
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
+  h->gradient(Of, ld_o, n, m, e_l, h->g);
+
+  const float* vcur = V;
+  for (int p = 1; p <= q; ++p) {
+    // sample side: y = A V (FP64), then its QR: Q_Y (float)
+    h->gemm_sample_side(Of, ld_o, n, m, vcur, r);
+    h->cholqr2<double, double>(h->y64, n, r, h->yq1, h->qy, true);
+    // parameter side: Z = A^T Q_Y, then CholeskyQR2 of Z
+    h->gemm_param_side(Of, ld_o, n, m, h->qy, r, h->z);
+    h->cholqr2<float, float>(h->z, m, r, h->q1, nullptr, false);
+    if (p < q) {
+      // next basis: Q_Z = Q1 R2^{-1}
+      h->apply((const float*)h->q1, m, r, r, h->R2i, rp, r, h->vw, r, true);
+      vcur = h->vw;
+    } else {
+      // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T with R_Z = R2 R1
+      h->apply((const double*)h->R2, rp, rp, rp, h->R1, rp, rp, h->Rz, rp, true);
+      h->small_svd(h->Rz, r);
+      // V = Q_Z P = Q1 (R2^{-1} P)
+      h->apply((const double*)h->R2i, rp, rp, rp, h->Ps, rp, rp, h->T, rp, false);
+      h->apply((const float*)h->q1, m, r, r, h->T, rp, r, h->vw, r, false);
+    }
+  }
+  // output signs, then V <- signed vw
+  {
+    const int64_t rpc = std::max<int64_t>(64, cdiv(m, kVecChunkMax));
+    const int nch = (int)cdiv(m, rpc);
+    hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->vw,
+                       (const float*)V, m, r, rpc, h->dots, h->maxval, h->maxrow, cst);
+    hipLaunchKernelGGL(k_sign_final, dim3(1), dim3(512), 0, stream, (const double*)h->dots, (const float*)h->maxval,
+                       (const int64_t*)h->maxrow, nch, r, h->sgn, cst);
+    const int64_t tot = m * r;
+    hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)h->vw,
+                       (const float*)h->sgn, tot, r, V, cst);
+    // Woodbury
+    hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
+                       (const double*)h->g, m, r, rpc, h->vpart, cst);
+    hipLaunchKernelGGL(k_vtg_final, dim3(1), dim3(512), 0, stream, (const double*)h->vpart, nch, r,
+                       (const double*)h->sig, lambda, (h->cfg.flags & WSSR_FLOOR_PRECOND) ? 1 : 0, h->cw, sigma, cst);
+    hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, (const double*)h->g,
+                       (const double*)h->cw, m, r, 1.0 / lambda, delta, cst);
+  }
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_status_sync(wssr_handle h, int32_t* numeric_status, double* diag) {
+  if (!h || !numeric_status) return WSSR_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipStreamSynchronize failed");
+  DevStatus s;
+  if (hipMemcpy(&s, h->st, sizeof s, hipMemcpyDeviceToHost) != hipSuccess)
+    return h->fail(WSSR_ERR_HIP, "status copy failed");
+  *numeric_status = s.code;
+  if (diag) {
+    diag[0] = s.min_rel_pivot;
+    diag[1] = s.jacobi_sweeps;
+    diag[2] = s.jacobi_cosine;
+    diag[3] = (double)s.chol_count;
+  }
+  return WSSR_OK;
+}
+
+wssr_status wssr_profile(wssr_handle h, int32_t enable) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipStreamSynchronize failed");
+  h->ev_marks.clear();
+  h->ev_used = 0;
+  h->prof = enable != 0;
+  return WSSR_OK;
+}
+
+wssr_status wssr_profile_read(wssr_handle h, double* ms, int64_t* counts, int32_t nslots) {
+  if (!h || !ms || !counts || nslots < 1 || nslots > 2) return WSSR_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipStreamSynchronize failed");
+  for (int i = 0; i < nslots; ++i) {
+    ms[i] = 0.0;
+    counts[i] = 0;
+  }
+  for (auto& mk : h->ev_marks) {
+    float t = 0.0f;
+    if (mk.first < nslots && hipEventElapsedTime(&t, mk.second.first, mk.second.second) == hipSuccess) {
+      ms[mk.first] += t;
+      counts[mk.first] += 1;
+    }
+  }
+  return WSSR_OK;
+}
+
+// ------------------------------------------------------------ single stages
+
+wssr_status wssr_dbg_sample_side(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const float* V,
+                                 int32_t r, double* y) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  wssr_status s = check_common(h, n, m, O, ld_o, r);
+  if (s != WSSR_OK) return s;
+  if (!V || !y) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  h->gemm_sample_side(static_cast<const float*>(O), ld_o, n, m, V, r);
+  (void)hipMemcpyAsync(y, h->y64, sizeof(double) * n * r, hipMemcpyDeviceToDevice, h->stream);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_dbg_param_side(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const float* X,
+                                int32_t r, float* z) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  wssr_status s = check_common(h, n, m, O, ld_o, r);
+  if (s != WSSR_OK) return s;
+  if (!X || !z) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  h->gemm_param_side(static_cast<const float*>(O), ld_o, n, m, X, r, z);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_dbg_gradient(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                              double* g) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  wssr_status s = check_common(h, n, m, O, ld_o, 1);
+  if (s != WSSR_OK) return s;
+  if (!e_l || !g) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  h->gradient(static_cast<const float*>(O), ld_o, n, m, e_l, g);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_t r, float* Q, double* R) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!X || !Q || !R) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (r < 1 || r > h->cfg.r_max) return h->fail(WSSR_ERR_INVALID_ARG, "r outside [1, r_max]");
+  if (rows < r || rows > h->rows_max) return h->fail(WSSR_ERR_INVALID_ARG, "rows outside [r, max(n_max, m_max)]");
+  const int rp = (int)rup(r, 64);
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  h->cholqr2<float, float>(X, rows, r, h->q1, Q, true);
+  h->apply((const double*)h->R2, rp, rp, rp, h->R1, rp, rp, h->Rz, rp, true);
+  (void)hipMemcpy2DAsync(R, sizeof(double) * r, h->Rz, sizeof(double) * rp, sizeof(double) * r, r,
+                         hipMemcpyDeviceToDevice, h->stream);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_dbg_small_svd(wssr_handle h, const double* C, int32_t r, double* s, double* P) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!C || !s || !P) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (r < 1 || r > h->cfg.r_max) return h->fail(WSSR_ERR_INVALID_ARG, "r outside [1, r_max]");
+  const int rp = (int)rup(r, 64);
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  hipLaunchKernelGGL(k_transpose_pad, dim3(cdiv((int64_t)rp * rp, 256)), dim3(256), 0, h->stream, C, r, rp, h->Rz);
+  h->small_svd(h->Rz, r);
+  (void)hipMemcpyAsync(s, h->sig, sizeof(double) * r, hipMemcpyDeviceToDevice, h->stream);
+  (void)hipMemcpy2DAsync(P, sizeof(double) * r, h->Ps, sizeof(double) * rp, sizeof(double) * r, r,
+                         hipMemcpyDeviceToDevice, h->stream);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+}  // extern "C"

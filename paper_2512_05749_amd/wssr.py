@@ -1,0 +1,225 @@
+"""ctypes binding of libwssr (include/wssr.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libwssr.so; this module checks
+tensor shapes, dtypes and devices, passes device pointers and the current
+stream, and turns negative status codes into exceptions.  It fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+import torch
+
+_PKG = pathlib.Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libwssr.so"
+
+OK = 0
+WARN_NOT_CONVERGED = 2
+ERR_INVALID_ARG = -1
+ERR_NO_DEVICE = -2
+ERR_OOM = -3
+ERR_HIP = -4
+ERR_NONFINITE = -5
+ERR_BREAKDOWN = -6
+STATUS_NAMES = {0: "OK", 2: "WARN_NOT_CONVERGED", -1: "ERR_INVALID_ARG", -2: "ERR_NO_DEVICE", -3: "ERR_OOM",
+                -4: "ERR_HIP", -5: "ERR_NONFINITE", -6: "ERR_BREAKDOWN"}
+
+F32 = 0
+FLOOR_PRECOND = 0x1
+
+
+class WssrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int64), ("m_max", ctypes.c_int64), ("r_max", ctypes.c_int32),
+                ("q_max", ctypes.c_int32), ("o_dtype", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+_SIGS = {
+    "wssr_create": ([ctypes.POINTER(Config), ctypes.POINTER(_P)], ctypes.c_int),
+    "wssr_destroy": ([_P], ctypes.c_int),
+    "wssr_step": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
+    "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
+    "wssr_last_error": ([_P], ctypes.c_char_p),
+    "wssr_version": ([], ctypes.c_char_p),
+    "wssr_profile": ([_P, _I32], ctypes.c_int),
+    "wssr_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), _I32], ctypes.c_int),
+    "wssr_dbg_sample_side": ([_P, _I64, _I64, _P, _I64, _P, _I32, _P], ctypes.c_int),
+    "wssr_dbg_param_side": ([_P, _I64, _I64, _P, _I64, _P, _I32, _P], ctypes.c_int),
+    "wssr_dbg_gradient": ([_P, _I64, _I64, _P, _I64, _P, _P], ctypes.c_int),
+    "wssr_dbg_cholqr2": ([_P, _I64, _P, _I32, _P, _P], ctypes.c_int),
+    "wssr_dbg_small_svd": ([_P, _P, _I32, _P, _P], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libwssr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_05749_amd.build`")
+        handle = ctypes.CDLL(str(LIB_PATH))
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = handle
+    return _lib
+
+
+def version():
+    return lib().wssr_version().decode()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name, dtype, device, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Wssr:
+    """One libwssr handle bound to a device and a stream."""
+
+    def __init__(self, n_max, m_max, r_max, q_max=8, floor_precond=False, device=None, stream=None):
+        device = torch.device(device if device is not None else "cuda")
+        if device.type != "cuda":
+            raise ValueError("libwssr runs on a HIP device")
+        self.device = torch.device("cuda", device.index if device.index is not None else torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        cfg = Config(int(n_max), int(m_max), int(r_max), int(q_max), F32,
+                     FLOOR_PRECOND if floor_precond else 0, ctypes.c_void_p(s.cuda_stream))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            code = lib().wssr_create(ctypes.byref(cfg), ctypes.byref(h))
+        if code != OK:
+            raise WssrError(code, lib().wssr_last_error(None).decode())
+        self._h = h
+        self.cfg = cfg
+
+    # ------------------------------------------------------------------ util
+    def _check(self, code):
+        if code != OK:
+            raise WssrError(code, lib().wssr_last_error(self._h).decode())
+
+    def _o(self, O):
+        if O.dim() != 2 or O.stride(1) != 1 or O.stride(0) < O.shape[1]:
+            raise ValueError("O must be 2-D, row-major with unit column stride")
+        _need(O, "O", torch.float32, self.device)
+        return O.shape[0], O.shape[1], O.stride(0)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wssr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ step
+    def step(self, O, e_l, V, lam, q=2, delta=None, sigma=None):
+        """One WSSR step.  V (m x r, float32) is updated in place; returns (delta, sigma)."""
+        n, m, ld = self._o(O)
+        if V.dim() != 2 or not V.is_contiguous():
+            raise ValueError("V must be a contiguous m x r tensor")
+        r = V.shape[1]
+        _need(V, "V", torch.float32, self.device, (m, r))
+        _need(e_l, "e_l", torch.float64, self.device, (n,))
+        if not e_l.is_contiguous():
+            raise ValueError("e_l must be contiguous")
+        if delta is None:
+            delta = torch.empty(m, dtype=torch.float64, device=self.device)
+        if sigma is None:
+            sigma = torch.empty(r, dtype=torch.float64, device=self.device)
+        _need(delta, "delta", torch.float64, self.device, (m,))
+        _need(sigma, "sigma", torch.float64, self.device, (r,))
+        self._check(lib().wssr_step(self._h, n, m, _ptr(O), ld, _ptr(e_l), _ptr(V), float(lam), r, int(q),
+                                    _ptr(delta), _ptr(sigma)))
+        return delta, sigma
+
+    def status(self):
+        """Synchronise and return (numeric status code, diagnostics dict)."""
+        code = ctypes.c_int32()
+        diag = (ctypes.c_double * 4)()
+        self._check(lib().wssr_status_sync(self._h, ctypes.byref(code), diag))
+        return code.value, dict(min_rel_pivot=diag[0], jacobi_sweeps=diag[1], jacobi_cosine=diag[2],
+                                cholesky_count=diag[3])
+
+    def profile(self, enable=True):
+        """Start (clearing) or stop recording HIP events around the product kernels."""
+        self._check(lib().wssr_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{'sample_side': (ms, launches), 'param_side': (ms, launches)} since profile(True)."""
+        ms = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int64 * 2)()
+        self._check(lib().wssr_profile_read(self._h, ms, cnt, 2))
+        return {"sample_side": (ms[0], cnt[0]), "param_side": (ms[1], cnt[1])}
+
+    # -------------------------------------------------------- single stages
+    def sample_side(self, O, V):
+        n, m, ld = self._o(O)
+        r = V.shape[1]
+        _need(V, "V", torch.float32, self.device, (m, r))
+        y = torch.empty(n, r, dtype=torch.float64, device=self.device)
+        self._check(lib().wssr_dbg_sample_side(self._h, n, m, _ptr(O), ld, _ptr(V.contiguous()), r, _ptr(y)))
+        return y
+
+    def param_side(self, O, X):
+        n, m, ld = self._o(O)
+        r = X.shape[1]
+        _need(X, "X", torch.float32, self.device, (n, r))
+        z = torch.empty(m, r, dtype=torch.float32, device=self.device)
+        self._check(lib().wssr_dbg_param_side(self._h, n, m, _ptr(O), ld, _ptr(X.contiguous()), r, _ptr(z)))
+        return z
+
+    def gradient(self, O, e_l):
+        n, m, ld = self._o(O)
+        _need(e_l, "e_l", torch.float64, self.device, (n,))
+        g = torch.empty(m, dtype=torch.float64, device=self.device)
+        self._check(lib().wssr_dbg_gradient(self._h, n, m, _ptr(O), ld, _ptr(e_l.contiguous()), _ptr(g)))
+        return g
+
+    def cholqr2(self, X):
+        rows, r = X.shape
+        _need(X, "X", torch.float32, self.device)
+        X = X.contiguous()
+        Q = torch.empty(rows, r, dtype=torch.float32, device=self.device)
+        R = torch.empty(r, r, dtype=torch.float64, device=self.device)
+        self._check(lib().wssr_dbg_cholqr2(self._h, rows, _ptr(X), r, _ptr(Q), _ptr(R)))
+        return Q, R
+
+    def small_svd(self, C):
+        r = C.shape[0]
+        _need(C, "C", torch.float64, self.device, (r, r))
+        C = C.contiguous()
+        s = torch.empty(r, dtype=torch.float64, device=self.device)
+        P = torch.empty(r, r, dtype=torch.float64, device=self.device)
+        self._check(lib().wssr_dbg_small_svd(self._h, _ptr(C), r, _ptr(s), _ptr(P)))
+        return s, P

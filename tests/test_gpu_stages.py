@@ -1,0 +1,121 @@
+"""Stage-by-stage parity of the HIP kernels (through the C ABI) with the FP64
+oracle, on shapes with ragged tiles in every dimension."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import wssr_oracle as orc
+from tests.metrics import orth_err, rel
+from workloads import random_problem
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # (n, m, r): ragged in N, M and r; r crossing one and two 64-column tiles
+    (257, 777, 7),
+    (300, 1001, 40),
+    (1000, 2999, 65),
+    (1024, 2000, 32),
+    (200, 4096, 130),
+]
+
+
+@pytest.fixture(scope="module")
+def ws():
+    from paper_2512_05749_amd import Wssr
+    h = Wssr(n_max=1024, m_max=4096, r_max=192, q_max=8)
+    yield h
+    h.close()
+
+
+def _inputs(n, m, r, seed, ld_pad=0):
+    o, e, v = random_problem(n, m, r, seed=seed, device="cuda")
+    if ld_pad:
+        big = torch.zeros(n, m + ld_pad, device="cuda", dtype=torch.float32)
+        big[:, m:] = float("nan")   # padding must never be read
+        big[:, :m] = o
+        o = big[:, :m]
+    return o, e, v
+
+
+@pytest.mark.parametrize("n,m,r", SHAPES)
+@pytest.mark.parametrize("ld_pad", [0, 3])
+def test_gradient(ws, n, m, r, ld_pad):
+    o, e, _ = _inputs(n, m, r, seed=n + m, ld_pad=ld_pad)
+    g = ws.gradient(o, e).cpu().numpy()
+    ref = orc.gradient(o.double().cpu().numpy(), e.cpu().numpy())
+    assert rel(g, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n,m,r", SHAPES)
+@pytest.mark.parametrize("ld_pad", [0, 4])
+def test_sample_side(ws, n, m, r, ld_pad):
+    o, _, v = _inputs(n, m, r, seed=2 * n + m, ld_pad=ld_pad)
+    y = ws.sample_side(o, v).cpu().numpy()
+    ref = orc.gemm_sample_side(o.double().cpu().numpy(), v.double().cpu().numpy())
+    assert rel(y, ref) < 2e-6
+
+
+@pytest.mark.parametrize("n,m,r", SHAPES)
+def test_param_side(ws, n, m, r):
+    o, _, _ = _inputs(n, m, r, seed=3 * n + m, ld_pad=0)
+    x = torch.randn(n, r, device="cuda", dtype=torch.float32)
+    x -= x.mean(0, keepdim=True)            # columns sum to zero -> O^T X = O_bar^T X
+    z = ws.param_side(o, x).cpu().numpy()
+    ref = orc.gemm_param_side(o.double().cpu().numpy(), x.double().cpu().numpy())
+    assert rel(z, ref) < 2e-6
+
+
+@pytest.mark.parametrize("rows,r", [(100, 1), (333, 7), (1000, 64), (4000, 65), (4096, 130), (2500, 192)])
+def test_cholqr2(ws, rows, r):
+    gen = torch.Generator(device="cuda").manual_seed(rows + r)
+    x = torch.randn(rows, r, device="cuda", generator=gen)
+    x = x * torch.logspace(0, -3, r, device="cuda")[None, :]        # condition number ~1e3
+    q, rr = ws.cholqr2(x)
+    q, rr = q.double().cpu().numpy(), rr.cpu().numpy()
+    xd = x.double().cpu().numpy()
+    assert orth_err(q) < 1e-6
+    assert rel(q @ rr, xd) < 1e-6
+    assert np.allclose(np.tril(rr, -1), 0) and np.all(np.diag(rr) > 0)
+    _, r_ref = orc.qr_positive(xd)
+    assert rel(rr, r_ref) < 1e-6
+
+
+@pytest.mark.parametrize("r", [1, 2, 7, 33, 64, 100, 128, 192])
+@pytest.mark.parametrize("kind", ["random", "graded", "near_diag"])
+def test_small_svd(ws, r, kind):
+    rng = np.random.default_rng(r)
+    if kind == "random":
+        c = rng.standard_normal((r, r))
+    elif kind == "graded":
+        qa = np.linalg.qr(rng.standard_normal((r, r)))[0]
+        qb = np.linalg.qr(rng.standard_normal((r, r)))[0]
+        c = (qa * np.logspace(0, -4, r)) @ qb.T
+    else:   # what the warm-started Rayleigh-Ritz sees: diagonal plus a small perturbation
+        c = np.diag(np.sort(rng.random(r))[::-1] + 0.1) + 1e-2 * rng.standard_normal((r, r))
+    s, p = ws.small_svd(torch.tensor(c, device="cuda"))
+    s, p = s.cpu().numpy(), p.cpu().numpy()
+    _, s_ref, p_ref = orc.jacobi_svd(c)
+    np.testing.assert_allclose(s, s_ref, rtol=1e-10, atol=1e-13 * s_ref[0])
+    assert orth_err(p) < 1e-12
+    # C P = U diag(s) with orthogonal U: columns of C P are orthogonal with norms s
+    cp = c @ p
+    gram = cp.T @ cp
+    assert np.abs(gram - np.diag(s ** 2)).max() < 1e-11 * s[0] ** 2
+    code, diag = ws.status()
+    assert code == 0, diag
+
+
+def test_argument_errors(ws):
+    from paper_2512_05749_amd import WssrError
+    o, e, v = random_problem(100, 300, 8, seed=1, device="cuda")
+    with pytest.raises(WssrError):
+        ws.step(o, e, torch.zeros(300, 100, device="cuda"), 1e-3)          # r > n - 1
+    with pytest.raises(WssrError):
+        ws.step(o, e, v.clone(), 0.0)                                       # lambda <= 0
+    with pytest.raises(WssrError):
+        ws.step(o, e, v.clone(), 1e-3, q=0)
+    with pytest.raises(WssrError):
+        ws.step(o, e, v.clone(), float("inf"))
+    big = torch.zeros(2000, 300, device="cuda")
+    with pytest.raises(WssrError):
+        ws.step(big, torch.zeros(2000, dtype=torch.float64, device="cuda"), v.clone(), 1e-3)   # n > n_max

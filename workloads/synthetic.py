@@ -83,7 +83,7 @@ def _orthonormal(x):
     q, r = torch.linalg.qr(x)
     d = torch.sign(torch.diagonal(r))
     d[d == 0] = 1
-    return q * d
+    return (q * d).contiguous()
 
 
 def _rotate_pairs(x, perm, angle):
@@ -130,7 +130,7 @@ class Workload:
                             device=dev, dtype=self.gen_dtype)
         o.add_(noise, alpha=cfg.eta)
         del noise
-        return o.to(dtype)
+        return o.to(dtype).contiguous()
 
     def e_l(self, t):
         cfg = self.cfg
@@ -142,7 +142,7 @@ class Workload:
         r = r or self.cfg.r
         g = torch.randn(self.m, r, generator=_gen(self.device, self.cfg.seed, "v0"),
                         device=self.device, dtype=self.gen_dtype)
-        return _orthonormal(g).to(dtype)
+        return _orthonormal(g).to(dtype).contiguous()
 
 
 def random_problem(n, m, r, seed, alpha=1.2, eta=1e-3, el_mean=-1.0, el_std=0.1,
