@@ -109,9 +109,11 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
 
 /* Synchronise the handle's stream and read the numerical status of the last
  * step (a wssr_status value) into *numeric_status.  If diag is non-NULL it
- * receives 4 doubles: the smallest relative Cholesky pivot of the last step,
- * the number of Rayleigh-Ritz Jacobi sweeps, the largest remaining column
- * cosine after them, and the number of Cholesky factorisations performed. */
+ * receives 6 doubles: the smallest relative Cholesky pivot of the last step,
+ * the number of Rayleigh-Ritz Jacobi sweeps, the largest column cosine seen in
+ * the last sweep, the number of Cholesky factorisations performed, the
+ * largest condition bound ||R D^-1||_F ||D R^-1||_F of a first CholeskyQR
+ * round (D = column norms), and the number of second CholeskyQR rounds run. */
 wssr_status wssr_status_sync(wssr_handle h, int32_t* numeric_status, double* diag);
 
 /* Text of the last host-side error on this handle (never NULL). */
@@ -150,8 +152,10 @@ wssr_status wssr_dbg_param_side(wssr_handle h, int64_t n, int64_t m, const void*
 wssr_status wssr_dbg_gradient(wssr_handle h, int64_t n, int64_t m, const void* O,
                               int64_t ld_o, const double* e_l, double* g);
 
-/* CholeskyQR2 of a tall matrix X (rows x r, float): X = Q R with Q^T Q = I,
- * R upper triangular with positive diagonal (Alg. 1 "QR decomposition").
+/* CholeskyQR of a tall matrix X (rows x r, float): X = Q R with Q^T Q = I,
+ * R upper triangular with positive diagonal (Alg. 1 "QR decomposition").  The
+ * Gram matrix and the factors are FP64; a second round (CholeskyQR2) runs when
+ * the first round's condition bound exceeds 1e4, as in wssr_step.
  * Q float[rows x r]; R double[r x r] row-major.  rows <= max(n_max, m_max). */
 wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_t r,
                              float* Q, double* R);

@@ -19,6 +19,9 @@ struct DevStatus {
   double jacobi_sweeps;
   double jacobi_cosine;   // largest column cosine left after the Rayleigh-Ritz Jacobi
   int jacobi_done;        // set once a Jacobi sweep found every column pair orthogonal
+  int round2;             // set by a first-round Cholesky when a second CholeskyQR round is needed
+  double kappa_max;       // largest condition bound ||R D^-1||_F ||D R^-1||_F seen
+  int round2_count;       // second rounds actually run
   int pad;
 };
 
@@ -30,6 +33,12 @@ __device__ __forceinline__ void raise_error(DevStatus* st, int code) {
 
 __device__ __forceinline__ bool failed(const DevStatus* st) {
   return *reinterpret_cast<const volatile int*>(&st->code) < 0;
+}
+
+// Kernels of an optional second CholeskyQR round run only when the first
+// round asked for it (st->round2); `gated` selects that behaviour.
+__device__ __forceinline__ bool skipped(const DevStatus* st, bool gated) {
+  return failed(st) || (gated && *reinterpret_cast<const volatile int*>(&st->round2) == 0);
 }
 
 // 32x32x2 FP32 MFMA.  Lane l: A[i][k] with i = l%32, k = l/32; B[k][j] with

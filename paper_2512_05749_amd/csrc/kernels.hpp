@@ -10,9 +10,10 @@ __global__ void k_gradient_partial(const float* O, int64_t ld, int64_t n, int64_
                                    int64_t rows_per_split, double* part, bool vec, const DevStatus* st);
 __global__ void k_gradient_reduce(const double* part, int nsplit, int64_t m, double inv_n, double* g,
                                   const DevStatus* st);
-__global__ void k_ysum(const float* ypart, int nsplit, int64_t n, int r, double* y, double* colpart,
-                       const DevStatus* st);
-__global__ void k_ycenter(double* y, const double* colpart, int nrowblk, int64_t n, int r, double inv_sqrt_n,
+__global__ void k_ysum(const float* ypart, int nsplit, int64_t total, double* y, const DevStatus* st);
+__global__ void k_colsum_partial(const double* y, int64_t n, int r, int rows, double* colpart, const DevStatus* st);
+__global__ void k_colreduce(const double* part, int nchunk, int r, double scale, double* out, const DevStatus* st);
+__global__ void k_ycenter(double* y, const double* mean, int64_t total, int r, double inv_sqrt_n,
                           const DevStatus* st);
 __global__ void k_sign_partial(const float* vnew, const float* vin, int64_t m, int r, int64_t rows_per_chunk,
                                double* dots, float* maxval, int64_t* maxrow, const DevStatus* st);
@@ -27,20 +28,27 @@ __global__ void k_vtg_final(const double* part, int nchunk, int r, const double*
 __global__ void k_delta(const float* v, const double* g, const double* cw, int64_t m, int r, double inv_lambda,
                         double* delta, const DevStatus* st);
 
+template <int BN>
 __global__ void k_gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* V, int r,
                                    float* ypart, int64_t kchunk, bool vec_o, bool vec_v, const DevStatus* st);
+template <int BN>
 __global__ void k_gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
                                   float scale, float* Z, bool vec_o, bool vec_q, const DevStatus* st);
 
 template <typename T>
 __global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,
-                               const DevStatus* st);
-__global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, double* G, const DevStatus* st);
+                               const DevStatus* st, bool gated);
+__global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, double* G, const DevStatus* st,
+                              bool gated);
 template <typename Tin, typename Tout>
 __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
-                        Tout* Out, int ldo, bool upper, const DevStatus* st);
+                        Tout* Out, int ldo, bool upper, const DevStatus* st, bool gated);
 
-__global__ void k_cholinv(double* G, int rp, double* R, double* Ri, DevStatus* st);
+// mode 0: first CholeskyQR round (sets st->round2 from the condition bound of
+// the factor: kappa_F > kappa_round2); mode 1: gated second round (writes
+// identity factors when st->round2 is 0); mode 2: plain.
+__global__ void k_cholinv(double* G, int rp, int r, double* R, double* Ri, DevStatus* st, int mode,
+                          double kappa_round2);
 __global__ void k_jacobi_prep(const double* Ct, int rp, int r, double* Bc, double* Pc, double* scal,
                               DevStatus* st);
 __global__ void k_jacobi_round(double* Bc, double* Pc, int rp, int rd, double tol, const double* scal,

@@ -21,8 +21,8 @@ constexpr int GP = 1;      // LDS row pad (doubles)
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ X, int64_t rows, int r, int ntile,
                                                       int64_t rows_per_chunk, double* __restrict__ part,
-                                                      const DevStatus* st) {
-  if (failed(st)) return;
+                                                      const DevStatus* st, bool gated) {
+  if (skipped(st, gated)) return;
   __shared__ double XI[GK][GT + GP];
   __shared__ double XJ[GK][GT + GP];
   // decode pair index -> (I, J), I <= J, row-major over the upper triangle
@@ -90,10 +90,11 @@ __global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ X, i
 }
 
 // Sum the partials in chunk order and write the symmetric rp x rp Gram matrix,
-// identity on the padding (rows/columns >= r).  grid.x = npairs, 256 threads.
+// identity on the padding (rows/columns >= r).  grid (npairs, 16): block y
+// covers 256 of the 4096 entries of its tile, one entry per thread.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nchunk, int ntile, int r,
-                                                     double* __restrict__ G, const DevStatus* st) {
-  if (failed(st)) return;
+                                                     double* __restrict__ G, const DevStatus* st, bool gated) {
+  if (skipped(st, gated)) return;
   int pair = blockIdx.x, I = 0;
   {
     int rem = pair;
@@ -106,19 +107,28 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   const int J = pair;
   const int npairs = ntile * (ntile + 1) / 2;
   const int rp = ntile * GT;
-  for (int e = threadIdx.x; e < GT * GT; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    const int gi = I * GT + i, gj = J * GT + j;
-    double s;
-    if (gi < r && gj < r) {
-      s = 0.0;
-      for (int c = 0; c < nchunk; ++c) s += part[((int64_t)c * npairs + blockIdx.x) * (GT * GT) + e];
-    } else {
-      s = (gi == gj) ? 1.0 : 0.0;
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  const int i = e >> 6, j = e & 63;
+  const int gi = I * GT + i, gj = J * GT + j;
+  double s;
+  if (gi < r && gj < r) {
+    const double* p = part + (int64_t)blockIdx.x * (GT * GT) + e;
+    const int64_t stride = (int64_t)npairs * (GT * GT);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int c = 0;
+    for (; c + 3 < nchunk; c += 4) {
+      a0 += p[(c + 0) * stride];
+      a1 += p[(c + 1) * stride];
+      a2 += p[(c + 2) * stride];
+      a3 += p[(c + 3) * stride];
     }
-    G[(int64_t)gi * rp + gj] = s;
-    G[(int64_t)gj * rp + gi] = s;
+    for (; c < nchunk; ++c) a0 += p[c * stride];
+    s = (a0 + a1) + (a2 + a3);
+  } else {
+    s = (gi == gj) ? 1.0 : 0.0;
   }
+  G[(int64_t)gi * rp + gj] = s;
+  G[(int64_t)gj * rp + gi] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -129,8 +139,9 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void k_apply(const Tin* __restrict__ X, int64_t rows, int ldx, int kdim,
                                                const double* __restrict__ Tm, int rp, int ncol,
-                                               Tout* __restrict__ Out, int ldo, bool upper, const DevStatus* st) {
-  if (failed(st)) return;
+                                               Tout* __restrict__ Out, int ldo, bool upper, const DevStatus* st,
+                                               bool gated) {
+  if (skipped(st, gated)) return;
   __shared__ double Xs[GK][GT + GP];   // [k][row]
   __shared__ double Ts[GK][GT + GP];   // [k][col]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -189,13 +200,15 @@ __global__ __launch_bounds__(256) void k_apply(const Tin* __restrict__ X, int64_
 }
 
 // explicit instantiations used by the host runtime
-template __global__ void k_gram_partial<float>(const float*, int64_t, int, int, int64_t, double*, const DevStatus*);
-template __global__ void k_gram_partial<double>(const double*, int64_t, int, int, int64_t, double*, const DevStatus*);
+template __global__ void k_gram_partial<float>(const float*, int64_t, int, int, int64_t, double*, const DevStatus*,
+                                               bool);
+template __global__ void k_gram_partial<double>(const double*, int64_t, int, int, int64_t, double*, const DevStatus*,
+                                                bool);
 template __global__ void k_apply<float, float>(const float*, int64_t, int, int, const double*, int, int, float*, int,
-                                               bool, const DevStatus*);
+                                               bool, const DevStatus*, bool);
 template __global__ void k_apply<double, float>(const double*, int64_t, int, int, const double*, int, int, float*,
-                                                int, bool, const DevStatus*);
+                                                int, bool, const DevStatus*, bool);
 template __global__ void k_apply<double, double>(const double*, int64_t, int, int, const double*, int, int, double*,
-                                                 int, bool, const DevStatus*);
+                                                 int, bool, const DevStatus*, bool);
 
 }  // namespace wssr

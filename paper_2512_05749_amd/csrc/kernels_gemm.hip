@@ -1,36 +1,43 @@
 // The two tall-skinny products of each subspace-iteration pass (Alg. 1), in
 // FP32 on the 32x32x2 FP32 MFMA with LDS-staged, double-buffered tiles.
 //
-//   sample side   Ypart[s] = O[:, Ks] V[Ks, :]     (N x r, K = M split into S ranges)
-//   parameter side Z = O^T Q / sqrt(N)              (M x r, K = N)
+//   sample side    Ypart[s] = O[:, Ks] V[Ks, :]     (N x r, K = M split into S ranges)
+//   parameter side Z = O^T Q * scale                 (M x r, K = N)
 //
-// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement, 128 x 128 output
-// tile, each wave a 64 x 64 block = 2 x 2 MFMA tiles of 32 x 32.  K advances
-// in steps of 32.
+// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; output tile
+// 128 rows x BN columns (BN = 128 or 256 over the rank dimension); each wave
+// owns a 64 x (BN/2) sub-tile = 2 x (BN/64) MFMA tiles of 32 x 32, i.e. 8 FP32
+// accumulator tiles at BN = 256.  K advances 16 at a time; one barrier per
+// K-step; the next tile's global loads are in flight during the MFMAs.
+// Inside a K-step the contraction index is permuted: lane (x, h) = (l%32,
+// l/32) feeds k = h*8 + s to MFMA step s (0 <= s < 8) for both operands, which
+// lets each lane read 4 consecutive k of an O row with one 16-byte LDS read.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace wssr {
 
 namespace {
-constexpr int BM = 128, BN = 128, BK = 32;
-constexpr int APAD = 4, BPAD = 4;
+constexpr int BM = 128, BK = 16;
+constexpr int PADK = 4;   // pad of K-contiguous rows (floats)
+constexpr int PADC = 4;   // pad of column-contiguous rows (floats)
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Sample-side product.  O is N x M row-major (K contiguous), V is M x r
-// row-major.  The contraction index inside a K-step is permuted so that each
-// lane reads 4 consecutive K values of its O row with one 16-byte LDS read:
-// lane (x, h) = (l%32, l/32) feeds k = h*16 + s to MFMA step s, for both
-// operands.
+// Sample side.  O is N x M row-major (K contiguous), V is M x r row-major.
+// grid (n tiles, r tiles, S).
 // ---------------------------------------------------------------------------
+template <int BN>
 __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __restrict__ O, int64_t ld, int64_t n,
                                                              int64_t m, const float* __restrict__ V, int r,
                                                              float* __restrict__ ypart, int64_t kchunk,
                                                              bool vec_o, bool vec_v, const DevStatus* st) {
   if (failed(st)) return;
-  __shared__ __attribute__((aligned(16))) float As[2][BM][BK + APAD];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BK][BN + BPAD];
+  constexpr int TB = BN / 64;                 // rank blocks per wave
+  constexpr int AV = BM * BK / 4 / 256;       // float4 per thread for the O tile (2)
+  constexpr int BV = BK * BN / 4 / 256;       // float4 per thread for the V tile (2 or 4)
+  __shared__ __attribute__((aligned(16))) float As[2][BM][BK + PADK];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK][BN + PADC];
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
@@ -41,72 +48,87 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
   const int64_t ke = min(m, kb + kchunk);
   float* out = ypart + (int64_t)blockIdx.z * n * r;
 
-  f32x16 acc[2][2];
+  f32x16 acc[2][TB];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{0};
+    for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
 
-  // global -> register staging: A tile 128 x 32 (4 float4 per thread),
-  // B tile 32 x 128 (4 float4 per thread)
-  f32x4 ra[4], rb[4];
+  f32x4 ra[AV], rb[BV];
+  // interior tiles (whole tile in range, 16-byte aligned rows) take plain
+  // vector loads; edge tiles the guarded path
+  const bool inner = vec_o && vec_v && (n0 + BM <= n) && (j0 + BN <= r);
   auto gload = [&](int64_t k0) {
+    if (inner && k0 + BK <= ke) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = (t >> 3) + 32 * i;
-      const int kq = (t & 7) * 4;
+      for (int i = 0; i < AV; ++i) {
+        const int idx = t + 256 * i;
+        const int row = idx >> 2, kq = (idx & 3) * 4;
+        ra[i] = *reinterpret_cast<const f32x4*>(O + (n0 + row) * ld + k0 + kq);
+      }
+#pragma unroll
+      for (int i = 0; i < BV; ++i) {
+        const int idx = t + 256 * i;
+        const int krow = idx / (BN / 4), jq = (idx % (BN / 4)) * 4;
+        rb[i] = *reinterpret_cast<const f32x4*>(V + (k0 + krow) * r + j0 + jq);
+      }
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+      const int idx = t + 256 * i;
+      const int row = idx >> 2, kq = (idx & 3) * 4;
       const int64_t gi = n0 + row;
       ra[i] = (gi < n) ? load4(O + gi * ld, k0 + kq, ke, vec_o) : f32x4{0};
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int krow = (t >> 5) + 8 * i;
-      const int jq = (t & 31) * 4;
+    for (int i = 0; i < BV; ++i) {
+      const int idx = t + 256 * i;
+      const int krow = idx / (BN / 4), jq = (idx % (BN / 4)) * 4;
       const int64_t gk = k0 + krow;
       rb[i] = (gk < ke) ? load4(V + gk * r, j0 + jq, r, vec_v) : f32x4{0};
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = (t >> 3) + 32 * i;
-      const int kq = (t & 7) * 4;
+    for (int i = 0; i < AV; ++i) {
+      const int idx = t + 256 * i;
+      const int row = idx >> 2, kq = (idx & 3) * 4;
       *reinterpret_cast<f32x4*>(&As[buf][row][kq]) = ra[i];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int krow = (t >> 5) + 8 * i;
-      const int jq = (t & 31) * 4;
+    for (int i = 0; i < BV; ++i) {
+      const int idx = t + 256 * i;
+      const int krow = idx / (BN / 4), jq = (idx % (BN / 4)) * 4;
       *reinterpret_cast<f32x4*>(&Bs[buf][krow][jq]) = rb[i];
     }
   };
 
-  const int64_t nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
-  if (nk > 0) {
-    gload(kb);
-    sstore(0);
-  }
+  const int64_t nk = (ke - kb + BK - 1) / BK;
+  gload(kb);
+  sstore(0);
   __syncthreads();
   for (int64_t it = 0; it < nk; ++it) {
     const int buf = (int)(it & 1);
     if (it + 1 < nk) gload(kb + (it + 1) * BK);
 #pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4) {
+    for (int half = 0; half < 2; ++half) {
+      // fragments for MFMA steps s = 4*half .. 4*half+3
       f32x4 av[2];
+      float bv[4][TB];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
-        av[a] = *reinterpret_cast<const f32x4*>(&As[buf][wm * 64 + a * 32 + x][h * 16 + q4 * 4]);
+        av[a] = *reinterpret_cast<const f32x4*>(&As[buf][wm * 64 + a * 32 + x][h * 8 + half * 4]);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int kk = h * 16 + q4 * 4 + e;
-        float bv[2];
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk][wn * 64 + b * 32 + x];
+        for (int b = 0; b < TB; ++b) bv[e][b] = Bs[buf][h * 8 + half * 4 + e][wn * (BN / 2) + b * 32 + x];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = mfma32x32x2(av[a][e], bv[b], acc[a][b]);
-      }
+          for (int b = 0; b < TB; ++b) acc[a][b] = mfma32x32x2(av[a][e], bv[e][b], acc[a][b]);
     }
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
@@ -115,8 +137,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int col = j0 + wn * 64 + b * 32 + x;
+    for (int b = 0; b < TB; ++b) {
+      const int col = j0 + wn * (BN / 2) + b * 32 + x;
       if (col >= r) continue;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -127,18 +149,22 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Parameter-side product Z = O^T Q * scale.  O is N x M row-major, Q is N x r
+// Parameter side Z = O^T Q * scale.  O is N x M row-major, Q is N x r
 // row-major; both tiles are staged K-major ([k][column]) so every lane reads
 // consecutive addresses.  The MFMA computes the transposed block Z^T:
-// A[i][k] = Q[k][j0+i], B[k][jj] = O[k][m0+jj].
+// A[i][k] = Q[k][j0+i], B[k][jj] = O[k][m0+jj].  grid (m tiles, r tiles).
 // ---------------------------------------------------------------------------
+template <int BN>
 __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restrict__ O, int64_t ld, int64_t n,
                                                             int64_t m, const float* __restrict__ Q, int r,
                                                             float scale, float* __restrict__ Z, bool vec_o,
                                                             bool vec_q, const DevStatus* st) {
   if (failed(st)) return;
-  __shared__ __attribute__((aligned(16))) float Os[2][BK][BM + BPAD];
-  __shared__ __attribute__((aligned(16))) float Qs[2][BK][BN + BPAD];
+  constexpr int TB = BN / 64;
+  constexpr int OV = BK * BM / 4 / 256;       // float4 per thread for the O tile (2)
+  constexpr int QV = BK * BN / 4 / 256;       // float4 per thread for the Q tile (2 or 4)
+  __shared__ __attribute__((aligned(16))) float Os[2][BK][BM + PADC];
+  __shared__ __attribute__((aligned(16))) float Qs[2][BK][BN + PADC];
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wj = w & 1;
@@ -146,29 +172,56 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
   const int64_t m0 = (int64_t)blockIdx.x * BM;
   const int j0 = blockIdx.y * BN;
 
-  f32x16 acc[2][2];
+  f32x16 acc[TB][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TB; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{0};
 
-  f32x4 ro[4], rq[4];
+  f32x4 ro[OV], rq[QV];
+  const bool inner = vec_o && vec_q && (m0 + BM <= m) && (j0 + BN <= r);
   auto gload = [&](int64_t k0) {
+    if (inner && k0 + BK <= n) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int krow = (t >> 5) + 8 * i;
-      const int cq = (t & 31) * 4;
+      for (int i = 0; i < OV; ++i) {
+        const int idx = t + 256 * i;
+        const int krow = idx / (BM / 4), cq = (idx % (BM / 4)) * 4;
+        ro[i] = *reinterpret_cast<const f32x4*>(O + (k0 + krow) * ld + m0 + cq);
+      }
+#pragma unroll
+      for (int i = 0; i < QV; ++i) {
+        const int idx = t + 256 * i;
+        const int krow = idx / (BN / 4), cq = (idx % (BN / 4)) * 4;
+        rq[i] = *reinterpret_cast<const f32x4*>(Q + (k0 + krow) * r + j0 + cq);
+      }
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < OV; ++i) {
+      const int idx = t + 256 * i;
+      const int krow = idx / (BM / 4), cq = (idx % (BM / 4)) * 4;
       const int64_t gk = k0 + krow;
       ro[i] = (gk < n) ? load4(O + gk * ld, m0 + cq, m, vec_o) : f32x4{0};
+    }
+#pragma unroll
+    for (int i = 0; i < QV; ++i) {
+      const int idx = t + 256 * i;
+      const int krow = idx / (BN / 4), cq = (idx % (BN / 4)) * 4;
+      const int64_t gk = k0 + krow;
       rq[i] = (gk < n) ? load4(Q + gk * r, j0 + cq, r, vec_q) : f32x4{0};
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int krow = (t >> 5) + 8 * i;
-      const int cq = (t & 31) * 4;
+    for (int i = 0; i < OV; ++i) {
+      const int idx = t + 256 * i;
+      const int krow = idx / (BM / 4), cq = (idx % (BM / 4)) * 4;
       *reinterpret_cast<f32x4*>(&Os[buf][krow][cq]) = ro[i];
+    }
+#pragma unroll
+    for (int i = 0; i < QV; ++i) {
+      const int idx = t + 256 * i;
+      const int krow = idx / (BN / 4), cq = (idx % (BN / 4)) * 4;
       *reinterpret_cast<f32x4*>(&Qs[buf][krow][cq]) = rq[i];
     }
   };
@@ -181,37 +234,60 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
     const int buf = (int)(it & 1);
     if (it + 1 < nk) gload((it + 1) * BK);
 #pragma unroll
-    for (int s = 0; s < BK / 2; ++s) {
-      const int kk = h * 16 + s;
-      float av[2], bv[2];
+    for (int half = 0; half < 2; ++half) {
+      float av[4][TB], bv[4][2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = Qs[buf][kk][wj * 64 + a * 32 + x];
+      for (int e = 0; e < 4; ++e) {
+        const int kk = h * 8 + half * 4 + e;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Os[buf][kk][wm * 64 + b * 32 + x];
+        for (int a = 0; a < TB; ++a) av[e][a] = Qs[buf][kk][wj * (BN / 2) + a * 32 + x];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) bv[e][b] = Os[buf][kk][wm * 64 + b * 32 + x];
+      }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma32x32x2(av[a], bv[b], acc[a][b]);
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int a = 0; a < TB; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = mfma32x32x2(av[e][a], bv[e][b], acc[a][b]);
     }
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
 
-  // acc[a][b] holds Z^T rows (j) a-block, columns (m) b-block
+  // acc[a][b]: rows (rank index) of block a, columns (parameter index) of block b
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TB; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int64_t row = m0 + wm * 64 + b * 32 + x;
       if (row >= m) continue;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int jb = j0 + wj * 64 + a * 32 + 8 * g + 4 * h;
+        const int jb = j0 + wj * (BN / 2) + a * 32 + 8 * g + 4 * h;
+        if (jb + 3 < r) {
+          f32x4 v4;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v4[e] = acc[a][b][4 * g + e] * scale;
+          if ((r & 3) == 0) {
+            *reinterpret_cast<f32x4*>(&Z[row * r + jb]) = v4;
+            continue;
+          }
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           if (jb + e < r) Z[row * r + jb + e] = acc[a][b][4 * g + e] * scale;
       }
     }
 }
+
+template __global__ void k_gemm_sample_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
+                                                 int64_t, bool, bool, const DevStatus*);
+template __global__ void k_gemm_sample_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
+                                                 int64_t, bool, bool, const DevStatus*);
+template __global__ void k_gemm_param_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
+                                                float*, bool, bool, const DevStatus*);
+template __global__ void k_gemm_param_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
+                                                float*, bool, bool, const DevStatus*);
 
 }  // namespace wssr

@@ -74,21 +74,45 @@ __device__ __forceinline__ f64x4 tile_to_acc(const double (*T)[TP]) {
 // row-major; rp a multiple of 64 (padding rows/columns of G are identity).
 // One workgroup.  G is overwritten (trailing updates).  A pivot d_k with
 // !(d_k > rp * eps * G_kk) is a breakdown (NaN: non-finite input).
+//
+// Blocked right-looking over 64-wide block columns.  Each 64 x 64 diagonal
+// tile is factored by a single wavefront (lane j owns column j; no workgroup
+// barriers inside), its triangular inverse is formed one column per
+// wavefront (lanes = rows), and the panel and trailing updates are 64 x 64 x 64
+// tile products on the FP64 MFMA by all 16 wavefronts.
+//
+// mode 0 (first CholeskyQR round) also computes the condition bound
+// kappa_F = ||R D^-1||_F ||D R^-1||_F with D = diag(G)^(1/2), an upper bound
+// on the 2-norm condition number of the column-equilibrated input, and sets
+// st->round2 = (kappa_F > kappa_round2): one round leaves an orthogonality
+// error of order eps * kappa^2, so a second round is run only when that is
+// not negligible.  mode 1 (the gated second round) writes identity factors
+// when st->round2 is 0.  mode 2 is a plain factorisation.
 // Dynamic LDS: 4 tiles.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp, double* __restrict__ R,
-                                                 double* __restrict__ Ri, DevStatus* st) {
+__global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp, int r, double* __restrict__ R,
+                                                 double* __restrict__ Ri, DevStatus* st, int mode,
+                                                 double kappa_round2) {
   if (failed(st)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (mode == 1 && *reinterpret_cast<volatile int*>(&st->round2) == 0) {
+    for (int64_t e = tid; e < (int64_t)rp * rp; e += NTH) {
+      const double v = ((e / rp) == (e % rp)) ? 1.0 : 0.0;
+      R[e] = v;
+      Ri[e] = v;
+    }
+    return;
+  }
   extern __shared__ double smem[];
   double(*T0)[TP] = reinterpret_cast<double(*)[TP]>(smem);
   double(*T1)[TP] = reinterpret_cast<double(*)[TP]>(smem + TS * TP);
   double(*T2)[TP] = reinterpret_cast<double(*)[TP]>(smem + 2 * TS * TP);
   double(*T3)[TP] = reinterpret_cast<double(*)[TP]>(smem + 3 * TS * TP);
   __shared__ double dorig[512];
-  __shared__ double piv;
+  __shared__ double invd[TS];
   __shared__ int err;
   __shared__ double minrel;
-  const int tid = threadIdx.x;
+  __shared__ double red[2][NTH / 64];
   const int nt = rp / TS;
   const double tiny = (double)rp * 2.220446049250313e-16;
   for (int i = tid; i < rp; i += NTH) dorig[i] = G[(int64_t)i * rp + i];
@@ -96,7 +120,6 @@ __global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp,
     err = 0;
     minrel = 1.0;
   }
-  // lower tiles of R and Ri are zero
   for (int bi = 1; bi < nt; ++bi)
     for (int bj = 0; bj < bi; ++bj) {
       tile_fill(R, rp, bi, bj, 0.0, 0.0);
@@ -106,51 +129,58 @@ __global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp,
 
   for (int kb = 0; kb < nt; ++kb) {
     tile_load(T0, G, rp, kb, kb);
-    // T1 = identity for the inverse of the diagonal block
-    for (int e = tid; e < TS * TS; e += NTH) T1[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
     __syncthreads();
-    // unblocked upper Cholesky of the diagonal tile
-    for (int k = 0; k < TS; ++k) {
-      if (tid == 0) {
+    if (wv == 0) {
+      // right-looking factorisation of the diagonal tile, lane j = column j
+      const int j = lane;
+      double mrel = 1.0;
+      int bad = 0;
+      for (int k = 0; k < TS; ++k) {
         const double d = T0[k][k];
         const double d0 = dorig[kb * TS + k];
         if (!(d > tiny * d0)) {
-          err = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
-        } else {
-          piv = sqrt(d);
-          const double rel = sqrt(d / d0);
-          if (rel < minrel) minrel = rel;
+          bad = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
+          break;
         }
+        const double piv = sqrt(d);
+        mrel = fmin(mrel, sqrt(d / d0));
+        const double rkj = (j > k) ? T0[k][j] / piv : piv;
+        __builtin_amdgcn_wave_barrier();
+        if (j >= k) T0[k][j] = rkj;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (j > k)
+          for (int i = k + 1; i <= j; ++i) T0[i][j] -= T0[k][i] * rkj;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      __syncthreads();
-      if (err) break;
-      const double p = piv;
-      if (tid > k && tid < TS) T0[k][tid] /= p;
-      __syncthreads();
-      for (int e = tid; e < TS * TS; e += NTH) {
-        const int i = e >> 6, j = e & 63;
-        if (i > k && j >= i) T0[i][j] -= T0[k][i] * T0[k][j];
+      if (lane == 0) {
+        if (bad) err = bad;
+        if (mrel < minrel) minrel = mrel;
       }
-      if (tid == 0) T0[k][k] = p;
-      __syncthreads();
     }
+    __syncthreads();
     if (err) break;
     for (int e = tid; e < TS * TS; e += NTH) {
       const int i = e >> 6, j = e & 63;
       if (i > j) T0[i][j] = 0.0;
     }
+    if (tid < TS) invd[tid] = 1.0 / T0[tid][tid];
     __syncthreads();
-    // inverse of the upper triangular tile (Gauss-Jordan from the bottom row)
-    for (int k = TS - 1; k >= 0; --k) {
-      const double s = 1.0 / T0[k][k];
-      if (tid >= k && tid < TS) T1[k][tid] *= s;
-      __syncthreads();
-      for (int e = tid; e < TS * TS; e += NTH) {
-        const int i = e >> 6, j = e & 63;
-        if (i < k && j >= k) T1[i][j] -= T0[i][k] * T1[k][j];
+    // inverse of the triangular tile: column j by back substitution, one
+    // wavefront per column (lanes = rows)
+    for (int j = wv; j < TS; j += NTH / 64) {
+      double b = (lane == j) ? 1.0 : 0.0, x = 0.0;
+      for (int l = j; l >= 0; --l) {
+        const double xl = __shfl(b, l, 64) * invd[l];
+        if (lane == l) x = xl;
+        if (lane < l) b -= T0[lane][l] * xl;
       }
-      __syncthreads();
+      T1[lane][j] = (lane <= j) ? x : 0.0;
     }
+    __syncthreads();
     tile_store(R, rp, kb, kb, T0);
     tile_store(Ri, rp, kb, kb, T1);
     // panel: R[kb][j] = R_kk^{-T} G[kb][j]
@@ -207,9 +237,43 @@ __global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp,
       __syncthreads();
     }
   }
+  if (mode == 0) {
+    // kappa_F over the real r x r block
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t e = tid; e < (int64_t)rp * rp; e += NTH) {
+      const int i = (int)(e / rp), j = (int)(e % rp);
+      if (i <= j && j < r) {
+        const double a = R[e] / sqrt(dorig[j]);
+        const double b = Ri[e] * sqrt(dorig[i]);
+        s1 += a * a;
+        s2 += b * b;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s1 += __shfl_xor(s1, o, 64);
+      s2 += __shfl_xor(s2, o, 64);
+    }
+    if (lane == 0) {
+      red[0][wv] = s1;
+      red[1][wv] = s2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < NTH / 64; ++w) {
+        a += red[0][w];
+        b += red[1][w];
+      }
+      const double kap = sqrt(a * b);
+      const int need = !(kap <= kappa_round2);
+      st->round2 = need;
+      if (need) st->round2_count += 1;
+      if (kap > st->kappa_max) st->kappa_max = kap;
+    }
+  }
   if (tid == 0) {
-    atomicAdd(&st->chol_count, 1);
-    // diagnostics only; one writer per launch, launches are stream-ordered
+    st->chol_count += 1;
     if (minrel < st->min_rel_pivot) st->min_rel_pivot = minrel;
   }
 }
@@ -316,7 +380,9 @@ __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, d
   __syncthreads();
   if (!(red[0] > tol)) return;
 
-  // cyclic Jacobi on the 64 x 64 Gram, accumulating the rotation in Js
+  // cyclic Jacobi on the 64 x 64 Gram, accumulating the rotation in Js.  Per
+  // round: the 32 rotation parameters, then every thread transforms one 2 x 2
+  // block (row pair a, column pair b) of H and two entries of J.
   for (int sweep = 0; sweep < 16; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -328,7 +394,8 @@ __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, d
         double c = 1.0, s = 0.0;
         if (a > floor && d > floor && fabs(b) > absfloor && fabs(b) > tol * sqrt(a * d)) {
           const double zeta = (d - a) / (2.0 * b);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+          const double az = fabs(zeta);
+          const double tt = az > 1e100 ? 0.5 / zeta : (zeta >= 0.0 ? 1.0 : -1.0) / (az + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + tt * tt);
           s = c * tt;
           rotated = 1;
@@ -339,28 +406,32 @@ __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, d
         qq[tid] = q;
       }
       __syncthreads();
-      // rows p, q of H
-      for (int e = tid; e < 32 * TS; e += NTH) {
-        const int k = e >> 6, col = e & 63;
-        const double s = sn[k];
-        if (s != 0.0) {
-          const double c = cs[k];
-          const double hp = Hs[pp[k]][col], hq = Hs[qq[k]][col];
-          Hs[pp[k]][col] = c * hp - s * hq;
-          Hs[qq[k]][col] = s * hp + c * hq;
+      {
+        const int a = tid >> 5, b = tid & 31;
+        const double sa = sn[a], sb = sn[b];
+        if (sa != 0.0 || sb != 0.0) {
+          const double ca = cs[a], cb = cs[b];
+          const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+          const double x11 = Hs[pa][pb], x12 = Hs[pa][qb], x21 = Hs[qa][pb], x22 = Hs[qa][qb];
+          const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
+          const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
+          double z11 = cb * y11 - sb * y12, z12 = sb * y11 + cb * y12;
+          double z21 = cb * y21 - sb * y22, z22 = sb * y21 + cb * y22;
+          if (a == b && sa != 0.0) z12 = z21 = 0.0;
+          Hs[pa][pb] = z11;
+          Hs[pa][qb] = z12;
+          Hs[qa][pb] = z21;
+          Hs[qa][qb] = z22;
         }
-      }
-      __syncthreads();
-      // columns p, q of H and of J
-      for (int e = tid; e < 2 * 32 * TS; e += NTH) {
-        const int which = e >> 11, k = (e >> 6) & 31, row = e & 63;
-        const double s = sn[k];
-        if (s != 0.0) {
-          const double c = cs[k];
-          double(*M)[TP] = which ? Js : Hs;
-          const double xp = M[row][pp[k]], xq = M[row][qq[k]];
-          M[row][pp[k]] = c * xp - s * xq;
-          M[row][qq[k]] = s * xp + c * xq;
+        for (int e = tid; e < 32 * TS; e += NTH) {
+          const int k = e >> 6, row = e & 63;
+          const double sk = sn[k];
+          if (sk != 0.0) {
+            const double ck = cs[k];
+            const double xp = Js[row][pp[k]], xq = Js[row][qq[k]];
+            Js[row][pp[k]] = ck * xp - sk * xq;
+            Js[row][qq[k]] = sk * xp + ck * xq;
+          }
         }
       }
       __syncthreads();

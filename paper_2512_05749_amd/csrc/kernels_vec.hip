@@ -80,42 +80,63 @@ __global__ __launch_bounds__(256) void k_gradient_reduce(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Sample side: y = sum_s ypart[s] (split-K partial products), then centre the
-// columns and scale: y <- (y - 1 mean^T) / sqrt(N)   (implicit centring of O:
-// O_bar V = O V - 1 (mu^T V), and mu^T V is the column mean of O V).
-// grid (row blocks of 64, column blocks of 256).
+// Sample side: y = sum_s ypart[s] (split-K partial products, fixed order), then
+// centre the columns and scale: y <- (y - 1 mean^T) / sqrt(N).  This is the
+// implicit centring of O: O_bar V = O V - 1 (mu^T V), and mu^T V is the
+// column mean of O V.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ysum(const float* __restrict__ ypart, int nsplit, int64_t n, int r,
-                                              double* __restrict__ y, double* __restrict__ colpart,
-                                              const DevStatus* st) {
+__global__ __launch_bounds__(256) void k_ysum(const float* __restrict__ ypart, int nsplit, int64_t total,
+                                              double* __restrict__ y, const DevStatus* st) {
   if (failed(st)) return;
-  const int j = blockIdx.y * 256 + threadIdx.x;
-  if (j >= r) return;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int64_t i1 = min(n, i0 + 64);
-  const int64_t plane = n * r;
-  double cs = 0.0;
-  for (int64_t i = i0; i < i1; ++i) {
-    double v = 0.0;
-    for (int s = 0; s < nsplit; ++s) v += (double)ypart[s * plane + i * r + j];
-    y[i * r + j] = v;
-    cs += v;
-  }
-  colpart[(int64_t)blockIdx.x * r + j] = cs;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  double v = 0.0;
+  for (int s = 0; s < nsplit; ++s) v += (double)ypart[s * total + e];
+  y[e] = v;
 }
 
-__global__ __launch_bounds__(256) void k_ycenter(double* __restrict__ y, const double* __restrict__ colpart,
-                                                 int nrowblk, int64_t n, int r, double inv_sqrt_n,
-                                                 const DevStatus* st) {
+// Column sums over row blocks: grid (row blocks of `rows` rows, column blocks of 256).
+__global__ __launch_bounds__(256) void k_colsum_partial(const double* __restrict__ y, int64_t n, int r, int rows,
+                                                        double* __restrict__ colpart, const DevStatus* st) {
   if (failed(st)) return;
   const int j = blockIdx.y * 256 + threadIdx.x;
   if (j >= r) return;
-  double cs = 0.0;
-  for (int b = 0; b < nrowblk; ++b) cs += colpart[(int64_t)b * r + j];
-  const double mean = cs / (double)n;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int64_t i1 = min(n, i0 + 64);
-  for (int64_t i = i0; i < i1; ++i) y[i * r + j] = (y[i * r + j] - mean) * inv_sqrt_n;
+  const int64_t i0 = (int64_t)blockIdx.x * rows;
+  const int64_t i1 = min(n, i0 + rows);
+  double a0 = 0.0, a1 = 0.0;
+  int64_t i = i0;
+  for (; i + 1 < i1; i += 2) {
+    a0 += y[i * r + j];
+    a1 += y[(i + 1) * r + j];
+  }
+  if (i < i1) a0 += y[i * r + j];
+  colpart[(int64_t)blockIdx.x * r + j] = a0 + a1;
+}
+
+// Column reduction of partials part[c][j] over c (fixed order): one block of
+// 256 threads per column, tree sum; out[j] = scale * sum.
+__global__ __launch_bounds__(256) void k_colreduce(const double* __restrict__ part, int nchunk, int r, double scale,
+                                                   double* __restrict__ out, const DevStatus* st) {
+  if (failed(st)) return;
+  __shared__ double red[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  double a = 0.0;
+  for (int c = t; c < nchunk; c += 256) a += part[(int64_t)c * r + j];
+  red[t] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[j] = scale * red[0];
+}
+
+__global__ __launch_bounds__(256) void k_ycenter(double* __restrict__ y, const double* __restrict__ mean,
+                                                 int64_t total, int r, double inv_sqrt_n, const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  y[e] = (y[e] - mean[e % r]) * inv_sqrt_n;
 }
 
 // ---------------------------------------------------------------------------
@@ -150,29 +171,47 @@ __global__ __launch_bounds__(256) void k_sign_partial(const float* __restrict__ 
   maxrow[o] = bestrow;
 }
 
-// Stage 2 (one block): sign_j from the partials; also copies sigma out.
-__global__ __launch_bounds__(512) void k_sign_final(const double* __restrict__ dots, const float* __restrict__ maxval,
+// Stage 2 (one block of 256 threads per column): sign_j from the partials.
+__global__ __launch_bounds__(256) void k_sign_final(const double* __restrict__ dots, const float* __restrict__ maxval,
                                                     const int64_t* __restrict__ maxrow, int nchunk, int r,
                                                     float* __restrict__ sgn, const DevStatus* st) {
   if (failed(st)) return;
-  for (int j = threadIdx.x; j < r; j += blockDim.x) {
-    double d = 0.0;
-    float bv = 0.0f, ba = -1.0f;
-    for (int c = 0; c < nchunk; ++c) {
-      d += dots[(int64_t)c * r + j];
-      const float v = maxval[(int64_t)c * r + j];
-      // chunks are in row order, so a strict > keeps the lowest row on ties
-      if (maxrow[(int64_t)c * r + j] >= 0 && fabsf(v) > ba) {
-        ba = fabsf(v);
-        bv = v;
+  __shared__ double rd[256];
+  __shared__ float rv[256];
+  __shared__ int64_t rr[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  double d = 0.0;
+  float bv = 0.0f;
+  int64_t brow = -1;
+  for (int c = t; c < nchunk; c += 256) {
+    const int64_t o = (int64_t)c * r + j;
+    d += dots[o];
+    const float v = maxval[o];
+    const int64_t row = maxrow[o];
+    if (row >= 0 && (brow < 0 || fabsf(v) > fabsf(bv) || (fabsf(v) == fabsf(bv) && row < brow))) {
+      bv = v;
+      brow = row;
+    }
+  }
+  rd[t] = d;
+  rv[t] = bv;
+  rr[t] = brow;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      rd[t] += rd[t + w];
+      const float v = rv[t + w];
+      const int64_t row = rr[t + w];
+      if (row >= 0 && (rr[t] < 0 || fabsf(v) > fabsf(rv[t]) || (fabsf(v) == fabsf(rv[t]) && row < rr[t]))) {
+        rv[t] = v;
+        rr[t] = row;
       }
     }
-    float s;
-    if (fabs(d) >= 1e-8)
-      s = d >= 0.0 ? 1.0f : -1.0f;
-    else
-      s = bv >= 0.0f ? 1.0f : -1.0f;
-    sgn[j] = s;
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double dd = rd[0];
+    sgn[j] = (fabs(dd) >= 1e-8) ? (dd >= 0.0 ? 1.0f : -1.0f) : (rv[0] >= 0.0f ? 1.0f : -1.0f);
   }
 }
 
@@ -205,23 +244,28 @@ __global__ __launch_bounds__(256) void k_vtg_partial(const float* __restrict__ v
   part[(int64_t)blockIdx.x * r + j] = d;
 }
 
-// Stage 2 (one block): cw_j = w_j * c_j; also writes sigma to the caller.
-__global__ __launch_bounds__(512) void k_vtg_final(const double* __restrict__ part, int nchunk, int r,
+// Stage 2 (one block of 256 threads per column): cw_j = w_j * c_j; also
+// writes sigma to the caller.
+__global__ __launch_bounds__(256) void k_vtg_final(const double* __restrict__ part, int nchunk, int r,
                                                    const double* __restrict__ sig_sorted, double lambda, int floor_form,
                                                    double* __restrict__ cw, double* __restrict__ sigma_out,
                                                    const DevStatus* st) {
   if (failed(st)) return;
-  for (int j = threadIdx.x; j < r; j += blockDim.x) {
-    double c = 0.0;
-    for (int k = 0; k < nchunk; ++k) c += part[(int64_t)k * r + j];
+  __shared__ double red[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  double a = 0.0;
+  for (int c = t; c < nchunk; c += 256) a += part[(int64_t)c * r + j];
+  red[t] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
     const double s = sig_sorted[j];
     const double s2 = s * s;
-    double w;
-    if (floor_form)
-      w = s2 > 0.0 ? 1.0 - lambda / s2 : 0.0;
-    else
-      w = s2 / (s2 + lambda);
-    cw[j] = w * c;
+    const double w = floor_form ? (s2 > 0.0 ? 1.0 - lambda / s2 : 0.0) : s2 / (s2 + lambda);
+    cw[j] = w * red[0];
     sigma_out[j] = s;
   }
 }
@@ -252,6 +296,9 @@ __global__ void k_status_init(DevStatus* st) {
     st->jacobi_sweeps = 0.0;
     st->jacobi_cosine = 0.0;
     st->jacobi_done = 0;
+    st->round2 = 0;
+    st->kappa_max = 0.0;
+    st->round2_count = 0;
     st->pad = 0;
   }
 }

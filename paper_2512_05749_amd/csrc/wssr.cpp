@@ -21,8 +21,9 @@ constexpr int kS1Max = 16;      // split-K ranges of the sample-side product
 constexpr int kGSplitMax = 16;  // row splits of the gradient
 constexpr int kGramChunkMax = 64;
 constexpr int kVecChunkMax = 1024;
-constexpr int kJacobiSweeps = 15;
-constexpr double kJacobiTol = 1e-12;
+constexpr int kJacobiSweeps = 10;
+constexpr double kJacobiTol = 1e-10;
+constexpr double kKappaRound2 = 1e4;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -46,7 +47,7 @@ struct wssr_ctx {
   double* gram_part = nullptr;
   double *G = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *Rz = nullptr;
   double *Bc = nullptr, *Pc = nullptr, *Ps = nullptr, *T = nullptr, *scal = nullptr, *sig = nullptr;
-  double *cosbuf = nullptr, *cw = nullptr, *vpart = nullptr, *dots = nullptr;
+  double *cosbuf = nullptr, *cw = nullptr, *vpart = nullptr, *dots = nullptr, *ymean = nullptr, *Tq = nullptr;
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
 
@@ -101,29 +102,47 @@ struct wssr_ctx {
   hipError_t last() { return hipGetLastError(); }
 
   void gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* V, int r) {
-    const int64_t tn = cdiv(n, 128), tj = cdiv(r, 128);
-    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(2048, tn * tj)));
-    int64_t kchunk = rup(cdiv(m, s1), 32);
+    const int bn = r > 128 ? 256 : 128;
+    const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
+    // about two workgroups per CU in one round; split K = M into s1 ranges
+    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(512, tn * tj)));
+    int64_t kchunk = rup(cdiv(m, s1), 16);
     s1 = (int)cdiv(m, kchunk);
     const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
     const bool vec_v = (r % 4 == 0) && ((uintptr_t)V % 16 == 0);
     timed(0, [&] {
-      hipLaunchKernelGGL(k_gemm_sample_side, dim3(tn, tj, s1), dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
-                         vec_o, vec_v, (const DevStatus*)st);
+      if (bn == 256)
+        hipLaunchKernelGGL(k_gemm_sample_side<256>, dim3(tn, tj, s1), dim3(256), 0, stream, O, ld, n, m, V, r, ypart,
+                           kchunk, vec_o, vec_v, (const DevStatus*)st);
+      else
+        hipLaunchKernelGGL(k_gemm_sample_side<128>, dim3(tn, tj, s1), dim3(256), 0, stream, O, ld, n, m, V, r, ypart,
+                           kchunk, vec_o, vec_v, (const DevStatus*)st);
     });
-    const int nrb = (int)cdiv(n, 64);
-    hipLaunchKernelGGL(k_ysum, dim3(nrb, cdiv(r, 256)), dim3(256), 0, stream, (const float*)ypart, s1, n, r, y64,
-                       colpart, (const DevStatus*)st);
-    hipLaunchKernelGGL(k_ycenter, dim3(nrb, cdiv(r, 256)), dim3(256), 0, stream, y64, (const double*)colpart, nrb, n,
-                       r, 1.0 / std::sqrt((double)n), (const DevStatus*)st);
+    const int64_t tot = n * r;
+    hipLaunchKernelGGL(k_ysum, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)ypart, s1, tot, y64,
+                       (const DevStatus*)st);
+    const int rows = 128, nrb = (int)cdiv(n, rows);
+    hipLaunchKernelGGL(k_colsum_partial, dim3(nrb, cdiv(r, 256)), dim3(256), 0, stream, (const double*)y64, n, r,
+                       rows, colpart, (const DevStatus*)st);
+    hipLaunchKernelGGL(k_colreduce, dim3(r), dim3(256), 0, stream, (const double*)colpart, nrb, r, 1.0 / (double)n,
+                       ymean, (const DevStatus*)st);
+    hipLaunchKernelGGL(k_ycenter, dim3(cdiv(tot, 256)), dim3(256), 0, stream, y64, (const double*)ymean, tot, r,
+                       1.0 / std::sqrt((double)n), (const DevStatus*)st);
   }
 
   void gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r, float* Z) {
+    const int bn = r > 128 ? 256 : 128;
     const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
     const bool vec_q = (r % 4 == 0) && ((uintptr_t)Q % 16 == 0);
+    const float scale = (float)(1.0 / std::sqrt((double)n));
+    const dim3 grid(cdiv(m, 128), cdiv(r, bn));
     timed(1, [&] {
-      hipLaunchKernelGGL(k_gemm_param_side, dim3(cdiv(m, 128), cdiv(r, 128)), dim3(256), 0, stream, O, ld, n, m, Q, r,
-                         (float)(1.0 / std::sqrt((double)n)), Z, vec_o, vec_q, (const DevStatus*)st);
+      if (bn == 256)
+        hipLaunchKernelGGL(k_gemm_param_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
+                           vec_q, (const DevStatus*)st);
+      else
+        hipLaunchKernelGGL(k_gemm_param_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
+                           vec_q, (const DevStatus*)st);
     });
   }
 
@@ -140,40 +159,44 @@ struct wssr_ctx {
   }
 
   template <typename T>
-  void gram(const T* X, int64_t rows, int r) {
+  void gram(const T* X, int64_t rows, int r, bool gated) {
     const int rp = (int)rup(r, 64), nt = rp / 64, npairs = nt * (nt + 1) / 2;
     int nch = (int)std::min<int64_t>(std::min<int64_t>(kGramChunkMax, std::max(1, 2048 / npairs)),
                                      std::max<int64_t>(1, cdiv(rows, 256)));
     const int64_t rpc = rup(cdiv(rows, nch), 32);
     nch = (int)std::max<int64_t>(1, cdiv(rows, rpc));
     hipLaunchKernelGGL(k_gram_partial<T>, dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, nt, rpc, gram_part,
-                       (const DevStatus*)st);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(npairs), dim3(256), 0, stream, (const double*)gram_part, nch, nt, r, G,
-                       (const DevStatus*)st);
+                       (const DevStatus*)st, gated);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(npairs, 16), dim3(256), 0, stream, (const double*)gram_part, nch, nt, r, G,
+                       (const DevStatus*)st, gated);
   }
 
-  void cholinv(int rp, double* R, double* Ri) {
-    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(1024), kCholinvLds, stream, G, rp, R, Ri, st);
+  void cholinv(int rp, int r, double* R, double* Ri, int mode) {
+    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(1024), kCholinvLds, stream, G, rp, r, R, Ri, st, mode, kKappaRound2);
   }
 
   template <typename Tin, typename Tout>
   void apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol, Tout* out, int ldo,
-             bool upper) {
+             bool upper, bool gated = false) {
     hipLaunchKernelGGL((k_apply<Tin, Tout>), dim3(cdiv(rows, 64), cdiv(ncol, 64)), dim3(256), 0, stream, X, rows, ldx,
-                       kdim, Tm, rp, ncol, out, ldo, upper, (const DevStatus*)st);
+                       kdim, Tm, rp, ncol, out, ldo, upper, (const DevStatus*)st, gated);
   }
 
-  // CholeskyQR2 of X (rows x r): Q (float) and, in R1/R1i/R2/R2i, both rounds'
-  // factors.  The first round's Q is kept in `mid` (type M).
+  // CholeskyQR of X (rows x r) with a second round when the first round's
+  // condition bound asks for it (decided on the device).  Leaves the combined
+  // orthonormaliser Tq = R1^{-1} R2^{-1} (upper, rp x rp) so that Q = X Tq, and,
+  // if Rout is given, the triangular factor Rout = R2 R1 (X = Q Rout).  The
+  // second round's X R1^{-1} goes to `mid`.
   template <typename Tin, typename Tmid>
-  void cholqr2(const Tin* X, int64_t rows, int r, Tmid* mid, float* Q, bool form_q) {
+  void cholqr(const Tin* X, int64_t rows, int r, Tmid* mid, double* Rout) {
     const int rp = (int)rup(r, 64);
-    gram(X, rows, r);
-    cholinv(rp, R1, R1i);
-    apply(X, rows, r, r, R1i, rp, r, mid, r, true);
-    gram((const Tmid*)mid, rows, r);
-    cholinv(rp, R2, R2i);
-    if (form_q) apply((const Tmid*)mid, rows, r, r, R2i, rp, r, Q, r, true);
+    gram(X, rows, r, false);
+    cholinv(rp, r, R1, R1i, 0);
+    apply(X, rows, r, r, R1i, rp, r, mid, r, true, true);
+    gram((const Tmid*)mid, rows, r, true);
+    cholinv(rp, r, R2, R2i, 1);
+    apply((const double*)R1i, rp, rp, rp, R2i, rp, rp, Tq, rp, true);
+    if (Rout) apply((const double*)R2, rp, rp, rp, R1, rp, rp, Rout, rp, true);
   }
 
   // SVD of the r x r matrix whose transpose is Ct (rp x rp row-major): sorted
@@ -253,7 +276,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
   bool ok = h->alloc(h->st, 1) && h->alloc(h->eps, n) && h->alloc(h->g, m) &&
             h->alloc(h->gpart, (size_t)kGSplitMax * m) && h->alloc(h->ypart, (size_t)kS1Max * n * r) &&
             h->alloc(h->y64, (size_t)n * r) && h->alloc(h->yq1, (size_t)n * r) &&
-            h->alloc(h->colpart, (size_t)cdiv(n, 64) * r) && h->alloc(h->qy, (size_t)n * r) &&
+            h->alloc(h->colpart, (size_t)cdiv(n, 128) * r) && h->alloc(h->qy, (size_t)n * r) &&
             h->alloc(h->z, (size_t)m * r) && h->alloc(h->q1, (size_t)rows * r) && h->alloc(h->vw, (size_t)m * r) &&
             h->alloc(h->gram_part, (size_t)kGramChunkMax * npairs * 4096) && h->alloc(h->G, (size_t)rp * rp) &&
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
@@ -262,7 +285,8 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
             h->alloc(h->scal, 4) && h->alloc(h->sig, rp) && h->alloc(h->cosbuf, (size_t)rp * rp / 64) &&
             h->alloc(h->cw, rp) && h->alloc(h->vpart, (size_t)kVecChunkMax * r) &&
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
-            h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp);
+            h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
+            h->alloc(h->Tq, (size_t)rp * rp);
   if (!ok) {
     (void)hipGetLastError();
     for (void* p : h->allocs) (void)hipFree(p);
@@ -333,32 +357,31 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
 
   const float* vcur = V;
   for (int p = 1; p <= q; ++p) {
-    // sample side: y = A V (FP64), then its QR: Q_Y (float)
+    // sample side: Y = A V (FP64), then its QR: Q_Y = Y Tq (float)
     h->gemm_sample_side(Of, ld_o, n, m, vcur, r);
-    h->cholqr2<double, double>(h->y64, n, r, h->yq1, h->qy, true);
-    // parameter side: Z = A^T Q_Y, then CholeskyQR2 of Z
+    h->cholqr<double, double>(h->y64, n, r, h->yq1, nullptr);
+    h->apply((const double*)h->y64, n, r, r, h->Tq, rp, r, h->qy, r, true);
+    // parameter side: Z = A^T Q_Y, then its QR: Q_Z = Z Tq, R_Z
     h->gemm_param_side(Of, ld_o, n, m, h->qy, r, h->z);
-    h->cholqr2<float, float>(h->z, m, r, h->q1, nullptr, false);
+    h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
     if (p < q) {
-      // next basis: Q_Z = Q1 R2^{-1}
-      h->apply((const float*)h->q1, m, r, r, h->R2i, rp, r, h->vw, r, true);
+      h->apply((const float*)h->z, m, r, r, h->Tq, rp, r, h->vw, r, true);
       vcur = h->vw;
     } else {
-      // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T with R_Z = R2 R1
-      h->apply((const double*)h->R2, rp, rp, rp, h->R1, rp, rp, h->Rz, rp, true);
+      // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T;  C = G diag(sigma) P^T
       h->small_svd(h->Rz, r);
-      // V = Q_Z P = Q1 (R2^{-1} P)
-      h->apply((const double*)h->R2i, rp, rp, rp, h->Ps, rp, rp, h->T, rp, false);
-      h->apply((const float*)h->q1, m, r, r, h->T, rp, r, h->vw, r, false);
+      // V = Q_Z P = Z (Tq P)
+      h->apply((const double*)h->Tq, rp, rp, rp, h->Ps, rp, rp, h->T, rp, false);
+      h->apply((const float*)h->z, m, r, r, h->T, rp, r, h->vw, r, false);
     }
   }
   // output signs, then V <- signed vw
   {
-    const int64_t rpc = std::max<int64_t>(64, cdiv(m, kVecChunkMax));
+    const int64_t rpc = std::max<int64_t>(256, cdiv(m, 256));
     const int nch = (int)cdiv(m, rpc);
     hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->vw,
                        (const float*)V, m, r, rpc, h->dots, h->maxval, h->maxrow, cst);
-    hipLaunchKernelGGL(k_sign_final, dim3(1), dim3(512), 0, stream, (const double*)h->dots, (const float*)h->maxval,
+    hipLaunchKernelGGL(k_sign_final, dim3(r), dim3(256), 0, stream, (const double*)h->dots, (const float*)h->maxval,
                        (const int64_t*)h->maxrow, nch, r, h->sgn, cst);
     const int64_t tot = m * r;
     hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)h->vw,
@@ -366,7 +389,7 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
     // Woodbury
     hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
                        (const double*)h->g, m, r, rpc, h->vpart, cst);
-    hipLaunchKernelGGL(k_vtg_final, dim3(1), dim3(512), 0, stream, (const double*)h->vpart, nch, r,
+    hipLaunchKernelGGL(k_vtg_final, dim3(r), dim3(256), 0, stream, (const double*)h->vpart, nch, r,
                        (const double*)h->sig, lambda, (h->cfg.flags & WSSR_FLOOR_PRECOND) ? 1 : 0, h->cw, sigma, cst);
     hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, (const double*)h->g,
                        (const double*)h->cw, m, r, 1.0 / lambda, delta, cst);
@@ -387,6 +410,8 @@ wssr_status wssr_status_sync(wssr_handle h, int32_t* numeric_status, double* dia
     diag[1] = s.jacobi_sweeps;
     diag[2] = s.jacobi_cosine;
     diag[3] = (double)s.chol_count;
+    diag[4] = s.kappa_max;
+    diag[5] = (double)s.round2_count;
   }
   return WSSR_OK;
 }
@@ -463,8 +488,8 @@ wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_
   if (rows < r || rows > h->rows_max) return h->fail(WSSR_ERR_INVALID_ARG, "rows outside [r, max(n_max, m_max)]");
   const int rp = (int)rup(r, 64);
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
-  h->cholqr2<float, float>(X, rows, r, h->q1, Q, true);
-  h->apply((const double*)h->R2, rp, rp, rp, h->R1, rp, rp, h->Rz, rp, true);
+  h->cholqr<float, float>(X, rows, r, h->q1, h->Rz);
+  h->apply(X, rows, r, r, h->Tq, rp, r, Q, r, true);
   (void)hipMemcpy2DAsync(R, sizeof(double) * r, h->Rz, sizeof(double) * rp, sizeof(double) * r, r,
                          hipMemcpyDeviceToDevice, h->stream);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");

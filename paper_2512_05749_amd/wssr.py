@@ -166,10 +166,10 @@ class Wssr:
     def status(self):
         """Synchronise and return (numeric status code, diagnostics dict)."""
         code = ctypes.c_int32()
-        diag = (ctypes.c_double * 4)()
+        diag = (ctypes.c_double * 6)()
         self._check(lib().wssr_status_sync(self._h, ctypes.byref(code), diag))
         return code.value, dict(min_rel_pivot=diag[0], jacobi_sweeps=diag[1], jacobi_cosine=diag[2],
-                                cholesky_count=diag[3])
+                                cholesky_count=diag[3], kappa_max=diag[4], second_rounds=diag[5])
 
     def profile(self, enable=True):
         """Start (clearing) or stop recording HIP events around the product kernels."""
