@@ -44,15 +44,17 @@ template <typename Tin, typename Tout>
 __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
                         Tout* Out, int ldo, bool upper, const DevStatus* st, bool gated);
 
-// mode 0: first CholeskyQR round (sets st->round2 from the condition bound of
-// the factor: kappa_F > kappa_round2); mode 1: gated second round (writes
-// identity factors when st->round2 is 0); mode 2: plain.
-__global__ void k_cholinv(double* G, int rp, int r, double* R, double* Ri, DevStatus* st, int mode,
-                          double kappa_round2);
+__global__ void k_chol(double* G, int rp, double* R, double* Rt, double* gdiag, DevStatus* st, bool gated);
+template <int RPL>
+__global__ void k_trinv(const double* Rt, int rp, double* Ri, const DevStatus* st, bool gated);
+__global__ void k_kappa(const double* gdiag, const double* R, const double* Ri, int rp, int r, double kappa_round2,
+                        DevStatus* st);
+__global__ void k_smallgemm(const double* A, const double* B, int rp, double* C, const DevStatus* st, bool gated,
+                            bool copy_b);
 __global__ void k_jacobi_prep(const double* Ct, int rp, int r, double* Bc, double* Pc, double* scal,
                               DevStatus* st);
 __global__ void k_jacobi_round(double* Bc, double* Pc, int rp, int rd, double tol, const double* scal,
-                               double* cosbuf, DevStatus* st);
+                               double* cosbuf, DevStatus* st, int inner_sweeps);
 __global__ void k_jacobi_check(const double* cosbuf, int n, double tol, DevStatus* st);
 __global__ void k_jacobi_final(const double* Bc, const double* Pc, int rp, int r, double* sig, double* Ps,
                                DevStatus* st);
@@ -60,7 +62,7 @@ __global__ void k_jacobi_final(const double* Bc, const double* Pc, int rp, int r
 __global__ void k_transpose_pad(const double* C, int r, int rp, double* Ct);
 
 // dynamic LDS sizes (bytes)
-constexpr size_t kCholinvLds = 4 * 64 * 65 * sizeof(double);
+constexpr size_t kCholLds = 4 * 64 * 65 * sizeof(double);
 constexpr size_t kJacobiLds = 3 * 64 * 65 * sizeof(double);
 
 }  // namespace wssr

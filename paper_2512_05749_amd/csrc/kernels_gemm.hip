@@ -7,11 +7,17 @@
 // Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; output tile
 // 128 rows x BN columns (BN = 128 or 256 over the rank dimension); each wave
 // owns a 64 x (BN/2) sub-tile = 2 x (BN/64) MFMA tiles of 32 x 32, i.e. 8 FP32
-// accumulator tiles at BN = 256.  K advances 16 at a time; one barrier per
-// K-step; the next tile's global loads are in flight during the MFMAs.
+// accumulator tiles at BN = 256.  K advances 16 at a time with one barrier per
+// K-step; the next K-step's global loads are in flight during the MFMAs.
+//
+// Both operand tiles are kept K-contiguous in LDS ([row][k]), so a lane reads
+// the four K values it needs for four MFMA steps with one 16-byte LDS read.
 // Inside a K-step the contraction index is permuted: lane (x, h) = (l%32,
-// l/32) feeds k = h*8 + s to MFMA step s (0 <= s < 8) for both operands, which
-// lets each lane read 4 consecutive k of an O row with one 16-byte LDS read.
+// l/32) feeds k = h*8 + s to MFMA step s (0 <= s < 8) for both operands.
+// Operands whose global rows are not K-contiguous (V, Q and O in the
+// parameter-side product) are transposed on their way into LDS; their loads
+// map consecutive lanes to consecutive k so the transposed LDS writes do not
+// conflict.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -19,13 +25,40 @@ namespace wssr {
 
 namespace {
 constexpr int BM = 128, BK = 16;
-constexpr int PADK = 4;   // pad of K-contiguous rows (floats)
-constexpr int PADC = 4;   // pad of column-contiguous rows (floats)
+constexpr int LDK = BK + 4;   // LDS row length of a K-contiguous tile (floats)
+
+// 32 k-steps' worth of MFMAs on one K-step of LDS tiles:
+// acc[a][b] += A[a-block rows][k] * B[b-block cols][k].
+template <int TA, int TB>
+__device__ __forceinline__ void mma_kstep(f32x16 (&acc)[TA][TB], const float (*As)[LDK], int arow0,
+                                          const float (*Bs)[LDK], int brow0, int x, int h) {
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    f32x4 av[TA], bv[TB];
+#pragma unroll
+    for (int a = 0; a < TA; ++a) av[a] = *reinterpret_cast<const f32x4*>(&As[arow0 + a * 32 + x][h * 8 + half * 4]);
+#pragma unroll
+    for (int b = 0; b < TB; ++b) bv[b] = *reinterpret_cast<const f32x4*>(&Bs[brow0 + b * 32 + x][h * 8 + half * 4]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int a = 0; a < TA; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) acc[a][b] = mfma32x32x2(av[a][e], bv[b][e], acc[a][b]);
+  }
+}
+
+// store a float4 that holds 4 consecutive columns c..c+3 of global row k into
+// a K-contiguous LDS tile T[col][k]
+__device__ __forceinline__ void st_transposed(float (*T)[LDK], int c, int k, f32x4 v) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) T[c + e][k] = v[e];
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Sample side.  O is N x M row-major (K contiguous), V is M x r row-major.
-// grid (n tiles, r tiles, S).
+// grid (n tiles, r tiles, S).  D[i = sample][j = rank]: A = O tile, B = V^T tile.
 // ---------------------------------------------------------------------------
 template <int BN>
 __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __restrict__ O, int64_t ld, int64_t n,
@@ -36,8 +69,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
   constexpr int TB = BN / 64;                 // rank blocks per wave
   constexpr int AV = BM * BK / 4 / 256;       // float4 per thread for the O tile (2)
   constexpr int BV = BK * BN / 4 / 256;       // float4 per thread for the V tile (2 or 4)
-  __shared__ __attribute__((aligned(16))) float As[2][BM][BK + PADK];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BK][BN + PADC];
+  __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
@@ -69,7 +102,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
 #pragma unroll
       for (int i = 0; i < BV; ++i) {
         const int idx = t + 256 * i;
-        const int krow = idx / (BN / 4), jq = (idx % (BN / 4)) * 4;
+        const int krow = idx & (BK - 1), jq = (idx / BK) * 4;
         rb[i] = *reinterpret_cast<const f32x4*>(V + (k0 + krow) * r + j0 + jq);
       }
       return;
@@ -84,7 +117,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
       const int idx = t + 256 * i;
-      const int krow = idx / (BN / 4), jq = (idx % (BN / 4)) * 4;
+      const int krow = idx & (BK - 1), jq = (idx / BK) * 4;
       const int64_t gk = k0 + krow;
       rb[i] = (gk < ke) ? load4(V + gk * r, j0 + jq, r, vec_v) : f32x4{0};
     }
@@ -99,8 +132,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
       const int idx = t + 256 * i;
-      const int krow = idx / (BN / 4), jq = (idx % (BN / 4)) * 4;
-      *reinterpret_cast<f32x4*>(&Bs[buf][krow][jq]) = rb[i];
+      const int krow = idx & (BK - 1), jq = (idx / BK) * 4;
+      st_transposed(Bs[buf], jq, krow, rb[i]);
     }
   };
 
@@ -111,25 +144,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
   for (int64_t it = 0; it < nk; ++it) {
     const int buf = (int)(it & 1);
     if (it + 1 < nk) gload(kb + (it + 1) * BK);
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      // fragments for MFMA steps s = 4*half .. 4*half+3
-      f32x4 av[2];
-      float bv[4][TB];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-        av[a] = *reinterpret_cast<const f32x4*>(&As[buf][wm * 64 + a * 32 + x][h * 8 + half * 4]);
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int b = 0; b < TB; ++b) bv[e][b] = Bs[buf][h * 8 + half * 4 + e][wn * (BN / 2) + b * 32 + x];
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < TB; ++b) acc[a][b] = mfma32x32x2(av[a][e], bv[e][b], acc[a][b]);
-    }
+    mma_kstep<2, TB>(acc, As[buf], wm * 64, Bs[buf], wn * (BN / 2), x, h);
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
@@ -150,9 +165,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
 
 // ---------------------------------------------------------------------------
 // Parameter side Z = O^T Q * scale.  O is N x M row-major, Q is N x r
-// row-major; both tiles are staged K-major ([k][column]) so every lane reads
-// consecutive addresses.  The MFMA computes the transposed block Z^T:
-// A[i][k] = Q[k][j0+i], B[k][jj] = O[k][m0+jj].  grid (m tiles, r tiles).
+// row-major.  D[i = parameter][j = rank]: A = (O^T) tile, B = Q^T tile, both
+// transposed into K-contiguous LDS rows.  grid (m tiles, r tiles).
 // ---------------------------------------------------------------------------
 template <int BN>
 __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restrict__ O, int64_t ld, int64_t n,
@@ -163,8 +177,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
   constexpr int TB = BN / 64;
   constexpr int OV = BK * BM / 4 / 256;       // float4 per thread for the O tile (2)
   constexpr int QV = BK * BN / 4 / 256;       // float4 per thread for the Q tile (2 or 4)
-  __shared__ __attribute__((aligned(16))) float Os[2][BK][BM + PADC];
-  __shared__ __attribute__((aligned(16))) float Qs[2][BK][BN + PADC];
+  __shared__ __attribute__((aligned(16))) float Os[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) float Qs[2][BN][LDK];
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wj = w & 1;
@@ -172,11 +186,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
   const int64_t m0 = (int64_t)blockIdx.x * BM;
   const int j0 = blockIdx.y * BN;
 
-  f32x16 acc[TB][2];
+  f32x16 acc[2][TB];
 #pragma unroll
-  for (int a = 0; a < TB; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{0};
+    for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
 
   f32x4 ro[OV], rq[QV];
   const bool inner = vec_o && vec_q && (m0 + BM <= m) && (j0 + BN <= r);
@@ -185,13 +199,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
 #pragma unroll
       for (int i = 0; i < OV; ++i) {
         const int idx = t + 256 * i;
-        const int krow = idx / (BM / 4), cq = (idx % (BM / 4)) * 4;
+        const int krow = idx & (BK - 1), cq = (idx / BK) * 4;
         ro[i] = *reinterpret_cast<const f32x4*>(O + (k0 + krow) * ld + m0 + cq);
       }
 #pragma unroll
       for (int i = 0; i < QV; ++i) {
         const int idx = t + 256 * i;
-        const int krow = idx / (BN / 4), cq = (idx % (BN / 4)) * 4;
+        const int krow = idx & (BK - 1), cq = (idx / BK) * 4;
         rq[i] = *reinterpret_cast<const f32x4*>(Q + (k0 + krow) * r + j0 + cq);
       }
       return;
@@ -199,14 +213,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
 #pragma unroll
     for (int i = 0; i < OV; ++i) {
       const int idx = t + 256 * i;
-      const int krow = idx / (BM / 4), cq = (idx % (BM / 4)) * 4;
+      const int krow = idx & (BK - 1), cq = (idx / BK) * 4;
       const int64_t gk = k0 + krow;
       ro[i] = (gk < n) ? load4(O + gk * ld, m0 + cq, m, vec_o) : f32x4{0};
     }
 #pragma unroll
     for (int i = 0; i < QV; ++i) {
       const int idx = t + 256 * i;
-      const int krow = idx / (BN / 4), cq = (idx % (BN / 4)) * 4;
+      const int krow = idx & (BK - 1), cq = (idx / BK) * 4;
       const int64_t gk = k0 + krow;
       rq[i] = (gk < n) ? load4(Q + gk * r, j0 + cq, r, vec_q) : f32x4{0};
     }
@@ -215,14 +229,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
 #pragma unroll
     for (int i = 0; i < OV; ++i) {
       const int idx = t + 256 * i;
-      const int krow = idx / (BM / 4), cq = (idx % (BM / 4)) * 4;
-      *reinterpret_cast<f32x4*>(&Os[buf][krow][cq]) = ro[i];
+      const int krow = idx & (BK - 1), cq = (idx / BK) * 4;
+      st_transposed(Os[buf], cq, krow, ro[i]);
     }
 #pragma unroll
     for (int i = 0; i < QV; ++i) {
       const int idx = t + 256 * i;
-      const int krow = idx / (BN / 4), cq = (idx % (BN / 4)) * 4;
-      *reinterpret_cast<f32x4*>(&Qs[buf][krow][cq]) = rq[i];
+      const int krow = idx & (BK - 1), cq = (idx / BK) * 4;
+      st_transposed(Qs[buf], cq, krow, rq[i]);
     }
   };
 
@@ -233,50 +247,21 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
   for (int64_t it = 0; it < nk; ++it) {
     const int buf = (int)(it & 1);
     if (it + 1 < nk) gload((it + 1) * BK);
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      float av[4][TB], bv[4][2];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int kk = h * 8 + half * 4 + e;
-#pragma unroll
-        for (int a = 0; a < TB; ++a) av[e][a] = Qs[buf][kk][wj * (BN / 2) + a * 32 + x];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) bv[e][b] = Os[buf][kk][wm * 64 + b * 32 + x];
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int a = 0; a < TB; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = mfma32x32x2(av[e][a], bv[e][b], acc[a][b]);
-    }
+    mma_kstep<2, TB>(acc, Os[buf], wm * 64, Qs[buf], wj * (BN / 2), x, h);
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
 
-  // acc[a][b]: rows (rank index) of block a, columns (parameter index) of block b
 #pragma unroll
-  for (int a = 0; a < TB; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int64_t row = m0 + wm * 64 + b * 32 + x;
-      if (row >= m) continue;
+    for (int b = 0; b < TB; ++b) {
+      const int col = j0 + wj * (BN / 2) + b * 32 + x;
+      if (col >= r) continue;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int jb = j0 + wj * (BN / 2) + a * 32 + 8 * g + 4 * h;
-        if (jb + 3 < r) {
-          f32x4 v4;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v4[e] = acc[a][b][4 * g + e] * scale;
-          if ((r & 3) == 0) {
-            *reinterpret_cast<f32x4*>(&Z[row * r + jb]) = v4;
-            continue;
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (jb + e < r) Z[row * r + jb + e] = acc[a][b][4 * g + e] * scale;
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = m0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < m) Z[row * r + col] = acc[a][b][v] * scale;
       }
     }
 }

@@ -70,36 +70,63 @@ __device__ __forceinline__ f64x4 tile_to_acc(const double (*T)[TP]) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Cholesky G = R^T R (R upper, positive diagonal) and R^{-1}, both rp x rp
-// row-major; rp a multiple of 64 (padding rows/columns of G are identity).
-// One workgroup.  G is overwritten (trailing updates).  A pivot d_k with
-// !(d_k > rp * eps * G_kk) is a breakdown (NaN: non-finite input).
+// Jacobi rotation that zeroes b in the symmetric 2 x 2 [[a, b], [b, d]]:
+// columns (p, q) -> (c p - s q, s p + c q) with t = s/c the smaller root of
+// t^2 + 2 zeta t - 1 = 0, zeta = (d - a) / (2b):
+//   t = sign(zeta) 2|b| / (|d - a| + sqrt((d - a)^2 + 4 b^2)),  c = 1/sqrt(1+t^2).
+// Reciprocal and reciprocal square root come from the hardware estimates
+// refined by Newton steps (two for 1/sqrt, which fixes c^2 + s^2 = 1 to FP64
+// rounding; the angle itself only needs to be close, the next sweep measures
+// what is left).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  return y * (2.0 - x * y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y * (1.5 - 0.5 * x * y * y);
+}
+__device__ __forceinline__ void rot_params(double a, double d, double b, double& c, double& s) {
+  const double dm = d - a;
+  const double h2 = dm * dm + 4.0 * b * b;
+  const double hyp = h2 * rsq_nr(h2);              // sqrt(h2)
+  const double sgn = ((dm >= 0.0) == (b >= 0.0)) ? 1.0 : -1.0;
+  const double t = sgn * 2.0 * fabs(b) * rcp_nr(fabs(dm) + hyp);
+  c = rsq_nr(1.0 + t * t);
+  s = c * t;
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky G = R^T R (R upper, positive diagonal), rp x rp row-major; rp a
+// multiple of 64 (padding rows/columns of G are identity).  One workgroup of
+// 1024 threads; G is overwritten (trailing updates).  Writes R and its
+// transpose Rt (so that columns of R can be read contiguously).  A pivot d_k
+// with !(d_k > rp * eps * G_kk) is a breakdown (NaN: non-finite input).
 //
-// Blocked right-looking over 64-wide block columns.  Each 64 x 64 diagonal
-// tile is factored by a single wavefront (lane j owns column j; no workgroup
-// barriers inside), its triangular inverse is formed one column per
-// wavefront (lanes = rows), and the panel and trailing updates are 64 x 64 x 64
-// tile products on the FP64 MFMA by all 16 wavefronts.
+// Blocked right-looking over 64-wide block columns.  The 64 x 64 diagonal
+// tile is factored in LDS with lanes = rows and wavefront w owning columns
+// w, w+16, w+32, w+48 (two barriers per column); its triangular inverse
+// (needed for the panel) is formed one column per wavefront by back
+// substitution; the panel and trailing updates are 64 x 64 x 64 tile
+// products on the FP64 MFMA.
 //
-// mode 0 (first CholeskyQR round) also computes the condition bound
-// kappa_F = ||R D^-1||_F ||D R^-1||_F with D = diag(G)^(1/2), an upper bound
-// on the 2-norm condition number of the column-equilibrated input, and sets
-// st->round2 = (kappa_F > kappa_round2): one round leaves an orthogonality
-// error of order eps * kappa^2, so a second round is run only when that is
-// not negligible.  mode 1 (the gated second round) writes identity factors
-// when st->round2 is 0.  mode 2 is a plain factorisation.
+// gated: a second CholeskyQR round; when st->round2 is 0 the kernel only
+// writes identity factors.
 // Dynamic LDS: 4 tiles.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp, int r, double* __restrict__ R,
-                                                 double* __restrict__ Ri, DevStatus* st, int mode,
-                                                 double kappa_round2) {
+__global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, double* __restrict__ R,
+                                              double* __restrict__ Rt, double* __restrict__ gdiag, DevStatus* st,
+                                              bool gated) {
   if (failed(st)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (mode == 1 && *reinterpret_cast<volatile int*>(&st->round2) == 0) {
+  if (gated && *reinterpret_cast<volatile int*>(&st->round2) == 0) {
     for (int64_t e = tid; e < (int64_t)rp * rp; e += NTH) {
       const double v = ((e / rp) == (e % rp)) ? 1.0 : 0.0;
       R[e] = v;
-      Ri[e] = v;
+      Rt[e] = v;
     }
     return;
   }
@@ -112,10 +139,12 @@ __global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp,
   __shared__ double invd[TS];
   __shared__ int err;
   __shared__ double minrel;
-  __shared__ double red[2][NTH / 64];
   const int nt = rp / TS;
   const double tiny = (double)rp * 2.220446049250313e-16;
-  for (int i = tid; i < rp; i += NTH) dorig[i] = G[(int64_t)i * rp + i];
+  for (int i = tid; i < rp; i += NTH) {
+    dorig[i] = G[(int64_t)i * rp + i];
+    gdiag[i] = dorig[i];
+  }
   if (tid == 0) {
     err = 0;
     minrel = 1.0;
@@ -123,53 +152,55 @@ __global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp,
   for (int bi = 1; bi < nt; ++bi)
     for (int bj = 0; bj < bi; ++bj) {
       tile_fill(R, rp, bi, bj, 0.0, 0.0);
-      tile_fill(Ri, rp, bi, bj, 0.0, 0.0);
+      tile_fill(Rt, rp, bj, bi, 0.0, 0.0);
     }
   __syncthreads();
 
   for (int kb = 0; kb < nt; ++kb) {
     tile_load(T0, G, rp, kb, kb);
     __syncthreads();
-    if (wv == 0) {
-      // right-looking factorisation of the diagonal tile, lane j = column j
-      const int j = lane;
-      double mrel = 1.0;
-      int bad = 0;
+    // factor the diagonal tile: lane i = row, wavefront wv owns columns wv + 16c
+    {
+      const int i = lane;
       for (int k = 0; k < TS; ++k) {
         const double d = T0[k][k];
         const double d0 = dorig[kb * TS + k];
         if (!(d > tiny * d0)) {
-          bad = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
-          break;
+          if (tid == 0) err = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
+          break;  // uniform: every thread sees the same d
         }
-        const double piv = sqrt(d);
-        mrel = fmin(mrel, sqrt(d / d0));
-        const double rkj = (j > k) ? T0[k][j] / piv : piv;
-        __builtin_amdgcn_wave_barrier();
-        if (j >= k) T0[k][j] = rkj;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (j > k)
-          for (int i = k + 1; i <= j; ++i) T0[i][j] -= T0[k][i] * rkj;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-      if (lane == 0) {
-        if (bad) err = bad;
-        if (mrel < minrel) minrel = mrel;
+        const double ipiv = rsq_nr(d);   // 1/sqrt(d)
+        const double piv = d * ipiv;
+        if (tid == 0) minrel = fmin(minrel, d / d0);
+        if (i == k) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int j = wv + 16 * c;
+            if (j > k) T0[k][j] *= ipiv;
+          }
+        }
+        __syncthreads();
+        if (i > k) {
+          const double rki = T0[k][i];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int j = wv + 16 * c;
+            if (j >= i) T0[i][j] -= rki * T0[k][j];
+          }
+        }
+        if (tid == 0) T0[k][k] = piv;
+        __syncthreads();
       }
     }
     __syncthreads();
     if (err) break;
     for (int e = tid; e < TS * TS; e += NTH) {
-      const int i = e >> 6, j = e & 63;
-      if (i > j) T0[i][j] = 0.0;
+      const int a = e >> 6, b = e & 63;
+      if (a > b) T0[a][b] = 0.0;
     }
-    if (tid < TS) invd[tid] = 1.0 / T0[tid][tid];
+    if (tid < TS) invd[tid] = rcp_nr(T0[tid][tid]);
     __syncthreads();
-    // inverse of the triangular tile: column j by back substitution, one
+    // inverse of the diagonal tile: column j by back substitution, one
     // wavefront per column (lanes = rows)
     for (int j = wv; j < TS; j += NTH / 64) {
       double b = (lane == j) ? 1.0 : 0.0, x = 0.0;
@@ -182,7 +213,6 @@ __global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp,
     }
     __syncthreads();
     tile_store(R, rp, kb, kb, T0);
-    tile_store(Ri, rp, kb, kb, T1);
     // panel: R[kb][j] = R_kk^{-T} G[kb][j]
     for (int j = kb + 1; j < nt; ++j) {
       tile_load(T2, G, rp, kb, j);
@@ -216,67 +246,155 @@ __global__ __launch_bounds__(NTH) void k_cholinv(double* __restrict__ G, int rp,
     if (tid == 0) raise_error(st, err);
     return;
   }
-  // off-diagonal tiles of R^{-1}: Ri[i][j] = -Ri[i][i] * sum_{k=i+1..j} R[i][k] Ri[k][j]
-  for (int j = 1; j < nt; ++j) {
-    for (int i = j - 1; i >= 0; --i) {
-      f64x4 acc = f64x4{0};
-      for (int k = i + 1; k <= j; ++k) {
-        tile_load(T0, R, rp, i, k);
-        tile_load(T1, Ri, rp, k, j);
-        __syncthreads();
-        acc = tile_mma<false>(acc, T0, T1);
-        __syncthreads();
+  // Rt = R^T (upper tiles of R -> lower tiles of Rt)
+  for (int bi = 0; bi < nt; ++bi)
+    for (int bj = bi; bj < nt; ++bj) {
+      tile_load(T0, R, rp, bi, bj);
+      __syncthreads();
+      for (int e = tid; e < TS * TS; e += NTH) {
+        const int a = e >> 6, b = e & 63;
+        Rt[(int64_t)(bj * TS + a) * rp + bi * TS + b] = T0[b][a];
       }
-      acc_to_tile(T2, acc, 1.0);
-      tile_load(T0, Ri, rp, i, i);
-      __syncthreads();
-      f64x4 acc2 = tile_mma<false>(f64x4{0}, T0, T2);
-      acc_to_tile(T3, acc2, -1.0);
-      __syncthreads();
-      tile_store(Ri, rp, i, j, T3);
       __syncthreads();
     }
-  }
-  if (mode == 0) {
-    // kappa_F over the real r x r block
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t e = tid; e < (int64_t)rp * rp; e += NTH) {
-      const int i = (int)(e / rp), j = (int)(e % rp);
-      if (i <= j && j < r) {
-        const double a = R[e] / sqrt(dorig[j]);
-        const double b = Ri[e] * sqrt(dorig[i]);
-        s1 += a * a;
-        s2 += b * b;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      s1 += __shfl_xor(s1, o, 64);
-      s2 += __shfl_xor(s2, o, 64);
-    }
-    if (lane == 0) {
-      red[0][wv] = s1;
-      red[1][wv] = s2;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double a = 0.0, b = 0.0;
-      for (int w = 0; w < NTH / 64; ++w) {
-        a += red[0][w];
-        b += red[1][w];
-      }
-      const double kap = sqrt(a * b);
-      const int need = !(kap <= kappa_round2);
-      st->round2 = need;
-      if (need) st->round2_count += 1;
-      if (kap > st->kappa_max) st->kappa_max = kap;
-    }
-  }
   if (tid == 0) {
     st->chol_count += 1;
-    if (minrel < st->min_rel_pivot) st->min_rel_pivot = minrel;
+    const double mr = sqrt(minrel);
+    if (mr < st->min_rel_pivot) st->min_rel_pivot = mr;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Ri = R^{-1} for the upper triangular R (rp x rp), column-parallel: one
+// wavefront per column j solves R x = e_j by back substitution, lanes = rows
+// (RPL >= rp/64 rows per lane), reading column l of R as row l of Rt.
+// grid: rp / 4 workgroups of 256 threads.  gated as in k_chol.
+// ---------------------------------------------------------------------------
+template <int RPL>
+__global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Rt, int rp, double* __restrict__ Ri,
+                                               const DevStatus* st, bool gated) {
+  if (skipped(st, gated)) return;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= rp) return;
+  double b[RPL], x[RPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    b[s] = (s * 64 + lane == j) ? 1.0 : 0.0;
+    x[s] = 0.0;
+  }
+  const int jb = j >> 6;
+#pragma unroll
+  for (int sb = RPL - 1; sb >= 0; --sb) {
+    if (sb > jb) continue;
+    const int lstart = (sb == jb) ? (j & 63) : 63;
+#pragma unroll 4
+    for (int ll = lstart; ll >= 0; --ll) {
+      const int l = sb * 64 + ll;
+      const double* col = Rt + (int64_t)l * rp;   // column l of R
+      const double xl = __shfl(b[sb], ll, 64) * rcp_nr(col[l]);
+      if (lane == ll) x[sb] = xl;
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int row = s * 64 + lane;
+        if (s <= sb && row < l) b[s] -= col[row] * xl;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < RPL; ++s)
+    if (s * 64 + lane < rp) Ri[(int64_t)(s * 64 + lane) * rp + j] = x[s];
+}
+
+// Condition bound of a first CholeskyQR round from R and R^{-1}:
+// kappa_F = ||R D^-1||_F ||D R^-1||_F with D = diag(G)^(1/2) (column norms of
+// the input, as saved by k_chol in gdiag), an upper bound on the 2-norm
+// condition number of the column-equilibrated input.  One round leaves an
+// orthogonality error of order eps * kappa^2, so
+// st->round2 = (kappa_F > kappa_round2).
+__global__ __launch_bounds__(1024) void k_kappa(const double* __restrict__ gdiag, const double* __restrict__ R,
+                                                const double* __restrict__ Ri, int rp, int r, double kappa_round2,
+                                                DevStatus* st) {
+  if (failed(st)) return;
+  __shared__ double red[2][1024 / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t e = tid; e < (int64_t)rp * rp; e += 1024) {
+    const int i = (int)(e / rp), j = (int)(e % rp);
+    if (i <= j && j < r) {
+      const double a = R[e] / sqrt(gdiag[j]);
+      const double b = Ri[e] * sqrt(gdiag[i]);
+      s1 += a * a;
+      s2 += b * b;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+  }
+  if (lane == 0) {
+    red[0][wv] = s1;
+    red[1][wv] = s2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 1024 / 64; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    const double kap = sqrt(a * b);
+    const int need = !(kap <= kappa_round2);
+    st->round2 = need;
+    if (need) st->round2_count += 1;
+    if (kap > st->kappa_max) st->kappa_max = kap;
+  }
+}
+
+// C = A B for rp x rp row-major FP64 matrices; one wavefront per 16 x 16
+// output tile on the FP64 MFMA, operands read straight from global memory
+// (L2-resident).  gated: when st->round2 is 0 the product is replaced by a
+// copy of A (copy_b = false) or of B (copy_b = true), i.e. the other factor
+// is taken as the identity.  grid: rp*rp/256/4 workgroups of 256 threads.
+__global__ __launch_bounds__(256) void k_smallgemm(const double* __restrict__ A, const double* __restrict__ B,
+                                                   int rp, double* __restrict__ C, const DevStatus* st, bool gated,
+                                                   bool copy_b) {
+  if (failed(st)) return;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nt16 = rp / 16;
+  if (tile >= nt16 * nt16) return;
+  const int row0 = (tile / nt16) * 16, col0 = (tile % nt16) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  if (gated && *reinterpret_cast<const volatile int*>(&st->round2) == 0) {
+    const double* S = copy_b ? B : A;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t o = (int64_t)(row0 + 4 * v + lk) * rp + col0 + li;
+      C[o] = S[o];
+    }
+    return;
+  }
+  f64x4 acc = f64x4{0};
+  for (int k0 = 0; k0 < rp; k0 += 16) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A[(int64_t)(row0 + li) * rp + k0 + 4 * u + lk];
+      b[u] = B[(int64_t)(k0 + 4 * u + lk) * rp + col0 + li];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = mfma16x16x4d(a[u], b[u], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(int64_t)(row0 + 4 * v + lk) * rp + col0 + li] = acc[v];
+}
+
+template __global__ void k_trinv<1>(const double*, int, double*, const DevStatus*, bool);
+template __global__ void k_trinv<2>(const double*, int, double*, const DevStatus*, bool);
+template __global__ void k_trinv<4>(const double*, int, double*, const DevStatus*, bool);
+template __global__ void k_trinv<8>(const double*, int, double*, const DevStatus*, bool);
 
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz SVD of C (r x r) by block one-sided Jacobi.
@@ -321,7 +439,7 @@ __global__ __launch_bounds__(NTH) void k_jacobi_prep(const double* __restrict__ 
 
 __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, double* __restrict__ Pc, int rp,
                                                       int rd, double tol, const double* __restrict__ scal,
-                                                      double* __restrict__ cosbuf, DevStatus* st) {
+                                                      double* __restrict__ cosbuf, DevStatus* st, int inner_sweeps) {
   if (failed(st) || *reinterpret_cast<volatile int*>(&st->jacobi_done)) return;
   extern __shared__ double smem[];
   double(*Hs)[TP] = reinterpret_cast<double(*)[TP]>(smem);
@@ -329,7 +447,6 @@ __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, d
   double(*Xs)[TP] = reinterpret_cast<double(*)[TP]>(smem + 2 * TS * TP);
   __shared__ int colidx[TS];
   __shared__ double cs[32], sn[32];
-  __shared__ int pp[32], qq[32];
   __shared__ int rotated;
   __shared__ double red[NTH / 64];
   const int tid = threadIdx.x;
@@ -343,14 +460,30 @@ __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, d
   const double absfloor = 64.0 * 2.220446049250313e-16 * scal[0];
   __syncthreads();
 
-  // H = X^T X over the rows of the 64 selected columns
+  // H = X^T X over the rows of the 64 selected columns; the next 64-row
+  // chunk is fetched into registers while the current one is multiplied
   f64x4 acc = f64x4{0};
-  for (int k0 = 0; k0 < rp; k0 += TS) {
-    for (int e = tid; e < TS * TS; e += NTH) {
-      const int c = e >> 6, k = e & 63;
-      Xs[k][c] = Bc[(int64_t)colidx[c] * rp + k0 + k];
+  const int nchunk = rp / TS;
+  double pre[4];
+  auto fetch = [&](const double* M, int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + NTH * u;
+      pre[u] = M[(int64_t)colidx[e >> 6] * rp + k0 + (e & 63)];
     }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + NTH * u;
+      Xs[e & 63][e >> 6] = pre[u];
+    }
+  };
+  fetch(Bc, 0);
+  for (int ch = 0; ch < nchunk; ++ch) {
+    put();
     __syncthreads();
+    if (ch + 1 < nchunk) fetch(Bc, (ch + 1) * TS);
     acc = tile_mma<true>(acc, Xs, Xs);
     __syncthreads();
   }
@@ -381,64 +514,74 @@ __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, d
   if (!(red[0] > tol)) return;
 
   // cyclic Jacobi on the 64 x 64 Gram, accumulating the rotation in Js.  Per
-  // round: the 32 rotation parameters, then every thread transforms one 2 x 2
-  // block (row pair a, column pair b) of H and two entries of J.
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int ird = 0; ird < TS - 1; ++ird) {
-      if (tid < 32) {
-        int p, q;
-        rr_pair(TS, ird, tid, p, q);
-        const double a = Hs[p][p], d = Hs[q][q], b = Hs[p][q];
-        double c = 1.0, s = 0.0;
-        if (a > floor && d > floor && fabs(b) > absfloor && fabs(b) > tol * sqrt(a * d)) {
-          const double zeta = (d - a) / (2.0 * b);
-          const double az = fabs(zeta);
-          const double tt = az > 1e100 ? 0.5 / zeta : (zeta >= 0.0 ? 1.0 : -1.0) / (az + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = c * tt;
-          rotated = 1;
-        }
-        cs[tid] = c;
-        sn[tid] = s;
-        pp[tid] = p;
-        qq[tid] = q;
-      }
+  // round: the 32 rotation parameters (one thread each), then every thread
+  // transforms one 2 x 2 block (row pair a, column pair b) of H and two
+  // entries of J.  Pair indices come from the round-robin formula in
+  // registers, so each phase needs a single round of LDS reads.
+  {
+    const int ra = tid >> 5, rb = tid & 31;          // 2 x 2 block of H owned by this thread
+    const int jrow = tid & 63, jk0 = tid >> 6;        // J entries: row jrow, pairs jk0 and jk0 + 16
+    for (int sweep = 0; sweep < inner_sweeps; ++sweep) {
+      if (tid == 0) rotated = 0;
       __syncthreads();
-      {
-        const int a = tid >> 5, b = tid & 31;
-        const double sa = sn[a], sb = sn[b];
-        if (sa != 0.0 || sb != 0.0) {
-          const double ca = cs[a], cb = cs[b];
-          const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
-          const double x11 = Hs[pa][pb], x12 = Hs[pa][qb], x21 = Hs[qa][pb], x22 = Hs[qa][qb];
-          const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
-          const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
-          double z11 = cb * y11 - sb * y12, z12 = sb * y11 + cb * y12;
-          double z21 = cb * y21 - sb * y22, z22 = sb * y21 + cb * y22;
-          if (a == b && sa != 0.0) z12 = z21 = 0.0;
-          Hs[pa][pb] = z11;
-          Hs[pa][qb] = z12;
-          Hs[qa][pb] = z21;
-          Hs[qa][qb] = z22;
+      for (int ird = 0; ird < TS - 1; ++ird) {
+        if (tid < 32) {
+          int p, q;
+          rr_pair(TS, ird, tid, p, q);
+          const double a = Hs[p][p], d = Hs[q][q], b = Hs[p][q];
+          double c = 1.0, s = 0.0;
+          if (a > floor && d > floor && fabs(b) > absfloor && b * b > tol * tol * (a * d)) {
+            // angle from an FP32 estimate of t; c and s in FP64 with
+            // c^2 + s^2 = 1 to FP64 rounding (the angle only needs to be
+            // close: whatever is left is measured and removed later)
+            const float dm = (float)(d - a), bf = (float)b;
+            const float hy = sqrtf(dm * dm + 4.0f * bf * bf);
+            const float sg = ((dm >= 0.0f) == (bf >= 0.0f)) ? 2.0f : -2.0f;
+            const double t = (double)(sg * fabsf(bf) / (fabsf(dm) + hy));
+            c = rsq_nr(1.0 + t * t);
+            s = c * t;
+            rotated = 1;
+          }
+          cs[tid] = c;
+          sn[tid] = s;
         }
-        for (int e = tid; e < 32 * TS; e += NTH) {
-          const int k = e >> 6, row = e & 63;
-          const double sk = sn[k];
-          if (sk != 0.0) {
-            const double ck = cs[k];
-            const double xp = Js[row][pp[k]], xq = Js[row][qq[k]];
-            Js[row][pp[k]] = ck * xp - sk * xq;
-            Js[row][qq[k]] = sk * xp + ck * xq;
+        __syncthreads();
+        {
+          int pa, qa, pb, qb;
+          rr_pair(TS, ird, ra, pa, qa);
+          rr_pair(TS, ird, rb, pb, qb);
+          const double sa = sn[ra], sb = sn[rb], ca = cs[ra], cb = cs[rb];
+          if (sa != 0.0 || sb != 0.0) {
+            const double x11 = Hs[pa][pb], x12 = Hs[pa][qb], x21 = Hs[qa][pb], x22 = Hs[qa][qb];
+            const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
+            const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
+            double z11 = cb * y11 - sb * y12, z12 = sb * y11 + cb * y12;
+            double z21 = cb * y21 - sb * y22, z22 = sb * y21 + cb * y22;
+            if (ra == rb && sa != 0.0) z12 = z21 = 0.0;
+            Hs[pa][pb] = z11;
+            Hs[pa][qb] = z12;
+            Hs[qa][pb] = z21;
+            Hs[qa][qb] = z22;
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int k = jk0 + 16 * u;
+            int pk, qk;
+            rr_pair(TS, ird, k, pk, qk);
+            const double sk = sn[k], ck = cs[k];
+            if (sk != 0.0) {
+              const double xp = Js[jrow][pk], xq = Js[jrow][qk];
+              Js[jrow][pk] = ck * xp - sk * xq;
+              Js[jrow][qk] = sk * xp + ck * xq;
+            }
           }
         }
+        __syncthreads();
       }
+      const int any = rotated;
       __syncthreads();
+      if (!any) break;
     }
-    const int any = rotated;
-    __syncthreads();
-    if (!any) break;
   }
 
   // order the 64 rotated columns by decreasing norm (eigenvalue of the Gram):
@@ -461,18 +604,19 @@ __global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, d
   }
   __syncthreads();
 
-  // rotate the 64 columns of Bc and of Pc: X <- X J, 64 rows at a time
-  for (int which = 0; which < 2; ++which) {
-    double* M = which ? Pc : Bc;
-    for (int k0 = 0; k0 < rp; k0 += TS) {
-      for (int e = tid; e < TS * TS; e += NTH) {
-        const int c = e >> 6, k = e & 63;
-        Xs[k][c] = M[(int64_t)colidx[c] * rp + k0 + k];
-      }
+  // rotate the 64 columns of Bc and of Pc: X <- X J, 64 rows at a time, with
+  // the next chunk in flight during the current product
+  {
+    const int lane = tid & 63, w = tid >> 6;
+    const int bi = w >> 2, bj = w & 3, li = lane & 15, lk = lane >> 4;
+    fetch(Bc, 0);
+    for (int step = 0; step < 2 * nchunk; ++step) {
+      double* M = step < nchunk ? Bc : Pc;
+      const int k0 = (step % nchunk) * TS;
+      put();
       __syncthreads();
-      f64x4 y = tile_mma<false>(f64x4{0}, Xs, Hs);
-      const int lane = tid & 63, w = tid >> 6;
-      const int bi = w >> 2, bj = w & 3, li = lane & 15, lk = lane >> 4;
+      if (step + 1 < 2 * nchunk) fetch(step + 1 < nchunk ? Bc : Pc, ((step + 1) % nchunk) * TS);
+      const f64x4 y = tile_mma<false>(f64x4{0}, Xs, Hs);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int k = bi * 16 + 4 * v + lk, c = bj * 16 + li;

@@ -21,8 +21,9 @@ constexpr int kS1Max = 16;      // split-K ranges of the sample-side product
 constexpr int kGSplitMax = 16;  // row splits of the gradient
 constexpr int kGramChunkMax = 64;
 constexpr int kVecChunkMax = 1024;
-constexpr int kJacobiSweeps = 10;
-constexpr double kJacobiTol = 1e-10;
+constexpr int kJacobiSweeps = 12;
+constexpr int kJacobiInner = 2;     // inner sweeps per block step
+constexpr double kJacobiTol = 1e-8;
 constexpr double kKappaRound2 = 1e4;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -48,6 +49,7 @@ struct wssr_ctx {
   double *G = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *Rz = nullptr;
   double *Bc = nullptr, *Pc = nullptr, *Ps = nullptr, *T = nullptr, *scal = nullptr, *sig = nullptr;
   double *cosbuf = nullptr, *cw = nullptr, *vpart = nullptr, *dots = nullptr, *ymean = nullptr, *Tq = nullptr;
+  double *Rt = nullptr, *gdiag = nullptr;
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
 
@@ -171,8 +173,28 @@ struct wssr_ctx {
                        (const DevStatus*)st, gated);
   }
 
-  void cholinv(int rp, int r, double* R, double* Ri, int mode) {
-    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(1024), kCholinvLds, stream, G, rp, r, R, Ri, st, mode, kKappaRound2);
+  // Cholesky of G into R and R^{-1}; a first round (gated = false) also sets
+  // the device flag that decides the second round.
+  void chol(int rp, int r, double* R, double* Ri, bool gated) {
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), kCholLds, stream, G, rp, R, Rt, gdiag, st, gated);
+    const dim3 g(cdiv(rp, 4));
+    switch (rp / 64) {
+      case 1: hipLaunchKernelGGL(k_trinv<1>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
+      case 2: hipLaunchKernelGGL(k_trinv<2>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
+      case 3:
+      case 4: hipLaunchKernelGGL(k_trinv<4>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
+      default: hipLaunchKernelGGL(k_trinv<8>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
+    }
+    if (!gated)
+      hipLaunchKernelGGL(k_kappa, dim3(1), dim3(1024), 0, stream, (const double*)gdiag, (const double*)R,
+                         (const double*)Ri, rp, r, kKappaRound2, st);
+  }
+
+  // C = A B (rp x rp); gated: C = A (copy_b = false) or B when no second round ran
+  void smallgemm(const double* A, const double* B, int rp, double* C, bool gated, bool copy_b) {
+    const int tiles = (rp / 16) * (rp / 16);
+    hipLaunchKernelGGL(k_smallgemm, dim3(cdiv(tiles, 4)), dim3(256), 0, stream, A, B, rp, C, (const DevStatus*)st,
+                       gated, copy_b);
   }
 
   template <typename Tin, typename Tout>
@@ -191,12 +213,12 @@ struct wssr_ctx {
   void cholqr(const Tin* X, int64_t rows, int r, Tmid* mid, double* Rout) {
     const int rp = (int)rup(r, 64);
     gram(X, rows, r, false);
-    cholinv(rp, r, R1, R1i, 0);
+    chol(rp, r, R1, R1i, false);
     apply(X, rows, r, r, R1i, rp, r, mid, r, true, true);
     gram((const Tmid*)mid, rows, r, true);
-    cholinv(rp, r, R2, R2i, 1);
-    apply((const double*)R1i, rp, rp, rp, R2i, rp, rp, Tq, rp, true);
-    if (Rout) apply((const double*)R2, rp, rp, rp, R1, rp, rp, Rout, rp, true);
+    chol(rp, r, R2, R2i, true);
+    smallgemm(R1i, R2i, rp, Tq, true, false);
+    if (Rout) smallgemm(R2, R1, rp, Rout, true, true);
   }
 
   // SVD of the r x r matrix whose transpose is Ct (rp x rp row-major): sorted
@@ -207,7 +229,7 @@ struct wssr_ctx {
     for (int sw = 0; sw < kJacobiSweeps; ++sw) {
       for (int rd = 0; rd < nb - 1; ++rd)
         hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2), dim3(1024), kJacobiLds, stream, Bc, Pc, rp, rd, kJacobiTol,
-                           (const double*)scal, cosbuf + (int64_t)rd * (nb / 2), st);
+                           (const double*)scal, cosbuf + (int64_t)rd * (nb / 2), st, kJacobiInner);
       hipLaunchKernelGGL(k_jacobi_check, dim3(1), dim3(64), 0, stream, (const double*)cosbuf, (nb - 1) * (nb / 2),
                          kJacobiTol, st);
     }
@@ -286,7 +308,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
             h->alloc(h->cw, rp) && h->alloc(h->vpart, (size_t)kVecChunkMax * r) &&
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
             h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
-            h->alloc(h->Tq, (size_t)rp * rp);
+            h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp);
   if (!ok) {
     (void)hipGetLastError();
     for (void* p : h->allocs) (void)hipFree(p);
@@ -294,7 +316,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
     g_create_error = "workspace allocation failed";
     return WSSR_ERR_OOM;
   }
-  if (hipFuncSetAttribute((const void*)k_cholinv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholinvLds) !=
+  if (hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholLds) !=
           hipSuccess ||
       hipFuncSetAttribute((const void*)k_jacobi_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJacobiLds) !=
           hipSuccess) {
@@ -371,7 +393,7 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
       // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T;  C = G diag(sigma) P^T
       h->small_svd(h->Rz, r);
       // V = Q_Z P = Z (Tq P)
-      h->apply((const double*)h->Tq, rp, rp, rp, h->Ps, rp, rp, h->T, rp, false);
+      h->smallgemm(h->Tq, h->Ps, rp, h->T, false, false);
       h->apply((const float*)h->z, m, r, r, h->T, rp, r, h->vw, r, false);
     }
   }
