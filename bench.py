@@ -2,7 +2,7 @@
 
 Workload (default): the FP32 form, N=8192 samples, M=100000 parameters, rank
 r=256, q=2 passes, lambda=1e-3, synthetic O with a k^-1.2 spectrum rotating by
-0.01 per step (workloads.CONFIGS["c2"]).  Inputs are generated on the GPU and
+0.01 per step (workloads.CONFIGS["f32_n8192_m100k_r256"]).  Inputs are generated on the GPU and
 resident in HBM before timing.  A step is one whole call of wssr_step: centring,
 gradient, q passes (two products, CholeskyQR2 of both sides), Rayleigh-Ritz,
 signs and the Woodbury apply.
@@ -30,10 +30,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="f32_n8192_m100k_r256", help="workload name (workloads.CONFIGS)")
     ap.add_argument("--ring", type=int, default=4, help="distinct O_t held in HBM and cycled")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-cols", type=int, default=0, help="columns of the oracle sample (0: auto)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="run one elementwise copy of this many MiB before timing, as the reference "
+                         "point that scales the HBM byte counters of a counter-collection run")
     return ap.parse_args()
 
 
@@ -63,6 +66,14 @@ def main():
     del wl.w0, wl.u0
     torch.cuda.synchronize()
     log(f"generated {args.ring} x O ({cfg.n}x{cfg.m}) in {time.time() - t0:.1f}s")
+    if args.copy_calibration:
+        # one elementwise kernel reading and writing exactly copy_calibration MiB
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + written by one neg kernel")
+        del src, dst
 
     n, m, r, q, lam = cfg.n, cfg.m, cfg.r, cfg.q, cfg.lam
     h = Wssr(n_max=n, m_max=m, r_max=r, q_max=8, device=dev)
@@ -156,11 +167,11 @@ def main():
 def cpu_baseline(args, cfg, o_dev, e_dev, v_dev, h):
     """Time the FP64 oracle on a column sample of the same workload (the first
     `cols` parameters of one step's O, same E_L, the matching rows of V as the
-    warm start) and scale the per-step time to the full M (every stage of the
-    step is linear in M except the N x r and r x r ones, so this slightly
-    overstates the oracle's full-size time... i.e. understates its rate by
-    less than the M-independent share).  The GPU path is run on the same sample
-    instance to report its delta error against the oracle."""
+    warm start) and scale the per-step time by M / cols to a full step.  Every
+    stage of the step is linear in M except the N x r and r x r ones, which the
+    scaling counts M / cols times over, so the reported rate is a slight
+    underestimate of the oracle's full-size rate.  The GPU path is run on the
+    same sample instance to report its delta error against the oracle."""
     import numpy as np
     import torch
 

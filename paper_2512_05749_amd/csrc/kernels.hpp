@@ -33,7 +33,11 @@ __global__ void k_gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_
                                    float* ypart, int64_t kchunk, bool vec_o, bool vec_v, const DevStatus* st);
 template <int BN>
 __global__ void k_gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
-                                  float scale, float* Z, bool vec_o, bool vec_q, const DevStatus* st);
+                                  float scale, float* Z, bool vec_o, bool vec_q, const DevStatus* st, int tiles_j,
+                                  int full_tiles, int64_t sk_units, int sk_wgs, float* part);
+template <int BN>
+__global__ void k_streamk_fixup(const float* part, float* Z, int64_t m, int r, float scale, int tiles_j,
+                                int full_tiles, int64_t nk, int64_t sk_units, int sk_wgs, const DevStatus* st);
 
 template <typename T>
 __global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,

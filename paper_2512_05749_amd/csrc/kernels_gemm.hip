@@ -166,13 +166,26 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
 // ---------------------------------------------------------------------------
 // Parameter side Z = O^T Q * scale.  O is N x M row-major, Q is N x r
 // row-major.  D[i = parameter][j = rank]: A = (O^T) tile, B = Q^T tile, both
-// transposed into K-contiguous LDS rows.  grid (m tiles, r tiles).
+// transposed into K-contiguous LDS rows.
+//
+// 1-D grid over output tiles, tile = mi * tiles_j + ji (neighbouring
+// workgroups share the O tile).  Workgroups below full_tiles compute one whole
+// tile each.  When sk_wgs > 0, the remaining tiles are shared out stream-K
+// style: their K-steps, numbered u = t * nk + k over the leftover tiles t,
+// are cut into sk_wgs equal contiguous ranges, and workgroup full_tiles + w
+// accumulates range w.  A range is never longer than one tile's nk K-steps,
+// so it touches at most two tiles; the partial sums go to
+// part[(2 w + seg) * BM * BN] (seg = 0, 1 in tile order) and
+// k_streamk_fixup adds them.  This keeps every round of the launch full when
+// the tile count is not a multiple of the resident workgroup slots.
 // ---------------------------------------------------------------------------
 template <int BN>
 __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restrict__ O, int64_t ld, int64_t n,
                                                             int64_t m, const float* __restrict__ Q, int r,
                                                             float scale, float* __restrict__ Z, bool vec_o,
-                                                            bool vec_q, const DevStatus* st) {
+                                                            bool vec_q, const DevStatus* st, int tiles_j,
+                                                            int full_tiles, int64_t sk_units, int sk_wgs,
+                                                            float* __restrict__ part) {
   if (failed(st)) return;
   constexpr int TB = BN / 64;
   constexpr int OV = BK * BM / 4 / 256;       // float4 per thread for the O tile (2)
@@ -183,17 +196,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wj = w & 1;
   const int x = lane & 31, h = lane >> 5;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int j0 = blockIdx.y * BN;
+  int64_t m0 = 0;
+  int j0 = 0;
+  bool inner = false;
 
   f32x16 acc[2][TB];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
-
   f32x4 ro[OV], rq[QV];
-  const bool inner = vec_o && vec_q && (m0 + BM <= m) && (j0 + BN <= r);
   auto gload = [&](int64_t k0) {
     if (inner && k0 + BK <= n) {
 #pragma unroll
@@ -239,31 +247,99 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side(const float* __restr
       st_transposed(Qs[buf], cq, krow, rq[i]);
     }
   };
+  // acc = the product of tile `tile` over K-steps [kb, ke)
+  auto run = [&](int64_t tile, int64_t kb, int64_t ke) {
+    m0 = (tile / tiles_j) * BM;
+    j0 = (int)(tile % tiles_j) * BN;
+    inner = vec_o && vec_q && (m0 + BM <= m) && (j0 + BN <= r);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
+    gload(kb * BK);
+    sstore(0);
+    __syncthreads();
+    for (int64_t it = kb; it < ke; ++it) {
+      const int buf = (int)((it - kb) & 1);
+      if (it + 1 < ke) gload((it + 1) * BK);
+      mma_kstep<2, TB>(acc, Os[buf], wm * 64, Qs[buf], wj * (BN / 2), x, h);
+      if (it + 1 < ke) sstore(buf ^ 1);
+      __syncthreads();
+    }
+  };
 
   const int64_t nk = (n + BK - 1) / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int64_t it = 0; it < nk; ++it) {
-    const int buf = (int)(it & 1);
-    if (it + 1 < nk) gload((it + 1) * BK);
-    mma_kstep<2, TB>(acc, Os[buf], wm * 64, Qs[buf], wj * (BN / 2), x, h);
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
+  if ((int)blockIdx.x < full_tiles) {
+    run(blockIdx.x, 0, nk);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < TB; ++b) {
-      const int col = j0 + wj * (BN / 2) + b * 32 + x;
-      if (col >= r) continue;
+      for (int b = 0; b < TB; ++b) {
+        const int col = j0 + wj * (BN / 2) + b * 32 + x;
+        if (col >= r) continue;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = m0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (row < m) Z[row * r + col] = acc[a][b][v] * scale;
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = m0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          if (row < m) Z[row * r + col] = acc[a][b][v] * scale;
+        }
       }
-    }
+    return;
+  }
+  const int64_t wg = (int64_t)blockIdx.x - full_tiles;
+  const int64_t ubeg = wg * sk_units / sk_wgs, uend = (wg + 1) * sk_units / sk_wgs;
+  int seg = 0;
+  for (int64_t u = ubeg; u < uend; ++seg) {
+    const int64_t tl = u / nk, kb = u - tl * nk, ke = min(nk, kb + (uend - u));
+    run(full_tiles + tl, kb, ke);
+    float* out = part + (wg * 2 + seg) * (int64_t)(BM * BN);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int col = wj * (BN / 2) + b * 32 + x;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          out[row * BN + col] = acc[a][b][v];
+        }
+      }
+    u += ke - kb;
+  }
+}
+
+// Adds the stream-K partials of the leftover tiles in workgroup order (fixed,
+// so the result is reproducible) and writes them, scaled, into Z.
+// grid (leftover tiles, BM * BN / 1024), 256 threads of 4 consecutive columns.
+template <int BN>
+__global__ __launch_bounds__(256) void k_streamk_fixup(const float* __restrict__ part, float* __restrict__ Z,
+                                                       int64_t m, int r, float scale, int tiles_j, int full_tiles,
+                                                       int64_t nk, int64_t sk_units, int sk_wgs,
+                                                       const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t tl = blockIdx.x;
+  const int e0 = (blockIdx.y * 256 + threadIdx.x) * 4;
+  const int row = e0 / BN, col = e0 % BN;
+  const int64_t tile = full_tiles + tl;
+  const int64_t m0 = (tile / tiles_j) * BM;
+  const int j0 = (int)(tile % tiles_j) * BN;
+  const int64_t u0 = tl * nk, u1 = u0 + nk;
+  auto range_begin = [&](int64_t w) { return w * sk_units / sk_wgs; };
+  // the workgroup whose range holds u0: the last w with range_begin(w) <= u0
+  int64_t w = min<int64_t>(sk_wgs - 1, u0 * sk_wgs / sk_units);
+  while (w > 0 && range_begin(w) > u0) --w;
+  while (w + 1 < sk_wgs && range_begin(w + 1) <= u0) ++w;
+  f32x4 s = f32x4{0};
+  for (; w < sk_wgs && range_begin(w) < u1; ++w) {
+    const int64_t a = range_begin(w), e = range_begin(w + 1);
+    if (e <= a || e <= u0) continue;
+    const int seg = (int)(tl - a / nk);
+    s += *reinterpret_cast<const f32x4*>(part + (w * 2 + seg) * (int64_t)(BM * BN) + e0);
+  }
+  const int64_t grow = m0 + row;
+  if (grow >= m) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (j0 + col + c < r) Z[grow * r + j0 + col + c] = s[c] * scale;
 }
 
 template __global__ void k_gemm_sample_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
@@ -271,8 +347,12 @@ template __global__ void k_gemm_sample_side<128>(const float*, int64_t, int64_t,
 template __global__ void k_gemm_sample_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
                                                  int64_t, bool, bool, const DevStatus*);
 template __global__ void k_gemm_param_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
-                                                float*, bool, bool, const DevStatus*);
+                                                float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
 template __global__ void k_gemm_param_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
-                                                float*, bool, bool, const DevStatus*);
+                                                float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
+template __global__ void k_streamk_fixup<128>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
+                                              int, const DevStatus*);
+template __global__ void k_streamk_fixup<256>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
+                                              int, const DevStatus*);
 
 }  // namespace wssr

@@ -38,6 +38,8 @@ struct wssr_ctx {
   std::string err;
   int rp_max = 0;
   int64_t rows_max = 0;
+  int slots = 512;               // resident product workgroups: 2 per compute unit
+  float* skpart = nullptr;       // stream-K partial tiles of the parameter-side product
   std::vector<void*> allocs;
 
   DevStatus* st = nullptr;
@@ -107,7 +109,7 @@ struct wssr_ctx {
     const int bn = r > 128 ? 256 : 128;
     const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
     // about two workgroups per CU in one round; split K = M into s1 ranges
-    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(512, tn * tj)));
+    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(slots, tn * tj)));
     int64_t kchunk = rup(cdiv(m, s1), 16);
     s1 = (int)cdiv(m, kchunk);
     const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
@@ -137,14 +139,37 @@ struct wssr_ctx {
     const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
     const bool vec_q = (r % 4 == 0) && ((uintptr_t)Q % 16 == 0);
     const float scale = (float)(1.0 / std::sqrt((double)n));
-    const dim3 grid(cdiv(m, 128), cdiv(r, bn));
+    const int64_t tj = cdiv(r, bn), tiles = cdiv(m, 128) * tj, nk = cdiv(n, 16);
+    // whole tiles for every full round of resident workgroups; the leftover
+    // tiles' K-steps shared evenly by one more round (stream-K) unless the
+    // leftover round is nearly full anyway
+    int full = (int)tiles, skw = 0;
+    int64_t rem = 0, units = 0;
+    if (skpart && tiles > slots) {
+      rem = tiles % slots;
+      if (rem != 0 && rem * 5 < (int64_t)slots * 4) {
+        full = (int)(tiles - rem);
+        skw = slots;
+        units = rem * nk;
+      }
+    }
+    const dim3 grid(full + skw);
     timed(1, [&] {
-      if (bn == 256)
+      if (bn == 256) {
         hipLaunchKernelGGL(k_gemm_param_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
-                           vec_q, (const DevStatus*)st);
-      else
+                           vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        if (skw)
+          hipLaunchKernelGGL(k_streamk_fixup<256>, dim3(rem, 128 * 256 / 1024), dim3(256), 0, stream,
+                             (const float*)skpart, Z, m, r, scale, (int)tj, full, nk, units, skw,
+                             (const DevStatus*)st);
+      } else {
         hipLaunchKernelGGL(k_gemm_param_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
-                           vec_q, (const DevStatus*)st);
+                           vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        if (skw)
+          hipLaunchKernelGGL(k_streamk_fixup<128>, dim3(rem, 128 * 128 / 1024), dim3(256), 0, stream,
+                             (const float*)skpart, Z, m, r, scale, (int)tj, full, nk, units, skw,
+                             (const DevStatus*)st);
+      }
     });
   }
 
@@ -287,6 +312,9 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
   }
   auto* h = new wssr_ctx();
   h->device = dev;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    h->slots = 2 * cus;
   h->cfg = *cfg;
   h->stream = static_cast<hipStream_t>(cfg->stream);
   const int64_t n = cfg->n_max, m = cfg->m_max;
@@ -309,6 +337,10 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
             h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
             h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp);
+  // stream-K partials (two 128 x 256 tiles per workgroup of one round), only
+  // when a parameter-side product can have more tiles than one round holds
+  const int64_t ptiles = cdiv(m, 128) * cdiv(r, r > 128 ? 256 : 128);
+  if (ok && ptiles > h->slots) ok = h->alloc(h->skpart, (size_t)h->slots * 2 * 128 * 256);
   if (!ok) {
     (void)hipGetLastError();
     for (void* p : h->allocs) (void)hipFree(p);

@@ -65,6 +65,31 @@ def test_param_side(ws, n, m, r):
     assert rel(z, ref) < 2e-6
 
 
+@pytest.fixture(scope="module")
+def ws_wide():
+    from paper_2512_05749_amd import Wssr
+    h = Wssr(n_max=512, m_max=140_000, r_max=256, q_max=2)
+    yield h
+    h.close()
+
+
+# Enough parameter tiles (128 parameters each) that they exceed one round of
+# resident workgroups (512 on MI355X), so the leftover tiles are shared out
+# stream-K style and summed by the fix-up kernel; the last shape fills its
+# second round and runs whole tiles only.
+@pytest.mark.parametrize("n,m,r", [(200, 70_001, 40), (300, 100_003, 130), (77, 99_999, 256), (64, 128_000, 64)])
+def test_param_side_many_tiles(ws_wide, n, m, r):
+    o, _, _ = _inputs(n, m, r, seed=5 * n + r, ld_pad=0)
+    x = torch.randn(n, r, device="cuda", dtype=torch.float32)
+    x -= x.mean(0, keepdim=True)
+    z = ws_wide.param_side(o, x).cpu().numpy()
+    ref = orc.gemm_param_side(o.double().cpu().numpy(), x.double().cpu().numpy())
+    assert rel(z, ref) < 2e-6
+    # every parameter row is checked, not only the norm
+    row_err = np.abs(z - ref).max(1) / (np.abs(ref).max() + 1e-30)
+    assert row_err.max() < 1e-5
+
+
 @pytest.mark.parametrize("rows,r", [(100, 1), (333, 7), (1000, 64), (4000, 65), (4096, 130), (2500, 192)])
 def test_cholqr2(ws, rows, r):
     gen = torch.Generator(device="cuda").manual_seed(rows + r)

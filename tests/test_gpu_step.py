@@ -55,7 +55,7 @@ def test_small_workload_ten_steps(ws):
     """N=1024, M=2000, r=32, q=2, lambda=1e-3, rotation 0.02/step: step 1 cold
     (8 passes from V_0), then warm-started steps, each against the oracle given
     the same V_in (teacher forcing)."""
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["f32_n1024_m2k_r32"]
     wl = Workload(cfg, device="cuda")
     v = wl.v0()
     for t in range(1, cfg.steps + 1):

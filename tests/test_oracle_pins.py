@@ -276,6 +276,41 @@ def test_p11_projection_identity():
     np.testing.assert_allclose(c1, c2, atol=1e-12 * np.abs(c1).max())
 
 
+def test_stage_products_by_loops():
+    """The stage helpers the GPU stage tests compare against, checked against
+    element-by-element sums on a tiny input: Y = A V, Z = A^T X and G = X^T X with
+    A = (O - 1 mu^T)/sqrt(N) (eqs. Osr, Osrn)."""
+    rng = rng0(21)
+    n, m, r = 5, 7, 3
+    o = rng.standard_normal((n, m)) + 2.0
+    v = rng.standard_normal((m, r))
+    x = rng.standard_normal((n, r))
+    mu = [sum(o[i, j] for i in range(n)) / n for j in range(m)]
+    y = np.zeros((n, r))
+    z = np.zeros((m, r))
+    for i in range(n):
+        for k in range(r):
+            y[i, k] = sum((o[i, j] - mu[j]) * v[j, k] for j in range(m)) / np.sqrt(n)
+    for j in range(m):
+        for k in range(r):
+            z[j, k] = sum((o[i, j] - mu[j]) * x[i, k] for i in range(n)) / np.sqrt(n)
+    gx = np.array([[sum(x[i, a] * x[i, b] for i in range(n)) for b in range(r)] for a in range(r)])
+    assert _rel(orc.gemm_sample_side(o, v), y) < 1e-14
+    assert _rel(orc.gemm_param_side(o, x), z) < 1e-14
+    assert _rel(orc.gram(x), gx) < 1e-14
+    # the sample-side product of a centred matrix has zero column sums
+    assert np.abs(orc.gemm_sample_side(o, v).sum(0)).max() < 1e-12
+
+
+def test_subspace_distance_closed_form():
+    """span(e1, e2) against span(e1, cos t e2 + sin t e3): largest principal angle t."""
+    t = 0.3
+    v1 = np.eye(4)[:, :2]
+    v2 = np.stack([np.eye(4)[:, 0], np.cos(t) * np.eye(4)[:, 1] + np.sin(t) * np.eye(4)[:, 2]], 1)
+    assert abs(orc.subspace_distance(v1, 3.0 * v2) - np.sin(t)) < 1e-14
+    assert orc.subspace_distance(v1, v1 @ np.array([[0.0, 2.0], [1.0, 1.0]])) < 1e-7
+
+
 def test_woodbury_general_core_equals_dense_inverse():
     """Woodbury apply for a non-orthonormal V equals the dense (V S^2 V^T + lam I)^{-1} g."""
     rng = rng0(12)

@@ -54,20 +54,21 @@ class Config:
         return self.k if self.k else self.n
 
 
-# The workloads: a small exactly checkable one, the FP32 benchmark one, the
-# precision-form instance, and the large single instance.
-CONFIGS = {
-    "c1": Config("c1", n=1024, m=2000, r=32, q=2, lam=1e-3, steps=10, alpha=1.5,
-                 theta=0.02, eta=1e-3, el_mean=-1.0, el_std=0.1, seed=1),
-    "c2": Config("c2", n=8192, m=100_000, r=256, q=2, lam=1e-3, steps=20, alpha=1.2,
-                 theta=0.01, eta=1e-3, el_mean=-10.0, el_std=0.5, seed=2),
-    "c3": Config("c3", n=16384, m=1_000_000, r=512, q=2, lam=1e-3, steps=20, alpha=1.0,
-                 theta=0.01, eta=1e-4, el_mean=-10.0, el_std=0.5, seed=3, k=4096,
-                 dtype="bf16"),
-    "c5": Config("c5", n=16384, m=4_000_000, r=512, q=3, lam=1e-3, steps=10, alpha=1.3,
-                 theta=0.005, eta=1e-4, el_mean=-10.0, el_std=0.5, seed=5, k=4096,
-                 dtype="bf16"),
-}
+# The workloads, named by dtype and size: a small one the oracle checks in
+# seconds, the FP32 benchmark instance, the BF16 precision-form instance, and the
+# largest single instance.
+CONFIGS = {c.name: c for c in [
+    Config("f32_n1024_m2k_r32", n=1024, m=2000, r=32, q=2, lam=1e-3, steps=10,
+           alpha=1.5, theta=0.02, eta=1e-3, el_mean=-1.0, el_std=0.1, seed=1),
+    Config("f32_n8192_m100k_r256", n=8192, m=100_000, r=256, q=2, lam=1e-3, steps=20,
+           alpha=1.2, theta=0.01, eta=1e-3, el_mean=-10.0, el_std=0.5, seed=2),
+    Config("bf16_n16384_m1m_r512", n=16384, m=1_000_000, r=512, q=2, lam=1e-3, steps=20,
+           alpha=1.0, theta=0.01, eta=1e-4, el_mean=-10.0, el_std=0.5, seed=3, k=4096,
+           dtype="bf16"),
+    Config("bf16_n16384_m4m_r512_q3", n=16384, m=4_000_000, r=512, q=3, lam=1e-3, steps=10,
+           alpha=1.3, theta=0.005, eta=1e-4, el_mean=-10.0, el_std=0.5, seed=5, k=4096,
+           dtype="bf16"),
+]}
 
 _COMPONENT = {"u": 1, "w": 2, "perm_n": 3, "perm_m": 4, "v0": 5, "noise": 6, "el": 7}
 
