@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--ring", type=int, default=4, help="distinct O_t held in HBM and cycled")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-cols", type=int, default=0, help="columns of the oracle sample (0: auto)")
+    ap.add_argument("--plain-inputs", type=int, default=0,
+                    help="draw O, E_L and V_0 i.i.d. Gaussian (no QR factorisation in the generator); "
+                         "for hardware-counter runs, whose byte counts do not depend on the values")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run one elementwise copy of this many MiB before timing, as the reference "
                          "point that scales the HBM byte counters of a counter-collection run")
@@ -59,11 +62,18 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    wl = Workload(cfg, device=dev, gen_dtype=torch.float32)
-    os_ = [wl.o(t) for t in range(1, args.ring + 1)]
-    es = [wl.e_l(t) for t in range(1, args.ring + 1)]
-    v = wl.v0()
-    del wl.w0, wl.u0
+    if args.plain_inputs:
+        gen = torch.Generator(device=dev).manual_seed(cfg.seed)
+        os_ = [torch.randn(cfg.n, cfg.m, generator=gen, device=dev) for _ in range(args.ring)]
+        es = [cfg.el_mean + cfg.el_std * torch.randn(cfg.n, generator=gen, device=dev, dtype=torch.float64)
+              for _ in range(args.ring)]
+        v = torch.randn(cfg.m, cfg.r, generator=gen, device=dev) / math.sqrt(cfg.m)
+    else:
+        wl = Workload(cfg, device=dev, gen_dtype=torch.float32)
+        os_ = [wl.o(t) for t in range(1, args.ring + 1)]
+        es = [wl.e_l(t) for t in range(1, args.ring + 1)]
+        v = wl.v0()
+        del wl.w0, wl.u0
     torch.cuda.synchronize()
     log(f"generated {args.ring} x O ({cfg.n}x{cfg.m}) in {time.time() - t0:.1f}s")
     if args.copy_calibration:
@@ -148,7 +158,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic",
+        "data": "synthetic, i.i.d. Gaussian O (counter run)" if args.plain_inputs else "synthetic",
         "config": {"workload": f"{cfg.name}: FP32 WSSR step, N={n} M={m} r={r} q={q} lambda={lam}, "
                                f"spectrum k^-{cfg.alpha}, rotation {cfg.theta}/step",
                    "n": n, "m": m, "r": r, "q": q, "lambda": lam},

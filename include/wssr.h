@@ -27,8 +27,11 @@
  *
  * Streams.  All work is enqueued on the stream given at create time (a
  * hipStream_t; NULL means the null stream); calls return without waiting.
- * Results are valid once that stream has been synchronised.  A handle is not
- * thread-safe; use one handle per stream.
+ * Inside wssr_step, the gradient pass runs on a second, library-owned stream (beside the Rayleigh-Ritz SVD)
+ * forked from and joined back into that stream with events, so the step is
+ * still ordered on the caller's stream as one unit.  Results are valid once
+ * that stream has been synchronised.  A handle is not thread-safe; use one
+ * handle per stream.
  *
  * Errors.  Argument errors are detected on the host before anything is
  * enqueued and returned as negative codes; nothing is enqueued then.

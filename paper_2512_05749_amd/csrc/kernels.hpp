@@ -30,7 +30,8 @@ __global__ void k_delta(const float* v, const double* g, const double* cw, int64
 
 template <int BN>
 __global__ void k_gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* V, int r,
-                                   float* ypart, int64_t kchunk, bool vec_o, bool vec_v, const DevStatus* st);
+                                   float* ypart, int64_t kchunk, bool vec_o, bool vec_v, const DevStatus* st,
+                                   int tn, int tj, bool xcd_groups);
 template <int BN>
 __global__ void k_gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
                                   float scale, float* Z, bool vec_o, bool vec_q, const DevStatus* st, int tiles_j,

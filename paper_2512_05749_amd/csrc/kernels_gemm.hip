@@ -58,14 +58,36 @@ __device__ __forceinline__ void st_transposed(float (*T)[LDK], int c, int k, f32
 
 // ---------------------------------------------------------------------------
 // Sample side.  O is N x M row-major (K contiguous), V is M x r row-major.
-// grid (n tiles, r tiles, S).  D[i = sample][j = rank]: A = O tile, B = V^T tile.
+// D[i = sample][j = rank]: A = O tile, B = V^T tile.  1-D grid of
+// tn * tj * S workgroups over (n tile, r tile, K range).  The workgroups that
+// read the same rows of V (same K range and r tile: one "group" of tn) are
+// placed on the same XCD when the group count is a multiple of the 8 XCDs
+// (workgroups are dispatched round-robin over the XCDs by linear index), so
+// each V range is fetched into one L2 instead of all eight.
 // ---------------------------------------------------------------------------
 template <int BN>
 __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __restrict__ O, int64_t ld, int64_t n,
                                                              int64_t m, const float* __restrict__ V, int r,
                                                              float* __restrict__ ypart, int64_t kchunk,
-                                                             bool vec_o, bool vec_v, const DevStatus* st) {
+                                                             bool vec_o, bool vec_v, const DevStatus* st, int tn,
+                                                             int tj, bool xcd_groups) {
   if (failed(st)) return;
+  int bx, by, bz;
+  {
+    const int id = blockIdx.x;
+    int grp, i;
+    if (xcd_groups) {
+      const int xcd = id & 7, local = id >> 3;
+      grp = (local / tn) * 8 + xcd;
+      i = local % tn;
+    } else {
+      grp = id / tn;
+      i = id % tn;
+    }
+    bx = i;
+    by = grp % tj;
+    bz = grp / tj;
+  }
   constexpr int TB = BN / 64;                 // rank blocks per wave
   constexpr int AV = BM * BK / 4 / 256;       // float4 per thread for the O tile (2)
   constexpr int BV = BK * BN / 4 / 256;       // float4 per thread for the V tile (2 or 4)
@@ -75,11 +97,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side(const float* __rest
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int x = lane & 31, h = lane >> 5;
-  const int64_t n0 = (int64_t)blockIdx.x * BM;
-  const int j0 = blockIdx.y * BN;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t n0 = (int64_t)bx * BM;
+  const int j0 = by * BN;
+  const int64_t kb = (int64_t)bz * kchunk;
   const int64_t ke = min(m, kb + kchunk);
-  float* out = ypart + (int64_t)blockIdx.z * n * r;
+  float* out = ypart + (int64_t)bz * n * r;
 
   f32x16 acc[2][TB];
 #pragma unroll
@@ -343,9 +365,9 @@ __global__ __launch_bounds__(256) void k_streamk_fixup(const float* __restrict__
 }
 
 template __global__ void k_gemm_sample_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
-                                                 int64_t, bool, bool, const DevStatus*);
+                                                 int64_t, bool, bool, const DevStatus*, int, int, bool);
 template __global__ void k_gemm_sample_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
-                                                 int64_t, bool, bool, const DevStatus*);
+                                                 int64_t, bool, bool, const DevStatus*, int, int, bool);
 template __global__ void k_gemm_param_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
                                                 float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
 template __global__ void k_gemm_param_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float,

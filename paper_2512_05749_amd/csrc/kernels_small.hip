@@ -113,8 +113,8 @@ __device__ __forceinline__ void rot_params(double a, double d, double b, double&
 // substitution; the panel and trailing updates are 64 x 64 x 64 tile
 // products on the FP64 MFMA.
 //
-// gated: a second CholeskyQR round; when st->round2 is 0 the kernel only
-// writes identity factors.
+// gated: a second CholeskyQR round; when st->round2 is 0 the kernel does
+// nothing (the gated consumers of R and Rt then take the identity instead).
 // Dynamic LDS: 4 tiles.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, double* __restrict__ R,
@@ -122,14 +122,7 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
                                               bool gated) {
   if (failed(st)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (gated && *reinterpret_cast<volatile int*>(&st->round2) == 0) {
-    for (int64_t e = tid; e < (int64_t)rp * rp; e += NTH) {
-      const double v = ((e / rp) == (e % rp)) ? 1.0 : 0.0;
-      R[e] = v;
-      Rt[e] = v;
-    }
-    return;
-  }
+  if (gated && *reinterpret_cast<volatile int*>(&st->round2) == 0) return;
   extern __shared__ double smem[];
   double(*T0)[TP] = reinterpret_cast<double(*)[TP]>(smem);
   double(*T1)[TP] = reinterpret_cast<double(*)[TP]>(smem + TS * TP);

@@ -53,6 +53,7 @@ __global__ __launch_bounds__(256) void k_gradient_partial(const float* __restric
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r1 = min(n, r0 + rows_per_split);
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 8
   for (int64_t i = r0; i < r1; ++i) {
     const f32x4 v = load4(O + i * ld, c0, m, vec);
     const double e = eps[i];

@@ -39,6 +39,8 @@ struct wssr_ctx {
   int rp_max = 0;
   int64_t rows_max = 0;
   int slots = 512;               // resident product workgroups: 2 per compute unit
+  hipStream_t side = nullptr;    // second stream: the gradient pass runs beside the Rayleigh-Ritz SVD
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float* skpart = nullptr;       // stream-K partial tiles of the parameter-side product
   std::vector<void*> allocs;
 
@@ -93,6 +95,21 @@ struct wssr_ctx {
     return code;
   }
 
+  void release() {
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+    side = nullptr;
+    ev_fork = ev_join = nullptr;
+    ev_pool.clear();
+    allocs.clear();
+  }
+
   template <typename T>
   bool alloc(T*& p, size_t count) {
     void* q = nullptr;
@@ -114,13 +131,15 @@ struct wssr_ctx {
     s1 = (int)cdiv(m, kchunk);
     const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
     const bool vec_v = (r % 4 == 0) && ((uintptr_t)V % 16 == 0);
+    const bool xcd = ((int64_t)s1 * tj) % 8 == 0;
+    const dim3 grid((unsigned)(tn * tj * s1));
     timed(0, [&] {
       if (bn == 256)
-        hipLaunchKernelGGL(k_gemm_sample_side<256>, dim3(tn, tj, s1), dim3(256), 0, stream, O, ld, n, m, V, r, ypart,
-                           kchunk, vec_o, vec_v, (const DevStatus*)st);
+        hipLaunchKernelGGL(k_gemm_sample_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
+                           vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
       else
-        hipLaunchKernelGGL(k_gemm_sample_side<128>, dim3(tn, tj, s1), dim3(256), 0, stream, O, ld, n, m, V, r, ypart,
-                           kchunk, vec_o, vec_v, (const DevStatus*)st);
+        hipLaunchKernelGGL(k_gemm_sample_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
+                           vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
     });
     const int64_t tot = n * r;
     hipLaunchKernelGGL(k_ysum, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)ypart, s1, tot, y64,
@@ -173,10 +192,15 @@ struct wssr_ctx {
     });
   }
 
-  void gradient(const float* O, int64_t ld, int64_t n, int64_t m, const double* e_l, double* gout) {
+  // lean: at most about one workgroup per compute unit, for running beside
+  // other work without taking the compute units it needs
+  void gradient(const float* O, int64_t ld, int64_t n, int64_t m, const double* e_l, double* gout,
+                hipStream_t on = nullptr, bool lean = false) {
+    hipStream_t stream = on ? on : this->stream;
     hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, eps, st);
     const int64_t cb = cdiv(m, 1024);
-    const int gs = (int)std::min<int64_t>(kGSplitMax, std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, cb), n)));
+    const int64_t want = lean ? std::max<int64_t>(1, slots / 2 / cb) : cdiv(2048, cb);
+    const int gs = (int)std::min<int64_t>(kGSplitMax, std::max<int64_t>(1, std::min<int64_t>(want, n)));
     const int64_t rows = cdiv(n, gs);
     const bool vec = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
     hipLaunchKernelGGL(k_gradient_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n, m, (const double*)eps, rows,
@@ -343,7 +367,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
   if (ok && ptiles > h->slots) ok = h->alloc(h->skpart, (size_t)h->slots * 2 * 128 * 256);
   if (!ok) {
     (void)hipGetLastError();
-    for (void* p : h->allocs) (void)hipFree(p);
+    h->release();
     delete h;
     g_create_error = "workspace allocation failed";
     return WSSR_ERR_OOM;
@@ -352,14 +376,22 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
           hipSuccess ||
       hipFuncSetAttribute((const void*)k_jacobi_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJacobiLds) !=
           hipSuccess) {
-    for (void* p : h->allocs) (void)hipFree(p);
+    h->release();
     delete h;
     g_create_error = "hipFuncSetAttribute failed";
     return WSSR_ERR_HIP;
   }
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+    h->release();
+    delete h;
+    g_create_error = "stream or event creation failed";
+    return WSSR_ERR_HIP;
+  }
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
   if (hipGetLastError() != hipSuccess) {
-    for (void* p : h->allocs) (void)hipFree(p);
+    h->release();
     delete h;
     g_create_error = "kernel launch failed";
     return WSSR_ERR_HIP;
@@ -371,8 +403,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
 wssr_status wssr_destroy(wssr_handle h) {
   if (!h) return WSSR_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(h->stream);
-  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-  for (void* p : h->allocs) (void)hipFree(p);
+  h->release();
   delete h;
   return WSSR_OK;
 }
@@ -407,7 +438,6 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
   const DevStatus* cst = h->st;
   hipStream_t stream = h->stream;
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
-  h->gradient(Of, ld_o, n, m, e_l, h->g);
 
   const float* vcur = V;
   for (int p = 1; p <= q; ++p) {
@@ -422,6 +452,12 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
       h->apply((const float*)h->z, m, r, r, h->Tq, rp, r, h->vw, r, true);
       vcur = h->vw;
     } else {
+      // the gradient (one HBM-bound pass over O) runs on the second stream
+      // while this stream works through the few-workgroup Jacobi launches
+      (void)hipEventRecord(h->ev_fork, stream);
+      (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+      h->gradient(Of, ld_o, n, m, e_l, h->g, h->side, true);
+      (void)hipEventRecord(h->ev_join, h->side);
       // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T;  C = G diag(sigma) P^T
       h->small_svd(h->Rz, r);
       // V = Q_Z P = Z (Tq P)
@@ -429,9 +465,12 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
       h->apply((const float*)h->z, m, r, r, h->T, rp, r, h->vw, r, false);
     }
   }
+  (void)hipStreamWaitEvent(stream, h->ev_join, 0);
   // output signs, then V <- signed vw
   {
-    const int64_t rpc = std::max<int64_t>(256, cdiv(m, 256));
+    // row chunks: as many as the partial buffers hold (enough blocks to cover
+    // every compute unit several times), at least 64 rows each
+    const int64_t rpc = std::max<int64_t>(64, cdiv(m, kVecChunkMax));
     const int nch = (int)cdiv(m, rpc);
     hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->vw,
                        (const float*)V, m, r, rpc, h->dots, h->maxval, h->maxrow, cst);
