@@ -23,6 +23,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SR steps/s at N×M×r vs plain FP32; HBM GB/s; rel err of δ vs FP64 oracle"
 PEAK_FP32_TFLOPS = 157.3
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_wssr_step_f32_n8192_m100k_r256.md")
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel source changed since it was taken
+    (the summary records the SHA-256 of the source file it measured)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_RECORD).read()
+    except OSError:
+        return None
+    for mt in re.finditer(r"traffic-record: kernel=(\S+) bytes_per_launch=(\d+) source=(\S+) sha256=([0-9a-f]+)", text):
+        if mt.group(1) != kernel:
+            continue
+        try:
+            src = open(os.path.join(ROOT, mt.group(3)), "rb").read()
+        except OSError:
+            return None
+        return int(mt.group(2)) if hashlib.sha256(src).hexdigest() == mt.group(4) else None
+    return None
 
 
 def parse():
@@ -140,7 +162,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     achieved = kern[dom]["tflops"]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": recorded_traffic("k_gemm_" + dom),
                 "kernel": "k_gemm_" + dom, "avg_ms": round(kern[dom]["avg_ms"], 4),
                 "flops_per_launch": flops_gemm,
                 "other": {k: {"avg_ms": round(v_["avg_ms"], 4), "tflops": round(v_["tflops"], 2)}
