@@ -58,8 +58,10 @@ typedef enum {
   WSSR_ERR_OOM = -3,
   WSSR_ERR_HIP = -4,
   WSSR_ERR_NONFINITE = -5,       /* NaN/Inf in E_L, or reached the Gram matrices from O or V */
-  WSSR_ERR_BREAKDOWN = -6        /* a Cholesky pivot of a Gram matrix was not positive:
+  WSSR_ERR_BREAKDOWN = -6,       /* a Cholesky pivot of a Gram matrix was not positive:
                                     the iterated basis lost rank */
+  WSSR_ERR_TIMEOUT = -7          /* internal: a bounded wait between the workgroups of the
+                                    Rayleigh-Ritz SVD expired; outputs untouched */
 } wssr_status;
 
 /* Storage and multiply precision of O. */

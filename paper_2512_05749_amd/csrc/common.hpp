@@ -25,7 +25,7 @@ struct DevStatus {
   int pad;
 };
 
-enum : int { ST_OK = 0, ST_WARN_NOT_CONVERGED = 2, ST_NONFINITE = -5, ST_BREAKDOWN = -6 };
+enum : int { ST_OK = 0, ST_WARN_NOT_CONVERGED = 2, ST_NONFINITE = -5, ST_BREAKDOWN = -6, ST_TIMEOUT = -7 };
 
 __device__ __forceinline__ void raise_error(DevStatus* st, int code) {
   atomicCAS(&st->code, 0, code);

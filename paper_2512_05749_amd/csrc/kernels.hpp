@@ -4,6 +4,7 @@
 
 namespace wssr {
 
+__global__ void k_raise(DevStatus* st, int code);
 __global__ void k_status_init(DevStatus* st);
 __global__ void k_center_energies(const double* e_l, int64_t n, double* eps, DevStatus* st);
 __global__ void k_gradient_partial(const float* O, int64_t ld, int64_t n, int64_t m, const double* eps,
@@ -57,10 +58,9 @@ __global__ void k_kappa(const double* gdiag, const double* R, const double* Ri, 
 __global__ void k_smallgemm(const double* A, const double* B, int rp, double* C, const DevStatus* st, bool gated,
                             bool copy_b);
 __global__ void k_jacobi_prep(const double* Ct, int rp, int r, double* Bc, double* Pc, double* scal,
-                              DevStatus* st);
-__global__ void k_jacobi_round(double* Bc, double* Pc, int rp, int rd, double tol, const double* scal,
-                               double* cosbuf, DevStatus* st, int inner_sweeps);
-__global__ void k_jacobi_check(const double* cosbuf, int n, double tol, DevStatus* st);
+                              unsigned* sync, DevStatus* st);
+__global__ void k_jacobi_coop(double* Bc, double* Pc, int rp, double tol, const double* scal, double* cosbuf,
+                              unsigned* sync, DevStatus* st, int max_sweeps, int inner_sweeps);
 __global__ void k_jacobi_final(const double* Bc, const double* Pc, int rp, int r, double* sig, double* Ps,
                                DevStatus* st);
 
@@ -68,6 +68,7 @@ __global__ void k_transpose_pad(const double* C, int r, int rp, double* Ct);
 
 // dynamic LDS sizes (bytes)
 constexpr size_t kCholLds = 4 * 64 * 65 * sizeof(double);
-constexpr size_t kJacobiLds = 3 * 64 * 65 * sizeof(double);
+// dynamic LDS of k_jacobi_coop: the 32 columns of B, stride rp + 1
+inline size_t jacobi_lds(int rp) { return (size_t)32 * (rp + 1) * sizeof(double); }
 
 }  // namespace wssr

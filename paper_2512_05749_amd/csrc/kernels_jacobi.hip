@@ -1,0 +1,260 @@
+// Rayleigh-Ritz SVD of the small matrix C (r x r, FP64) by block one-sided
+// Jacobi, all sweeps in one cooperative launch.
+//
+// Columns of B = C P (P orthogonal, accumulated alongside) are rotated until
+// every pair is orthogonal: then sigma_j = ||b_j|| and P holds the right
+// singular vectors.  The rp columns (rp = r padded to 64; padding columns are
+// zero and never rotated) form nb = rp/16 blocks of 16.  One outer round
+// pairs the blocks by the round-robin tournament, nb/2 workgroups taking one
+// block pair (32 columns) each; nb - 1 rounds make a sweep, in which every
+// pair of columns meets once.  A workgroup
+//   1. stages its 32 columns of B in LDS,
+//   2. forms their 32 x 32 Gram matrix H on the FP64 MFMA (one 16 x 16 tile
+//      per wave),
+//   3. measures the largest column cosine of H (convergence test),
+//   4. if a cosine exceeds tol: diagonalises H by cyclic Jacobi (H and the
+//      accumulated rotation J in LDS; in each rotation round every thread
+//      owns one 2 x 2 block, computing the two rotations it needs from the
+//      diagonal blocks), orders the resulting columns by decreasing norm,
+//      and applies the ordered rotation to its columns of B (from LDS) and
+//      of P (read from L2) on the FP64 MFMA,
+//   5. meets the other workgroups at a grid barrier.
+// After the last round of a sweep every workgroup reads the sweep's largest
+// cosine and all stop together once it is <= tol (or after max_sweeps).
+//
+// The grid barrier is a counter in global memory (release add, acquire
+// spin).  Every wait is bounded: a workgroup that waits longer than the spin
+// limit sets the abort word, raises ST_TIMEOUT and leaves; waiting
+// workgroups see the abort word and leave too, so the grid always drains.
+// The launch is cooperative, which guarantees that all workgroups are
+// resident together.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace wssr {
+
+namespace {
+constexpr int JB = 16;            // columns per block
+constexpr int JC = 2 * JB;        // columns per block pair
+constexpr int JT = 256;           // threads per workgroup: one per 2 x 2 block of H
+constexpr int64_t kSpinLimit = int64_t(1) << 22;   // about 0.2 s of s_sleep(2)
+
+__device__ __forceinline__ double rsq_nr_j(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+}  // namespace
+
+// sync: [0] barrier counter, [1] abort word, [2] skip (the step had already
+// failed when the SVD started); zeroed / set by k_jacobi_prep.
+__global__ __launch_bounds__(JT) void k_jacobi_coop(double* __restrict__ Bc, double* __restrict__ Pc, int rp,
+                                                    double tol, const double* __restrict__ scal,
+                                                    double* __restrict__ cosbuf, unsigned* __restrict__ sync,
+                                                    DevStatus* st, int max_sweeps, int inner_sweeps) {
+  if (__hip_atomic_load((int*)&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  extern __shared__ double jsm[];
+  const int LX = rp + 1;                       // LDS column stride (odd: conflict-free column reads)
+  double* Xb = jsm;                            // [JC][LX] columns of B
+  __shared__ double H[JC][JC + 1], J[JC][JC + 1], Jp[JC][JC + 1];
+  __shared__ double wmax[4];
+  __shared__ int colidx[JC], rnk[JC];
+  __shared__ int proceed;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = rp / JB, nwg = nb / 2, wg = blockIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  const double floor = 4.93e-32 * scal[0];                 // (eps ||C||_F)^2
+  const double absfloor = 64.0 * 2.220446049250313e-16 * scal[0];
+  const int nld = JC * rp / 2;                              // double2 per column set
+  unsigned bars = 0;
+  double last_cos = 0.0;
+  int sweeps_done = 0, converged = 0;
+
+  // grid barrier; false when the grid is aborting
+  auto grid_barrier = [&]() -> bool {
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      ++bars;
+      const unsigned target = bars * (unsigned)nwg;
+      __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      int ok = 1;
+      for (int64_t spin = 0;; ++spin) {
+        if (__hip_atomic_load(&sync[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+        if (__hip_atomic_load((int*)&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        if (spin > kSpinLimit) {
+          __hip_atomic_store((int*)&sync[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          raise_error(st, ST_TIMEOUT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      proceed = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    return proceed != 0;
+  };
+
+  // rotation of the pair (p, q) of H that zeroes H[p][q]; false when the
+  // pair is already orthogonal (cosine <= tol or entries at rounding level)
+  auto rot = [&](int p, int q, double& c, double& s) -> bool {
+    const double a = H[p][p], d = H[q][q], b = H[p][q];
+    c = 1.0;
+    s = 0.0;
+    if (!(a > floor && d > floor && fabs(b) > absfloor && b * b > tol * tol * (a * d))) return false;
+    // angle from an FP32 estimate of t; c and s in FP64 with c^2 + s^2 = 1
+    // to rounding (a rough angle only slows the iteration; what it leaves is
+    // measured and removed later)
+    const float dm = (float)(d - a), bf = (float)b;
+    const float hy = sqrtf(dm * dm + 4.0f * bf * bf);
+    const float sg = ((dm >= 0.0f) == (bf >= 0.0f)) ? 2.0f : -2.0f;
+    const double t = (double)(sg * fabsf(bf) / (fabsf(dm) + hy));
+    c = rsq_nr_j(1.0 + t * t);
+    s = c * t;
+    return true;
+  };
+
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    double sweep_cos = 0.0;
+    for (int rd = 0; rd < nb - 1; ++rd) {
+      int bI, bJ;
+      rr_pair(nb, rd, wg, bI, bJ);
+      if (tid < JC) colidx[tid] = (tid < JB) ? bI * JB + tid : bJ * JB + (tid - JB);
+      __syncthreads();
+      for (int e = tid; e < nld; e += JT) {
+        const int c = e / (rp / 2), k2 = e % (rp / 2);
+        const double2 v = *reinterpret_cast<const double2*>(Bc + (int64_t)colidx[c] * rp + 2 * k2);
+        Xb[c * LX + 2 * k2] = v.x;
+        Xb[c * LX + 2 * k2 + 1] = v.y;
+      }
+      __syncthreads();
+      // H = X^T X: wave wv forms the 16 x 16 tile (wv / 2, wv % 2)
+      {
+        const int ti = (wv >> 1) * 16, tj = (wv & 1) * 16;
+        f64x4 acc = f64x4{0};
+        for (int k = 0; k < rp; k += 4) {
+          const double a = Xb[(ti + li) * LX + k + lk];
+          const double b = Xb[(tj + li) * LX + k + lk];
+          acc = mfma16x16x4d(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          H[ti + 4 * v + lk][tj + li] = acc[v];
+          J[ti + 4 * v + lk][tj + li] = (ti + 4 * v + lk == tj + li) ? 1.0 : 0.0;
+        }
+      }
+      __syncthreads();
+      // largest cosine of the pair's columns
+      double cmax = 0.0;
+      for (int e = tid; e < JC * JC; e += JT) {
+        const int p = e >> 5, q = e & 31;
+        if (p < q) {
+          const double a = H[p][p], d = H[q][q], b = H[p][q];
+          if (a > floor && d > floor && fabs(b) > absfloor) cmax = fmax(cmax, fabs(b) * rsq_nr_j(a * d));
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+      if (lane == 0) wmax[wv] = cmax;
+      __syncthreads();
+      cmax = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+      sweep_cos = fmax(sweep_cos, cmax);
+      if (cmax > tol) {
+        // cyclic Jacobi on H: thread (ra, rb) owns the 2 x 2 blocks of H and
+        // of J at row pair ra and column pair rb of the rotation round
+        const int ra = tid >> 4, rb = tid & 15;
+        for (int isw = 0; isw < inner_sweeps; ++isw) {
+          int myrot = 0;
+          for (int ird = 0; ird < JC - 1; ++ird) {
+            int pa, qa, pb, qb;
+            rr_pair(JC, ird, ra, pa, qa);
+            rr_pair(JC, ird, rb, pb, qb);
+            double ca, sa, cb, sb;
+            myrot |= (int)rot(pa, qa, ca, sa);
+            rot(pb, qb, cb, sb);
+            const double x11 = H[pa][pb], x12 = H[pa][qb], x21 = H[qa][pb], x22 = H[qa][qb];
+            const double j11 = J[pa][pb], j12 = J[pa][qb], j21 = J[qa][pb], j22 = J[qa][qb];
+            __syncthreads();
+            if (sa != 0.0 || sb != 0.0) {
+              // H <- R_a^T H R_b on the block; J <- J R_b on the block
+              const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
+              const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
+              double z11 = cb * y11 - sb * y12, z12 = sb * y11 + cb * y12;
+              double z21 = cb * y21 - sb * y22, z22 = sb * y21 + cb * y22;
+              if (ra == rb && sa != 0.0) z12 = z21 = 0.0;
+              H[pa][pb] = z11;
+              H[pa][qb] = z12;
+              H[qa][pb] = z21;
+              H[qa][qb] = z22;
+              if (sb != 0.0) {
+                J[pa][pb] = cb * j11 - sb * j12;
+                J[pa][qb] = sb * j11 + cb * j12;
+                J[qa][pb] = cb * j21 - sb * j22;
+                J[qa][qb] = sb * j21 + cb * j22;
+              }
+            }
+            __syncthreads();
+          }
+          if (!__syncthreads_or(myrot)) break;
+        }
+        // order the rotated columns by decreasing norm: larger ones go to
+        // the first block of the pair
+        if (tid < JC) {
+          const double ev = H[tid][tid];
+          int k = 0;
+          for (int c = 0; c < JC; ++c) {
+            const double e2 = H[c][c];
+            k += (e2 > ev) || (e2 == ev && c < tid);
+          }
+          rnk[tid] = k;
+        }
+        __syncthreads();
+        for (int e = tid; e < JC * JC; e += JT) Jp[e >> 5][rnk[e & 31]] = J[e >> 5][e & 31];
+        __syncthreads();
+        // B <- B Jp (B from LDS) and P <- P Jp (P from L2) in blocks of 16
+        // rows; one wave computes both 16-column halves of a row block before
+        // writing it, so P is read before it is overwritten
+        const int nrb = rp / 16;
+        for (int u = wv; u < 2 * nrb; u += 4) {
+          const int mtx = u / nrb, i0 = (u % nrb) * 16;
+          f64x4 acc0 = f64x4{0}, acc1 = f64x4{0};
+#pragma unroll
+          for (int k4 = 0; k4 < JC / 4; ++k4) {
+            const int k = k4 * 4 + lk;
+            const double a = mtx ? Pc[(int64_t)colidx[k] * rp + i0 + li] : Xb[k * LX + i0 + li];
+            acc0 = mfma16x16x4d(a, Jp[k][li], acc0);
+            acc1 = mfma16x16x4d(a, Jp[k][16 + li], acc1);
+          }
+          double* M = mtx ? Pc : Bc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            M[(int64_t)colidx[li] * rp + i0 + 4 * v + lk] = acc0[v];
+            M[(int64_t)colidx[16 + li] * rp + i0 + 4 * v + lk] = acc1[v];
+          }
+        }
+      }
+      // the sweep's largest cosine is published before its last barrier
+      if (rd == nb - 2 && tid == 0) cosbuf[wg] = sweep_cos;
+      if (!grid_barrier()) return;
+    }
+    double c = 0.0;
+    for (int w = 0; w < nwg; ++w) c = fmax(c, cosbuf[w]);
+    last_cos = c;
+    ++sweeps_done;
+    converged = !(c > tol);
+  }
+  if (wg == 0 && tid == 0) {
+    st->jacobi_sweeps = sweeps_done;
+    st->jacobi_cosine = last_cos;
+    st->jacobi_done = converged;
+  }
+}
+
+}  // namespace wssr

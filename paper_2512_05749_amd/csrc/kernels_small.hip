@@ -390,23 +390,27 @@ template __global__ void k_trinv<4>(const double*, int, double*, const DevStatus
 template __global__ void k_trinv<8>(const double*, int, double*, const DevStatus*, bool);
 
 // ---------------------------------------------------------------------------
-// Rayleigh-Ritz SVD of C (r x r) by block one-sided Jacobi.
+// Rayleigh-Ritz SVD of C (r x r) by block one-sided Jacobi (the sweeps are
+// k_jacobi_coop in kernels_jacobi.hip).
 //   prep: Bc (column-major C, i.e. column j contiguous) <- C with zero padding,
-//         Pc <- I, scal[0] <- ||C||_F^2.  C is given as its transpose Ct
-//         (rp x rp row-major, so row j of Ct is column j of C).
-//   round: nb/2 workgroups; workgroup t takes the block pair of round `rd` of
-//         the round-robin over nb = rp/32 column blocks, forms the 64 x 64
-//         Gram of those columns, diagonalises it by cyclic Jacobi in LDS and
-//         rotates the 64 columns of Bc and Pc by the result.
-//   check: after every sweep; marks convergence when no pair rotated.  A pair
-//         counts as orthogonal when its cosine is <= tol or its Gram entry is
-//         <= 64 eps ||C||_F^2.
+//         Pc <- I, scal[0] <- ||C||_F^2, and the grid-barrier words of the
+//         sweep kernel.  C is given as its transpose Ct (rp x rp row-major, so
+//         row j of Ct is column j of C).
+//   A column pair counts as orthogonal when its cosine is <= tol or its Gram
+//   entry is <= 64 eps ||C||_F^2.
 //   final: sigma_j = ||c_j||, sorted descending (stable), P permuted to match.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTH) void k_jacobi_prep(const double* __restrict__ Ct, int rp, int r,
                                                      double* __restrict__ Bc, double* __restrict__ Pc,
-                                                     double* __restrict__ scal, DevStatus* st) {
-  if (failed(st)) return;
+                                                     double* __restrict__ scal, unsigned* __restrict__ sync,
+                                                     DevStatus* st) {
+  const bool skip = failed(st);
+  if (threadIdx.x == 0) {
+    sync[0] = 0u;
+    sync[1] = 0u;
+    sync[2] = skip ? 1u : 0u;
+  }
+  if (skip) return;
   __shared__ double red[NTH];
   double s = 0.0;
   for (int64_t e = threadIdx.x; e < (int64_t)rp * rp; e += NTH) {
@@ -427,208 +431,6 @@ __global__ __launch_bounds__(NTH) void k_jacobi_prep(const double* __restrict__ 
     st->jacobi_done = 0;
     st->jacobi_sweeps = 0;
     st->jacobi_cosine = 0;
-  }
-}
-
-__global__ __launch_bounds__(NTH) void k_jacobi_round(double* __restrict__ Bc, double* __restrict__ Pc, int rp,
-                                                      int rd, double tol, const double* __restrict__ scal,
-                                                      double* __restrict__ cosbuf, DevStatus* st, int inner_sweeps) {
-  if (failed(st) || *reinterpret_cast<volatile int*>(&st->jacobi_done)) return;
-  extern __shared__ double smem[];
-  double(*Hs)[TP] = reinterpret_cast<double(*)[TP]>(smem);
-  double(*Js)[TP] = reinterpret_cast<double(*)[TP]>(smem + TS * TP);
-  double(*Xs)[TP] = reinterpret_cast<double(*)[TP]>(smem + 2 * TS * TP);
-  __shared__ int colidx[TS];
-  __shared__ double cs[32], sn[32];
-  __shared__ int rotated;
-  __shared__ double red[NTH / 64];
-  const int tid = threadIdx.x;
-  const int nb = rp / 32;
-  int bI, bJ;
-  rr_pair(nb, rd, blockIdx.x, bI, bJ);
-  if (tid < TS) colidx[tid] = (tid < 32) ? bI * 32 + tid : bJ * 32 + (tid - 32);
-  const double floor = 4.93e-32 * scal[0];  // (eps * ||C||_F)^2
-  // off-diagonal Gram entries below 64 eps ||C||_F^2 are at the rounding level
-  // of the Gram itself and are not rotated (absolute part of the criterion)
-  const double absfloor = 64.0 * 2.220446049250313e-16 * scal[0];
-  __syncthreads();
-
-  // H = X^T X over the rows of the 64 selected columns; the next 64-row
-  // chunk is fetched into registers while the current one is multiplied
-  f64x4 acc = f64x4{0};
-  const int nchunk = rp / TS;
-  double pre[4];
-  auto fetch = [&](const double* M, int k0) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + NTH * u;
-      pre[u] = M[(int64_t)colidx[e >> 6] * rp + k0 + (e & 63)];
-    }
-  };
-  auto put = [&]() {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + NTH * u;
-      Xs[e & 63][e >> 6] = pre[u];
-    }
-  };
-  fetch(Bc, 0);
-  for (int ch = 0; ch < nchunk; ++ch) {
-    put();
-    __syncthreads();
-    if (ch + 1 < nchunk) fetch(Bc, (ch + 1) * TS);
-    acc = tile_mma<true>(acc, Xs, Xs);
-    __syncthreads();
-  }
-  acc_to_tile(Hs, acc, 1.0);
-  for (int e = tid; e < TS * TS; e += NTH) Js[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
-  __syncthreads();
-
-  // largest cosine between any two of the 64 columns (both blocks and across)
-  double cmax = 0.0;
-  for (int e = tid; e < TS * TS; e += NTH) {
-    const int p = e >> 6, q = e & 63;
-    if (p < q) {
-      const double a = Hs[p][p], d = Hs[q][q];
-      if (a > floor && d > floor && fabs(Hs[p][q]) > absfloor) cmax = fmax(cmax, fabs(Hs[p][q]) / sqrt(a * d));
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
-  if ((tid & 63) == 0) red[tid >> 6] = cmax;
-  __syncthreads();
-  if (tid == 0) {
-    double c = 0.0;
-    for (int i = 0; i < NTH / 64; ++i) c = fmax(c, red[i]);
-    cosbuf[blockIdx.x] = c;
-    red[0] = c;
-  }
-  __syncthreads();
-  if (!(red[0] > tol)) return;
-
-  // cyclic Jacobi on the 64 x 64 Gram, accumulating the rotation in Js.  Per
-  // round: the 32 rotation parameters (one thread each), then every thread
-  // transforms one 2 x 2 block (row pair a, column pair b) of H and two
-  // entries of J.  Pair indices come from the round-robin formula in
-  // registers, so each phase needs a single round of LDS reads.
-  {
-    const int ra = tid >> 5, rb = tid & 31;          // 2 x 2 block of H owned by this thread
-    const int jrow = tid & 63, jk0 = tid >> 6;        // J entries: row jrow, pairs jk0 and jk0 + 16
-    for (int sweep = 0; sweep < inner_sweeps; ++sweep) {
-      if (tid == 0) rotated = 0;
-      __syncthreads();
-      for (int ird = 0; ird < TS - 1; ++ird) {
-        if (tid < 32) {
-          int p, q;
-          rr_pair(TS, ird, tid, p, q);
-          const double a = Hs[p][p], d = Hs[q][q], b = Hs[p][q];
-          double c = 1.0, s = 0.0;
-          if (a > floor && d > floor && fabs(b) > absfloor && b * b > tol * tol * (a * d)) {
-            // angle from an FP32 estimate of t; c and s in FP64 with
-            // c^2 + s^2 = 1 to FP64 rounding (the angle only needs to be
-            // close: whatever is left is measured and removed later)
-            const float dm = (float)(d - a), bf = (float)b;
-            const float hy = sqrtf(dm * dm + 4.0f * bf * bf);
-            const float sg = ((dm >= 0.0f) == (bf >= 0.0f)) ? 2.0f : -2.0f;
-            const double t = (double)(sg * fabsf(bf) / (fabsf(dm) + hy));
-            c = rsq_nr(1.0 + t * t);
-            s = c * t;
-            rotated = 1;
-          }
-          cs[tid] = c;
-          sn[tid] = s;
-        }
-        __syncthreads();
-        {
-          int pa, qa, pb, qb;
-          rr_pair(TS, ird, ra, pa, qa);
-          rr_pair(TS, ird, rb, pb, qb);
-          const double sa = sn[ra], sb = sn[rb], ca = cs[ra], cb = cs[rb];
-          if (sa != 0.0 || sb != 0.0) {
-            const double x11 = Hs[pa][pb], x12 = Hs[pa][qb], x21 = Hs[qa][pb], x22 = Hs[qa][qb];
-            const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
-            const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
-            double z11 = cb * y11 - sb * y12, z12 = sb * y11 + cb * y12;
-            double z21 = cb * y21 - sb * y22, z22 = sb * y21 + cb * y22;
-            if (ra == rb && sa != 0.0) z12 = z21 = 0.0;
-            Hs[pa][pb] = z11;
-            Hs[pa][qb] = z12;
-            Hs[qa][pb] = z21;
-            Hs[qa][qb] = z22;
-          }
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int k = jk0 + 16 * u;
-            int pk, qk;
-            rr_pair(TS, ird, k, pk, qk);
-            const double sk = sn[k], ck = cs[k];
-            if (sk != 0.0) {
-              const double xp = Js[jrow][pk], xq = Js[jrow][qk];
-              Js[jrow][pk] = ck * xp - sk * xq;
-              Js[jrow][qk] = sk * xp + ck * xq;
-            }
-          }
-        }
-        __syncthreads();
-      }
-      const int any = rotated;
-      __syncthreads();
-      if (!any) break;
-    }
-  }
-
-  // order the 64 rotated columns by decreasing norm (eigenvalue of the Gram):
-  // larger columns move to block I, smaller to block J, which speeds up the
-  // block iteration; the permuted rotation goes to Hs.
-  __shared__ int rnk[TS];
-  if (tid < TS) {
-    const double ev = Hs[tid][tid];
-    int k = 0;
-    for (int c = 0; c < TS; ++c) {
-      const double e2 = Hs[c][c];
-      k += (e2 > ev) || (e2 == ev && c < tid);
-    }
-    rnk[tid] = k;
-  }
-  __syncthreads();
-  for (int e = tid; e < TS * TS; e += NTH) {
-    const int row = e >> 6, c = e & 63;
-    Hs[row][rnk[c]] = Js[row][c];
-  }
-  __syncthreads();
-
-  // rotate the 64 columns of Bc and of Pc: X <- X J, 64 rows at a time, with
-  // the next chunk in flight during the current product
-  {
-    const int lane = tid & 63, w = tid >> 6;
-    const int bi = w >> 2, bj = w & 3, li = lane & 15, lk = lane >> 4;
-    fetch(Bc, 0);
-    for (int step = 0; step < 2 * nchunk; ++step) {
-      double* M = step < nchunk ? Bc : Pc;
-      const int k0 = (step % nchunk) * TS;
-      put();
-      __syncthreads();
-      if (step + 1 < 2 * nchunk) fetch(step + 1 < nchunk ? Bc : Pc, ((step + 1) % nchunk) * TS);
-      const f64x4 y = tile_mma<false>(f64x4{0}, Xs, Hs);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = bi * 16 + 4 * v + lk, c = bj * 16 + li;
-        M[(int64_t)colidx[c] * rp + k0 + k] = y[v];
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// After a sweep: converged when the largest cosine seen in the sweep is <= tol.
-__global__ void k_jacobi_check(const double* __restrict__ cosbuf, int n, double tol, DevStatus* st) {
-  if (failed(st) || st->jacobi_done) return;
-  if (threadIdx.x == 0) {
-    double c = 0.0;
-    for (int i = 0; i < n; ++i) c = fmax(c, cosbuf[i]);
-    st->jacobi_sweeps += 1.0;
-    st->jacobi_cosine = c;
-    if (!(c > tol)) st->jacobi_done = 1;
   }
 }
 

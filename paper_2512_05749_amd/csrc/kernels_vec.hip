@@ -10,6 +10,9 @@ namespace wssr {
 // ---------------------------------------------------------------------------
 // eps = E_L - mean(E_L)   (eq. Lbarn); one workgroup of 1024 threads.
 // ---------------------------------------------------------------------------
+// Fail the running step from the host side (a launch that could not be made).
+__global__ void k_raise(DevStatus* st, int code) { raise_error(st, code); }
+
 __global__ __launch_bounds__(1024) void k_center_energies(const double* __restrict__ e_l, int64_t n,
                                                           double* __restrict__ eps, DevStatus* st) {
   __shared__ double red[1024];

@@ -21,8 +21,8 @@ constexpr int kS1Max = 16;      // split-K ranges of the sample-side product
 constexpr int kGSplitMax = 16;  // row splits of the gradient
 constexpr int kGramChunkMax = 64;
 constexpr int kVecChunkMax = 1024;
-constexpr int kJacobiSweeps = 12;
-constexpr int kJacobiInner = 2;     // inner sweeps per block step
+constexpr int kJacobiSweeps = 30;
+constexpr int kJacobiInner = 1;     // inner sweeps per block step
 constexpr double kJacobiTol = 1e-8;
 constexpr double kKappaRound2 = 1e4;
 
@@ -39,6 +39,8 @@ struct wssr_ctx {
   int rp_max = 0;
   int64_t rows_max = 0;
   int slots = 512;               // resident product workgroups: 2 per compute unit
+  unsigned* jsync = nullptr;     // grid-barrier words of the Rayleigh-Ritz sweep kernel
+  hipError_t coop_err = hipSuccess;
   hipStream_t side = nullptr;    // second stream: the gradient pass runs beside the Rayleigh-Ritz SVD
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float* skpart = nullptr;       // stream-K partial tiles of the parameter-side product
@@ -273,18 +275,29 @@ struct wssr_ctx {
   // SVD of the r x r matrix whose transpose is Ct (rp x rp row-major): sorted
   // singular values into sig[0..rp), right singular vectors into Ps (rp x rp).
   void small_svd(const double* Ct, int r) {
-    const int rp = (int)rup(r, 64), nb = rp / 32;
-    hipLaunchKernelGGL(k_jacobi_prep, dim3(1), dim3(1024), 0, stream, Ct, rp, r, Bc, Pc, scal, st);
-    for (int sw = 0; sw < kJacobiSweeps; ++sw) {
-      for (int rd = 0; rd < nb - 1; ++rd)
-        hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2), dim3(1024), kJacobiLds, stream, Bc, Pc, rp, rd, kJacobiTol,
-                           (const double*)scal, cosbuf + (int64_t)rd * (nb / 2), st, kJacobiInner);
-      hipLaunchKernelGGL(k_jacobi_check, dim3(1), dim3(64), 0, stream, (const double*)cosbuf, (nb - 1) * (nb / 2),
-                         kJacobiTol, st);
+    int rp = (int)rup(r, 64);
+    hipLaunchKernelGGL(k_jacobi_prep, dim3(1), dim3(1024), 0, stream, Ct, rp, r, Bc, Pc, scal, jsync, st);
+    // all sweeps in one cooperative launch: rp/32 workgroups, one per block
+    // pair of 32 columns, meeting at grid barriers between rounds
+    double tol = kJacobiTol;
+    const double* scal_c = scal;
+    double* cosb = cosbuf;
+    unsigned* sy = jsync;
+    DevStatus* stp = st;
+    int sweeps = kJacobiSweeps, inner = kJacobiInner;
+    void* args[] = {&Bc, &Pc, &rp, &tol, &scal_c, &cosb, &sy, &stp, &sweeps, &inner};
+    coop_err = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(rp / 32), dim3(256), args,
+                                          (unsigned)jacobi_lds(rp), stream);
+    if (coop_err != hipSuccess) {
+      // nothing was rotated: fail the step on the device so that no later
+      // kernel writes an output
+      (void)hipGetLastError();
+      hipLaunchKernelGGL(k_raise, dim3(1), dim3(1), 0, stream, st, (int)WSSR_ERR_HIP);
     }
     hipLaunchKernelGGL(k_jacobi_final, dim3(1), dim3(1024), 0, stream, (const double*)Bc, (const double*)Pc, rp, r, sig,
                        Ps, st);
   }
+
 };
 
 namespace {
@@ -360,7 +373,8 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
             h->alloc(h->cw, rp) && h->alloc(h->vpart, (size_t)kVecChunkMax * r) &&
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
             h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
-            h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp);
+            h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp) &&
+            h->alloc(h->jsync, 4);
   // stream-K partials (two 128 x 256 tiles per workgroup of one round), only
   // when a parameter-side product can have more tiles than one round holds
   const int64_t ptiles = cdiv(m, 128) * cdiv(r, r > 128 ? 256 : 128);
@@ -374,8 +388,8 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
   }
   if (hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholLds) !=
           hipSuccess ||
-      hipFuncSetAttribute((const void*)k_jacobi_round, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJacobiLds) !=
-          hipSuccess) {
+      hipFuncSetAttribute((const void*)k_jacobi_coop, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)jacobi_lds(rp)) != hipSuccess) {
     h->release();
     delete h;
     g_create_error = "hipFuncSetAttribute failed";
@@ -466,6 +480,8 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
     }
   }
   (void)hipStreamWaitEvent(stream, h->ev_join, 0);
+  if (h->coop_err != hipSuccess)
+    return h->fail(WSSR_ERR_HIP, "cooperative launch of the SVD kernel failed: %s", hipGetErrorString(h->coop_err));
   // output signs, then V <- signed vw
   {
     // row chunks: as many as the partial buffers hold (enough blocks to cover
@@ -597,6 +613,8 @@ wssr_status wssr_dbg_small_svd(wssr_handle h, const double* C, int32_t r, double
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
   hipLaunchKernelGGL(k_transpose_pad, dim3(cdiv((int64_t)rp * rp, 256)), dim3(256), 0, h->stream, C, r, rp, h->Rz);
   h->small_svd(h->Rz, r);
+  if (h->coop_err != hipSuccess)
+    return h->fail(WSSR_ERR_HIP, "cooperative launch of the SVD kernel failed: %s", hipGetErrorString(h->coop_err));
   (void)hipMemcpyAsync(s, h->sig, sizeof(double) * r, hipMemcpyDeviceToDevice, h->stream);
   (void)hipMemcpy2DAsync(P, sizeof(double) * r, h->Ps, sizeof(double) * rp, sizeof(double) * r, r,
                          hipMemcpyDeviceToDevice, h->stream);

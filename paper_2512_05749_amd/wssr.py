@@ -23,8 +23,9 @@ ERR_OOM = -3
 ERR_HIP = -4
 ERR_NONFINITE = -5
 ERR_BREAKDOWN = -6
+ERR_TIMEOUT = -7
 STATUS_NAMES = {0: "OK", 2: "WARN_NOT_CONVERGED", -1: "ERR_INVALID_ARG", -2: "ERR_NO_DEVICE", -3: "ERR_OOM",
-                -4: "ERR_HIP", -5: "ERR_NONFINITE", -6: "ERR_BREAKDOWN"}
+                -4: "ERR_HIP", -5: "ERR_NONFINITE", -6: "ERR_BREAKDOWN", -7: "ERR_TIMEOUT"}
 
 F32 = 0
 FLOOR_PRECOND = 0x1
