@@ -64,9 +64,24 @@ typedef enum {
                                     Rayleigh-Ritz SVD expired; outputs untouched */
 } wssr_status;
 
-/* Storage and multiply precision of O. */
+/* Storage and multiply precision of O.  The Gram matrices, Cholesky factors,
+ * the r x r SVD, the gradient sums and the Woodbury core are FP64 in every
+ * form; V is FP32.  In the BF16 forms the products run on the BF16 MFMA with
+ * FP32 accumulation and the skinny operand (V or the sample-side basis, FP32)
+ * is rounded to BF16 on the fly: S_hi = RNE(S), S_lo = RNE(S - S_hi).
+ *   WSSR_F32         O float; FP32 products.
+ *   WSSR_BF16        O BF16; one product O S_hi.
+ *   WSSR_BF16_SPLIT  O BF16; two products O S_hi + O S_lo (the skinny operand
+ *                    kept to about 16 bits).
+ *   WSSR_BF16X2      O given as two BF16 planes, O_hi = RNE(O) at O and
+ *                    O_lo = RNE(O - O_hi) at O + n * ld_o elements; three
+ *                    products O_hi S_hi + O_hi S_lo + O_lo S_hi.  The gradient
+ *                    uses O_hi + O_lo. */
 typedef enum {
-  WSSR_F32 = 0
+  WSSR_F32 = 0,
+  WSSR_BF16 = 1,
+  WSSR_BF16X2 = 2,
+  WSSR_BF16_SPLIT = 3
 } wssr_dtype;
 
 /* Flags (wssr_config.flags). */
@@ -94,7 +109,8 @@ wssr_status wssr_destroy(wssr_handle h);
 
 /* One WSSR step (see the top of this file).
  *   n, m     sample and parameter counts, 2 <= n <= n_max, 1 <= m <= m_max
- *   O        device, n x m, row stride ld_o >= m elements (dtype as configured)
+ *   O        device, n x m, row stride ld_o >= m elements, in the configured dtype
+ *            (WSSR_BF16X2: the lo plane follows at O + n * ld_o elements)
  *   e_l      device, double[n]
  *   V        device, float[m x r] row-major (row stride r): in: warm start whose
  *            column span seeds the iteration (orthonormality not required);

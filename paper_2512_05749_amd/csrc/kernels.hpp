@@ -41,6 +41,23 @@ template <int BN>
 __global__ void k_streamk_fixup(const float* part, float* Z, int64_t m, int r, float scale, int tiles_j,
                                 int full_tiles, int64_t nk, int64_t sk_units, int sk_wgs, const DevStatus* st);
 
+__global__ void k_gradient16_partial(const unsigned short* O, int64_t ld, int64_t pstride, int planes, int64_t n,
+                                     int64_t m, const double* eps, int64_t rows_per_split, double* part, bool vec,
+                                     const DevStatus* st);
+
+// BF16 products (kernels_gemm16.hip): BN output columns per tile, BK K-step,
+// PA planes of O, PB planes of the FP32 skinny operand.
+template <int BN, int BK, int PA, int PB>
+__global__ void k_gemm16_sample_side(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
+                                     const float* V, int r, float* ypart, int64_t kchunk, bool vec_o, bool vec_v,
+                                     const DevStatus* st, int tn, int tj, bool xcd_groups);
+template <int BN, int BK, int PA, int PB>
+__global__ void k_gemm16_param_side(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
+                                    const float* Q, int r, float scale, float* Z, bool vec_o, bool vec_q,
+                                    const DevStatus* st, int tiles_j, int full_tiles, int64_t sk_units, int sk_wgs,
+                                    float* part);
+size_t gemm16_lds(int bn, int bk, int pa, int pb);
+
 template <typename T>
 __global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,
                                const DevStatus* st, bool gated);

@@ -376,5 +376,7 @@ template __global__ void k_streamk_fixup<128>(const float*, float*, int64_t, int
                                               int, const DevStatus*);
 template __global__ void k_streamk_fixup<256>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
                                               int, const DevStatus*);
+template __global__ void k_streamk_fixup<512>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
+                                              int, const DevStatus*);
 
 }  // namespace wssr

@@ -72,6 +72,43 @@ __global__ __launch_bounds__(256) void k_gradient_partial(const float* __restric
   if (c0 + 3 < m) p[c0 + 3] = a3;
 }
 
+// The same partial sums with O in BF16 (planes = 1) or as BF16 hi and lo
+// planes (planes = 2, O = hi + lo, plane stride pstride elements).
+__global__ __launch_bounds__(256) void k_gradient16_partial(const unsigned short* __restrict__ O, int64_t ld,
+                                                            int64_t pstride, int planes, int64_t n, int64_t m,
+                                                            const double* __restrict__ eps, int64_t rows_per_split,
+                                                            double* __restrict__ part, bool vec, const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (c0 >= m) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = min(n, r0 + rows_per_split);
+  auto val = [](unsigned short b) { return (double)(float)__builtin_bit_cast(__bf16, b); };
+  double a[4] = {0, 0, 0, 0};
+#pragma unroll 4
+  for (int64_t i = r0; i < r1; ++i) {
+    const double e = eps[i];
+    for (int p = 0; p < planes; ++p) {
+      const unsigned short* row = O + p * pstride + i * ld + c0;
+      if (vec && c0 + 3 < m) {
+        const uint2 w = *reinterpret_cast<const uint2*>(row);
+        a[0] += val((unsigned short)(w.x & 0xffffu)) * e;
+        a[1] += val((unsigned short)(w.x >> 16)) * e;
+        a[2] += val((unsigned short)(w.y & 0xffffu)) * e;
+        a[3] += val((unsigned short)(w.y >> 16)) * e;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (c0 + q < m) a[q] += val(row[q]) * e;
+      }
+    }
+  }
+  double* pp = part + (int64_t)blockIdx.y * m;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (c0 + q < m) pp[c0 + q] = a[q];
+}
+
 __global__ __launch_bounds__(256) void k_gradient_reduce(const double* __restrict__ part, int nsplit, int64_t m,
                                                          double inv_n, double* __restrict__ g,
                                                          const DevStatus* st) {

@@ -44,6 +44,7 @@ struct wssr_ctx {
   hipStream_t side = nullptr;    // second stream: the gradient pass runs beside the Rayleigh-Ritz SVD
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float* skpart = nullptr;       // stream-K partial tiles of the parameter-side product
+  int64_t skpart_elems = 0;
   std::vector<void*> allocs;
 
   DevStatus* st = nullptr;
@@ -124,25 +125,41 @@ struct wssr_ctx {
   // ---------------------------------------------------------------- kernels
   hipError_t last() { return hipGetLastError(); }
 
-  void gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* V, int r) {
-    const int bn = r > 128 ? 256 : 128;
-    const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
-    // about two workgroups per CU in one round; split K = M into s1 ranges
-    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(slots, tn * tj)));
-    int64_t kchunk = rup(cdiv(m, s1), 16);
-    s1 = (int)cdiv(m, kchunk);
-    const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
-    const bool vec_v = (r % 4 == 0) && ((uintptr_t)V % 16 == 0);
-    const bool xcd = ((int64_t)s1 * tj) % 8 == 0;
-    const dim3 grid((unsigned)(tn * tj * s1));
-    timed(0, [&] {
-      if (bn == 256)
-        hipLaunchKernelGGL(k_gemm_sample_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
-                           vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
-      else
-        hipLaunchKernelGGL(k_gemm_sample_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
-                           vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
-    });
+  // dynamic-LDS limits and occupancy (resident workgroups on the whole
+  // device) of the BF16 product variants
+  bool setup16() {
+    bool ok = true;
+    int cus = std::max(1, slots / 2);
+    auto one = [&](const void* fn, int bn, int bk, int pa, int pb, int& out) {
+      const int lds = (int)gemm16_lds(bn, bk, pa, pb);
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) ok = false;
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, (size_t)lds) != hipSuccess || per < 1) per = 1;
+      out = per * cus;
+    };
+#define WSSR_SETUP16(BN, BK, PA, PB)                                                                                 \
+  one((const void*)k_gemm16_sample_side<BN, BK, PA, PB>, BN, BK, PA, PB, slots16s[v16(BN, PA, PB)]);                 \
+  one((const void*)k_gemm16_param_side<BN, BK, PA, PB>, BN, BK, PA, PB, slots16p[v16(BN, PA, PB)]);
+    WSSR_SETUP16(128, 32, 1, 1) WSSR_SETUP16(128, 32, 1, 2) WSSR_SETUP16(128, 32, 2, 2)
+    WSSR_SETUP16(256, 32, 1, 1) WSSR_SETUP16(256, 32, 1, 2) WSSR_SETUP16(256, 32, 2, 2)
+    WSSR_SETUP16(512, 16, 1, 1) WSSR_SETUP16(512, 16, 1, 2) WSSR_SETUP16(512, 16, 2, 2)
+#undef WSSR_SETUP16
+    (void)hipGetLastError();
+    return ok;
+  }
+
+  // ---- storage precision of O
+  bool bf16() const { return cfg.o_dtype != WSSR_F32; }
+  int o_planes() const { return cfg.o_dtype == WSSR_BF16X2 ? 2 : 1; }
+  int s_planes() const { return cfg.o_dtype == WSSR_BF16 ? 1 : 2; }
+  static int bn_for(int r, bool b16) { return r <= 128 ? 128 : (r <= 256 || !b16 ? 256 : 512); }
+  // index of a BF16 product variant: (BN, PA, PB) with BN in {128, 256, 512}
+  static int v16(int bn, int pa, int pb) { return (bn == 128 ? 0 : bn == 256 ? 1 : 2) * 3 + (pa == 2 ? 2 : pb - 1); }
+  int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
+
+  // Y = A V (FP64) from the split-K partials: fixed-order sum, then centre
+  // the columns and scale (the implicit centring of O)
+  void y_finish(int64_t n, int r, int s1) {
     const int64_t tot = n * r;
     hipLaunchKernelGGL(k_ysum, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)ypart, s1, tot, y64,
                        (const DevStatus*)st);
@@ -155,48 +172,127 @@ struct wssr_ctx {
                        1.0 / std::sqrt((double)n), (const DevStatus*)st);
   }
 
-  void gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r, float* Z) {
-    const int bn = r > 128 ? 256 : 128;
-    const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+  void gemm_sample_side(const void* Ov, int64_t ld, int64_t n, int64_t m, const float* V, int r) {
+    const bool b16 = bf16();
+    const int bn = bn_for(r, b16), bk = b16 ? (bn == 512 ? 16 : 32) : 16;
+    const int pa = o_planes(), pb = s_planes();
+    const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
+    const int sl = b16 ? slots16s[v16(bn, pa, pb)] : slots;
+    // about one round of resident workgroups; split K = M into s1 ranges
+    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(sl, tn * tj)));
+    int64_t kchunk = rup(cdiv(m, s1), bk);
+    s1 = (int)cdiv(m, kchunk);
+    const bool vec_v = (r % 4 == 0) && ((uintptr_t)V % 16 == 0);
+    const bool xcd = ((int64_t)s1 * tj) % 8 == 0;
+    const dim3 grid((unsigned)(tn * tj * s1));
+    if (!b16) {
+      const float* O = static_cast<const float*>(Ov);
+      const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+      timed(0, [&] {
+        if (bn == 256)
+          hipLaunchKernelGGL(k_gemm_sample_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
+                             vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
+        else
+          hipLaunchKernelGGL(k_gemm_sample_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
+                             vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
+      });
+    } else {
+      const auto* O = static_cast<const unsigned short*>(Ov);
+      const int64_t ps = n * ld;
+      const bool vec_o = (ld % 8 == 0) && ((uintptr_t)O % 16 == 0);
+      const unsigned lds = (unsigned)gemm16_lds(bn, bk, pa, pb);
+      timed(0, [&] {
+#define WSSR_S16(BN, BK, PA, PB)                                                                                     \
+  hipLaunchKernelGGL((k_gemm16_sample_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m, V, r,     \
+                     ypart, kchunk, vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd)
+        switch (v16(bn, pa, pb)) {
+          case 0: WSSR_S16(128, 32, 1, 1); break;
+          case 1: WSSR_S16(128, 32, 1, 2); break;
+          case 2: WSSR_S16(128, 32, 2, 2); break;
+          case 3: WSSR_S16(256, 32, 1, 1); break;
+          case 4: WSSR_S16(256, 32, 1, 2); break;
+          case 5: WSSR_S16(256, 32, 2, 2); break;
+          case 6: WSSR_S16(512, 16, 1, 1); break;
+          case 7: WSSR_S16(512, 16, 1, 2); break;
+          default: WSSR_S16(512, 16, 2, 2); break;
+        }
+#undef WSSR_S16
+      });
+    }
+    y_finish(n, r, s1);
+  }
+
+  void gemm_param_side(const void* Ov, int64_t ld, int64_t n, int64_t m, const float* Q, int r, float* Z) {
+    const bool b16 = bf16();
+    const int bn = bn_for(r, b16), bk = b16 ? (bn == 512 ? 16 : 32) : 16;
+    const int pa = o_planes(), pb = s_planes();
     const bool vec_q = (r % 4 == 0) && ((uintptr_t)Q % 16 == 0);
     const float scale = (float)(1.0 / std::sqrt((double)n));
-    const int64_t tj = cdiv(r, bn), tiles = cdiv(m, 128) * tj, nk = cdiv(n, 16);
+    const int sl = b16 ? slots16p[v16(bn, pa, pb)] : slots;
+    const int64_t tj = cdiv(r, bn), tiles = cdiv(m, 128) * tj, nk = cdiv(n, bk);
     // whole tiles for every full round of resident workgroups; the leftover
     // tiles' K-steps shared evenly by one more round (stream-K) unless the
     // leftover round is nearly full anyway
     int full = (int)tiles, skw = 0;
     int64_t rem = 0, units = 0;
-    if (skpart && tiles > slots) {
-      rem = tiles % slots;
-      if (rem != 0 && rem * 5 < (int64_t)slots * 4) {
+    if (skpart && tiles > sl && (int64_t)sl * 2 * 128 * bn <= skpart_elems) {
+      rem = tiles % sl;
+      if (rem != 0 && rem * 5 < (int64_t)sl * 4) {
         full = (int)(tiles - rem);
-        skw = slots;
+        skw = sl;
         units = rem * nk;
       }
     }
     const dim3 grid(full + skw);
     timed(1, [&] {
-      if (bn == 256) {
-        hipLaunchKernelGGL(k_gemm_param_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
-                           vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
-        if (skw)
-          hipLaunchKernelGGL(k_streamk_fixup<256>, dim3(rem, 128 * 256 / 1024), dim3(256), 0, stream,
-                             (const float*)skpart, Z, m, r, scale, (int)tj, full, nk, units, skw,
-                             (const DevStatus*)st);
+      if (!b16) {
+        const float* O = static_cast<const float*>(Ov);
+        const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+        if (bn == 256)
+          hipLaunchKernelGGL(k_gemm_param_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
+                             vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        else
+          hipLaunchKernelGGL(k_gemm_param_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
+                             vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
       } else {
-        hipLaunchKernelGGL(k_gemm_param_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
-                           vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
-        if (skw)
-          hipLaunchKernelGGL(k_streamk_fixup<128>, dim3(rem, 128 * 128 / 1024), dim3(256), 0, stream,
-                             (const float*)skpart, Z, m, r, scale, (int)tj, full, nk, units, skw,
-                             (const DevStatus*)st);
+        const auto* O = static_cast<const unsigned short*>(Ov);
+        const int64_t ps = n * ld;
+        const bool vec_o = (ld % 8 == 0) && ((uintptr_t)O % 16 == 0);
+        const unsigned lds = (unsigned)gemm16_lds(bn, bk, pa, pb);
+#define WSSR_P16(BN, BK, PA, PB)                                                                                     \
+  hipLaunchKernelGGL((k_gemm16_param_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m, Q, r,      \
+                     scale, Z, vec_o, vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart)
+        switch (v16(bn, pa, pb)) {
+          case 0: WSSR_P16(128, 32, 1, 1); break;
+          case 1: WSSR_P16(128, 32, 1, 2); break;
+          case 2: WSSR_P16(128, 32, 2, 2); break;
+          case 3: WSSR_P16(256, 32, 1, 1); break;
+          case 4: WSSR_P16(256, 32, 1, 2); break;
+          case 5: WSSR_P16(256, 32, 2, 2); break;
+          case 6: WSSR_P16(512, 16, 1, 1); break;
+          case 7: WSSR_P16(512, 16, 1, 2); break;
+          default: WSSR_P16(512, 16, 2, 2); break;
+        }
+#undef WSSR_P16
+      }
+      if (skw) {
+        const dim3 fg(rem, 128 * bn / 1024);
+        if (bn == 512)
+          hipLaunchKernelGGL(k_streamk_fixup<512>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
+                             (int)tj, full, nk, units, skw, (const DevStatus*)st);
+        else if (bn == 256)
+          hipLaunchKernelGGL(k_streamk_fixup<256>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
+                             (int)tj, full, nk, units, skw, (const DevStatus*)st);
+        else
+          hipLaunchKernelGGL(k_streamk_fixup<128>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
+                             (int)tj, full, nk, units, skw, (const DevStatus*)st);
       }
     });
   }
 
   // lean: at most about one workgroup per compute unit, for running beside
   // other work without taking the compute units it needs
-  void gradient(const float* O, int64_t ld, int64_t n, int64_t m, const double* e_l, double* gout,
+  void gradient(const void* Ov, int64_t ld, int64_t n, int64_t m, const double* e_l, double* gout,
                 hipStream_t on = nullptr, bool lean = false) {
     hipStream_t stream = on ? on : this->stream;
     hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, eps, st);
@@ -204,9 +300,17 @@ struct wssr_ctx {
     const int64_t want = lean ? std::max<int64_t>(1, slots / 2 / cb) : cdiv(2048, cb);
     const int gs = (int)std::min<int64_t>(kGSplitMax, std::max<int64_t>(1, std::min<int64_t>(want, n)));
     const int64_t rows = cdiv(n, gs);
-    const bool vec = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
-    hipLaunchKernelGGL(k_gradient_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n, m, (const double*)eps, rows,
-                       gpart, vec, (const DevStatus*)st);
+    if (!bf16()) {
+      const float* O = static_cast<const float*>(Ov);
+      const bool vec = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+      hipLaunchKernelGGL(k_gradient_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n, m, (const double*)eps,
+                         rows, gpart, vec, (const DevStatus*)st);
+    } else {
+      const auto* O = static_cast<const unsigned short*>(Ov);
+      const bool vec = (ld % 4 == 0) && ((uintptr_t)O % 8 == 0);
+      hipLaunchKernelGGL(k_gradient16_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n * ld, o_planes(), n, m,
+                         (const double*)eps, rows, gpart, vec, (const DevStatus*)st);
+    }
     hipLaunchKernelGGL(k_gradient_reduce, dim3(cdiv(m, 256)), dim3(256), 0, stream, (const double*)gpart, gs, m,
                        1.0 / (double)n, gout, (const DevStatus*)st);
   }
@@ -337,7 +441,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
   if (!out) return WSSR_ERR_INVALID_ARG;
   *out = nullptr;
   if (!cfg || cfg->n_max < 2 || cfg->m_max < 1 || cfg->r_max < 1 || cfg->r_max > 512 || cfg->q_max < 1 ||
-      cfg->o_dtype != WSSR_F32) {
+      cfg->o_dtype < WSSR_F32 || cfg->o_dtype > WSSR_BF16_SPLIT) {
     g_create_error = "invalid config";
     return WSSR_ERR_INVALID_ARG;
   }
@@ -377,8 +481,12 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
             h->alloc(h->jsync, 4);
   // stream-K partials (two 128 x 256 tiles per workgroup of one round), only
   // when a parameter-side product can have more tiles than one round holds
-  const int64_t ptiles = cdiv(m, 128) * cdiv(r, r > 128 ? 256 : 128);
-  if (ok && ptiles > h->slots) ok = h->alloc(h->skpart, (size_t)h->slots * 2 * 128 * 256);
+  // (capacity for 2 slots per CU at 128 x 256 or 1 slot per CU at 128 x 512)
+  const int64_t ptiles = cdiv(m, 128);
+  if (ok && ptiles > h->slots / 2) {
+    h->skpart_elems = (int64_t)h->slots * 2 * 128 * 256;
+    ok = h->alloc(h->skpart, (size_t)h->skpart_elems);
+  }
   if (!ok) {
     (void)hipGetLastError();
     h->release();
@@ -393,6 +501,12 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
     h->release();
     delete h;
     g_create_error = "hipFuncSetAttribute failed";
+    return WSSR_ERR_HIP;
+  }
+  if (!h->setup16()) {
+    h->release();
+    delete h;
+    g_create_error = "BF16 kernel set-up failed";
     return WSSR_ERR_HIP;
   }
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
@@ -447,7 +561,6 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return h->fail(WSSR_ERR_INVALID_ARG, "lambda must be > 0 and finite");
   if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
 
-  const float* Of = static_cast<const float*>(O);
   const int rp = (int)rup(r, 64);
   const DevStatus* cst = h->st;
   hipStream_t stream = h->stream;
@@ -456,11 +569,11 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
   const float* vcur = V;
   for (int p = 1; p <= q; ++p) {
     // sample side: Y = A V (FP64), then its QR: Q_Y = Y Tq (float)
-    h->gemm_sample_side(Of, ld_o, n, m, vcur, r);
+    h->gemm_sample_side(O, ld_o, n, m, vcur, r);
     h->cholqr<double, double>(h->y64, n, r, h->yq1, nullptr);
     h->apply((const double*)h->y64, n, r, r, h->Tq, rp, r, h->qy, r, true);
     // parameter side: Z = A^T Q_Y, then its QR: Q_Z = Z Tq, R_Z
-    h->gemm_param_side(Of, ld_o, n, m, h->qy, r, h->z);
+    h->gemm_param_side(O, ld_o, n, m, h->qy, r, h->z);
     h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
     if (p < q) {
       h->apply((const float*)h->z, m, r, r, h->Tq, rp, r, h->vw, r, true);
@@ -470,7 +583,7 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
       // while this stream works through the few-workgroup Jacobi launches
       (void)hipEventRecord(h->ev_fork, stream);
       (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
-      h->gradient(Of, ld_o, n, m, e_l, h->g, h->side, true);
+      h->gradient(O, ld_o, n, m, e_l, h->g, h->side, true);
       (void)hipEventRecord(h->ev_join, h->side);
       // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T;  C = G diag(sigma) P^T
       h->small_svd(h->Rz, r);
@@ -560,7 +673,7 @@ wssr_status wssr_dbg_sample_side(wssr_handle h, int64_t n, int64_t m, const void
   if (s != WSSR_OK) return s;
   if (!V || !y) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
-  h->gemm_sample_side(static_cast<const float*>(O), ld_o, n, m, V, r);
+  h->gemm_sample_side(O, ld_o, n, m, V, r);
   (void)hipMemcpyAsync(y, h->y64, sizeof(double) * n * r, hipMemcpyDeviceToDevice, h->stream);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
   return WSSR_OK;
@@ -573,7 +686,7 @@ wssr_status wssr_dbg_param_side(wssr_handle h, int64_t n, int64_t m, const void*
   if (s != WSSR_OK) return s;
   if (!X || !z) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
-  h->gemm_param_side(static_cast<const float*>(O), ld_o, n, m, X, r, z);
+  h->gemm_param_side(O, ld_o, n, m, X, r, z);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
   return WSSR_OK;
 }
@@ -585,7 +698,7 @@ wssr_status wssr_dbg_gradient(wssr_handle h, int64_t n, int64_t m, const void* O
   if (s != WSSR_OK) return s;
   if (!e_l || !g) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
-  h->gradient(static_cast<const float*>(O), ld_o, n, m, e_l, g);
+  h->gradient(O, ld_o, n, m, e_l, g);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
   return WSSR_OK;
 }

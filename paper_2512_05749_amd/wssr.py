@@ -28,6 +28,10 @@ STATUS_NAMES = {0: "OK", 2: "WARN_NOT_CONVERGED", -1: "ERR_INVALID_ARG", -2: "ER
                 -4: "ERR_HIP", -5: "ERR_NONFINITE", -6: "ERR_BREAKDOWN", -7: "ERR_TIMEOUT"}
 
 F32 = 0
+BF16 = 1
+BF16X2 = 2
+BF16_SPLIT = 3
+DTYPES = {"f32": F32, "bf16": BF16, "bf16x2": BF16X2, "bf16_split": BF16_SPLIT}
 FLOOR_PRECOND = 0x1
 
 
@@ -103,7 +107,13 @@ def _need(t, name, dtype, device, shape=None):
 class Wssr:
     """One libwssr handle bound to a device and a stream."""
 
-    def __init__(self, n_max, m_max, r_max, q_max=8, floor_precond=False, device=None, stream=None):
+    def __init__(self, n_max, m_max, r_max, q_max=8, floor_precond=False, device=None, stream=None, dtype="f32"):
+        """dtype: storage and product precision of O -- "f32"; "bf16" (one BF16
+        product); "bf16_split" (BF16 O, skinny operand split in two); "bf16x2"
+        (O as BF16 hi and lo planes, shape (2, n, m), three products)."""
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
+        self.dtype = dtype
         device = torch.device(device if device is not None else "cuda")
         if device.type != "cuda":
             raise ValueError("libwssr runs on a HIP device")
@@ -111,7 +121,7 @@ class Wssr:
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
-        cfg = Config(int(n_max), int(m_max), int(r_max), int(q_max), F32,
+        cfg = Config(int(n_max), int(m_max), int(r_max), int(q_max), DTYPES[dtype],
                      FLOOR_PRECOND if floor_precond else 0, ctypes.c_void_p(s.cuda_stream))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -127,9 +137,16 @@ class Wssr:
             raise WssrError(code, lib().wssr_last_error(self._h).decode())
 
     def _o(self, O):
+        if self.dtype == "bf16x2":
+            # (2, n, m): hi plane then lo plane, the lo plane n * ld elements on
+            if O.dim() != 3 or O.shape[0] != 2 or O.stride(2) != 1 or O.stride(1) < O.shape[2] or \
+                    O.stride(0) != O.shape[1] * O.stride(1):
+                raise ValueError("O must be (2, n, m) BF16 planes, row-major, the lo plane right after the hi plane")
+            _need(O, "O", torch.bfloat16, self.device)
+            return O.shape[1], O.shape[2], O.stride(1)
         if O.dim() != 2 or O.stride(1) != 1 or O.stride(0) < O.shape[1]:
             raise ValueError("O must be 2-D, row-major with unit column stride")
-        _need(O, "O", torch.float32, self.device)
+        _need(O, "O", torch.float32 if self.dtype == "f32" else torch.bfloat16, self.device)
         return O.shape[0], O.shape[1], O.stride(0)
 
     def close(self):

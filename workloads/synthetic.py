@@ -146,6 +146,30 @@ class Workload:
         return _orthonormal(g).to(dtype).contiguous()
 
 
+def to_storage(o, form):
+    """O in the storage format of a precision form (input encoding, done once
+    by whoever produces O): "f32" -> float32; "bf16" and "bf16_split" ->
+    bfloat16 (round to nearest even); "bf16x2" -> (2, n, m) bfloat16 planes
+    hi = RNE(O), lo = RNE(O - hi)."""
+    o = o.float()
+    if form == "f32":
+        return o.contiguous()
+    hi = o.to(torch.bfloat16)
+    if form in ("bf16", "bf16_split"):
+        return hi.contiguous()
+    if form == "bf16x2":
+        lo = (o - hi.float()).to(torch.bfloat16)
+        return torch.stack([hi, lo]).contiguous()
+    raise ValueError(form)
+
+
+def stored_values(o_stored):
+    """The values a stored O represents, in float64 (hi + lo for two planes)."""
+    if o_stored.dim() == 3:
+        return o_stored[0].double() + o_stored[1].double()
+    return o_stored.double()
+
+
 def random_problem(n, m, r, seed, alpha=1.2, eta=1e-3, el_mean=-1.0, el_std=0.1,
                    device="cpu", dtype=torch.float32, theta=0.01, t=1):
     """A single step's inputs (O, E_L, V_in) of arbitrary shape, drawn with the
