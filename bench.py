@@ -1,11 +1,15 @@
 """Benchmark: SR steps/s of the warm-started SR step on one MI355X.
 
-Workload (default): the FP32 form, N=8192 samples, M=100000 parameters, rank
+Default workload: the FP32 form, N=8192 samples, M=100000 parameters, rank
 r=256, q=2 passes, lambda=1e-3, synthetic O with a k^-1.2 spectrum rotating by
-0.01 per step (workloads.CONFIGS["f32_n8192_m100k_r256"]).  Inputs are generated on the GPU and
-resident in HBM before timing.  A step is one whole call of wssr_step: centring,
-gradient, q passes (two products, CholeskyQR2 of both sides), Rayleigh-Ritz,
-signs and the Woodbury apply.
+0.01 per step (workloads.CONFIGS["f32_n8192_m100k_r256"]).  Inputs are
+generated on the GPU and resident in HBM before timing.  A step is one whole
+call of wssr_step: centring, gradient, q passes (two products, CholeskyQR2 of
+both sides), Rayleigh-Ritz, signs and the Woodbury apply.
+
+--form bf16 | bf16_split | bf16x2 times a BF16 precision form instead
+(--config bf16_n16384_m1m_r512 for the precision-form instance), and
+--compare-f32 1 times the FP32 form on the same instance beside it.
 
 Prints one JSON line.  `--gpus` above 1 is not supported (single-GPU build).
 """
@@ -53,7 +57,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="f32_n8192_m100k_r256", help="workload name (workloads.CONFIGS)")
-    ap.add_argument("--ring", type=int, default=4, help="distinct O_t held in HBM and cycled")
+    ap.add_argument("--ring", type=int, default=0,
+                    help="distinct O_t held in HBM and cycled (0: 4, or 1 above 2^30 elements)")
+    ap.add_argument("--form", default="f32", choices=["f32", "bf16", "bf16_split", "bf16x2"],
+                    help="storage and product precision of O")
+    ap.add_argument("--compare-f32", type=int, default=0,
+                    help="also time the FP32 form on the same instance and report the ratio")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-cols", type=int, default=0, help="columns of the oracle sample (0: auto)")
     ap.add_argument("--plain-inputs", type=int, default=0,
@@ -69,35 +78,131 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+PEAK_BF16_TFLOPS = 2516.6
+PRODUCTS = {"f32": 1, "bf16": 1, "bf16_split": 2, "bf16x2": 3}
+
+
+def time_form(form, o_ring, e_ring, v_start, cfg, args, dev):
+    """Cold step, warm-up and timed steps of one precision form; returns the
+    timings, the product-kernel profile and the last status."""
+    import numpy as np
+    import torch
+
+    from paper_2512_05749_amd import Wssr
+
+    n, m, r, q, lam = cfg.n, cfg.m, cfg.r, cfg.q, cfg.lam
+    ring = len(o_ring)
+    v = v_start.clone()
+    h = Wssr(n_max=n, m_max=m, r_max=r, q_max=8, device=dev, dtype=form)
+    delta = torch.empty(m, dtype=torch.float64, device=dev)
+    sigma = torch.empty(r, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    # step 1: cold start (8 passes from V_0), reported separately
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    h.step(o_ring[0], e_ring[0], v, lam, q=8, delta=delta, sigma=sigma)
+    e1.record(stream)
+    code, diag = h.status()
+    cold_ms = e0.elapsed_time(e1)
+    log(f"[{form}] cold step (q=8): {cold_ms:.2f} ms, status {code}, diag {diag}")
+    if code < 0:
+        raise SystemExit(f"cold step failed with status {code}")
+
+    t = 1
+    for _ in range(args.warmup):
+        h.step(o_ring[t % ring], e_ring[t % ring], v, lam, q=q, delta=delta, sigma=sigma)
+        t += 1
+    torch.cuda.synchronize()
+    log(f"[{form}] warmup done")
+
+    h.profile(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        h.step(o_ring[t % ring], e_ring[t % ring], v, lam, q=q, delta=delta, sigma=sigma)
+        ends[k].record(stream)
+        t += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    prof = h.profile_read()
+    h.profile(False)
+    code, diag = h.status()
+    h.close()
+    per_step = [s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)]
+    ms_per_step = wall * 1e3 / args.steps
+    log(f"[{form}] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall), median event "
+        f"{np.median(per_step):.3f} ms, status {code}, diag {diag}")
+    if code < 0:
+        raise SystemExit(f"timed steps failed with status {code}")
+    return dict(ms_per_step=ms_per_step, median_ms=float(np.median(per_step)), cold_ms=cold_ms, prof=prof,
+                diag=diag, v=v)
+
+
+def roofline_of(form, prof, cfg):
+    n, m, r = cfg.n, cfg.m, cfg.r
+    flops_gemm = 2.0 * n * m * r * PRODUCTS[form]     # MFMA flops of one product launch
+    peak = PEAK_FP32_TFLOPS if form == "f32" else PEAK_BF16_TFLOPS
+    kern = {}
+    for name, (ms, cnt) in prof.items():
+        avg = ms / max(cnt, 1)
+        kern[name] = dict(avg_ms=avg, launches=cnt, tflops=flops_gemm / (avg * 1e-3) / 1e12)
+    log(f"[{form}] kernels: {kern}")
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    achieved = kern[dom]["tflops"]
+    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": recorded_traffic("k_gemm_" + dom) if form == "f32" else None,
+            "kernel": "k_gemm_" + dom if form == "f32" else "k_gemm16_" + dom, "avg_ms": round(kern[dom]["avg_ms"], 4),
+            "flops_per_launch": flops_gemm, "products": PRODUCTS[form],
+            "other": {k: {"avg_ms": round(v_["avg_ms"], 4), "tflops": round(v_["tflops"], 2)}
+                      for k, v_ in kern.items() if k != dom}}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
-    from paper_2512_05749_amd import Wssr
-    from workloads import CONFIGS, Workload
+    from workloads import CONFIGS, Workload, to_storage
 
     cfg = CONFIGS[args.config]
+    form = args.form
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    ring = args.ring or (4 if cfg.n * cfg.m <= (1 << 30) else 1)
+    keep_f32 = form == "f32" or args.compare_f32 or args.cpu_baseline
     t0 = time.time()
+    o32, ost, es = [], [], []
     if args.plain_inputs:
         gen = torch.Generator(device=dev).manual_seed(cfg.seed)
-        os_ = [torch.randn(cfg.n, cfg.m, generator=gen, device=dev) for _ in range(args.ring)]
-        es = [cfg.el_mean + cfg.el_std * torch.randn(cfg.n, generator=gen, device=dev, dtype=torch.float64)
-              for _ in range(args.ring)]
+        for _ in range(ring):
+            o = torch.randn(cfg.n, cfg.m, generator=gen, device=dev)
+            es.append(cfg.el_mean + cfg.el_std * torch.randn(cfg.n, generator=gen, device=dev, dtype=torch.float64))
+            if form != "f32":
+                ost.append(to_storage(o, form))
+            o32.append(o if keep_f32 else None)
+            del o
         v = torch.randn(cfg.m, cfg.r, generator=gen, device=dev) / math.sqrt(cfg.m)
     else:
         wl = Workload(cfg, device=dev, gen_dtype=torch.float32)
-        os_ = [wl.o(t) for t in range(1, args.ring + 1)]
-        es = [wl.e_l(t) for t in range(1, args.ring + 1)]
+        for t in range(1, ring + 1):
+            o = wl.o(t)
+            es.append(wl.e_l(t))
+            if form != "f32":
+                ost.append(to_storage(o, form))
+            o32.append(o if keep_f32 else None)
+            del o
         v = wl.v0()
-        del wl.w0, wl.u0
+        del wl
     torch.cuda.synchronize()
-    log(f"generated {args.ring} x O ({cfg.n}x{cfg.m}) in {time.time() - t0:.1f}s")
+    torch.cuda.empty_cache()
+    log(f"generated {ring} x O ({cfg.n}x{cfg.m}, form {form}) in {time.time() - t0:.1f}s")
     if args.copy_calibration:
         # one elementwise kernel reading and writing exactly copy_calibration MiB
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
@@ -108,102 +213,50 @@ def main():
         del src, dst
 
     n, m, r, q, lam = cfg.n, cfg.m, cfg.r, cfg.q, cfg.lam
-    h = Wssr(n_max=n, m_max=m, r_max=r, q_max=8, device=dev)
-    delta = torch.empty(m, dtype=torch.float64, device=dev)
-    sigma = torch.empty(r, dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    # step 1: cold start (8 passes from V_0), reported separately
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    h.step(os_[0], es[0], v, lam, q=8, delta=delta, sigma=sigma)
-    e1.record(stream)
-    code, diag = h.status()
-    cold_ms = e0.elapsed_time(e1)
-    log(f"cold step (q=8): {cold_ms:.2f} ms, status {code}, diag {diag}")
-    if code < 0:
-        raise SystemExit(f"cold step failed with status {code}")
-
-    t = 1
-    for _ in range(args.warmup):
-        h.step(os_[t % args.ring], es[t % args.ring], v, lam, q=q, delta=delta, sigma=sigma)
-        t += 1
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    h.profile(True)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        h.step(os_[t % args.ring], es[t % args.ring], v, lam, q=q, delta=delta, sigma=sigma)
-        ends[k].record(stream)
-        t += 1
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    prof = h.profile_read()
-    h.profile(False)
-    code, diag = h.status()
-    per_step = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    ms_per_step = wall * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall), median event {np.median(per_step):.3f} ms, "
-        f"status {code}, diag {diag}")
-    if code < 0:
-        raise SystemExit(f"timed steps failed with status {code}")
-
-    flops_gemm = 2.0 * n * m * r            # one product launch (2 N M r)
-    kern = {}
-    for name, (ms, cnt) in prof.items():
-        avg = ms / max(cnt, 1)
-        kern[name] = dict(avg_ms=avg, launches=cnt, tflops=flops_gemm / (avg * 1e-3) / 1e12)
-    log(f"kernels: {kern}")
-    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
-    achieved = kern[dom]["tflops"]
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": recorded_traffic("k_gemm_" + dom),
-                "kernel": "k_gemm_" + dom, "avg_ms": round(kern[dom]["avg_ms"], 4),
-                "flops_per_launch": flops_gemm,
-                "other": {k: {"avg_ms": round(v_["avg_ms"], 4), "tflops": round(v_["tflops"], 2)}
-                          for k, v_ in kern.items() if k != dom}}
-
+    res = time_form(form, o32 if form == "f32" else ost, es, v, cfg, args, dev)
     out = {
         "metric": METRIC,
-        "value": round(1e3 / ms_per_step, 3),
+        "value": round(1e3 / res["ms_per_step"], 3),
         "unit": "SR steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(res["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if form == "f32" else "bf16",
         "data": "synthetic, i.i.d. Gaussian O (counter run)" if args.plain_inputs else "synthetic",
-        "config": {"workload": f"{cfg.name}: FP32 WSSR step, N={n} M={m} r={r} q={q} lambda={lam}, "
+        "config": {"workload": f"{cfg.name}: WSSR step, O {form}, N={n} M={m} r={r} q={q} lambda={lam}, "
                                f"spectrum k^-{cfg.alpha}, rotation {cfg.theta}/step",
-                   "n": n, "m": m, "r": r, "q": q, "lambda": lam},
-        "cold_step_ms": round(cold_ms, 3),
-        "step_ms_median_events": round(float(np.median(per_step)), 4),
-        "roofline": roofline,
+                   "n": n, "m": m, "r": r, "q": q, "lambda": lam, "form": form},
+        "cold_step_ms": round(res["cold_ms"], 3),
+        "step_ms_median_events": round(res["median_ms"], 4),
+        "roofline": roofline_of(form, res["prof"], cfg),
     }
-
+    if form != "f32" and args.compare_f32:
+        ref = time_form("f32", o32, es, v, cfg, args, dev)
+        out["fp32_same_instance"] = {"ms_per_step": round(ref["ms_per_step"], 4),
+                                     "value": round(1e3 / ref["ms_per_step"], 3),
+                                     "roofline": roofline_of("f32", ref["prof"], cfg)}
+        out["vs_fp32_same_instance"] = round(ref["ms_per_step"] / res["ms_per_step"], 3)
     if args.cpu_baseline:
-        out["cpu_baseline"], acc = cpu_baseline(args, cfg, os_[1], es[1], v, h)
+        out["cpu_baseline"], acc = cpu_baseline(args, cfg, o32[min(1, ring - 1)], es[min(1, ring - 1)], v, form)
         out["accuracy_vs_oracle"] = acc
-    h.close()
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(args, cfg, o_dev, e_dev, v_dev, h):
+def cpu_baseline(args, cfg, o_dev, e_dev, v_dev, form="f32"):
     """Time the FP64 oracle on a column sample of the same workload (the first
     `cols` parameters of one step's O, same E_L, the matching rows of V as the
     warm start) and scale the per-step time by M / cols to a full step.  Every
     stage of the step is linear in M except the N x r and r x r ones, which the
     scaling counts M / cols times over, so the reported rate is a slight
     underestimate of the oracle's full-size rate.  The GPU path is run on the
-    same sample instance to report its delta error against the oracle."""
+    same sample instance, in the benchmarked precision form, to report its
+    errors against the oracle: on the values O holds in storage (the
+    implementation error) and, for the BF16 forms, also on the unrounded O
+    (the end-to-end error of the form)."""
     import numpy as np
     import torch
 
@@ -211,7 +264,8 @@ def cpu_baseline(args, cfg, o_dev, e_dev, v_dev, h):
     from tests.metrics import rel, sigma_rel_gated
 
     n, m, r, q, lam = cfg.n, cfg.m, cfg.r, cfg.q, cfg.lam
-    cols = args.cpu_cols or max(4 * r, m // 8)
+    # about 10-30 s of oracle work on the machine's cores at the benchmark shape
+    cols = args.cpu_cols or min(m, max(4 * r, m // 8, 1), max(4 * r, int(1.3e12 / (8.0 * n * r * q))))
     o_s = o_dev[:, :cols].contiguous()
     v_s = v_dev[:cols].contiguous()
     o_np = o_s.double().cpu().numpy()
@@ -234,17 +288,26 @@ def cpu_baseline(args, cfg, o_dev, e_dev, v_dev, h):
 
     # GPU on the same sample instance
     from paper_2512_05749_amd import Wssr
-    hs = Wssr(n_max=n, m_max=cols, r_max=r, q_max=q)
+    from workloads import stored_values, to_storage
+    hs = Wssr(n_max=n, m_max=cols, r_max=r, q_max=q, dtype=form)
+    o_in = to_storage(o_s, form)
     vv = v_s.clone()
-    d, s = hs.step(o_s, e_dev, vv, lam, q=q)
+    d, s = hs.step(o_in, e_dev, vv, lam, q=q)
     code, _ = hs.status()
     hs.close()
     acc = {"sample": f"N={n}, first {cols} of M={m} columns, warm start = matching rows of V",
-           "status": code,
+           "status": code, "form": form,
            "delta_rel_err": rel(d.cpu().numpy(), ref["delta"]),
            "sigma_rel_err_gated": sigma_rel_gated(s.cpu().numpy(), ref["sigma"], lam),
            "v_orth_err": float(np.abs(vv.double().cpu().numpy().T @ vv.double().cpu().numpy()
                                       - np.eye(r)).max())}
+    if form != "f32":
+        # the oracle on the values O holds in storage
+        ref_s = orc.wssr_step(stored_values(o_in).cpu().numpy(), e_np, v_np, lam, r, q)
+        acc["vs_unrounded_O"] = {"delta_rel_err": acc.pop("delta_rel_err"),
+                                 "sigma_rel_err_gated": acc.pop("sigma_rel_err_gated")}
+        acc["vs_stored_O"] = {"delta_rel_err": rel(d.cpu().numpy(), ref_s["delta"]),
+                              "sigma_rel_err_gated": sigma_rel_gated(s.cpu().numpy(), ref_s["sigma"], lam)}
     log(f"accuracy on the sample: {acc}")
     base = {"value": round(1.0 / full_s, 6), "unit": "SR steps/s", "cores": threads, "kind": "oracle",
             "sample": f"one step of the FP64 oracle on N={n} x {cols} columns (of M={m}), r={r}, q={q}: "

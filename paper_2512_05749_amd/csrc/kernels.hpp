@@ -46,16 +46,20 @@ __global__ void k_gradient16_partial(const unsigned short* O, int64_t ld, int64_
                                      const DevStatus* st);
 
 // BF16 products (kernels_gemm16.hip): BN output columns per tile, BK K-step,
-// PA planes of O, PB planes of the FP32 skinny operand.
+// PA planes of O, PB planes of the skinny operand, which k_split_skinny has
+// split into BF16 planes laid out [k / 16][column][k % 16] (plane stride in
+// elements).
+__global__ void k_split_skinny(const float* S, int64_t K, int r, unsigned short* out, int64_t pstride, int planes,
+                               const DevStatus* st);
 template <int BN, int BK, int PA, int PB>
 __global__ void k_gemm16_sample_side(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
-                                     const float* V, int r, float* ypart, int64_t kchunk, bool vec_o, bool vec_v,
-                                     const DevStatus* st, int tn, int tj, bool xcd_groups);
+                                     const unsigned short* Vs, int64_t vstride, int r, float* ypart, int64_t kchunk,
+                                     bool vec_o, const DevStatus* st, int tn, int tj, bool xcd_groups);
 template <int BN, int BK, int PA, int PB>
 __global__ void k_gemm16_param_side(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
-                                    const float* Q, int r, float scale, float* Z, bool vec_o, bool vec_q,
-                                    const DevStatus* st, int tiles_j, int full_tiles, int64_t sk_units, int sk_wgs,
-                                    float* part);
+                                    const unsigned short* Qs, int64_t qstride, int r, float scale, float* Z,
+                                    bool vec_o, const DevStatus* st, int tiles_j, int full_tiles, int64_t sk_units,
+                                    int sk_wgs, float* part);
 size_t gemm16_lds(int bn, int bk, int pa, int pb);
 
 template <typename T>

@@ -4,8 +4,10 @@
 //   sample side    Ypart[s] = O[:, Ks] S[Ks, :]      (N x r, K = M split into ranges)
 //   parameter side Z = O^T S * scale                  (M x r, K = N)
 //
-// S (V or Q_Y) arrives in FP32 and is rounded to BF16 on its way into LDS:
-// S = S_hi + S_lo with S_hi = RNE(S), S_lo = RNE(S - S_hi).  O has PA planes
+// S (V or Q_Y) arrives in FP32.  k_split_skinny rounds it once per product,
+// S = S_hi + S_lo with S_hi = RNE(S), S_lo = RNE(S - S_hi), into BF16 planes
+// laid out K-blocked, [k / 16][column][k % 16], so that one K-step's tile of
+// S is a contiguous block copied into LDS with 16-byte loads.  O has PA planes
 // (1: O itself; 2: O_hi and O_lo = RNE(O_fp32 - O_hi), the split form) and S
 // is used with PB planes.  The products summed are
 //   O_hi S_hi                      always
@@ -18,9 +20,9 @@
 // 32 x 32.  Both operand tiles are staged K-contiguous in LDS ([row][k], row
 // stride BK + 8 elements, an odd multiple of 16 bytes, so the 16-byte
 // fragment reads are conflict-free); a lane's MFMA fragment is one 16-byte
-// read.  Operands whose global rows are the K index (O on the parameter side,
-// S on both sides) are loaded as 8 K-rows per thread and transposed in
-// registers, so their LDS stores are 16-byte stores too.  The next K-step's
+// read.  O on the parameter side, whose global rows are the K index, is
+// loaded as 8 K-rows x 2 parameters per thread and transposed in registers,
+// so its LDS stores are 16-byte stores too.  The next K-step's
 // global loads are in flight during the current MFMAs (double-buffered LDS).
 #include "common.hpp"
 #include "kernels.hpp"
@@ -50,21 +52,25 @@ __device__ __forceinline__ void split_bf16(float x, u16& hi, u16& lo) {
 
 __device__ __forceinline__ unsigned pack2(u16 a, u16 b) { return (unsigned)a | ((unsigned)b << 16); }
 
-// Tile geometry shared by the kernels.
-template <int BN, int BK, int PA, int PB>
+// Tile geometry shared by the kernels.  ATR: the A tile is kept as it lies
+// in memory, [k][row] with row stride LDM (the parameter side, where O's rows
+// are the K index), and its MFMA fragments are gathered with 2-byte reads;
+// otherwise A is K-contiguous like B.
+template <int BN, int BK, int PA, int PB, bool ATR>
 struct Geo {
-  static constexpr int LDK = BK + 8;                        // LDS row stride (bf16 elements)
-  static constexpr int A_PLANE = BM * LDK;                  // elements per A plane
+  static constexpr int LDK = BK + 8;                        // K-contiguous row stride (bf16 elements)
+  static constexpr int LDM = BM + 8;                        // [k][row] row stride when ATR
+  static constexpr int A_PLANE = ATR ? BK * LDM : BM * LDK; // elements per A plane
   static constexpr int B_PLANE = BN * LDK;
   static constexpr int STAGE = PA * A_PLANE + PB * B_PLANE;  // elements per stage
   static constexpr int TB = BN / 64;                        // 32-column MFMA tiles per wave
 };
 
 // MFMAs of one LDS stage: acc[a][b] += sum over products of A_p[rows] B_q[cols]^T
-template <int BN, int BK, int PA, int PB>
+template <int BN, int BK, int PA, int PB, bool ATR>
 __device__ __forceinline__ void mma_stage(f32x16 (&acc)[2][BN / 64], const u16* __restrict__ S, int wm, int wn,
                                           int lane) {
-  using G = Geo<BN, BK, PA, PB>;
+  using G = Geo<BN, BK, PA, PB, ATR>;
   const int x = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int kc = 0; kc < BK / 16; ++kc) {
@@ -72,9 +78,18 @@ __device__ __forceinline__ void mma_stage(f32x16 (&acc)[2][BN / 64], const u16* 
 #pragma unroll
     for (int p = 0; p < PA; ++p)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-        av[p][a] = *reinterpret_cast<const u32x4*>(S + p * G::A_PLANE + (wm * 64 + a * 32 + x) * G::LDK + kc * 16 +
-                                                   8 * h);
+      for (int a = 0; a < 2; ++a) {
+        if constexpr (ATR) {
+          const u16* col = S + p * G::A_PLANE + (kc * 16 + 8 * h) * G::LDM + wm * 64 + a * 32 + x;
+          u16 e[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) e[i] = col[i * G::LDM];
+          av[p][a] = u32x4{pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7])};
+        } else {
+          av[p][a] = *reinterpret_cast<const u32x4*>(S + p * G::A_PLANE + (wm * 64 + a * 32 + x) * G::LDK +
+                                                     kc * 16 + 8 * h);
+        }
+      }
 #pragma unroll
     for (int q = 0; q < PB; ++q)
 #pragma unroll
@@ -92,80 +107,104 @@ __device__ __forceinline__ void mma_stage(f32x16 (&acc)[2][BN / 64], const u16* 
   }
 }
 
-// ---- S loader: FP32 rows k (K index) x columns j, to K-contiguous BF16 planes.
-// A unit is 8 K-rows x 4 columns: 8 float4 loads, transposed into 4 columns of
-// 8 BF16 (one 16-byte store per column and plane).
+// ---- S loader: BN columns x BK K-values of each split plane, copied from the
+// K-blocked layout (16-byte units: column j, 8 K-values) into LDS rows.
 template <int BN, int BK>
 struct SUnit {
-  static constexpr int UNITS = (BK / 8) * (BN / 4);
+  static constexpr int UNITS = BN * (BK / 8);
   static constexpr int PER_T = (UNITS + 255) / 256;
 };
 
-template <int BN, int BK, int PT>
-__device__ __forceinline__ void s_load(f32x4 (&rs)[PT][8], const float* __restrict__ Sm, int r, int j0, int64_t k0,
-                                       int64_t kend, bool fast, int t) {
+template <int BN, int BK, int PB, int PT>
+__device__ __forceinline__ void s_load(u32x4 (&rs)[PB][PT], const u16* __restrict__ Ss, int64_t pstride, int r,
+                                       int64_t kblocks, int j0, int64_t k0, bool fast, int t) {
 #pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    const int unit = t + 256 * u;
-    if (unit >= SUnit<BN, BK>::UNITS) break;
-    const int kg = unit / (BN / 4), cq = (unit % (BN / 4)) * 4;
+  for (int q = 0; q < PB; ++q)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int64_t k = k0 + kg * 8 + s;
-      const int c = j0 + cq;
-      if (fast) {
-        rs[u][s] = *reinterpret_cast<const f32x4*>(Sm + k * r + c);
-      } else {
-        f32x4 v = f32x4{0};
-        if (k < kend) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (c + e < r) v[e] = Sm[k * r + c + e];
-        }
-        rs[u][s] = v;
-      }
+    for (int u = 0; u < PT; ++u) {
+      const int unit = t + 256 * u;
+      if (unit >= SUnit<BN, BK>::UNITS) break;
+      // unit -> (K-block of the stage kb, column c, half h8): consecutive
+      // threads read consecutive 16-byte pieces of one K-block
+      const int kb = unit / (2 * BN), c = (unit % (2 * BN)) >> 1, h8 = unit & 1;
+      const int64_t blk = k0 / 16 + kb;
+      const int j = j0 + c;
+      const u16* src = Ss + q * pstride + (blk * r + j) * 16 + h8 * 8;
+      if (fast || (j < r && blk < kblocks))
+        rs[q][u] = *reinterpret_cast<const u32x4*>(src);
+      else
+        rs[q][u] = u32x4{0, 0, 0, 0};
     }
-  }
 }
 
 template <int BN, int BK, int PB, int PT>
-__device__ __forceinline__ void s_store(const f32x4 (&rs)[PT][8], u16* __restrict__ Bp, int plane_elems, int ldk,
+__device__ __forceinline__ void s_store(const u32x4 (&rs)[PB][PT], u16* __restrict__ Bp, int plane_elems, int ldk,
                                         int t) {
 #pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    const int unit = t + 256 * u;
-    if (unit >= SUnit<BN, BK>::UNITS) break;
-    const int kg = unit / (BN / 4), cq = (unit % (BN / 4)) * 4;
+  for (int q = 0; q < PB; ++q)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      u16 hi[8], lo[8];
-#pragma unroll
-      for (int s = 0; s < 8; ++s) split_bf16(rs[u][s][e], hi[s], lo[s]);
-      u32x4 vh = {pack2(hi[0], hi[1]), pack2(hi[2], hi[3]), pack2(hi[4], hi[5]), pack2(hi[6], hi[7])};
-      *reinterpret_cast<u32x4*>(Bp + (cq + e) * ldk + kg * 8) = vh;
-      if constexpr (PB == 2) {
-        u32x4 vl = {pack2(lo[0], lo[1]), pack2(lo[2], lo[3]), pack2(lo[4], lo[5]), pack2(lo[6], lo[7])};
-        *reinterpret_cast<u32x4*>(Bp + plane_elems + (cq + e) * ldk + kg * 8) = vl;
-      }
+    for (int u = 0; u < PT; ++u) {
+      const int unit = t + 256 * u;
+      if (unit >= SUnit<BN, BK>::UNITS) break;
+      const int kb = unit / (2 * BN), c = (unit % (2 * BN)) >> 1, h8 = unit & 1;
+      *reinterpret_cast<u32x4*>(Bp + q * plane_elems + c * ldk + kb * 16 + h8 * 8) = rs[q][u];
     }
-  }
 }
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// S (K x r FP32, row-major) -> BF16 planes hi (and lo when two planes) in the
+// K-blocked layout [kb][j][k % 16], zero for k >= K.  One thread per (kb, j):
+// 16 loads that are coalesced across threads (consecutive j), two 32-byte
+// stores per plane.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_split_skinny(const float* __restrict__ S, int64_t K, int r,
+                                                      u16* __restrict__ out, int64_t pstride, int planes,
+                                                      const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t kblocks = (K + 15) / 16;
+  if (id >= kblocks * r) return;
+  const int64_t kb = id / r;
+  const int j = (int)(id % r);
+  u16 hi[16], lo[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int64_t k = kb * 16 + e;
+    const float x = (k < K) ? S[k * r + j] : 0.0f;
+    split_bf16(x, hi[e], lo[e]);
+  }
+  u16* dst = out + id * 16;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    u32x4 v = {pack2(hi[8 * h], hi[8 * h + 1]), pack2(hi[8 * h + 2], hi[8 * h + 3]),
+               pack2(hi[8 * h + 4], hi[8 * h + 5]), pack2(hi[8 * h + 6], hi[8 * h + 7])};
+    *reinterpret_cast<u32x4*>(dst + 8 * h) = v;
+  }
+  if (planes == 2) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      u32x4 v = {pack2(lo[8 * h], lo[8 * h + 1]), pack2(lo[8 * h + 2], lo[8 * h + 3]),
+                 pack2(lo[8 * h + 4], lo[8 * h + 5]), pack2(lo[8 * h + 6], lo[8 * h + 7])};
+      *reinterpret_cast<u32x4*>(dst + pstride + 8 * h) = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Sample side.  O planes: N x M BF16 row-major (row stride ld, plane stride
-// pstride elements), K-contiguous; S = V: M x r FP32.  1-D grid over
+// pstride elements), K-contiguous; S = V split into BF16 planes (Vs).  1-D grid over
 // (n tile, r tile, K range) with the XCD grouping of the FP32 kernel.
 // ---------------------------------------------------------------------------
 template <int BN, int BK, int PA, int PB>
 __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __restrict__ O, int64_t ld,
                                                                int64_t pstride, int64_t n, int64_t m,
-                                                               const float* __restrict__ V, int r,
+                                                               const u16* __restrict__ Vs, int64_t vstride, int r,
                                                                float* __restrict__ ypart, int64_t kchunk,
-                                                               bool vec_o, bool vec_v, const DevStatus* st, int tn,
-                                                               int tj, bool xcd_groups) {
+                                                               bool vec_o, const DevStatus* st, int tn, int tj,
+                                                               bool xcd_groups) {
   if (failed(st)) return;
-  using G = Geo<BN, BK, PA, PB>;
+  using G = Geo<BN, BK, PA, PB, false>;
   constexpr int AU = BM * BK / 8;                 // 16-byte A units per plane
   constexpr int APT = (AU + 255) / 256;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem16[];
@@ -203,9 +242,10 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
 
   u32x4 ra[PA][APT];
   constexpr int SPT = SUnit<BN, BK>::PER_T;
-  f32x4 rs[SPT][8];
-  const bool inner = vec_o && vec_v && (n0 + BM <= n) && (j0 + BN <= r);
-  auto gload = [&](int64_t k0) {
+  u32x4 rs[PB][SPT];
+  const int64_t kblocks = (m + 15) / 16;
+  const bool inner = vec_o && (n0 + BM <= n) && (j0 + BN <= r);
+  auto gload = [&](int64_t k0) __attribute__((always_inline)) {
     const bool fast = inner && k0 + BK <= ke;
 #pragma unroll
     for (int p = 0; p < PA; ++p)
@@ -224,9 +264,9 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
           ra[p][u] = u32x4{pack2(e8[0], e8[1]), pack2(e8[2], e8[3]), pack2(e8[4], e8[5]), pack2(e8[6], e8[7])};
         }
       }
-    s_load<BN, BK, SPT>(rs, V, r, j0, k0, ke, fast, t);
+    s_load<BN, BK, PB, SPT>(rs, Vs, vstride, r, kblocks, j0, k0, fast, t);
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf) __attribute__((always_inline)) {
     u16* S = lds + buf * G::STAGE;
 #pragma unroll
     for (int p = 0; p < PA; ++p)
@@ -247,7 +287,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
   for (int64_t it = 0; it < nk; ++it) {
     const int buf = (int)(it & 1);
     if (it + 1 < nk) gload(kb + (it + 1) * BK);
-    mma_stage<BN, BK, PA, PB>(acc, lds + buf * G::STAGE, wm, wn, lane);
+    mma_stage<BN, BK, PA, PB, false>(acc, lds + buf * G::STAGE, wm, wn, lane);
     if (it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
@@ -269,7 +309,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
 
 // ---------------------------------------------------------------------------
 // Parameter side Z = O^T S * scale.  O planes: N x M BF16 row-major (the K
-// index is the row); S = Q: N x r FP32.  A unit of the O tile is 8 K-rows x 2
+// index is the row); S = Q_Y split into BF16 planes (Qs).  A unit of the O tile is 8 K-rows x 2
 // parameters (8 four-byte loads, transposed into two 16-byte LDS rows).
 // Scheduling as in the FP32 kernel: whole tiles for every full round of
 // resident workgroups, the leftover tiles' K-steps shared out stream-K style
@@ -277,14 +317,14 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
 // ---------------------------------------------------------------------------
 template <int BN, int BK, int PA, int PB>
 __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restrict__ O, int64_t ld, int64_t pstride,
-                                                              int64_t n, int64_t m, const float* __restrict__ Q,
-                                                              int r, float scale, float* __restrict__ Z, bool vec_o,
-                                                              bool vec_q, const DevStatus* st, int tiles_j,
-                                                              int full_tiles, int64_t sk_units, int sk_wgs,
-                                                              float* __restrict__ part) {
+                                                              int64_t n, int64_t m, const u16* __restrict__ Qs,
+                                                              int64_t qstride, int r, float scale,
+                                                              float* __restrict__ Z, bool vec_o, const DevStatus* st,
+                                                              int tiles_j, int full_tiles, int64_t sk_units,
+                                                              int sk_wgs, float* __restrict__ part) {
   if (failed(st)) return;
-  using G = Geo<BN, BK, PA, PB>;
-  constexpr int AU = (BK / 8) * (BM / 2);          // 8 x 2 units per plane
+  using G = Geo<BN, BK, PA, PB, true>;
+  constexpr int AU = BK * (BM / 8);                // 16-byte units (8 parameters of one K-row) per plane
   constexpr int APT = (AU + 255) / 256;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem16[];
   u16* lds = reinterpret_cast<u16*>(smem16);
@@ -296,10 +336,11 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
   bool inner = false;
 
   f32x16 acc[2][G::TB];
-  unsigned ro[PA][APT][8];
+  u32x4 ro[PA][APT];
   constexpr int SPT = SUnit<BN, BK>::PER_T;
-  f32x4 rs[SPT][8];
-  auto gload = [&](int64_t k0) {
+  u32x4 rs[PB][SPT];
+  const int64_t kblocks = (n + 15) / 16;
+  auto gload = [&](int64_t k0) __attribute__((always_inline)) {
     const bool fast = inner && k0 + BK <= n;
 #pragma unroll
     for (int p = 0; p < PA; ++p)
@@ -307,23 +348,21 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
       for (int u = 0; u < APT; ++u) {
         const int unit = t + 256 * u;
         if (unit >= AU) break;
-        const int kg = unit / (BM / 2), mp = (unit % (BM / 2)) * 2;
+        const int kr = unit / (BM / 8), mq = (unit % (BM / 8)) * 8;
+        const int64_t k = k0 + kr;
+        const u16* src = O + p * pstride + k * ld + m0 + mq;
+        if (fast) {
+          ro[p][u] = *reinterpret_cast<const u32x4*>(src);
+        } else {
+          u16 e8[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int64_t k = k0 + kg * 8 + s;
-          const u16* src = O + p * pstride + k * ld + m0 + mp;
-          if (fast) {
-            ro[p][u][s] = *reinterpret_cast<const unsigned*>(src);
-          } else {
-            const u16 e0 = (k < n && m0 + mp < m) ? src[0] : (u16)0;
-            const u16 e1 = (k < n && m0 + mp + 1 < m) ? src[1] : (u16)0;
-            ro[p][u][s] = pack2(e0, e1);
-          }
+          for (int e = 0; e < 8; ++e) e8[e] = (k < n && m0 + mq + e < m) ? src[e] : (u16)0;
+          ro[p][u] = u32x4{pack2(e8[0], e8[1]), pack2(e8[2], e8[3]), pack2(e8[4], e8[5]), pack2(e8[6], e8[7])};
         }
       }
-    s_load<BN, BK, SPT>(rs, Q, r, j0, k0, n, fast, t);
+    s_load<BN, BK, PB, SPT>(rs, Qs, qstride, r, kblocks, j0, k0, fast, t);
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf) __attribute__((always_inline)) {
     u16* S = lds + buf * G::STAGE;
 #pragma unroll
     for (int p = 0; p < PA; ++p)
@@ -331,22 +370,15 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
       for (int u = 0; u < APT; ++u) {
         const int unit = t + 256 * u;
         if (unit >= AU) break;
-        const int kg = unit / (BM / 2), mp = (unit % (BM / 2)) * 2;
-        const unsigned* d = ro[p][u];
-        // even parameter: low halves of the 8 words; odd: high halves
-        u32x4 ev = {__builtin_amdgcn_perm(d[1], d[0], 0x05040100u), __builtin_amdgcn_perm(d[3], d[2], 0x05040100u),
-                    __builtin_amdgcn_perm(d[5], d[4], 0x05040100u), __builtin_amdgcn_perm(d[7], d[6], 0x05040100u)};
-        u32x4 od = {__builtin_amdgcn_perm(d[1], d[0], 0x07060302u), __builtin_amdgcn_perm(d[3], d[2], 0x07060302u),
-                    __builtin_amdgcn_perm(d[5], d[4], 0x07060302u), __builtin_amdgcn_perm(d[7], d[6], 0x07060302u)};
-        *reinterpret_cast<u32x4*>(S + p * G::A_PLANE + mp * G::LDK + kg * 8) = ev;
-        *reinterpret_cast<u32x4*>(S + p * G::A_PLANE + (mp + 1) * G::LDK + kg * 8) = od;
+        const int kr = unit / (BM / 8), mq = (unit % (BM / 8)) * 8;
+        *reinterpret_cast<u32x4*>(S + p * G::A_PLANE + kr * G::LDM + mq) = ro[p][u];
       }
     s_store<BN, BK, PB, SPT>(rs, S + PA * G::A_PLANE, G::B_PLANE, G::LDK, t);
   };
-  auto run = [&](int64_t tile, int64_t kb, int64_t ke) {
+  auto run = [&](int64_t tile, int64_t kb, int64_t ke) __attribute__((always_inline)) {
     m0 = (tile / tiles_j) * BM;
     j0 = (int)(tile % tiles_j) * BN;
-    inner = vec_o && vec_q && (m0 + BM <= m) && (j0 + BN <= r);
+    inner = vec_o && (m0 + BM <= m) && (j0 + BN <= r);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -357,7 +389,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
     for (int64_t it = kb; it < ke; ++it) {
       const int buf = (int)((it - kb) & 1);
       if (it + 1 < ke) gload((it + 1) * BK);
-      mma_stage<BN, BK, PA, PB>(acc, lds + buf * G::STAGE, wm, wn, lane);
+      mma_stage<BN, BK, PA, PB, true>(acc, lds + buf * G::STAGE, wm, wn, lane);
       if (it + 1 < ke) sstore(buf ^ 1);
       __syncthreads();
     }
@@ -381,10 +413,13 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
       }
     return;
   }
+  // stream-K: this workgroup's range of K-steps touches at most two tiles
+  // (it is never longer than one tile's nk steps); written out without a
+  // loop, so that no epilogue address is hoisted over the K-loop
   const int64_t wg = (int64_t)blockIdx.x - full_tiles;
-  const int64_t ubeg = wg * sk_units / sk_wgs, uend = (wg + 1) * sk_units / sk_wgs;
-  int seg = 0;
-  for (int64_t u = ubeg; u < uend; ++seg) {
+  int64_t u = wg * sk_units / sk_wgs;
+  const int64_t uend = (wg + 1) * sk_units / sk_wgs;
+  auto segment = [&](int seg) __attribute__((always_inline)) {
     const int64_t tl = u / nk, kb = u - tl * nk, ke = min(nk, kb + (uend - u));
     run(full_tiles + tl, kb, ke);
     float* outp = part + (wg * 2 + seg) * (int64_t)(BM * BN);
@@ -400,20 +435,23 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
         }
       }
     u += ke - kb;
-  }
+  };
+  if (u < uend) segment(0);
+  if (u < uend) segment(1);
 }
 
 // dynamic LDS bytes of a BF16 product kernel
 size_t gemm16_lds(int bn, int bk, int pa, int pb) {
-  return (size_t)2 * (pa * BM + pb * bn) * (bk + 8) * sizeof(u16);
+  const size_t a_k = (size_t)BM * (bk + 8), a_t = (size_t)bk * (BM + 8);
+  return 2 * (pa * (a_k > a_t ? a_k : a_t) + (size_t)pb * bn * (bk + 8)) * sizeof(u16);
 }
 
 #define WSSR_GEMM16_INST(BN, BK, PA, PB)                                                                             \
   template __global__ void k_gemm16_sample_side<BN, BK, PA, PB>(const u16*, int64_t, int64_t, int64_t, int64_t,     \
-                                                                const float*, int, float*, int64_t, bool, bool,     \
+                                                                const u16*, int64_t, int, float*, int64_t, bool,    \
                                                                 const DevStatus*, int, int, bool);                  \
   template __global__ void k_gemm16_param_side<BN, BK, PA, PB>(const u16*, int64_t, int64_t, int64_t, int64_t,      \
-                                                               const float*, int, float, float*, bool, bool,        \
+                                                               const u16*, int64_t, int, float, float*, bool,       \
                                                                const DevStatus*, int, int, int64_t, int, float*);
 WSSR_GEMM16_INST(128, 32, 1, 1)
 WSSR_GEMM16_INST(128, 32, 1, 2)

@@ -44,6 +44,7 @@ struct wssr_ctx {
   hipStream_t side = nullptr;    // second stream: the gradient pass runs beside the Rayleigh-Ritz SVD
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float* skpart = nullptr;       // stream-K partial tiles of the parameter-side product
+  unsigned short* s16 = nullptr; // BF16 forms: split planes of the skinny operand of a product
   int64_t skpart_elems = 0;
   std::vector<void*> allocs;
 
@@ -157,6 +158,15 @@ struct wssr_ctx {
   static int v16(int bn, int pa, int pb) { return (bn == 128 ? 0 : bn == 256 ? 1 : 2) * 3 + (pa == 2 ? 2 : pb - 1); }
   int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
 
+  // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
+  // when pb = 2), K-blocked; returns the plane stride in elements
+  int64_t split_skinny(const float* S, int64_t K, int r, int pb) {
+    const int64_t kblocks = cdiv(K, 16), ps = kblocks * 16 * r;
+    hipLaunchKernelGGL(k_split_skinny, dim3(cdiv(kblocks * r, 256)), dim3(256), 0, stream, S, K, r, s16, ps, pb,
+                       (const DevStatus*)st);
+    return ps;
+  }
+
   // Y = A V (FP64) from the split-K partials: fixed-order sum, then centre
   // the columns and scale (the implicit centring of O)
   void y_finish(int64_t n, int r, int s1) {
@@ -201,10 +211,12 @@ struct wssr_ctx {
       const int64_t ps = n * ld;
       const bool vec_o = (ld % 8 == 0) && ((uintptr_t)O % 16 == 0);
       const unsigned lds = (unsigned)gemm16_lds(bn, bk, pa, pb);
+      const int64_t vs = split_skinny(V, m, r, pb);
       timed(0, [&] {
 #define WSSR_S16(BN, BK, PA, PB)                                                                                     \
-  hipLaunchKernelGGL((k_gemm16_sample_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m, V, r,     \
-                     ypart, kchunk, vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd)
+  hipLaunchKernelGGL((k_gemm16_sample_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,          \
+                     (const unsigned short*)s16, vs, r, ypart, kchunk, vec_o, (const DevStatus*)st, (int)tn,          \
+                     (int)tj, xcd)
         switch (v16(bn, pa, pb)) {
           case 0: WSSR_S16(128, 32, 1, 1); break;
           case 1: WSSR_S16(128, 32, 1, 2); break;
@@ -244,6 +256,7 @@ struct wssr_ctx {
       }
     }
     const dim3 grid(full + skw);
+    const int64_t qs = b16 ? split_skinny(Q, n, r, pb) : 0;
     timed(1, [&] {
       if (!b16) {
         const float* O = static_cast<const float*>(Ov);
@@ -260,8 +273,9 @@ struct wssr_ctx {
         const bool vec_o = (ld % 8 == 0) && ((uintptr_t)O % 16 == 0);
         const unsigned lds = (unsigned)gemm16_lds(bn, bk, pa, pb);
 #define WSSR_P16(BN, BK, PA, PB)                                                                                     \
-  hipLaunchKernelGGL((k_gemm16_param_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m, Q, r,      \
-                     scale, Z, vec_o, vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart)
+  hipLaunchKernelGGL((k_gemm16_param_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,           \
+                     (const unsigned short*)s16, qs, r, scale, Z, vec_o, (const DevStatus*)st, (int)tj, full, units,  \
+                     skw, skpart)
         switch (v16(bn, pa, pb)) {
           case 0: WSSR_P16(128, 32, 1, 1); break;
           case 1: WSSR_P16(128, 32, 1, 2); break;
@@ -483,6 +497,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
   // when a parameter-side product can have more tiles than one round holds
   // (capacity for 2 slots per CU at 128 x 256 or 1 slot per CU at 128 x 512)
   const int64_t ptiles = cdiv(m, 128);
+  if (ok && cfg->o_dtype != WSSR_F32) ok = h->alloc(h->s16, (size_t)2 * cdiv(rows, 16) * 16 * r);
   if (ok && ptiles > h->slots / 2) {
     h->skpart_elems = (int64_t)h->slots * 2 * 128 * 256;
     ok = h->alloc(h->skpart, (size_t)h->skpart_elems);

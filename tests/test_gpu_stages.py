@@ -90,8 +90,10 @@ def test_param_side_many_tiles(ws_wide, n, m, r):
     assert row_err.max() < 1e-5
 
 
-@pytest.mark.parametrize("rows,r", [(100, 1), (333, 7), (1000, 64), (4000, 65), (4096, 130), (2500, 192)])
-def test_cholqr2(ws, rows, r):
+@pytest.mark.parametrize("rows,r", [(100, 1), (333, 7), (1000, 64), (4000, 65), (4096, 130), (2500, 192),
+                                    (3000, 512)])
+def test_cholqr2(ws, ws512, rows, r):
+    ws = ws512 if r > 192 else ws
     gen = torch.Generator(device="cuda").manual_seed(rows + r)
     x = torch.randn(rows, r, device="cuda", generator=gen)
     x = x * torch.logspace(0, -3, r, device="cuda")[None, :]        # condition number ~1e3
@@ -122,9 +124,20 @@ def test_cholqr_second_round(ws, rows, r):
     assert rel(q @ rr, x.double().cpu().numpy()) < 1e-6
 
 
-@pytest.mark.parametrize("r", [1, 2, 7, 33, 64, 100, 128, 192])
-@pytest.mark.parametrize("kind", ["random", "graded", "near_diag"])
-def test_small_svd(ws, r, kind):
+@pytest.fixture(scope="module")
+def ws512():
+    from paper_2512_05749_amd import Wssr
+    h = Wssr(n_max=1200, m_max=3000, r_max=512, q_max=4)
+    yield h
+    h.close()
+
+
+# r = 512 (the largest rank) only for the near-diagonal kind: the oracle's
+# Jacobi takes about half a minute per 512 x 512 matrix
+@pytest.mark.parametrize("r,kind", [(r, k) for r in [1, 2, 7, 33, 64, 100, 128, 192]
+                                    for k in ["random", "graded", "near_diag"]] + [(512, "near_diag")])
+def test_small_svd(ws, ws512, r, kind):
+    ws = ws512 if r > 192 else ws
     rng = np.random.default_rng(r)
     if kind == "random":
         c = rng.standard_normal((r, r))

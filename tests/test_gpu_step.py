@@ -79,6 +79,19 @@ def test_ragged_shapes(ws, n, m, r, q):
     _check_against_oracle(o, e, v_in, v, delta, sigma, 1e-3, q)
 
 
+def test_rank_512():
+    """The largest rank: 512 columns (8 Cholesky tiles, 16 Jacobi workgroups)."""
+    from paper_2512_05749_amd import Wssr
+    h = Wssr(n_max=1100, m_max=2600, r_max=512, q_max=4)
+    o, e, v = random_problem(1100, 2600, 512, seed=512, device="cuda", alpha=1.0)
+    v_in = v.clone()
+    delta, sigma = h.step(o, e, v, 1e-3, q=1)
+    code, diag = h.status()
+    h.close()
+    assert code == 0, diag
+    _check_against_oracle(o, e, v_in, v, delta, sigma, 1e-3, 1)
+
+
 def test_floor_preconditioner():
     from paper_2512_05749_amd import Wssr
     h = Wssr(n_max=600, m_max=1500, r_max=16, q_max=4, floor_precond=True)

@@ -28,6 +28,7 @@ from __future__ import annotations
 import dataclasses
 import math
 
+import numpy as np
 import torch
 
 
@@ -79,8 +80,25 @@ def _gen(device, seed, component, step=0):
     return g
 
 
+_BIG = 1 << 28   # elements above which the large-instance code paths are used
+
+
 def _orthonormal(x):
-    """Q factor with a positive diagonal of R (Haar-distributed for Gaussian x)."""
+    """Q factor with a positive diagonal of R (Haar-distributed for Gaussian x).
+    Tall matrices of more than 2^28 elements go through two rounds of
+    Cholesky QR in float64 (a Gaussian matrix that tall is well conditioned,
+    so this reaches the same unique Q as Householder QR, to rounding)."""
+    if x.numel() > _BIG:
+        # Gram on the device, its Cholesky factor and the inverse of that
+        # (k x k) on the host, then one plain product on the device
+        dt = x.dtype
+        y = x.double()
+        for _ in range(2):
+            gram = (y.T @ y).cpu().numpy()
+            low = np.linalg.cholesky(gram)
+            rinv = np.linalg.inv(low.T)
+            y = y @ torch.from_numpy(np.ascontiguousarray(rinv)).to(y.device)
+        return y.to(dt).contiguous()
     q, r = torch.linalg.qr(x)
     d = torch.sign(torch.diagonal(r))
     d[d == 0] = 1
@@ -121,17 +139,27 @@ class Workload:
         self.spectrum = torch.arange(1, k + 1, device=dev, dtype=gen_dtype) ** (-cfg.alpha)
 
     def o(self, t, dtype=torch.float32):
-        """O_t (N x M) in the storage dtype."""
+        """O_t (N x M) in the given dtype.  Instances of more than 2^28
+        elements are built in blocks of 1024 rows (noise drawn block by block
+        from the same generator), which bounds the temporaries."""
         cfg, dev = self.cfg, self.device
         ut = _rotate_pairs(self.u0, self.perm_n, t * cfg.theta)
         wt = _rotate_pairs(self.w0, self.perm_m, t * cfg.theta)
-        o = (math.sqrt(self.n) * ut * self.spectrum[None, :]) @ wt.T
-        del ut, wt
-        noise = torch.randn(self.n, self.m, generator=_gen(dev, cfg.seed, "noise", t),
-                            device=dev, dtype=self.gen_dtype)
-        o.add_(noise, alpha=cfg.eta)
-        del noise
-        return o.to(dtype).contiguous()
+        left = math.sqrt(self.n) * ut * self.spectrum[None, :]
+        del ut
+        gen = _gen(dev, cfg.seed, "noise", t)
+        if self.n * self.m <= _BIG:
+            o = left @ wt.T
+            noise = torch.randn(self.n, self.m, generator=gen, device=dev, dtype=self.gen_dtype)
+            o.add_(noise, alpha=cfg.eta)
+            return o.to(dtype).contiguous()
+        out = torch.empty(self.n, self.m, device=dev, dtype=dtype)
+        for i in range(0, self.n, 1024):
+            blk = left[i:i + 1024] @ wt.T
+            blk.add_(torch.randn(blk.shape, generator=gen, device=dev, dtype=self.gen_dtype), alpha=cfg.eta)
+            out[i:i + 1024] = blk.to(dtype)
+            del blk
+        return out
 
     def e_l(self, t):
         cfg = self.cfg
