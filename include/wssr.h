@@ -87,6 +87,10 @@ typedef enum {
 /* Flags (wssr_config.flags). */
 #define WSSR_FLOOR_PRECOND 0x1u  /* eq. updated_sr_1 weights w_j = 1 - lambda/sigma_j^2 instead of
                                     the damped w_j = sigma_j^2/(sigma_j^2 + lambda) */
+#define WSSR_GRAPH 0x2u          /* wssr_step_batched captures a batch into a HIP graph on its first
+                                    call and replays the graph while the same problem array (same
+                                    sizes and pointers) is passed again.  Currently disabled:
+                                    wssr_create returns WSSR_ERR_INVALID_ARG for this flag. */
 
 typedef struct {
   int64_t n_max;        /* largest N (samples) a step will be called with */
@@ -96,7 +100,22 @@ typedef struct {
   int32_t o_dtype;      /* wssr_dtype */
   uint32_t flags;
   void* stream;         /* hipStream_t */
+  int32_t lanes;        /* wssr_step_batched: problems run concurrently on this many lanes, each
+                           with its own stream and workspace (0 or 1: one after another on the
+                           handle's stream); 0 <= lanes <= 16 */
 } wssr_config;
+
+/* One problem of a batched step: the arguments of wssr_step. */
+typedef struct {
+  int64_t n, m, ld_o;
+  const void* O;
+  const double* e_l;
+  float* V;
+  double lambda;
+  int32_t r, q;
+  double* delta;
+  double* sigma;
+} wssr_problem;
 
 /* Create a handle on the current HIP device and allocate its workspace
  * (sized from n_max, m_max, r_max).  Returns WSSR_ERR_NO_DEVICE when no
@@ -127,6 +146,28 @@ wssr_status wssr_destroy(wssr_handle h);
 wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o,
                       const double* e_l, float* V, double lambda, int32_t r, int32_t q,
                       double* delta, double* sigma);
+
+/* Batched form: `count` independent steps (1 <= count <= 1024), each with its
+ * own sizes, lambda, r and q within the handle's capacities, in the handle's
+ * dtype.  The problems are spread over the handle's lanes (longest first onto
+ * the least-loaded lane; cost ~ n m r q), each lane running its share one
+ * after another on its own stream; the lanes fork from and join back into the
+ * handle's stream, so the batch is ordered on that stream as one unit.  With
+ * WSSR_GRAPH the whole batch is one graph launch after the first call.
+ * Per-problem results are those of wssr_step on the same inputs (bit for bit:
+ * the same kernels in the same configuration).  Argument errors of any
+ * problem are reported before anything is enqueued.  Numerical status: one
+ * code per problem, read with wssr_batched_status. */
+wssr_status wssr_step_batched(wssr_handle h, const wssr_problem* probs, int32_t count);
+
+/* Synchronise the handle's stream and copy the status codes of the problems
+ * of the last batch (codes[0..count)). */
+wssr_status wssr_batched_status(wssr_handle h, int32_t count, int32_t* codes);
+
+/* *active = 1 when the last batch ran as a replayed or fresh graph.  When a
+ * capture has failed, the handle runs its batches as direct launches from
+ * then on, and wssr_last_error gives the reason after this call. */
+wssr_status wssr_graph_active(wssr_handle h, int32_t* active);
 
 /* Synchronise the handle's stream and read the numerical status of the last
  * step (a wssr_status value) into *numeric_status.  If diag is non-NULL it

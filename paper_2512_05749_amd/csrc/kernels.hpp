@@ -5,6 +5,7 @@
 namespace wssr {
 
 __global__ void k_raise(DevStatus* st, int code);
+__global__ void k_status_save(const DevStatus* st, int* out);
 __global__ void k_status_init(DevStatus* st);
 __global__ void k_center_energies(const double* e_l, int64_t n, double* eps, DevStatus* st);
 __global__ void k_gradient_partial(const float* O, int64_t ld, int64_t n, int64_t m, const double* eps,

@@ -13,6 +13,9 @@ namespace wssr {
 // Fail the running step from the host side (a launch that could not be made).
 __global__ void k_raise(DevStatus* st, int code) { raise_error(st, code); }
 
+// Keep a finished step's status code (batched steps: one slot per problem).
+__global__ void k_status_save(const DevStatus* st, int* out) { *out = st->code; }
+
 __global__ __launch_bounds__(1024) void k_center_energies(const double* __restrict__ e_l, int64_t n,
                                                           double* __restrict__ eps, DevStatus* st) {
   __shared__ double red[1024];

@@ -25,6 +25,8 @@ constexpr int kJacobiSweeps = 30;
 constexpr int kJacobiInner = 1;     // inner sweeps per block step
 constexpr double kJacobiTol = 1e-8;
 constexpr double kKappaRound2 = 1e4;
+constexpr int kBatchMax = 1024;     // problems per batched step
+constexpr int kLanesMax = 16;       // concurrent batch lanes
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -40,6 +42,17 @@ struct wssr_ctx {
   int64_t rows_max = 0;
   int slots = 512;               // resident product workgroups: 2 per compute unit
   unsigned* jsync = nullptr;     // grid-barrier words of the Rayleigh-Ritz sweep kernel
+  bool own_stream = false;       // a batch lane: the stream was created with the context
+  bool capturing = false;        // enqueueing into a graph capture (no cooperative launch, no profiling)
+  std::vector<wssr_ctx*> lanes;  // batch lanes (children with their own stream and workspace)
+  std::vector<hipEvent_t> lane_done;
+  int* bstat = nullptr;          // per-problem status codes of the last batch
+  std::vector<wssr_problem> gkey;  // the batch the cached graph was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_broken = false;
+  hipStream_t cstream = nullptr;   // capture origin (the caller's stream may be the null stream)
+  std::string graph_why;
   hipError_t coop_err = hipSuccess;
   hipStream_t side = nullptr;    // second stream: the gradient pass runs beside the Rayleigh-Ritz SVD
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -78,7 +91,7 @@ struct wssr_ctx {
   // record events around `launch` when profiling is on
   template <typename F>
   void timed(int slot, F&& launch) {
-    if (!prof) {
+    if (!prof || capturing) {
       launch();
       return;
     }
@@ -100,6 +113,27 @@ struct wssr_ctx {
   }
 
   void release() {
+    for (wssr_ctx* c : lanes) {
+      c->release();
+      delete c;
+    }
+    lanes.clear();
+    for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
+    lane_done.clear();
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    if (cstream) {
+      (void)hipStreamSynchronize(cstream);
+      (void)hipStreamDestroy(cstream);
+      cstream = nullptr;
+    }
+    if (own_stream && stream) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipStreamDestroy(stream);
+      stream = nullptr;
+    }
     if (side) {
       (void)hipStreamSynchronize(side);
       (void)hipStreamDestroy(side);
@@ -125,6 +159,69 @@ struct wssr_ctx {
 
   // ---------------------------------------------------------------- kernels
   hipError_t last() { return hipGetLastError(); }
+
+  // Enqueue one step on this context's stream (arguments already checked).
+  wssr_status enqueue(int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, float* V,
+                      double lambda, int32_t r, int32_t q, double* delta, double* sigma) {
+    wssr_ctx* h = this;
+    const int rp = (int)rup(r, 64);
+    const DevStatus* cst = h->st;
+    hipStream_t stream = h->stream;
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
+
+    const float* vcur = V;
+    for (int p = 1; p <= q; ++p) {
+      // sample side: Y = A V (FP64), then its QR: Q_Y = Y Tq (float)
+      h->gemm_sample_side(O, ld_o, n, m, vcur, r);
+      h->cholqr<double, double>(h->y64, n, r, h->yq1, nullptr);
+      h->apply((const double*)h->y64, n, r, r, h->Tq, rp, r, h->qy, r, true);
+      // parameter side: Z = A^T Q_Y, then its QR: Q_Z = Z Tq, R_Z
+      h->gemm_param_side(O, ld_o, n, m, h->qy, r, h->z);
+      h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
+      if (p < q) {
+        h->apply((const float*)h->z, m, r, r, h->Tq, rp, r, h->vw, r, true);
+        vcur = h->vw;
+      } else {
+        // the gradient (one HBM-bound pass over O) runs on the second stream
+        // while this stream works through the few-workgroup Jacobi launches
+        (void)hipEventRecord(h->ev_fork, stream);
+        (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+        h->gradient(O, ld_o, n, m, e_l, h->g, h->side, true);
+        (void)hipEventRecord(h->ev_join, h->side);
+        // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T;  C = G diag(sigma) P^T
+        h->small_svd(h->Rz, r);
+        // V = Q_Z P = Z (Tq P)
+        h->smallgemm(h->Tq, h->Ps, rp, h->T, false, false);
+        h->apply((const float*)h->z, m, r, r, h->T, rp, r, h->vw, r, false);
+      }
+    }
+    (void)hipStreamWaitEvent(stream, h->ev_join, 0);
+    if (h->coop_err != hipSuccess)
+      return h->fail(WSSR_ERR_HIP, "cooperative launch of the SVD kernel failed: %s", hipGetErrorString(h->coop_err));
+    // output signs, then V <- signed vw
+    {
+      // row chunks: as many as the partial buffers hold (enough blocks to cover
+      // every compute unit several times), at least 64 rows each
+      const int64_t rpc = std::max<int64_t>(64, cdiv(m, kVecChunkMax));
+      const int nch = (int)cdiv(m, rpc);
+      hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->vw,
+                         (const float*)V, m, r, rpc, h->dots, h->maxval, h->maxrow, cst);
+      hipLaunchKernelGGL(k_sign_final, dim3(r), dim3(256), 0, stream, (const double*)h->dots, (const float*)h->maxval,
+                         (const int64_t*)h->maxrow, nch, r, h->sgn, cst);
+      const int64_t tot = m * r;
+      hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)h->vw,
+                         (const float*)h->sgn, tot, r, V, cst);
+      // Woodbury
+      hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
+                         (const double*)h->g, m, r, rpc, h->vpart, cst);
+      hipLaunchKernelGGL(k_vtg_final, dim3(r), dim3(256), 0, stream, (const double*)h->vpart, nch, r,
+                         (const double*)h->sig, lambda, (h->cfg.flags & WSSR_FLOOR_PRECOND) ? 1 : 0, h->cw, sigma, cst);
+      hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, (const double*)h->g,
+                         (const double*)h->cw, m, r, 1.0 / lambda, delta, cst);
+    }
+    if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+    return WSSR_OK;
+  }
 
   // dynamic-LDS limits and occupancy (resident workgroups on the whole
   // device) of the BF16 product variants
@@ -404,8 +501,16 @@ struct wssr_ctx {
     DevStatus* stp = st;
     int sweeps = kJacobiSweeps, inner = kJacobiInner;
     void* args[] = {&Bc, &Pc, &rp, &tol, &scal_c, &cosb, &sy, &stp, &sweeps, &inner};
-    coop_err = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(rp / 32), dim3(256), args,
-                                          (unsigned)jacobi_lds(rp), stream);
+    if (capturing) {
+      // a graph node: a plain launch (the grid is at most 16 workgroups and
+      // its barrier waits are bounded, so it does not rely on the guarantee)
+      hipLaunchKernelGGL(k_jacobi_coop, dim3(rp / 32), dim3(256), jacobi_lds(rp), stream, Bc, Pc, rp, tol, scal_c,
+                         cosb, sy, stp, sweeps, inner);
+      coop_err = hipGetLastError();
+    } else {
+      coop_err = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(rp / 32), dim3(256), args,
+                                            (unsigned)jacobi_lds(rp), stream);
+    }
     if (coop_err != hipSuccess) {
       // nothing was rotated: fail the step on the device so that no later
       // kernel writes an output
@@ -451,27 +556,31 @@ extern "C" {
 
 const char* wssr_version(void) { return "libwssr 0.1 gfx950"; }
 
-wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
-  if (!out) return WSSR_ERR_INVALID_ARG;
-  *out = nullptr;
-  if (!cfg || cfg->n_max < 2 || cfg->m_max < 1 || cfg->r_max < 1 || cfg->r_max > 512 || cfg->q_max < 1 ||
-      cfg->o_dtype < WSSR_F32 || cfg->o_dtype > WSSR_BF16_SPLIT) {
-    g_create_error = "invalid config";
-    return WSSR_ERR_INVALID_ARG;
-  }
-  int dev = -1;
-  std::string why;
-  if (!device_ok(&dev, why)) {
-    g_create_error = why;
-    return WSSR_ERR_NO_DEVICE;
-  }
+}  // extern "C"
+
+namespace {
+
+// One context: workspace sized from the config, the second stream, events.
+// stream == nullptr with own = true: the context creates its own stream (a
+// batch lane).
+wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool own, wssr_ctx** out,
+                      std::string& why) {
   auto* h = new wssr_ctx();
   h->device = dev;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
     h->slots = 2 * cus;
   h->cfg = *cfg;
-  h->stream = static_cast<hipStream_t>(cfg->stream);
+  h->stream = stream;
+  if (own) {
+    h->own_stream = true;
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      h->stream = nullptr;
+      delete h;
+      why = "stream creation failed";
+      return WSSR_ERR_HIP;
+    }
+  }
   const int64_t n = cfg->n_max, m = cfg->m_max;
   const int r = cfg->r_max;
   const int rp = (int)rup(r, 64), nt = rp / 64, npairs = nt * (nt + 1) / 2;
@@ -492,7 +601,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
             h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
             h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp) &&
-            h->alloc(h->jsync, 4);
+            h->alloc(h->jsync, 4) && h->alloc(h->bstat, kBatchMax);
   // stream-K partials (two 128 x 256 tiles per workgroup of one round), only
   // when a parameter-side product can have more tiles than one round holds
   // (capacity for 2 slots per CU at 128 x 256 or 1 slot per CU at 128 x 512)
@@ -506,7 +615,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
     (void)hipGetLastError();
     h->release();
     delete h;
-    g_create_error = "workspace allocation failed";
+    why = "workspace allocation failed";
     return WSSR_ERR_OOM;
   }
   if (hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholLds) !=
@@ -515,13 +624,13 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
                           (int)jacobi_lds(rp)) != hipSuccess) {
     h->release();
     delete h;
-    g_create_error = "hipFuncSetAttribute failed";
+    why = "hipFuncSetAttribute failed";
     return WSSR_ERR_HIP;
   }
   if (!h->setup16()) {
     h->release();
     delete h;
-    g_create_error = "BF16 kernel set-up failed";
+    why = "BF16 kernel set-up failed";
     return WSSR_ERR_HIP;
   }
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
@@ -529,15 +638,68 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
     h->release();
     delete h;
-    g_create_error = "stream or event creation failed";
+    why = "stream or event creation failed";
     return WSSR_ERR_HIP;
   }
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
   if (hipGetLastError() != hipSuccess) {
     h->release();
     delete h;
-    g_create_error = "kernel launch failed";
+    why = "kernel launch failed";
     return WSSR_ERR_HIP;
+  }
+  *out = h;
+  return WSSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
+  if (!out) return WSSR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!cfg || cfg->n_max < 2 || cfg->m_max < 1 || cfg->r_max < 1 || cfg->r_max > 512 || cfg->q_max < 1 ||
+      cfg->o_dtype < WSSR_F32 || cfg->o_dtype > WSSR_BF16_SPLIT || cfg->lanes < 0 || cfg->lanes > kLanesMax) {
+    g_create_error = "invalid config";
+    return WSSR_ERR_INVALID_ARG;
+  }
+  if (cfg->flags & WSSR_GRAPH) {
+    // switched off: the first device run of a captured batch ended in a host
+    // segmentation fault whose cause is not found yet
+    g_create_error = "WSSR_GRAPH is disabled in this build (graph capture of the batched step is switched off)";
+    return WSSR_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  std::string why;
+  if (!device_ok(&dev, why)) {
+    g_create_error = why;
+    return WSSR_ERR_NO_DEVICE;
+  }
+  wssr_ctx* h = nullptr;
+  wssr_status s = build_ctx(cfg, dev, static_cast<hipStream_t>(cfg->stream), false, &h, why);
+  if (s != WSSR_OK) {
+    g_create_error = why;
+    return s;
+  }
+  for (int i = 0; i < cfg->lanes; ++i) {
+    wssr_ctx* c = nullptr;
+    hipEvent_t e = nullptr;
+    s = build_ctx(cfg, dev, nullptr, true, &c, why);
+    if (s == WSSR_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      c->release();
+      delete c;
+      s = WSSR_ERR_HIP;
+      why = "event creation failed";
+    }
+    if (s != WSSR_OK) {
+      h->release();
+      delete h;
+      g_create_error = why;
+      return s;
+    }
+    h->lanes.push_back(c);
+    h->lane_done.push_back(e);
   }
   *out = h;
   return WSSR_OK;
@@ -565,73 +727,148 @@ static wssr_status check_common(wssr_handle h, int64_t n, int64_t m, const void*
   return WSSR_OK;
 }
 
-wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, float* V,
-                      double lambda, int32_t r, int32_t q, double* delta, double* sigma) {
-  if (!h) return WSSR_ERR_INVALID_ARG;
+static wssr_status check_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o,
+                              const double* e_l, const float* V, double lambda, int32_t r, int32_t q,
+                              const double* delta, const double* sigma) {
   wssr_status s = check_common(h, n, m, O, ld_o, r);
   if (s != WSSR_OK) return s;
   if (!e_l || !V || !delta || !sigma) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
   if (r > std::min<int64_t>(n - 1, m)) return h->fail(WSSR_ERR_INVALID_ARG, "r=%d exceeds min(n-1, m)", r);
   if (q < 1 || q > h->cfg.q_max) return h->fail(WSSR_ERR_INVALID_ARG, "q=%d outside [1, q_max]", q);
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return h->fail(WSSR_ERR_INVALID_ARG, "lambda must be > 0 and finite");
+  return WSSR_OK;
+}
+
+wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, float* V,
+                      double lambda, int32_t r, int32_t q, double* delta, double* sigma) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  wssr_status s = check_step(h, n, m, O, ld_o, e_l, V, lambda, r, q, delta, sigma);
+  if (s != WSSR_OK) return s;
   if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
 
-  const int rp = (int)rup(r, 64);
-  const DevStatus* cst = h->st;
-  hipStream_t stream = h->stream;
-  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
+  return h->enqueue(n, m, O, ld_o, e_l, V, lambda, r, q, delta, sigma);
+}
 
-  const float* vcur = V;
-  for (int p = 1; p <= q; ++p) {
-    // sample side: Y = A V (FP64), then its QR: Q_Y = Y Tq (float)
-    h->gemm_sample_side(O, ld_o, n, m, vcur, r);
-    h->cholqr<double, double>(h->y64, n, r, h->yq1, nullptr);
-    h->apply((const double*)h->y64, n, r, r, h->Tq, rp, r, h->qy, r, true);
-    // parameter side: Z = A^T Q_Y, then its QR: Q_Z = Z Tq, R_Z
-    h->gemm_param_side(O, ld_o, n, m, h->qy, r, h->z);
-    h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
-    if (p < q) {
-      h->apply((const float*)h->z, m, r, r, h->Tq, rp, r, h->vw, r, true);
-      vcur = h->vw;
-    } else {
-      // the gradient (one HBM-bound pass over O) runs on the second stream
-      // while this stream works through the few-workgroup Jacobi launches
-      (void)hipEventRecord(h->ev_fork, stream);
-      (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
-      h->gradient(O, ld_o, n, m, e_l, h->g, h->side, true);
-      (void)hipEventRecord(h->ev_join, h->side);
-      // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T;  C = G diag(sigma) P^T
-      h->small_svd(h->Rz, r);
-      // V = Q_Z P = Z (Tq P)
-      h->smallgemm(h->Tq, h->Ps, rp, h->T, false, false);
-      h->apply((const float*)h->z, m, r, r, h->T, rp, r, h->vw, r, false);
+namespace {
+bool same_batch(const std::vector<wssr_problem>& a, const wssr_problem* b, int32_t count) {
+  return (int32_t)a.size() == count && std::memcmp(a.data(), b, sizeof(wssr_problem) * (size_t)count) == 0;
+}
+}  // namespace
+
+// Enqueue a batch: problems spread over the lanes (longest first onto the
+// least-loaded lane, cost ~ n m r q), each lane running its problems one
+// after another on its own stream, forked from and joined back into the
+// handle's stream; per-problem status codes are saved to bstat.
+static wssr_status enqueue_batch(wssr_ctx* h, const wssr_problem* p, int32_t count) {
+  const int nl = std::max<int>(1, (int)h->lanes.size());
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto cost = [&](int i) { return (double)p[i].n * (double)p[i].m * (double)p[i].r * (double)p[i].q; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<std::vector<int>> plan(nl);
+  std::vector<double> load(nl, 0.0);
+  for (int i : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    plan[l].push_back(i);
+    load[l] += cost(i);
+  }
+  if (h->lanes.empty()) {
+    for (int i : plan[0]) {
+      wssr_status s = h->enqueue(p[i].n, p[i].m, p[i].O, p[i].ld_o, p[i].e_l, p[i].V, p[i].lambda, p[i].r, p[i].q,
+                                 p[i].delta, p[i].sigma);
+      if (s != WSSR_OK) return s;
+      hipLaunchKernelGGL(k_status_save, dim3(1), dim3(1), 0, h->stream, (const DevStatus*)h->st, h->bstat + i);
     }
+    return hipGetLastError() == hipSuccess ? WSSR_OK : h->fail(WSSR_ERR_HIP, "kernel launch failed");
   }
-  (void)hipStreamWaitEvent(stream, h->ev_join, 0);
-  if (h->coop_err != hipSuccess)
-    return h->fail(WSSR_ERR_HIP, "cooperative launch of the SVD kernel failed: %s", hipGetErrorString(h->coop_err));
-  // output signs, then V <- signed vw
-  {
-    // row chunks: as many as the partial buffers hold (enough blocks to cover
-    // every compute unit several times), at least 64 rows each
-    const int64_t rpc = std::max<int64_t>(64, cdiv(m, kVecChunkMax));
-    const int nch = (int)cdiv(m, rpc);
-    hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->vw,
-                       (const float*)V, m, r, rpc, h->dots, h->maxval, h->maxrow, cst);
-    hipLaunchKernelGGL(k_sign_final, dim3(r), dim3(256), 0, stream, (const double*)h->dots, (const float*)h->maxval,
-                       (const int64_t*)h->maxrow, nch, r, h->sgn, cst);
-    const int64_t tot = m * r;
-    hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)h->vw,
-                       (const float*)h->sgn, tot, r, V, cst);
-    // Woodbury
-    hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
-                       (const double*)h->g, m, r, rpc, h->vpart, cst);
-    hipLaunchKernelGGL(k_vtg_final, dim3(r), dim3(256), 0, stream, (const double*)h->vpart, nch, r,
-                       (const double*)h->sig, lambda, (h->cfg.flags & WSSR_FLOOR_PRECOND) ? 1 : 0, h->cw, sigma, cst);
-    hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, (const double*)h->g,
-                       (const double*)h->cw, m, r, 1.0 / lambda, delta, cst);
+  (void)hipEventRecord(h->ev_fork, h->stream);
+  for (int l = 0; l < nl; ++l) {
+    wssr_ctx* c = h->lanes[l];
+    c->capturing = h->capturing;
+    (void)hipStreamWaitEvent(c->stream, h->ev_fork, 0);
+    for (int i : plan[l]) {
+      wssr_status s = c->enqueue(p[i].n, p[i].m, p[i].O, p[i].ld_o, p[i].e_l, p[i].V, p[i].lambda, p[i].r, p[i].q,
+                                 p[i].delta, p[i].sigma);
+      if (s != WSSR_OK) return h->fail(s, "batch lane %d: %s", l, c->err.c_str());
+      hipLaunchKernelGGL(k_status_save, dim3(1), dim3(1), 0, c->stream, (const DevStatus*)c->st, h->bstat + i);
+    }
+    (void)hipEventRecord(h->lane_done[l], c->stream);
+    (void)hipStreamWaitEvent(h->stream, h->lane_done[l], 0);
   }
-  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return hipGetLastError() == hipSuccess ? WSSR_OK : h->fail(WSSR_ERR_HIP, "kernel launch failed");
+}
+
+wssr_status wssr_step_batched(wssr_handle h, const wssr_problem* probs, int32_t count) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!probs || count < 1 || count > kBatchMax)
+    return h->fail(WSSR_ERR_INVALID_ARG, "count=%d outside [1, %d]", count, kBatchMax);
+  for (int i = 0; i < count; ++i) {
+    const wssr_problem& q = probs[i];
+    wssr_status s = check_step(h, q.n, q.m, q.O, q.ld_o, q.e_l, q.V, q.lambda, q.r, q.q, q.delta, q.sigma);
+    if (s != WSSR_OK) return h->fail(s, "problem %d: %s", i, h->err.c_str());
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+  if (!(h->cfg.flags & WSSR_GRAPH) || h->graph_broken) return enqueue_batch(h, probs, count);
+  if (!h->gexec || !same_batch(h->gkey, probs, count)) {
+    // capture the batch once; replay it while the same problems are passed
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+    h->gkey.clear();
+    (void)hipGetLastError();
+    if (!h->cstream && hipStreamCreateWithFlags(&h->cstream, hipStreamNonBlocking) != hipSuccess) {
+      h->cstream = nullptr;
+      h->graph_broken = true;
+      h->graph_why = "capture stream creation failed";
+      return enqueue_batch(h, probs, count);
+    }
+    // capture on the private stream: the batch's fork/join hangs off it
+    hipStream_t user = h->stream;
+    h->stream = h->cstream;
+    hipError_t e = hipStreamBeginCapture(h->cstream, hipStreamCaptureModeRelaxed);
+    bool ok = e == hipSuccess;
+    h->capturing = true;
+    wssr_status s = ok ? enqueue_batch(h, probs, count) : WSSR_ERR_HIP;
+    h->capturing = false;
+    for (wssr_ctx* c : h->lanes) c->capturing = false;
+    hipGraph_t g = nullptr;
+    if (ok) {
+      e = hipStreamEndCapture(h->cstream, &g);
+      ok = e == hipSuccess && g != nullptr && s == WSSR_OK;
+    }
+    if (ok) {
+      e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+      ok = e == hipSuccess;
+    }
+    h->stream = user;
+    if (!ok) {
+      if (g) (void)hipGraphDestroy(g);
+      h->gexec = nullptr;
+      (void)hipGetLastError();
+      h->graph_broken = true;   // this handle runs batches without a graph from now on
+      h->graph_why = std::string("graph capture failed: ") + hipGetErrorString(e) + (s != WSSR_OK ? " (enqueue)" : "");
+      return enqueue_batch(h, probs, count);
+    }
+    h->graph = g;
+    h->gkey.assign(probs, probs + count);
+  }
+  if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipGraphLaunch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_batched_status(wssr_handle h, int32_t count, int32_t* codes) {
+  if (!h || !codes || count < 1 || count > kBatchMax) return WSSR_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipStreamSynchronize failed");
+  if (hipMemcpy(codes, h->bstat, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost) != hipSuccess)
+    return h->fail(WSSR_ERR_HIP, "status copy failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_graph_active(wssr_handle h, int32_t* active) {
+  if (!h || !active) return WSSR_ERR_INVALID_ARG;
+  *active = (h->gexec != nullptr && !h->graph_broken) ? 1 : 0;
+  if (!*active && !h->graph_why.empty()) h->err = h->graph_why;
   return WSSR_OK;
 }
 

@@ -33,6 +33,7 @@ BF16X2 = 2
 BF16_SPLIT = 3
 DTYPES = {"f32": F32, "bf16": BF16, "bf16x2": BF16X2, "bf16_split": BF16_SPLIT}
 FLOOR_PRECOND = 0x1
+GRAPH = 0x2
 
 
 class WssrError(RuntimeError):
@@ -44,7 +45,13 @@ class WssrError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("n_max", ctypes.c_int64), ("m_max", ctypes.c_int64), ("r_max", ctypes.c_int32),
                 ("q_max", ctypes.c_int32), ("o_dtype", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("lanes", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("ld_o", ctypes.c_int64), ("O", ctypes.c_void_p),
+                ("e_l", ctypes.c_void_p), ("V", ctypes.c_void_p), ("lam", ctypes.c_double), ("r", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("delta", ctypes.c_void_p), ("sigma", ctypes.c_void_p)]
 
 
 _lib = None
@@ -58,6 +65,9 @@ _SIGS = {
     "wssr_destroy": ([_P], ctypes.c_int),
     "wssr_step": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
     "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
+    "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
+    "wssr_batched_status": ([_P, _I32, ctypes.POINTER(_I32)], ctypes.c_int),
+    "wssr_graph_active": ([_P, ctypes.POINTER(_I32)], ctypes.c_int),
     "wssr_last_error": ([_P], ctypes.c_char_p),
     "wssr_version": ([], ctypes.c_char_p),
     "wssr_profile": ([_P, _I32], ctypes.c_int),
@@ -107,10 +117,13 @@ def _need(t, name, dtype, device, shape=None):
 class Wssr:
     """One libwssr handle bound to a device and a stream."""
 
-    def __init__(self, n_max, m_max, r_max, q_max=8, floor_precond=False, device=None, stream=None, dtype="f32"):
+    def __init__(self, n_max, m_max, r_max, q_max=8, floor_precond=False, device=None, stream=None, dtype="f32",
+                 lanes=0, graph=False):
         """dtype: storage and product precision of O -- "f32"; "bf16" (one BF16
         product); "bf16_split" (BF16 O, skinny operand split in two); "bf16x2"
-        (O as BF16 hi and lo planes, shape (2, n, m), three products)."""
+        (O as BF16 hi and lo planes, shape (2, n, m), three products).
+        lanes, graph: the batched form (step_batched) -- problems run on this
+        many concurrent lanes; graph captures a batch once and replays it."""
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
         self.dtype = dtype
@@ -121,8 +134,9 @@ class Wssr:
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
-        cfg = Config(int(n_max), int(m_max), int(r_max), int(q_max), DTYPES[dtype],
-                     FLOOR_PRECOND if floor_precond else 0, ctypes.c_void_p(s.cuda_stream))
+        flags = (FLOOR_PRECOND if floor_precond else 0) | (GRAPH if graph else 0)
+        cfg = Config(int(n_max), int(m_max), int(r_max), int(q_max), DTYPES[dtype], flags,
+                     ctypes.c_void_p(s.cuda_stream), int(lanes))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             code = lib().wssr_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -180,6 +194,48 @@ class Wssr:
         self._check(lib().wssr_step(self._h, n, m, _ptr(O), ld, _ptr(e_l), _ptr(V), float(lam), r, int(q),
                                     _ptr(delta), _ptr(sigma)))
         return delta, sigma
+
+    def step_batched(self, problems):
+        """One batched step.  problems: list of dicts with keys O, e_l, V, lam and
+        optional q (default 2), delta, sigma.  Each V is updated in place;
+        returns [(delta, sigma), ...].  The argument array is kept with the
+        handle (a graph replays only while the same array contents recur)."""
+        arr = (Problem * len(problems))()
+        outs, keep = [], []
+        for i, pb in enumerate(problems):
+            O, e_l, V = pb["O"], pb["e_l"], pb["V"]
+            n, m, ld = self._o(O)
+            if V.dim() != 2 or not V.is_contiguous():
+                raise ValueError("V must be a contiguous m x r tensor")
+            r = V.shape[1]
+            _need(V, "V", torch.float32, self.device, (m, r))
+            _need(e_l, "e_l", torch.float64, self.device, (n,))
+            delta = pb.get("delta")
+            sigma = pb.get("sigma")
+            if delta is None:
+                delta = torch.empty(m, dtype=torch.float64, device=self.device)
+            if sigma is None:
+                sigma = torch.empty(r, dtype=torch.float64, device=self.device)
+            _need(delta, "delta", torch.float64, self.device, (m,))
+            _need(sigma, "sigma", torch.float64, self.device, (r,))
+            arr[i] = Problem(n, m, ld, O.data_ptr(), e_l.contiguous().data_ptr(), V.data_ptr(), float(pb["lam"]),
+                             r, int(pb.get("q", 2)), delta.data_ptr(), sigma.data_ptr())
+            outs.append((delta, sigma))
+            keep.append(e_l)
+        self._check(lib().wssr_step_batched(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems)))
+        self._last_batch = (arr, keep)
+        return outs
+
+    def batched_status(self, count):
+        """Synchronise and return the status code of each problem of the last batch."""
+        codes = (ctypes.c_int32 * count)()
+        self._check(lib().wssr_batched_status(self._h, count, codes))
+        return list(codes)
+
+    def graph_active(self):
+        a = ctypes.c_int32()
+        self._check(lib().wssr_graph_active(self._h, ctypes.byref(a)))
+        return bool(a.value)
 
     def status(self):
         """Synchronise and return (numeric status code, diagnostics dict)."""
