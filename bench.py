@@ -10,6 +10,8 @@ both sides), Rayleigh-Ritz, signs and the Woodbury apply.
 --form bf16 | bf16_split | bf16x2 times a BF16 precision form instead
 (--config bf16_n16384_m1m_r512 for the precision-form instance), and
 --compare-f32 1 times the FP32 form on the same instance beside it.
+--config batch16_mixed times the batched form (16 uneven problems per
+wssr_step_batched call) beside the same problems run one after another.
 
 Prints one JSON line.  `--gpus` above 1 is not supported (single-GPU build).
 """
@@ -56,11 +58,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="f32_n8192_m100k_r256", help="workload name (workloads.CONFIGS)")
+    ap.add_argument("--config", default="f32_n8192_m100k_r256",
+                    help="workload name (workloads.CONFIGS), or batch16_mixed for the batched form")
     ap.add_argument("--ring", type=int, default=0,
                     help="distinct O_t held in HBM and cycled (0: 4, or 1 above 2^30 elements)")
     ap.add_argument("--form", default="f32", choices=["f32", "bf16", "bf16_split", "bf16x2"],
                     help="storage and product precision of O")
+    ap.add_argument("--lanes", type=int, default=4, help="batched workload: concurrent lanes of the handle")
     ap.add_argument("--compare-f32", type=int, default=0,
                     help="also time the FP32 form on the same instance and report the ratio")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -162,11 +166,111 @@ def roofline_of(form, prof, cfg):
                       for k, v_ in kern.items() if k != dom}}
 
 
+def run_batched(args):
+    """The batched form: 16 uneven problems (workloads.batch_configs) in one
+    wssr_step_batched call per step, lanes picked by the autotuner; beside it,
+    the same problems one after another on a single stream."""
+    import numpy as np
+    import torch
+
+    from paper_2512_05749_amd import Wssr
+    from workloads import Workload, batch_configs
+
+    cfgs = batch_configs()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    probs = []
+    for c in cfgs:
+        wl = Workload(c, device=dev, gen_dtype=torch.float32)
+        probs.append(dict(O=wl.o(1), e_l=wl.e_l(1), V=wl.v0(), lam=c.lam, q=8))
+        del wl
+        torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    count = len(probs)
+    log(f"generated {count} problems ({sum(c.n * c.m for c in cfgs) * 4 / 1e9:.1f} GB of O) in "
+        f"{time.time() - t0:.1f}s")
+    nmax, mmax, rmax = max(c.n for c in cfgs), max(c.m for c in cfgs), max(c.r for c in cfgs)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed_batches(h, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(k):
+            h.step_batched(probs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        codes = h.batched_status(count)
+        if any(c < 0 for c in codes):
+            raise SystemExit(f"batched step failed: {codes}")
+        return (time.perf_counter() - w0) * 1e3 / k, e0.elapsed_time(e1) / k
+
+    h = Wssr(n_max=nmax, m_max=mmax, r_max=rmax, q_max=8, device=dev, lanes=args.lanes)
+    c0 = time.perf_counter()
+    h.step_batched(probs)                    # step 1: cold start, 8 passes
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - c0) * 1e3
+    log(f"cold batched step (q=8): {cold_ms:.1f} ms, status {h.batched_status(count)}")
+    for p in probs:
+        p["q"] = 2
+    tl, td, tms = h.tune_batched(probs, reps=1)
+    log(f"autotuner: {tl} lanes, split sized for slots/{td}, {tms:.1f} ms per batch")
+    for _ in range(args.warmup):
+        h.step_batched(probs)
+    ms_wall, ms_ev = timed_batches(h, args.steps)
+    log(f"batched: {ms_wall:.2f} ms per batched step (wall), {ms_ev:.2f} ms (events)")
+    h.close()
+    hs = Wssr(n_max=nmax, m_max=mmax, r_max=rmax, q_max=8, device=dev, lanes=0)
+    hs.step_batched(probs)
+    seq_wall, seq_ev = timed_batches(hs, args.steps)
+    hs.close()
+    log(f"one after another: {seq_wall:.2f} ms per batched step")
+    flops = sum(4.0 * c.q * c.n * c.m * c.r for c in cfgs)      # the products of one batched step
+    achieved = flops / (ms_wall * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(count * 1e3 / ms_wall, 3),
+        "unit": "SR steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_wall, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch16_mixed: {count} independent FP32 WSSR problems per batched step, "
+                               f"N in {{2048..16384}}, M in [2e4, 4e5], r in {{64, 128, 256}}, q=2, "
+                               f"lambda log-uniform [1e-4, 1e-2]",
+                   "problems": [dict(n=c.n, m=c.m, r=c.r, lam=round(c.lam, 6), a=round(c.alpha, 3)) for c in cfgs],
+                   "lanes": args.lanes},
+        "value_note": "problem steps per second (problems x batched steps / s); ms_per_step is per batched step",
+        "cold_step_ms": round(cold_ms, 3),
+        "autotuner": {"lanes": tl, "split_divisor": td, "ms": round(tms, 3)},
+        "one_after_another": {"ms_per_step": round(seq_wall, 4), "value": round(count * 1e3 / seq_wall, 3)},
+        "vs_one_after_another": round(seq_wall / ms_wall, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "all product kernels of the batch over the whole batched step",
+                     "flops_per_launch": flops},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.config == "batch16_mixed":
+        # the lanes and their second streams need their own hardware queues to
+        # run side by side (HIP maps streams onto this many queues; set before
+        # the runtime starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, 2 * args.lanes + 2)))
+        return run_batched(args)
     import torch
 
     from workloads import CONFIGS, Workload, to_storage

@@ -164,6 +164,18 @@ wssr_status wssr_step_batched(wssr_handle h, const wssr_problem* probs, int32_t 
  * of the last batch (codes[0..count)). */
 wssr_status wssr_batched_status(wssr_handle h, int32_t count, int32_t* codes);
 
+/* Autotuner of the batched form: runs the batch `reps` times under each
+ * candidate configuration -- lanes in use (1, 2, 4, ... up to the handle's
+ * lanes) and, per lane count, the number of resident workgroups the product
+ * kernels size their split-K / stream-K decomposition for (the whole device,
+ * or its share, slots / lanes) -- and keeps the fastest for later batches.
+ * It works on scratch copies of V, delta and sigma (it allocates them), so the
+ * caller's buffers are not written; O and e_l are only read.  Outputs
+ * (nullable): the chosen lane count, the split divisor and the batch time in
+ * milliseconds. */
+wssr_status wssr_tune_batched(wssr_handle h, const wssr_problem* probs, int32_t count, int32_t reps,
+                              int32_t* best_lanes, int32_t* best_div, double* best_ms);
+
 /* *active = 1 when the last batch ran as a replayed or fresh graph.  When a
  * capture has failed, the handle runs its batches as direct launches from
  * then on, and wssr_last_error gives the reason after this call. */

@@ -5,9 +5,9 @@
 //   parameter side Z = O^T Q * scale                 (M x r, K = N)
 //
 // Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; output tile
-// 128 rows x BN columns (BN = 128 or 256 over the rank dimension); each wave
-// owns a 64 x (BN/2) sub-tile = 2 x (BN/64) MFMA tiles of 32 x 32, i.e. 8 FP32
-// accumulator tiles at BN = 256.  K advances 16 at a time with one barrier per
+// 128 rows x BN columns (BN = 64, 128 or 256 over the rank dimension); each
+// wave owns a 64 x (BN/2) sub-tile = 2 x (BN/64) MFMA tiles of 32 x 32, i.e.
+// 8 FP32 accumulator tiles at BN = 256.  K advances 16 at a time with one barrier per
 // K-step; the next K-step's global loads are in flight during the MFMAs.
 //
 // Both operand tiles are kept K-contiguous in LDS ([row][k]), so a lane reads
@@ -364,14 +364,20 @@ __global__ __launch_bounds__(256) void k_streamk_fixup(const float* __restrict__
     if (j0 + col + c < r) Z[grow * r + j0 + col + c] = s[c] * scale;
 }
 
+template __global__ void k_gemm_sample_side<64>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
+                                                int64_t, bool, bool, const DevStatus*, int, int, bool);
 template __global__ void k_gemm_sample_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
                                                  int64_t, bool, bool, const DevStatus*, int, int, bool);
 template __global__ void k_gemm_sample_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
                                                  int64_t, bool, bool, const DevStatus*, int, int, bool);
+template __global__ void k_gemm_param_side<64>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
+                                               float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
 template __global__ void k_gemm_param_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
                                                 float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
 template __global__ void k_gemm_param_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
                                                 float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
+template __global__ void k_streamk_fixup<64>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
+                                             int, const DevStatus*);
 template __global__ void k_streamk_fixup<128>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
                                               int, const DevStatus*);
 template __global__ void k_streamk_fixup<256>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,

@@ -17,7 +17,7 @@ using namespace wssr;
 
 namespace {
 
-constexpr int kS1Max = 16;      // split-K ranges of the sample-side product
+constexpr int kS1Max = 32;      // split-K ranges of the sample-side product
 constexpr int kGSplitMax = 16;  // row splits of the gradient
 constexpr int kGramChunkMax = 64;
 constexpr int kVecChunkMax = 1024;
@@ -44,9 +44,12 @@ struct wssr_ctx {
   unsigned* jsync = nullptr;     // grid-barrier words of the Rayleigh-Ritz sweep kernel
   bool own_stream = false;       // a batch lane: the stream was created with the context
   bool capturing = false;        // enqueueing into a graph capture (no cooperative launch, no profiling)
+  bool plain_svd = false;        // batch lanes: the Jacobi grid as a plain launch (see small_svd)
   std::vector<wssr_ctx*> lanes;  // batch lanes (children with their own stream and workspace)
   std::vector<hipEvent_t> lane_done;
   int* bstat = nullptr;          // per-problem status codes of the last batch
+  int active_lanes = 0;          // lanes a batch uses (0: all); set by wssr_tune_batched
+  int slot_div = 1;              // product kernels size their split for slots / slot_div workgroups
   std::vector<wssr_problem> gkey;  // the batch the cached graph was captured for
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -250,7 +253,9 @@ struct wssr_ctx {
   bool bf16() const { return cfg.o_dtype != WSSR_F32; }
   int o_planes() const { return cfg.o_dtype == WSSR_BF16X2 ? 2 : 1; }
   int s_planes() const { return cfg.o_dtype == WSSR_BF16 ? 1 : 2; }
-  static int bn_for(int r, bool b16) { return r <= 128 ? 128 : (r <= 256 || !b16 ? 256 : 512); }
+  static int bn_for(int r, bool b16) {
+    return r <= 64 && !b16 ? 64 : r <= 128 ? 128 : (r <= 256 || !b16 ? 256 : 512);
+  }
   // index of a BF16 product variant: (BN, PA, PB) with BN in {128, 256, 512}
   static int v16(int bn, int pa, int pb) { return (bn == 128 ? 0 : bn == 256 ? 1 : 2) * 3 + (pa == 2 ? 2 : pb - 1); }
   int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
@@ -284,7 +289,7 @@ struct wssr_ctx {
     const int bn = bn_for(r, b16), bk = b16 ? (bn == 512 ? 16 : 32) : 16;
     const int pa = o_planes(), pb = s_planes();
     const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
-    const int sl = b16 ? slots16s[v16(bn, pa, pb)] : slots;
+    const int sl = std::max(1, (b16 ? slots16s[v16(bn, pa, pb)] : slots) / slot_div);
     // about one round of resident workgroups; split K = M into s1 ranges
     int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(sl, tn * tj)));
     int64_t kchunk = rup(cdiv(m, s1), bk);
@@ -299,8 +304,11 @@ struct wssr_ctx {
         if (bn == 256)
           hipLaunchKernelGGL(k_gemm_sample_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
                              vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
-        else
+        else if (bn == 128)
           hipLaunchKernelGGL(k_gemm_sample_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
+                             vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
+        else
+          hipLaunchKernelGGL(k_gemm_sample_side<64>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
                              vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
       });
     } else {
@@ -337,7 +345,7 @@ struct wssr_ctx {
     const int pa = o_planes(), pb = s_planes();
     const bool vec_q = (r % 4 == 0) && ((uintptr_t)Q % 16 == 0);
     const float scale = (float)(1.0 / std::sqrt((double)n));
-    const int sl = b16 ? slots16p[v16(bn, pa, pb)] : slots;
+    const int sl = std::max(1, (b16 ? slots16p[v16(bn, pa, pb)] : slots) / slot_div);
     const int64_t tj = cdiv(r, bn), tiles = cdiv(m, 128) * tj, nk = cdiv(n, bk);
     // whole tiles for every full round of resident workgroups; the leftover
     // tiles' K-steps shared evenly by one more round (stream-K) unless the
@@ -361,8 +369,11 @@ struct wssr_ctx {
         if (bn == 256)
           hipLaunchKernelGGL(k_gemm_param_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
                              vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
-        else
+        else if (bn == 128)
           hipLaunchKernelGGL(k_gemm_param_side<128>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
+                             vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        else
+          hipLaunchKernelGGL(k_gemm_param_side<64>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
                              vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
       } else {
         const auto* O = static_cast<const unsigned short*>(Ov);
@@ -394,8 +405,11 @@ struct wssr_ctx {
         else if (bn == 256)
           hipLaunchKernelGGL(k_streamk_fixup<256>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
                              (int)tj, full, nk, units, skw, (const DevStatus*)st);
-        else
+        else if (bn == 128)
           hipLaunchKernelGGL(k_streamk_fixup<128>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
+                             (int)tj, full, nk, units, skw, (const DevStatus*)st);
+        else
+          hipLaunchKernelGGL(k_streamk_fixup<64>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
                              (int)tj, full, nk, units, skw, (const DevStatus*)st);
       }
     });
@@ -501,9 +515,11 @@ struct wssr_ctx {
     DevStatus* stp = st;
     int sweeps = kJacobiSweeps, inner = kJacobiInner;
     void* args[] = {&Bc, &Pc, &rp, &tol, &scal_c, &cosb, &sy, &stp, &sweeps, &inner};
-    if (capturing) {
-      // a graph node: a plain launch (the grid is at most 16 workgroups and
-      // its barrier waits are bounded, so it does not rely on the guarantee)
+    if (capturing || plain_svd) {
+      // a graph node, or a batch lane running beside other lanes: a plain
+      // launch (a cooperative launch may hold the whole device).  The grid is
+      // at most 16 workgroups, which the device schedules as other work
+      // drains, and its barrier waits are bounded.
       hipLaunchKernelGGL(k_jacobi_coop, dim3(rp / 32), dim3(256), jacobi_lds(rp), stream, Bc, Pc, rp, tol, scal_c,
                          cosb, sy, stp, sweeps, inner);
       coop_err = hipGetLastError();
@@ -698,6 +714,7 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
       g_create_error = why;
       return s;
     }
+    c->plain_svd = true;
     h->lanes.push_back(c);
     h->lane_done.push_back(e);
   }
@@ -760,7 +777,8 @@ bool same_batch(const std::vector<wssr_problem>& a, const wssr_problem* b, int32
 // after another on its own stream, forked from and joined back into the
 // handle's stream; per-problem status codes are saved to bstat.
 static wssr_status enqueue_batch(wssr_ctx* h, const wssr_problem* p, int32_t count) {
-  const int nl = std::max<int>(1, (int)h->lanes.size());
+  const int avail = (int)h->lanes.size();
+  const int nl = std::max(1, h->active_lanes > 0 ? std::min(h->active_lanes, avail) : avail);
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   auto cost = [&](int i) { return (double)p[i].n * (double)p[i].m * (double)p[i].r * (double)p[i].q; };
@@ -862,6 +880,100 @@ wssr_status wssr_batched_status(wssr_handle h, int32_t count, int32_t* codes) {
   if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipStreamSynchronize failed");
   if (hipMemcpy(codes, h->bstat, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost) != hipSuccess)
     return h->fail(WSSR_ERR_HIP, "status copy failed");
+  return WSSR_OK;
+}
+
+// Autotuner of the batched form.  Candidates: the number of lanes in use
+// (1, 2, 4, ... up to the handle's lanes) and, for each, how many resident
+// workgroups a product sizes its split-K and stream-K decomposition for (the
+// whole device, or its share: slots / lanes).  Each candidate runs the batch
+// `reps` times on scratch copies of V, delta and sigma (the caller's buffers
+// are not written) and the fastest by HIP events is kept.
+wssr_status wssr_tune_batched(wssr_handle h, const wssr_problem* probs, int32_t count, int32_t reps,
+                              int32_t* best_lanes, int32_t* best_div, double* best_ms) {
+  if (!h || !probs || count < 1 || count > kBatchMax || reps < 1) return WSSR_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    const wssr_problem& q = probs[i];
+    wssr_status s = check_step(h, q.n, q.m, q.O, q.ld_o, q.e_l, q.V, q.lambda, q.r, q.q, q.delta, q.sigma);
+    if (s != WSSR_OK) return h->fail(s, "problem %d: %s", i, h->err.c_str());
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+  // scratch copies of the written arguments
+  std::vector<wssr_problem> work(probs, probs + count);
+  std::vector<void*> scratch;
+  bool ok = true;
+  for (auto& q : work) {
+    void *v = nullptr, *d = nullptr, *sg = nullptr;
+    ok = ok && hipMalloc(&v, sizeof(float) * q.m * q.r) == hipSuccess;
+    ok = ok && hipMalloc(&d, sizeof(double) * q.m) == hipSuccess;
+    ok = ok && hipMalloc(&sg, sizeof(double) * q.r) == hipSuccess;
+    scratch.push_back(v);
+    scratch.push_back(d);
+    scratch.push_back(sg);
+    if (!ok) break;
+    (void)hipMemcpyAsync(v, q.V, sizeof(float) * q.m * q.r, hipMemcpyDeviceToDevice, h->stream);
+    q.V = static_cast<float*>(v);
+    q.delta = static_cast<double*>(d);
+    q.sigma = static_cast<double*>(sg);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  const int saved_lanes = h->active_lanes;
+  std::vector<int> saved_div;
+  for (wssr_ctx* c : h->lanes) saved_div.push_back(c->slot_div);
+  const int saved_div0 = h->slot_div;
+  int bl = std::max(1, (int)h->lanes.size()), bd = 1;
+  double bms = 1e300;
+  const int avail = std::max(1, (int)h->lanes.size());
+  std::vector<int> cands;
+  for (int nl = 1; nl < avail; nl *= 2) cands.push_back(nl);
+  cands.push_back(avail);
+  for (int nl : cands) {
+    for (int div : {1, nl}) {
+      if (!ok) break;
+      h->active_lanes = nl;
+      h->slot_div = div;
+      for (wssr_ctx* c : h->lanes) c->slot_div = div;
+      // one untimed run (first use of the configuration), then `reps` timed
+      if (enqueue_batch(h, work.data(), count) != WSSR_OK) {
+        ok = false;
+        break;
+      }
+      (void)hipEventRecord(e0, h->stream);
+      for (int k = 0; k < reps && ok; ++k) ok = enqueue_batch(h, work.data(), count) == WSSR_OK;
+      (void)hipEventRecord(e1, h->stream);
+      if (!ok || hipEventSynchronize(e1) != hipSuccess) {
+        ok = false;
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double per = ms / reps;
+      if (per < bms) {
+        bms = per;
+        bl = nl;
+        bd = div;
+      }
+      if (nl == 1) break;   // the device share of one lane is the device
+    }
+    if (!ok) break;
+  }
+  (void)hipStreamSynchronize(h->stream);
+  for (void* p : scratch) (void)hipFree(p);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!ok) {
+    h->active_lanes = saved_lanes;
+    h->slot_div = saved_div0;
+    for (size_t i = 0; i < h->lanes.size(); ++i) h->lanes[i]->slot_div = saved_div[i];
+    return h->fail(WSSR_ERR_HIP, "tuning run failed");
+  }
+  h->active_lanes = bl;
+  h->slot_div = bd;
+  for (wssr_ctx* c : h->lanes) c->slot_div = bd;
+  if (best_lanes) *best_lanes = bl;
+  if (best_div) *best_div = bd;
+  if (best_ms) *best_ms = bms;
   return WSSR_OK;
 }
 

@@ -68,6 +68,8 @@ _SIGS = {
     "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
     "wssr_batched_status": ([_P, _I32, ctypes.POINTER(_I32)], ctypes.c_int),
     "wssr_graph_active": ([_P, ctypes.POINTER(_I32)], ctypes.c_int),
+    "wssr_tune_batched": ([_P, _P, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_D)],
+                          ctypes.c_int),
     "wssr_last_error": ([_P], ctypes.c_char_p),
     "wssr_version": ([], ctypes.c_char_p),
     "wssr_profile": ([_P, _I32], ctypes.c_int),
@@ -198,8 +200,13 @@ class Wssr:
     def step_batched(self, problems):
         """One batched step.  problems: list of dicts with keys O, e_l, V, lam and
         optional q (default 2), delta, sigma.  Each V is updated in place;
-        returns [(delta, sigma), ...].  The argument array is kept with the
-        handle (a graph replays only while the same array contents recur)."""
+        returns [(delta, sigma), ...]."""
+        arr, outs, keep = self._problem_array(problems)
+        self._check(lib().wssr_step_batched(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems)))
+        self._last_batch = (arr, keep)
+        return outs
+
+    def _problem_array(self, problems):
         arr = (Problem * len(problems))()
         outs, keep = [], []
         for i, pb in enumerate(problems):
@@ -210,21 +217,30 @@ class Wssr:
             r = V.shape[1]
             _need(V, "V", torch.float32, self.device, (m, r))
             _need(e_l, "e_l", torch.float64, self.device, (n,))
-            delta = pb.get("delta")
-            sigma = pb.get("sigma")
+            delta, sigma = pb.get("delta"), pb.get("sigma")
             if delta is None:
                 delta = torch.empty(m, dtype=torch.float64, device=self.device)
             if sigma is None:
                 sigma = torch.empty(r, dtype=torch.float64, device=self.device)
             _need(delta, "delta", torch.float64, self.device, (m,))
             _need(sigma, "sigma", torch.float64, self.device, (r,))
-            arr[i] = Problem(n, m, ld, O.data_ptr(), e_l.contiguous().data_ptr(), V.data_ptr(), float(pb["lam"]),
+            e_c = e_l.contiguous()
+            arr[i] = Problem(n, m, ld, O.data_ptr(), e_c.data_ptr(), V.data_ptr(), float(pb["lam"]),
                              r, int(pb.get("q", 2)), delta.data_ptr(), sigma.data_ptr())
             outs.append((delta, sigma))
-            keep.append(e_l)
-        self._check(lib().wssr_step_batched(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems)))
-        self._last_batch = (arr, keep)
-        return outs
+            keep.append(e_c)
+        return arr, outs, keep
+
+    def tune_batched(self, problems, reps=2):
+        """Pick the lane count and split sizing for this batch by timing it
+        (on scratch copies; the problems' V is not written).  Returns
+        (lanes, split divisor, ms per batch)."""
+        arr, _, keep = self._problem_array(problems)
+        bl, bd, bms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._check(lib().wssr_tune_batched(self._h, ctypes.cast(arr, ctypes.c_void_p), len(problems), int(reps),
+                                            ctypes.byref(bl), ctypes.byref(bd), ctypes.byref(bms)))
+        del keep
+        return bl.value, bd.value, bms.value
 
     def batched_status(self, count):
         """Synchronise and return the status code of each problem of the last batch."""

@@ -115,6 +115,24 @@ def test_graph_replays_match_eager(batch):
     h.close()
 
 
+def test_tuner_keeps_inputs_and_results(batch):
+    """The autotuner times the batch on scratch copies (the problems' V stays
+    as it was) and the tuned batch still meets the oracle tolerances."""
+    from paper_2512_05749_amd import Wssr
+    h = Wssr(n_max=1024, m_max=4000, r_max=32, q_max=4, lanes=4)
+    probs = _copy(batch[:8])
+    v_in = [p["V"].clone() for p in probs]
+    lanes, div, ms = h.tune_batched(probs, reps=1)
+    assert 1 <= lanes <= 4 and div in (1, lanes) and ms > 0
+    assert all(torch.equal(p["V"], v) for p, v in zip(probs, v_in))
+    outs = h.step_batched(probs)
+    assert h.batched_status(len(probs)) == [0] * len(probs)
+    for j, (p, (d, s)) in enumerate(zip(probs, outs)):
+        ref = orc.wssr_step(_np(p["O"]), _np(p["e_l"]), _np(v_in[j]), p["lam"], p["V"].shape[1], p["q"])
+        assert rel(_np(d), ref["delta"]) <= 1e-4, j
+    h.close()
+
+
 def test_graph_flag_is_rejected_while_switched_off():
     from paper_2512_05749_amd import Wssr, WssrError
     with pytest.raises(WssrError):

@@ -71,6 +71,28 @@ CONFIGS = {c.name: c for c in [
            dtype="bf16"),
 ]}
 
+
+
+def batch_configs(count=16, seed=4):
+    """The batched workload: `count` independent problems with N in {2048,
+    4096, 8192, 16384}, M uniform in [20000, 400000], r in {64, 128, 256},
+    lambda log-uniform in [1e-4, 1e-2] and spectrum k^-a, a uniform in
+    [1.0, 1.5]; rotation 0.01 per step, noise 1e-4, E_L ~ N(-10, 0.5^2),
+    min(N, 4096) spectral components (the components beyond are below the
+    noise floor).  Problem j is seeded with 4000 + j."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(rng.choice([2048, 4096, 8192, 16384]))
+        m = int(rng.integers(20_000, 400_001))
+        r = int(rng.choice([64, 128, 256]))
+        lam = float(10 ** rng.uniform(-4, -2))
+        a = float(rng.uniform(1.0, 1.5))
+        out.append(Config(f"batch16_mixed[{j}]", n=n, m=m, r=r, q=2, lam=lam, steps=20, alpha=a, theta=0.01,
+                          eta=1e-4, el_mean=-10.0, el_std=0.5, seed=4000 + j, k=min(n, 4096)))
+    return out
+
+
 _COMPONENT = {"u": 1, "w": 2, "perm_n": 3, "perm_m": 4, "v0": 5, "noise": 6, "el": 7}
 
 
