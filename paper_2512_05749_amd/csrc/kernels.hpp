@@ -65,12 +65,15 @@ size_t gemm16_lds(int bn, int bk, int pa, int pb);
 
 template <typename T>
 __global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,
-                               const DevStatus* st, bool gated);
-__global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, double* G, const DevStatus* st,
-                              bool gated);
+                               bool vec, const DevStatus* st, bool gated);
+__global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, int rp, double* G,
+                              const DevStatus* st, bool gated);
 template <typename Tin, typename Tout>
 __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
-                        Tout* Out, int ldo, bool upper, const DevStatus* st, bool gated);
+                        Tout* Out, int ldo, bool upper, bool vec, const DevStatus* st, bool gated);
+// tile of the Gram and apply kernels, and the Gram partial-buffer budget
+constexpr int kF64Tile = 128;
+constexpr size_t kGramPartBytes = (size_t)64 << 20;
 
 __global__ void k_chol(double* G, int rp, double* R, double* Rt, double* gdiag, DevStatus* st, bool gated);
 template <int RPL>

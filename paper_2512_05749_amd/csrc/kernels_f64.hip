@@ -7,35 +7,69 @@
 namespace wssr {
 
 namespace {
-constexpr int GT = 64;     // output tile
-constexpr int GK = 32;     // K step
-constexpr int GP = 1;      // LDS row pad (doubles)
+constexpr int GT = 128;         // output tile (rows and columns)
+constexpr int GK = 16;          // K step
+constexpr int GS = GT + 16;     // LDS row stride in doubles: the four K-rows of one
+                                // MFMA operand read fall into two halves of the banks
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// four consecutive elements p[0..3] as doubles; n of them valid (the rest 0)
+__device__ __forceinline__ f64x4 load4d(const float* __restrict__ p, int n, bool vec) {
+  if (vec && n >= 4) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(p);
+    return f64x4{(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+  }
+  f64x4 v = f64x4{0, 0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (e < n) v[e] = (double)p[e];
+  return v;
+}
+__device__ __forceinline__ f64x4 load4d(const double* __restrict__ p, int n, bool vec) {
+  if (vec && n >= 4) {
+    const f64x2 a = *reinterpret_cast<const f64x2*>(p), b = *reinterpret_cast<const f64x2*>(p + 2);
+    return f64x4{a[0], a[1], b[0], b[1]};
+  }
+  f64x4 v = f64x4{0, 0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (e < n) v[e] = p[e];
+  return v;
+}
+
+// decode a pair index to (I, J), I <= J, row-major over the upper triangle of
+// ntile x ntile tiles
+__device__ __forceinline__ void tile_pair(int pair, int ntile, int& I, int& J) {
+  int rem = pair;
+  I = 0;
+  while (rem >= ntile - I) {
+    rem -= ntile - I;
+    ++I;
+  }
+  J = rem + I;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Gram partials.  X is rows x r row-major.  grid.x enumerates the tile pairs
-// (I <= J) of the rp x rp output (rp = r padded to 64), grid.y the row chunks.
-// 4 waves, each a 32 x 32 quadrant = 2 x 2 MFMA tiles of 16 x 16.
-// part[(chunk * npairs + pair) * 4096 + i * 64 + j].
+// Gram partials.  X is rows x r row-major (row stride r).  grid.x enumerates
+// the tile pairs (I <= J) of 128 x 128 tiles of the Gram matrix, grid.y the
+// row chunks.  4 waves in a 2 x 2 arrangement, each a 64 x 64 quadrant =
+// 4 x 4 MFMA tiles of 16 x 16; a diagonal pair (I = J) stages its one column
+// block once.  Each K-step stages 16 rows of the two column blocks in LDS as
+// FP64 while the next 16 rows are being loaded into registers.
+// part[(chunk * npairs + pair) * 16384 + i * 128 + j].
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ X, int64_t rows, int r, int ntile,
-                                                      int64_t rows_per_chunk, double* __restrict__ part,
-                                                      const DevStatus* st, bool gated) {
+__global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X, int64_t rows, int r, int ntile,
+                                                         int64_t rows_per_chunk, double* __restrict__ part, bool vec,
+                                                         const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
-  __shared__ double XI[GK][GT + GP];
-  __shared__ double XJ[GK][GT + GP];
-  // decode pair index -> (I, J), I <= J, row-major over the upper triangle
-  int pair = blockIdx.x, I = 0;
-  {
-    int rem = pair;
-    while (rem >= ntile - I) {
-      rem -= ntile - I;
-      ++I;
-    }
-    pair = rem + I;  // J
-  }
-  const int J = pair;
+  __shared__ double XI[GK][GS];
+  __shared__ double XJ[GK][GS];
+  int I, J;
+  tile_pair(blockIdx.x, ntile, I, J);
+  const bool diag = I == J;
   const int npairs = ntile * (ntile + 1) / 2;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int qi = w >> 1, qj = w & 1;
@@ -43,73 +77,89 @@ __global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ X, i
   const int64_t rbeg = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t rend = min(rows, rbeg + rows_per_chunk);
 
-  f64x4 acc[2][2];
+  f64x4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0};
 
-  for (int64_t k0 = rbeg; k0 < rend; k0 += GK) {
-    // load 32 rows x 64 columns for tile I and tile J: 2048 elements each, 8 per thread
+  // thread -> (K-row, 4 columns) of a 16 x 128 block, two units per thread
+  f64x4 pi[2], pj[2];
+  auto load = [&](int64_t k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < 2; ++e) {
       const int idx = t + 256 * e;
-      const int kr = idx >> 6, c = idx & 63;
-      const int64_t gr = k0 + kr;
-      const int ci = I * GT + c, cj = J * GT + c;
-      XI[kr][c] = (gr < rend && ci < r) ? (double)X[gr * r + ci] : 0.0;
-      XJ[kr][c] = (gr < rend && cj < r) ? (double)X[gr * r + cj] : 0.0;
+      const int64_t gr = k0 + (idx >> 5);
+      const int c4 = (idx & 31) * 4;
+      const int ci = I * GT + c4, cj = J * GT + c4;
+      const bool row_ok = gr < rend;
+      pi[e] = load4d(X + gr * r + ci, row_ok ? min(4, r - ci) : 0, vec);
+      if (!diag) pj[e] = load4d(X + gr * r + cj, row_ok ? min(4, r - cj) : 0, vec);
     }
+  };
+  auto store = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = t + 256 * e;
+      const int kr = idx >> 5, c4 = (idx & 31) * 4;
+      *reinterpret_cast<f64x2*>(&XI[kr][c4]) = f64x2{pi[e][0], pi[e][1]};
+      *reinterpret_cast<f64x2*>(&XI[kr][c4 + 2]) = f64x2{pi[e][2], pi[e][3]};
+      if (!diag) {
+        *reinterpret_cast<f64x2*>(&XJ[kr][c4]) = f64x2{pj[e][0], pj[e][1]};
+        *reinterpret_cast<f64x2*>(&XJ[kr][c4 + 2]) = f64x2{pj[e][2], pj[e][3]};
+      }
+    }
+  };
+  if (rbeg < rend) load(rbeg);
+  for (int64_t k0 = rbeg; k0 < rend; k0 += GK) {
+    store();
     __syncthreads();
+    if (k0 + GK < rend) load(k0 + GK);
+    const double(*B)[GS] = diag ? XI : XJ;
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int k = kk * 4 + lk;
-      double av[2], bv[2];
+      double av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = XI[k][qi * 32 + a * 16 + li];
+      for (int a = 0; a < 4; ++a) av[a] = XI[k][qi * 64 + a * 16 + li];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = XJ[k][qj * 32 + b * 16 + li];
+      for (int b = 0; b < 4; ++b) bv[b] = B[k][qj * 64 + b * 16 + li];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
   double* out = part + ((int64_t)blockIdx.y * npairs + blockIdx.x) * (GT * GT);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = qi * 32 + a * 16 + 4 * v + lk;
-        const int j = qj * 32 + b * 16 + li;
+        const int i = qi * 64 + a * 16 + 4 * v + lk;
+        const int j = qj * 64 + b * 16 + li;
         out[i * GT + j] = acc[a][b][v];
       }
 }
 
-// Sum the partials in chunk order and write the symmetric rp x rp Gram matrix,
-// identity on the padding (rows/columns >= r).  grid (npairs, 16): block y
-// covers 256 of the 4096 entries of its tile, one entry per thread.
+// Sum the partials in chunk order and write the symmetric rp x rp Gram matrix
+// (rp = r padded to 64), identity on the padding (rows/columns >= r).  grid
+// (npairs, 64): block y covers 256 of the 16384 entries of its tile pair, one
+// entry per thread; in a diagonal pair only the upper triangle is summed and
+// mirrored.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nchunk, int ntile, int r,
-                                                     double* __restrict__ G, const DevStatus* st, bool gated) {
+                                                     int rp, double* __restrict__ G, const DevStatus* st,
+                                                     bool gated) {
   if (skipped(st, gated)) return;
-  int pair = blockIdx.x, I = 0;
-  {
-    int rem = pair;
-    while (rem >= ntile - I) {
-      rem -= ntile - I;
-      ++I;
-    }
-    pair = rem + I;
-  }
-  const int J = pair;
+  int I, J;
+  tile_pair(blockIdx.x, ntile, I, J);
   const int npairs = ntile * (ntile + 1) / 2;
-  const int rp = ntile * GT;
   const int e = blockIdx.y * 256 + threadIdx.x;
-  const int i = e >> 6, j = e & 63;
+  const int i = e / GT, j = e % GT;
   const int gi = I * GT + i, gj = J * GT + j;
+  if (gi >= rp || gj >= rp || (I == J && i > j)) return;
   double s;
   if (gi < r && gj < r) {
     const double* p = part + (int64_t)blockIdx.x * (GT * GT) + e;
@@ -132,18 +182,20 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Apply: Out[rows x ldo] = X[rows x ldx] * Tm[0:kdim, 0:ncol] (Tm rp x rp row-major,
-// FP64).  grid (row tiles of 64, column tiles of 64).  When `upper`, Tm is upper
-// triangular and K-steps below the column tile are skipped.
+// Apply: Out[rows x ldo] = X[rows x ldx] * Tm[0:kdim, 0:ncol] (Tm rp x rp
+// row-major, FP64).  grid (row tiles of 128, column tiles of 128); 4 waves of
+// 64 x 64 as in the Gram kernel.  When `upper`, Tm is upper triangular and
+// K-steps below the column tile are skipped.  The next K-step's tiles are
+// loaded into registers while the current ones are multiplied.
 // ---------------------------------------------------------------------------
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_apply(const Tin* __restrict__ X, int64_t rows, int ldx, int kdim,
-                                               const double* __restrict__ Tm, int rp, int ncol,
-                                               Tout* __restrict__ Out, int ldo, bool upper, const DevStatus* st,
-                                               bool gated) {
+__global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int64_t rows, int ldx, int kdim,
+                                                  const double* __restrict__ Tm, int rp, int ncol,
+                                                  Tout* __restrict__ Out, int ldo, bool upper, bool vec,
+                                                  const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
-  __shared__ double Xs[GK][GT + GP];   // [k][row]
-  __shared__ double Ts[GK][GT + GP];   // [k][col]
+  __shared__ double Xs[GK][GS];   // [k][row]
+  __shared__ double Ts[GK][GS];   // [k][col]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int qi = w >> 1, qj = w & 1;
   const int li = lane & 15, lk = lane >> 4;
@@ -151,64 +203,94 @@ __global__ __launch_bounds__(256) void k_apply(const Tin* __restrict__ X, int64_
   const int col0 = blockIdx.y * GT;
   const int kend = upper ? min(kdim, col0 + GT) : kdim;
 
-  f64x4 acc[2][2];
+  f64x4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0};
 
-  for (int k0 = 0; k0 < kend; k0 += GK) {
+  // X: thread -> (row, 4 K-values), two units; T: thread -> (K-row, 2 columns), four units
+  f64x4 px[2];
+  f64x2 pt[4];
+  auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < 2; ++e) {
       const int idx = t + 256 * e;
-      // X tile: 64 rows x 32 k, read along k (8 threads per row... 32 k per row)
-      const int rr = idx >> 5, kk = idx & 31;
-      const int64_t gr = row0 + rr;
-      const int gk = k0 + kk;
-      Xs[kk][rr] = (gr < rows && gk < kdim) ? (double)X[gr * ldx + gk] : 0.0;
-      // T tile: 32 k x 64 cols
-      const int tk = idx >> 6, tc = idx & 63;
-      const int gtk = k0 + tk, gtc = col0 + tc;
-      Ts[tk][tc] = (gtk < kdim && gtc < ncol) ? Tm[(int64_t)gtk * rp + gtc] : 0.0;
+      const int64_t gr = row0 + (idx >> 2);
+      const int gk = k0 + (idx & 3) * 4;
+      px[e] = load4d(X + gr * ldx + gk, gr < rows ? min(4, kdim - gk) : 0, vec);
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = t + 256 * e;
+      const int gtk = k0 + (idx >> 6), gtc = col0 + (idx & 63) * 2;
+      f64x2 v = f64x2{0, 0};
+      if (gtk < kdim) {
+        const double* src = Tm + (int64_t)gtk * rp + gtc;
+        if (gtc + 1 < ncol)
+          v = *reinterpret_cast<const f64x2*>(src);
+        else if (gtc < ncol)
+          v[0] = src[0];
+      }
+      pt[e] = v;
+    }
+  };
+  auto store = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = t + 256 * e;
+      const int rr = idx >> 2, kq = (idx & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Xs[kq + q][rr] = px[e][q];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = t + 256 * e;
+      *reinterpret_cast<f64x2*>(&Ts[idx >> 6][(idx & 63) * 2]) = pt[e];
+    }
+  };
+  if (kend > 0) load(0);
+  for (int k0 = 0; k0 < kend; k0 += GK) {
+    store();
     __syncthreads();
+    if (k0 + GK < kend) load(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int k = kk * 4 + lk;
-      double av[2], bv[2];
+      double av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = Xs[k][qi * 32 + a * 16 + li];
+      for (int a = 0; a < 4; ++a) av[a] = Xs[k][qi * 64 + a * 16 + li];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Ts[k][qj * 32 + b * 16 + li];
+      for (int b = 0; b < 4; ++b) bv[b] = Ts[k][qj * 64 + b * 16 + li];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t i = row0 + qi * 32 + a * 16 + 4 * v + lk;
-        const int j = col0 + qj * 32 + b * 16 + li;
+        const int64_t i = row0 + qi * 64 + a * 16 + 4 * v + lk;
+        const int j = col0 + qj * 64 + b * 16 + li;
         if (i < rows && j < ncol) Out[i * ldo + j] = (Tout)acc[a][b][v];
       }
 }
 
 // explicit instantiations used by the host runtime
-template __global__ void k_gram_partial<float>(const float*, int64_t, int, int, int64_t, double*, const DevStatus*,
-                                               bool);
-template __global__ void k_gram_partial<double>(const double*, int64_t, int, int, int64_t, double*, const DevStatus*,
-                                                bool);
+template __global__ void k_gram_partial<float>(const float*, int64_t, int, int, int64_t, double*, bool,
+                                               const DevStatus*, bool);
+template __global__ void k_gram_partial<double>(const double*, int64_t, int, int, int64_t, double*, bool,
+                                                const DevStatus*, bool);
 template __global__ void k_apply<float, float>(const float*, int64_t, int, int, const double*, int, int, float*, int,
-                                               bool, const DevStatus*, bool);
+                                               bool, bool, const DevStatus*, bool);
 template __global__ void k_apply<double, float>(const double*, int64_t, int, int, const double*, int, int, float*,
-                                                int, bool, const DevStatus*, bool);
+                                                int, bool, bool, const DevStatus*, bool);
 template __global__ void k_apply<double, double>(const double*, int64_t, int, int, const double*, int, int, double*,
-                                                 int, bool, const DevStatus*, bool);
+                                                 int, bool, bool, const DevStatus*, bool);
 
 }  // namespace wssr

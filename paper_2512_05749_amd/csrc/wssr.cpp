@@ -19,7 +19,6 @@ namespace {
 
 constexpr int kS1Max = 32;      // split-K ranges of the sample-side product
 constexpr int kGSplitMax = 16;  // row splits of the gradient
-constexpr int kGramChunkMax = 64;
 constexpr int kVecChunkMax = 1024;
 constexpr int kJacobiSweeps = 30;
 constexpr int kJacobiInner = 1;     // inner sweeps per block step
@@ -440,17 +439,25 @@ struct wssr_ctx {
                        1.0 / (double)n, gout, (const DevStatus*)st);
   }
 
+  // row chunks of the Gram partials: about 512 workgroups, at least 256 rows
+  // each, within the partial buffer
+  static int gram_chunks(int64_t rows, int npairs) {
+    const int64_t per = (int64_t)npairs * kF64Tile * kF64Tile * (int64_t)sizeof(double);
+    const int64_t cap = std::max<int64_t>(1, (int64_t)kGramPartBytes / per);
+    return (int)std::max<int64_t>(1, std::min(std::min(cdiv(512, npairs), cdiv(rows, 256)), cap));
+  }
+
   template <typename T>
   void gram(const T* X, int64_t rows, int r, bool gated) {
-    const int rp = (int)rup(r, 64), nt = rp / 64, npairs = nt * (nt + 1) / 2;
-    int nch = (int)std::min<int64_t>(std::min<int64_t>(kGramChunkMax, std::max(1, 2048 / npairs)),
-                                     std::max<int64_t>(1, cdiv(rows, 256)));
-    const int64_t rpc = rup(cdiv(rows, nch), 32);
+    const int rp = (int)rup(r, 64), nt = (int)cdiv(r, kF64Tile), npairs = nt * (nt + 1) / 2;
+    int nch = gram_chunks(rows, npairs);
+    const int64_t rpc = std::max<int64_t>(16, rup(cdiv(rows, nch), 16));
     nch = (int)std::max<int64_t>(1, cdiv(rows, rpc));
+    const bool vec = (r % 4 == 0) && ((uintptr_t)X % 16 == 0);
     hipLaunchKernelGGL(k_gram_partial<T>, dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, nt, rpc, gram_part,
-                       (const DevStatus*)st, gated);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(npairs, 16), dim3(256), 0, stream, (const double*)gram_part, nch, nt, r, G,
-                       (const DevStatus*)st, gated);
+                       vec, (const DevStatus*)st, gated);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(npairs, kF64Tile * kF64Tile / 256), dim3(256), 0, stream,
+                       (const double*)gram_part, nch, nt, r, rp, G, (const DevStatus*)st, gated);
   }
 
   // Cholesky of G into R and R^{-1}; a first round (gated = false) also sets
@@ -480,8 +487,9 @@ struct wssr_ctx {
   template <typename Tin, typename Tout>
   void apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol, Tout* out, int ldo,
              bool upper, bool gated = false) {
-    hipLaunchKernelGGL((k_apply<Tin, Tout>), dim3(cdiv(rows, 64), cdiv(ncol, 64)), dim3(256), 0, stream, X, rows, ldx,
-                       kdim, Tm, rp, ncol, out, ldo, upper, (const DevStatus*)st, gated);
+    const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    hipLaunchKernelGGL((k_apply<Tin, Tout>), dim3(cdiv(rows, kF64Tile), cdiv(ncol, kF64Tile)), dim3(256), 0, stream,
+                       X, rows, ldx, kdim, Tm, rp, ncol, out, ldo, upper, vec, (const DevStatus*)st, gated);
   }
 
   // CholeskyQR of X (rows x r) with a second round when the first round's
@@ -599,7 +607,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
   }
   const int64_t n = cfg->n_max, m = cfg->m_max;
   const int r = cfg->r_max;
-  const int rp = (int)rup(r, 64), nt = rp / 64, npairs = nt * (nt + 1) / 2;
+  const int rp = (int)rup(r, 64), nt = (int)cdiv(r, kF64Tile), npairs = nt * (nt + 1) / 2;
   h->rp_max = rp;
   h->rows_max = std::max(n, m);
   const int64_t rows = h->rows_max;
@@ -608,7 +616,9 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->y64, (size_t)n * r) && h->alloc(h->yq1, (size_t)n * r) &&
             h->alloc(h->colpart, (size_t)cdiv(n, 128) * r) && h->alloc(h->qy, (size_t)n * r) &&
             h->alloc(h->z, (size_t)m * r) && h->alloc(h->q1, (size_t)rows * r) && h->alloc(h->vw, (size_t)m * r) &&
-            h->alloc(h->gram_part, (size_t)kGramChunkMax * npairs * 4096) && h->alloc(h->G, (size_t)rp * rp) &&
+            h->alloc(h->gram_part,
+                     (size_t)wssr_ctx::gram_chunks(std::max(n, m), npairs) * npairs * kF64Tile * kF64Tile) &&
+            h->alloc(h->G, (size_t)rp * rp) &&
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
             h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
             h->alloc(h->Pc, (size_t)rp * rp) && h->alloc(h->Ps, (size_t)rp * rp) && h->alloc(h->T, (size_t)rp * rp) &&
