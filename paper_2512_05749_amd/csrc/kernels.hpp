@@ -84,6 +84,7 @@ __global__ void k_smallgemm(const double* A, const double* B, int rp, double* C,
                             bool copy_b);
 __global__ void k_jacobi_prep(const double* Ct, int rp, int r, double* Bc, double* Pc, double* scal,
                               unsigned* sync, DevStatus* st);
+template <int NPU>
 __global__ void k_jacobi_coop(double* Bc, double* Pc, int rp, double tol, const double* scal, double* cosbuf,
                               unsigned* sync, DevStatus* st, int max_sweeps, int inner_sweeps);
 __global__ void k_jacobi_final(const double* Bc, const double* Pc, int rp, int r, double* sig, double* Ps,

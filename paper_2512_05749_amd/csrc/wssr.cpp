@@ -509,6 +509,20 @@ struct wssr_ctx {
     if (Rout) smallgemm(R2, R1, rp, Rout, true, true);
   }
 
+  // the SVD kernel instantiated for rp (row blocks of 16 per wave: rp / 64)
+  static const void* jacobi_fn(int rp) {
+    switch (rp / 64) {
+      case 1: return (const void*)k_jacobi_coop<1>;
+      case 2: return (const void*)k_jacobi_coop<2>;
+      case 3: return (const void*)k_jacobi_coop<3>;
+      case 4: return (const void*)k_jacobi_coop<4>;
+      case 5: return (const void*)k_jacobi_coop<5>;
+      case 6: return (const void*)k_jacobi_coop<6>;
+      case 7: return (const void*)k_jacobi_coop<7>;
+      default: return (const void*)k_jacobi_coop<8>;
+    }
+  }
+
   // SVD of the r x r matrix whose transpose is Ct (rp x rp row-major): sorted
   // singular values into sig[0..rp), right singular vectors into Ps (rp x rp).
   void small_svd(const double* Ct, int r) {
@@ -523,17 +537,15 @@ struct wssr_ctx {
     DevStatus* stp = st;
     int sweeps = kJacobiSweeps, inner = kJacobiInner;
     void* args[] = {&Bc, &Pc, &rp, &tol, &scal_c, &cosb, &sy, &stp, &sweeps, &inner};
+    const void* fn = jacobi_fn(rp);
     if (capturing || plain_svd) {
       // a graph node, or a batch lane running beside other lanes: a plain
       // launch (a cooperative launch may hold the whole device).  The grid is
       // at most 16 workgroups, which the device schedules as other work
       // drains, and its barrier waits are bounded.
-      hipLaunchKernelGGL(k_jacobi_coop, dim3(rp / 32), dim3(256), jacobi_lds(rp), stream, Bc, Pc, rp, tol, scal_c,
-                         cosb, sy, stp, sweeps, inner);
-      coop_err = hipGetLastError();
+      coop_err = hipLaunchKernel(fn, dim3(rp / 32), dim3(256), args, jacobi_lds(rp), stream);
     } else {
-      coop_err = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(rp / 32), dim3(256), args,
-                                            (unsigned)jacobi_lds(rp), stream);
+      coop_err = hipLaunchCooperativeKernel(fn, dim3(rp / 32), dim3(256), args, (unsigned)jacobi_lds(rp), stream);
     }
     if (coop_err != hipSuccess) {
       // nothing was rotated: fail the step on the device so that no later
@@ -644,10 +656,12 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
     why = "workspace allocation failed";
     return WSSR_ERR_OOM;
   }
-  if (hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholLds) !=
-          hipSuccess ||
-      hipFuncSetAttribute((const void*)k_jacobi_coop, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)jacobi_lds(rp)) != hipSuccess) {
+  bool attr_ok =
+      hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholLds) == hipSuccess;
+  for (int k = 64; k <= rp; k += 64)
+    attr_ok = attr_ok && hipFuncSetAttribute(wssr_ctx::jacobi_fn(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)jacobi_lds(k)) == hipSuccess;
+  if (!attr_ok) {
     h->release();
     delete h;
     why = "hipFuncSetAttribute failed";
