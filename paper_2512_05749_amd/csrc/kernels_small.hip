@@ -1,5 +1,5 @@
 // Small (r x r, r <= 512) FP64 kernels: blocked Cholesky with the inverse of
-// the factor, and the Rayleigh-Ritz SVD by block one-sided Jacobi.  The
+// the factor, and the set-up and read-out of the Rayleigh-Ritz SVD.  The
 // matrices live in global memory (L2-resident at these sizes) and are worked
 // on in 64 x 64 tiles staged in LDS; tile products use the FP64 MFMA.
 #include "common.hpp"
@@ -70,56 +70,49 @@ __device__ __forceinline__ f64x4 tile_to_acc(const double (*T)[TP]) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Jacobi rotation that zeroes b in the symmetric 2 x 2 [[a, b], [b, d]]:
-// columns (p, q) -> (c p - s q, s p + c q) with t = s/c the smaller root of
-// t^2 + 2 zeta t - 1 = 0, zeta = (d - a) / (2b):
-//   t = sign(zeta) 2|b| / (|d - a| + sqrt((d - a)^2 + 4 b^2)),  c = 1/sqrt(1+t^2).
-// Reciprocal and reciprocal square root come from the hardware estimates
-// refined by Newton steps (two for 1/sqrt, which fixes c^2 + s^2 = 1 to FP64
-// rounding; the angle itself only needs to be close, the next sweep measures
-// what is left).
+// Reciprocal and reciprocal square root from the hardware estimates refined
+// by two Newton steps (full FP64 accuracy).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double rcp_nr(double x) {
   double y = __builtin_amdgcn_rcp(x);
   y = y * (2.0 - x * y);
   return y * (2.0 - x * y);
 }
+// x of lane l (l uniform across the wavefront)
+__device__ __forceinline__ double bcast_lane(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 __device__ __forceinline__ double rsq_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * (1.5 - 0.5 * x * y * y);
   return y * (1.5 - 0.5 * x * y * y);
-}
-__device__ __forceinline__ void rot_params(double a, double d, double b, double& c, double& s) {
-  const double dm = d - a;
-  const double h2 = dm * dm + 4.0 * b * b;
-  const double hyp = h2 * rsq_nr(h2);              // sqrt(h2)
-  const double sgn = ((dm >= 0.0) == (b >= 0.0)) ? 1.0 : -1.0;
-  const double t = sgn * 2.0 * fabs(b) * rcp_nr(fabs(dm) + hyp);
-  c = rsq_nr(1.0 + t * t);
-  s = c * t;
 }
 
 // ---------------------------------------------------------------------------
 // Cholesky G = R^T R (R upper, positive diagonal), rp x rp row-major; rp a
 // multiple of 64 (padding rows/columns of G are identity).  One workgroup of
 // 1024 threads; G is overwritten (trailing updates).  Writes R and its
-// transpose Rt (so that columns of R can be read contiguously).  A pivot d_k
+// transpose Rt (so that columns of R can be read contiguously) and the
+// reciprocals of its diagonal (invdiag).  A pivot d_k
 // with !(d_k > rp * eps * G_kk) is a breakdown (NaN: non-finite input).
 //
 // Blocked right-looking over 64-wide block columns.  The 64 x 64 diagonal
-// tile is factored in LDS with lanes = rows and wavefront w owning columns
-// w, w+16, w+32, w+48 (two barriers per column); its triangular inverse
-// (needed for the panel) is formed one column per wavefront by back
-// substitution; the panel and trailing updates are 64 x 64 x 64 tile
-// products on the FP64 MFMA.
+// tile is factored in LDS in four sub-blocks of 16 rows (one wavefront per
+// sub-block, then a workgroup-wide trailing update: two barriers per 16
+// columns); its triangular inverse (needed for the panel) is formed one
+// column per wavefront by back substitution; the panel and trailing updates
+// are 64 x 64 x 64 tile products on the FP64 MFMA.
 //
 // gated: a second CholeskyQR round; when st->round2 is 0 the kernel does
 // nothing (the gated consumers of R and Rt then take the identity instead).
 // Dynamic LDS: 4 tiles.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, double* __restrict__ R,
-                                              double* __restrict__ Rt, double* __restrict__ gdiag, DevStatus* st,
-                                              bool gated) {
+                                              double* __restrict__ Rt, double* __restrict__ gdiag,
+                                              double* __restrict__ invdiag, DevStatus* st, bool gated) {
   if (failed(st)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (gated && *reinterpret_cast<volatile int*>(&st->round2) == 0) return;
@@ -152,38 +145,54 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
   for (int kb = 0; kb < nt; ++kb) {
     tile_load(T0, G, rp, kb, kb);
     __syncthreads();
-    // factor the diagonal tile: lane i = row, wavefront wv owns columns wv + 16c
-    {
-      const int i = lane;
-      for (int k = 0; k < TS; ++k) {
-        const double d = T0[k][k];
-        const double d0 = dorig[kb * TS + k];
-        if (!(d > tiny * d0)) {
-          if (tid == 0) err = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
-          break;  // uniform: every thread sees the same d
-        }
-        const double ipiv = rsq_nr(d);   // 1/sqrt(d)
-        const double piv = d * ipiv;
-        if (tid == 0) minrel = fmin(minrel, d / d0);
-        if (i == k) {
+    // factor the diagonal tile in four sub-blocks of 16 rows.  For each,
+    // wavefront 0 alone runs the 16 right-looking steps over those rows with
+    // lane j holding column j (rows s0..s0+15) in registers; pivots and row
+    // entries are broadcast by readlane, so the steps need no barrier.  Then
+    // all threads apply the sub-block's 16 rows to the trailing part of the
+    // tile.
+    for (int s0 = 0; s0 < TS; s0 += 16) {
+      if (wv == 0) {
+        const int j = lane;
+        double col[16];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int j = wv + 16 * c;
-            if (j > k) T0[k][j] *= ipiv;
-          }
-        }
-        __syncthreads();
-        if (i > k) {
-          const double rki = T0[k][i];
+        for (int i = 0; i < 16; ++i) col[i] = T0[s0 + i][j];
+        int bad = 0;
+        double mr = 1.0;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int j = wv + 16 * c;
-            if (j >= i) T0[i][j] -= rki * T0[k][j];
-          }
+        for (int k = 0; k < 16; ++k) {
+          const double d = bcast_lane(col[k], s0 + k);
+          const double d0 = dorig[kb * TS + s0 + k];
+          // a failed pivot is recorded and the steps run on (uniform: every
+          // lane sees the same d); the kernel stops after the sub-block
+          if (!(d > tiny * d0) && !bad) bad = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
+          const double ipiv = rsq_nr(d);   // 1/sqrt(d)
+          mr = fmin(mr, d / d0);
+          col[k] = (j > s0 + k) ? col[k] * ipiv : (j == s0 + k ? d * ipiv : col[k]);
+#pragma unroll
+          for (int i = k + 1; i < 16; ++i) col[i] -= bcast_lane(col[k], s0 + i) * col[k];
         }
-        if (tid == 0) T0[k][k] = piv;
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (j >= s0 + i) T0[s0 + i][j] = col[i];
+        if (lane == 0) {
+          if (bad) err = bad;
+          minrel = fmin(minrel, mr);
+        }
       }
+      __syncthreads();
+      if (err) break;
+    const int s1 = s0 + 16, w = TS - s1;
+      for (int e = tid; e < w * w; e += NTH) {
+        const int i = s1 + e / w, j = s1 + e % w;
+        if (i <= j) {
+          double acc = T0[i][j];
+#pragma unroll
+          for (int l = 0; l < 16; ++l) acc -= T0[s0 + l][i] * T0[s0 + l][j];
+          T0[i][j] = acc;
+        }
+      }
+      __syncthreads();
     }
     __syncthreads();
     if (err) break;
@@ -191,20 +200,57 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
       const int a = e >> 6, b = e & 63;
       if (a > b) T0[a][b] = 0.0;
     }
-    if (tid < TS) invd[tid] = rcp_nr(T0[tid][tid]);
-    __syncthreads();
-    // inverse of the diagonal tile: column j by back substitution, one
-    // wavefront per column (lanes = rows)
-    for (int j = wv; j < TS; j += NTH / 64) {
-      double b = (lane == j) ? 1.0 : 0.0, x = 0.0;
-      for (int l = j; l >= 0; --l) {
-        const double xl = __shfl(b, l, 64) * invd[l];
-        if (lane == l) x = xl;
-        if (lane < l) b -= T0[lane][l] * xl;
-      }
-      T1[lane][j] = (lane <= j) ? x : 0.0;
+    if (tid < TS) {
+      invd[tid] = rcp_nr(T0[tid][tid]);
+      invdiag[kb * TS + tid] = invd[tid];
     }
     __syncthreads();
+    // inverse X of the diagonal tile in 16 x 16 blocks: wavefront w inverts
+    // the diagonal block w by back substitution (lane c holds column c in
+    // registers), then the blocks at distance d = 1, 2, 3 above the diagonal
+    // follow from X_ab = -X_aa sum_{c=a+1..b} T_ac X_cb on the FP64 MFMA,
+    // one block per wavefront (its partial sum staged in T2; the LDS
+    // accesses of one wavefront take effect in program order).
+    for (int e = tid; e < TS * TS; e += NTH) {
+      const int a = e >> 6, b = e & 63;
+      if ((a >> 4) > (b >> 4)) T1[a][b] = 0.0;
+    }
+    if (wv < 4 && lane < 16) {
+      const int o = 16 * wv, c = lane;
+      double x[16];
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        double sacc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = i + 1; l < 16; ++l) sacc -= T0[o + i][o + l] * x[l];
+        x[i] = sacc * invd[o + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) T1[o + i][o + c] = x[i];
+    }
+    __syncthreads();
+    for (int d = 1; d < 4; ++d) {
+      if (wv < 4 - d) {
+        const int ba = wv, bb = wv + d;
+        const int li = lane & 15, lk = lane >> 4;
+        f64x4 acc = f64x4{0};
+        for (int c = ba + 1; c <= bb; ++c) {
+#pragma unroll
+          for (int k0 = 0; k0 < 16; k0 += 4)
+            acc = mfma16x16x4d(T0[16 * ba + li][16 * c + k0 + lk], T1[16 * c + k0 + lk][16 * bb + li], acc);
+        }
+        double(*tmp)[TP] = T2 + 16 * wv;   // rows 16 wv .. 16 wv + 15 of T2: this wavefront's scratch
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tmp[4 * v + lk][li] = acc[v];
+        f64x4 out = f64x4{0};
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4)
+          out = mfma16x16x4d(T1[16 * ba + li][16 * ba + k0 + lk], tmp[k0 + lk][li], out);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T1[16 * ba + 4 * v + lk][16 * bb + li] = -out[v];
+      }
+      __syncthreads();
+    }
     tile_store(R, rp, kb, kb, T0);
     // panel: R[kb][j] = R_kk^{-T} G[kb][j]
     for (int j = kb + 1; j < nt; ++j) {
@@ -260,13 +306,17 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
 // ---------------------------------------------------------------------------
 // Ri = R^{-1} for the upper triangular R (rp x rp), column-parallel: one
 // wavefront per column j solves R x = e_j by back substitution, lanes = rows
-// (RPL >= rp/64 rows per lane), reading column l of R as row l of Rt.
+// (RPL >= rp/64 rows per lane), reading column l of R as row l of Rt and
+// 1 / R_ll from invdiag.  The column entries of the next 8 steps are loaded
+// into registers while the current 8 are applied.
 // grid: rp / 4 workgroups of 256 threads.  gated as in k_chol.
 // ---------------------------------------------------------------------------
 template <int RPL>
-__global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Rt, int rp, double* __restrict__ Ri,
+__global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Rt, int rp,
+                                               const double* __restrict__ invdiag, double* __restrict__ Ri,
                                                const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
+  constexpr int G = 8;
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= rp) return;
@@ -281,17 +331,42 @@ __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ Rt, in
   for (int sb = RPL - 1; sb >= 0; --sb) {
     if (sb > jb) continue;
     const int lstart = (sb == jb) ? (j & 63) : 63;
-#pragma unroll 4
-    for (int ll = lstart; ll >= 0; --ll) {
-      const int l = sb * 64 + ll;
-      const double* col = Rt + (int64_t)l * rp;   // column l of R
-      const double xl = __shfl(b[sb], ll, 64) * rcp_nr(col[l]);
-      if (lane == ll) x[sb] = xl;
+    double ca[G][RPL], cb[G][RPL], da[G], db[G];
+    // entries of column l = sb*64 + ll, ll = g0, g0-1, ..., g0-G+1 (0 past
+    // the end and for rows >= l, so that those steps change nothing)
+    auto fetch = [&](int g0, double (&c)[G][RPL], double (&d)[G]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int s = 0; s < RPL; ++s) {
-        const int row = s * 64 + lane;
-        if (s <= sb && row < l) b[s] -= col[row] * xl;
+      for (int g = 0; g < G; ++g) {
+        const int ll = g0 - g, l = sb * 64 + ll;
+        const bool ok = ll >= 0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+          const int row = s * 64 + lane;
+          c[g][s] = (s <= sb && ok && row < l) ? Rt[(int64_t)l * rp + row] : 0.0;
+        }
+        d[g] = ok ? invdiag[l] : 0.0;
       }
+    };
+    auto apply = [&](int g0, const double (&c)[G][RPL], const double (&d)[G]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int ll = g0 - g;
+        if (ll >= 0) {
+          const double xl = bcast_lane(b[sb], ll) * d[g];
+          if (lane == ll) x[sb] = xl;
+#pragma unroll
+          for (int s = 0; s < RPL; ++s)
+            if (s <= sb) b[s] -= c[g][s] * xl;
+        }
+      }
+    };
+    fetch(lstart, ca, da);
+    for (int g0 = lstart; g0 >= 0; g0 -= 2 * G) {
+      if (g0 - G >= 0) fetch(g0 - G, cb, db);
+      apply(g0, ca, da);
+      if (g0 - G < 0) break;
+      if (g0 - 2 * G >= 0) fetch(g0 - 2 * G, ca, da);
+      apply(g0 - G, cb, db);
     }
   }
 #pragma unroll
@@ -310,13 +385,23 @@ __global__ __launch_bounds__(1024) void k_kappa(const double* __restrict__ gdiag
                                                 DevStatus* st) {
   if (failed(st)) return;
   __shared__ double red[2][1024 / 64];
+  __shared__ double dsq[512], dinv[512];   // sqrt(G_jj) and its reciprocal
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < rp; i += 1024) {
+    const double q = sqrt(gdiag[i]);
+    dsq[i] = q;
+    dinv[i] = 1.0 / q;
+  }
+  __syncthreads();
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t e = tid; e < (int64_t)rp * rp; e += 1024) {
+  const int64_t tot = (int64_t)rp * rp;
+#pragma unroll 4
+  for (int64_t e = tid; e < tot; e += 1024) {
     const int i = (int)(e / rp), j = (int)(e % rp);
+    const double rv = R[e], ri = Ri[e];
     if (i <= j && j < r) {
-      const double a = R[e] / sqrt(gdiag[j]);
-      const double b = Ri[e] * sqrt(gdiag[i]);
+      const double a = rv * dinv[j];
+      const double b = ri * dsq[i];
       s1 += a * a;
       s2 += b * b;
     }
@@ -384,10 +469,10 @@ __global__ __launch_bounds__(256) void k_smallgemm(const double* __restrict__ A,
   for (int v = 0; v < 4; ++v) C[(int64_t)(row0 + 4 * v + lk) * rp + col0 + li] = acc[v];
 }
 
-template __global__ void k_trinv<1>(const double*, int, double*, const DevStatus*, bool);
-template __global__ void k_trinv<2>(const double*, int, double*, const DevStatus*, bool);
-template __global__ void k_trinv<4>(const double*, int, double*, const DevStatus*, bool);
-template __global__ void k_trinv<8>(const double*, int, double*, const DevStatus*, bool);
+template __global__ void k_trinv<1>(const double*, int, const double*, double*, const DevStatus*, bool);
+template __global__ void k_trinv<2>(const double*, int, const double*, double*, const DevStatus*, bool);
+template __global__ void k_trinv<4>(const double*, int, const double*, double*, const DevStatus*, bool);
+template __global__ void k_trinv<8>(const double*, int, const double*, double*, const DevStatus*, bool);
 
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz SVD of C (r x r) by block one-sided Jacobi (the sweeps are

@@ -72,7 +72,7 @@ struct wssr_ctx {
   double *G = nullptr, *R1 = nullptr, *R1i = nullptr, *R2 = nullptr, *R2i = nullptr, *Rz = nullptr;
   double *Bc = nullptr, *Pc = nullptr, *Ps = nullptr, *T = nullptr, *scal = nullptr, *sig = nullptr;
   double *cosbuf = nullptr, *cw = nullptr, *vpart = nullptr, *dots = nullptr, *ymean = nullptr, *Tq = nullptr;
-  double *Rt = nullptr, *gdiag = nullptr;
+  double *Rt = nullptr, *gdiag = nullptr, *invdiag = nullptr;
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
 
@@ -463,14 +463,14 @@ struct wssr_ctx {
   // Cholesky of G into R and R^{-1}; a first round (gated = false) also sets
   // the device flag that decides the second round.
   void chol(int rp, int r, double* R, double* Ri, bool gated) {
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), kCholLds, stream, G, rp, R, Rt, gdiag, st, gated);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), kCholLds, stream, G, rp, R, Rt, gdiag, invdiag, st, gated);
     const dim3 g(cdiv(rp, 4));
     switch (rp / 64) {
-      case 1: hipLaunchKernelGGL(k_trinv<1>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
-      case 2: hipLaunchKernelGGL(k_trinv<2>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
+      case 1: hipLaunchKernelGGL(k_trinv<1>, g, dim3(256), 0, stream, (const double*)Rt, rp, (const double*)invdiag, Ri, (const DevStatus*)st, gated); break;
+      case 2: hipLaunchKernelGGL(k_trinv<2>, g, dim3(256), 0, stream, (const double*)Rt, rp, (const double*)invdiag, Ri, (const DevStatus*)st, gated); break;
       case 3:
-      case 4: hipLaunchKernelGGL(k_trinv<4>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
-      default: hipLaunchKernelGGL(k_trinv<8>, g, dim3(256), 0, stream, (const double*)Rt, rp, Ri, (const DevStatus*)st, gated); break;
+      case 4: hipLaunchKernelGGL(k_trinv<4>, g, dim3(256), 0, stream, (const double*)Rt, rp, (const double*)invdiag, Ri, (const DevStatus*)st, gated); break;
+      default: hipLaunchKernelGGL(k_trinv<8>, g, dim3(256), 0, stream, (const double*)Rt, rp, (const double*)invdiag, Ri, (const DevStatus*)st, gated); break;
     }
     if (!gated)
       hipLaunchKernelGGL(k_kappa, dim3(1), dim3(1024), 0, stream, (const double*)gdiag, (const double*)R,
@@ -638,7 +638,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->cw, rp) && h->alloc(h->vpart, (size_t)kVecChunkMax * r) &&
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
             h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
-            h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp) &&
+            h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp) && h->alloc(h->invdiag, rp) &&
             h->alloc(h->jsync, 4) && h->alloc(h->bstat, kBatchMax);
   // stream-K partials (two 128 x 256 tiles per workgroup of one round), only
   // when a parameter-side product can have more tiles than one round holds
