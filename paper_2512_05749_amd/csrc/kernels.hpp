@@ -35,6 +35,16 @@ __global__ void k_gemm_sample_side(const float* O, int64_t ld, int64_t n, int64_
                                    float* ypart, int64_t kchunk, bool vec_o, bool vec_v, const DevStatus* st,
                                    int tn, int tj, bool xcd_groups);
 template <int BN>
+__global__ void k_gemm_sample_side_dma(const float* O, int64_t ld, int64_t n, int64_t m, const float* V, int r,
+                                       float* ypart, int64_t kchunk, const float* zeros, const DevStatus* st, int tn,
+                                       int tj, bool xcd_groups);
+template <int BN>
+__global__ void k_gemm_param_side_dma(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
+                                      float scale, float* Z, const float* zeros, const DevStatus* st, int tiles_j,
+                                      int full_tiles, int64_t sk_units, int sk_wgs, float* part);
+// dynamic LDS bytes of the direct-to-LDS product kernels
+size_t gemm_dma_lds(bool param_side, int bn);
+template <int BN>
 __global__ void k_gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
                                   float scale, float* Z, bool vec_o, bool vec_q, const DevStatus* st, int tiles_j,
                                   int full_tiles, int64_t sk_units, int sk_wgs, float* part);

@@ -364,6 +364,323 @@ __global__ __launch_bounds__(256) void k_streamk_fixup(const float* __restrict__
     if (j0 + col + c < r) Z[grow * r + j0 + col + c] = s[c] * scale;
 }
 
+// ---------------------------------------------------------------------------
+// Direct-to-LDS forms of the two products (used when O and the skinny operand
+// have 16-byte aligned rows).  global_load_lds_dwordx4 copies 16 bytes per
+// lane from any global address into LDS at (M0 base + 16 * lane), without
+// passing through registers.  That frees the prefetch registers, so the LDS
+// holds a ring of three K-steps: while the MFMAs work on step i, steps i+1
+// and i+2 are in flight.  A step's copies are waited for with an explicit
+// vmcnt (each wave knows how many copies it issued after them) and published
+// to the other waves by a bare s_barrier; the slot a copy overwrites was read
+// in the previous step, before that barrier.
+//
+// LDS layouts (one ring slot):
+//   skinny operand S (V or Q_Y), 16 K-rows x BN: K-row major; one copy
+//     instruction moves 1 KB = 256 / BN K-rows, and consecutive instructions
+//     sit SP bytes apart.  Lane (x, h) of MFMA step s reads S[k][j] with
+//     k = s + 8h: rows k and k + 8 then fall into opposite halves of the banks.
+//   parameter side O tile, 16 K-rows x 128 parameters: K-row pairs per copy
+//     instruction, pairs 1056 bytes apart (same argument).
+//   sample side O tile, 128 rows x 16 K-values: 16-byte chunk c of row i sits
+//     at slot 4i + (c ^ ((i >> 2) & 3)); the lane reads of one MFMA fragment
+//     (one 16-byte chunk per lane) then cover distinct banks in every group
+//     of eight lanes.
+// Out-of-range rows and columns of the skinny operand are read from a zero
+// buffer, so they add nothing; out-of-range rows of O are clamped to a valid
+// row (they only meet those zeros, or feed output rows that are not stored).
+// ---------------------------------------------------------------------------
+namespace {
+#define WSSR_LDSP(p) ((__attribute__((address_space(3))) void*)(p))
+constexpr int kDmaStages = 3;
+constexpr int kPairPitch = 1056;   // bytes between K-row pairs of the parameter-side O tile
+constexpr int kSampleA = BM * BK * 4;   // bytes of the sample-side O tile (swizzled, no padding)
+
+template <int BN>
+struct DmaS {
+  static constexpr int RPI = 256 / BN;                                  // K-rows per copy instruction
+  static constexpr int PITCH = 1024 + (RPI == 1 ? 16 : RPI == 2 ? 32 : 64);
+  static constexpr int INSTR = BK / RPI;                                // copy instructions per step
+  static constexpr int BYTES = INSTR * PITCH;
+  // byte offset of element (k, j) of the skinny tile
+  __device__ static __forceinline__ int off(int k, int j) { return (k / RPI) * PITCH + (k % RPI) * (BN * 4) + j * 4; }
+};
+
+// vmcnt wait with lgkmcnt / expcnt left alone
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// copy instructions of one K-step of the skinny tile (rows k0.., columns j0..)
+// issued by wave w into `dst`
+template <int BN>
+__device__ __forceinline__ void dma_skinny(const float* __restrict__ S, int r, int64_t k0, int64_t kend, int j0,
+                                           const float* __restrict__ zeros, unsigned char* dst, int w, int lane) {
+  using D = DmaS<BN>;
+  constexpr int PER_W = D::INSTR / 4;
+#pragma unroll
+  for (int q = 0; q < PER_W; ++q) {
+    const int ins = w * PER_W + q;
+    const int kr = ins * D::RPI + (lane * 4) / BN;
+    const int j = j0 + (lane * 4) % BN;
+    const int64_t k = k0 + kr;
+    const float* src = (k < kend && j < r) ? S + k * r + j : zeros;
+    __builtin_amdgcn_global_load_lds((const void*)src, WSSR_LDSP(dst + ins * D::PITCH), 16, 0, 0);
+  }
+}
+}  // namespace
+
+// Sample side, direct-to-LDS form.  Arguments as k_gemm_sample_side, plus a
+// zero buffer of at least 16 bytes.
+template <int BN>
+__global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __restrict__ O, int64_t ld, int64_t n,
+                                                                 int64_t m, const float* __restrict__ V, int r,
+                                                                 float* __restrict__ ypart, int64_t kchunk,
+                                                                 const float* __restrict__ zeros,
+                                                                 const DevStatus* st, int tn, int tj,
+                                                                 bool xcd_groups) {
+  if (failed(st)) return;
+  using D = DmaS<BN>;
+  constexpr int TB = BN / 64;
+  constexpr int STAGE = kSampleA + D::BYTES;
+  constexpr int PER_STEP = 2 + D::INSTR / 4;    // copy instructions per wave per K-step
+  extern __shared__ __attribute__((aligned(16))) unsigned char smd[];
+  int bx, by, bz;
+  {
+    const int id = blockIdx.x;
+    int grp, i;
+    if (xcd_groups) {
+      const int xcd = id & 7, local = id >> 3;
+      grp = (local / tn) * 8 + xcd;
+      i = local % tn;
+    } else {
+      grp = id / tn;
+      i = id % tn;
+    }
+    bx = i;
+    by = grp % tj;
+    bz = grp / tj;
+  }
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int x = lane & 31, h = lane >> 5;
+  const int64_t n0 = (int64_t)bx * BM;
+  const int j0 = by * BN;
+  const int64_t kb = (int64_t)bz * kchunk;
+  const int64_t ke = min(m, kb + kchunk);
+  float* out = ypart + (int64_t)bz * n * r;
+
+  f32x16 acc[2][TB];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
+
+  auto issue = [&](int64_t k0, int slot) __attribute__((always_inline)) {
+    unsigned char* base = smd + slot * STAGE;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int ins = 2 * w + q;                    // rows 16 ins .. 16 ins + 15
+      const int row = 16 * ins + (lane >> 2);
+      const int c = (lane & 3) ^ ((row >> 2) & 3);  // chunk held by this slot
+      const int64_t gr = min(n0 + row, n - 1);
+      const int64_t gk = k0 + 4 * c;
+      const float* src = (gk < ke) ? O + gr * ld + gk : zeros;
+      __builtin_amdgcn_global_load_lds((const void*)src, WSSR_LDSP(base + ins * 1024), 16, 0, 0);
+    }
+    dma_skinny<BN>(V, r, k0, ke, j0, zeros, base + kSampleA, w, lane);
+  };
+
+  const int64_t ns = (ke - kb + BK - 1) / BK;
+  if (ns > 0) issue(kb, 0);
+  if (ns > 1) issue(kb + BK, 1);
+  int slot = 0;
+  for (int64_t it = 0; it < ns; ++it) {
+    if (it + 1 < ns)
+      wait_vmcnt<PER_STEP>();
+    else
+      wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (it + 2 < ns) issue(kb + (it + 2) * BK, slot == 0 ? 2 : slot - 1);
+    const unsigned char* S = smd + slot * STAGE;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      f32x4 av[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int row = wm * 64 + a * 32 + x;
+        const int c = 2 * h + half;
+        av[a] = *reinterpret_cast<const f32x4*>(S + (row * 4 + (c ^ ((row >> 2) & 3))) * 16);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 8 * h + 4 * half + e;
+        float bv[TB];
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+          bv[b] = *reinterpret_cast<const float*>(S + kSampleA + D::off(k, wn * (BN / 2) + b * 32 + x));
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) acc[a][b] = mfma32x32x2(av[a][e], bv[b], acc[a][b]);
+      }
+    }
+    slot = slot == 2 ? 0 : slot + 1;
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+      const int col = j0 + wn * (BN / 2) + b * 32 + x;
+      if (col >= r) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = n0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < n) out[row * r + col] = acc[a][b][v];
+      }
+    }
+}
+
+// Parameter side, direct-to-LDS form.  Arguments as k_gemm_param_side, plus a
+// zero buffer of at least 16 bytes.
+template <int BN>
+__global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __restrict__ O, int64_t ld, int64_t n,
+                                                                int64_t m, const float* __restrict__ Q, int r,
+                                                                float scale, float* __restrict__ Z,
+                                                                const float* __restrict__ zeros, const DevStatus* st,
+                                                                int tiles_j, int full_tiles, int64_t sk_units,
+                                                                int sk_wgs, float* __restrict__ part) {
+  if (failed(st)) return;
+  using D = DmaS<BN>;
+  constexpr int TB = BN / 64;
+  constexpr int SO = 8 * kPairPitch;
+  constexpr int STAGE = SO + D::BYTES;
+  constexpr int PER_STEP = 2 + D::INSTR / 4;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smd[];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wj = w & 1;
+  const int x = lane & 31, h = lane >> 5;
+  int64_t m0 = 0;
+  int j0 = 0;
+  f32x16 acc[2][TB];
+  const int64_t mlast = ((m - 1) / 4) * 4;      // last 16-byte chunk of a row of O
+
+  auto issue = [&](int64_t ks, int slot) __attribute__((always_inline)) {
+    unsigned char* base = smd + slot * STAGE;
+    const int64_t k0 = ks * BK;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = 2 * w + q;                      // K-rows 2p, 2p + 1
+      const int64_t k = min(k0 + 2 * p + (lane >> 5), n - 1);
+      const int64_t mm = min(m0 + (lane & 31) * 4, mlast);
+      __builtin_amdgcn_global_load_lds((const void*)(O + k * ld + mm), WSSR_LDSP(base + p * kPairPitch), 16, 0, 0);
+    }
+    dma_skinny<BN>(Q, r, k0, n, j0, zeros, base + SO, w, lane);
+  };
+  // acc = the product of tile `tile` over K-steps [kb, ke)
+  auto run = [&](int64_t tile, int64_t kb, int64_t ke) __attribute__((always_inline)) {
+    m0 = (tile / tiles_j) * BM;
+    j0 = (int)(tile % tiles_j) * BN;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
+    const int64_t ns = ke - kb;
+    wait_vmcnt<0>();        // no older stores in the count
+    if (ns > 0) issue(kb, 0);
+    if (ns > 1) issue(kb + 1, 1);
+    int slot = 0;
+    for (int64_t it = 0; it < ns; ++it) {
+      if (it + 1 < ns)
+        wait_vmcnt<PER_STEP>();
+      else
+        wait_vmcnt<0>();
+      __builtin_amdgcn_s_barrier();
+      if (it + 2 < ns) issue(kb + it + 2, slot == 0 ? 2 : slot - 1);
+      const unsigned char* S = smd + slot * STAGE;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = s + 8 * h;
+        float av[2], bv[TB];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          av[a] = *reinterpret_cast<const float*>(S + (k >> 1) * kPairPitch + (k & 1) * 512 +
+                                                  (wm * 64 + a * 32 + x) * 4);
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+          bv[b] = *reinterpret_cast<const float*>(S + SO + D::off(k, wj * (BN / 2) + b * 32 + x));
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) acc[a][b] = mfma32x32x2(av[a], bv[b], acc[a][b]);
+      }
+      slot = slot == 2 ? 0 : slot + 1;
+    }
+    __syncthreads();        // every wave is done with the ring before it is refilled
+  };
+
+  const int64_t nk = (n + BK - 1) / BK;
+  if ((int)blockIdx.x < full_tiles) {
+    run(blockIdx.x, 0, nk);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int col = j0 + wj * (BN / 2) + b * 32 + x;
+        if (col >= r) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = m0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          if (row < m) Z[row * r + col] = acc[a][b][v] * scale;
+        }
+      }
+    return;
+  }
+  // stream-K: at most two tiles per workgroup, written out without a loop
+  const int64_t wg = (int64_t)blockIdx.x - full_tiles;
+  int64_t u = wg * sk_units / sk_wgs;
+  const int64_t uend = (wg + 1) * sk_units / sk_wgs;
+  auto segment = [&](int seg) __attribute__((always_inline)) {
+    const int64_t tl = u / nk, kb = u - tl * nk, ke = min(nk, kb + (uend - u));
+    run(full_tiles + tl, kb, ke);
+    float* outp = part + (wg * 2 + seg) * (int64_t)(BM * BN);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int col = wj * (BN / 2) + b * 32 + x;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          outp[row * BN + col] = acc[a][b][v];
+        }
+      }
+    u += ke - kb;
+  };
+  if (u < uend) segment(0);
+  if (u < uend) segment(1);
+}
+
+size_t gemm_dma_lds(bool param_side, int bn) {
+  const size_t a = param_side ? (size_t)8 * kPairPitch : (size_t)kSampleA;
+  const size_t b = bn == 256 ? DmaS<256>::BYTES : bn == 128 ? DmaS<128>::BYTES : DmaS<64>::BYTES;
+  return kDmaStages * (a + b);
+}
+
+#define WSSR_GEMM_DMA_INST(BN)                                                                                       \
+  template __global__ void k_gemm_sample_side_dma<BN>(const float*, int64_t, int64_t, int64_t, const float*, int,   \
+                                                      float*, int64_t, const float*, const DevStatus*, int, int,    \
+                                                      bool);                                                        \
+  template __global__ void k_gemm_param_side_dma<BN>(const float*, int64_t, int64_t, int64_t, const float*, int,    \
+                                                     float, float*, const float*, const DevStatus*, int, int,       \
+                                                     int64_t, int, float*);
+WSSR_GEMM_DMA_INST(64)
+WSSR_GEMM_DMA_INST(128)
+WSSR_GEMM_DMA_INST(256)
+
 template __global__ void k_gemm_sample_side<64>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
                                                 int64_t, bool, bool, const DevStatus*, int, int, bool);
 template __global__ void k_gemm_sample_side<128>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,

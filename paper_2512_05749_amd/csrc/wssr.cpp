@@ -59,6 +59,7 @@ struct wssr_ctx {
   hipStream_t side = nullptr;    // second stream: the gradient pass runs beside the Rayleigh-Ritz SVD
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float* skpart = nullptr;       // stream-K partial tiles of the parameter-side product
+  float* zeros = nullptr;        // 4 KB of zeros: the source of out-of-range direct-to-LDS copies
   unsigned short* s16 = nullptr; // BF16 forms: split planes of the skinny operand of a product
   int64_t skpart_elems = 0;
   std::vector<void*> allocs;
@@ -299,8 +300,21 @@ struct wssr_ctx {
     if (!b16) {
       const float* O = static_cast<const float*>(Ov);
       const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
+      // direct-to-LDS form: 16-byte aligned rows of O and V, whole 16-byte
+      // chunks of O's rows
+      const bool dma = vec_o && vec_v && (m % 4 == 0);
+      const unsigned dl = (unsigned)gemm_dma_lds(false, bn);
       timed(0, [&] {
-        if (bn == 256)
+        if (dma && bn == 256)
+          hipLaunchKernelGGL(k_gemm_sample_side_dma<256>, grid, dim3(256), dl, stream, O, ld, n, m, V, r, ypart,
+                             kchunk, (const float*)zeros, (const DevStatus*)st, (int)tn, (int)tj, xcd);
+        else if (dma && bn == 128)
+          hipLaunchKernelGGL(k_gemm_sample_side_dma<128>, grid, dim3(256), dl, stream, O, ld, n, m, V, r, ypart,
+                             kchunk, (const float*)zeros, (const DevStatus*)st, (int)tn, (int)tj, xcd);
+        else if (dma)
+          hipLaunchKernelGGL(k_gemm_sample_side_dma<64>, grid, dim3(256), dl, stream, O, ld, n, m, V, r, ypart,
+                             kchunk, (const float*)zeros, (const DevStatus*)st, (int)tn, (int)tj, xcd);
+        else if (bn == 256)
           hipLaunchKernelGGL(k_gemm_sample_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, V, r, ypart, kchunk,
                              vec_o, vec_v, (const DevStatus*)st, (int)tn, (int)tj, xcd);
         else if (bn == 128)
@@ -365,7 +379,18 @@ struct wssr_ctx {
       if (!b16) {
         const float* O = static_cast<const float*>(Ov);
         const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
-        if (bn == 256)
+        const bool dma = vec_o && vec_q;   // direct-to-LDS form: 16-byte aligned rows of O and Q
+        const unsigned dl = (unsigned)gemm_dma_lds(true, bn);
+        if (dma && bn == 256)
+          hipLaunchKernelGGL(k_gemm_param_side_dma<256>, grid, dim3(256), dl, stream, O, ld, n, m, Q, r, scale, Z,
+                             (const float*)zeros, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        else if (dma && bn == 128)
+          hipLaunchKernelGGL(k_gemm_param_side_dma<128>, grid, dim3(256), dl, stream, O, ld, n, m, Q, r, scale, Z,
+                             (const float*)zeros, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        else if (dma)
+          hipLaunchKernelGGL(k_gemm_param_side_dma<64>, grid, dim3(256), dl, stream, O, ld, n, m, Q, r, scale, Z,
+                             (const float*)zeros, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        else if (bn == 256)
           hipLaunchKernelGGL(k_gemm_param_side<256>, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z, vec_o,
                              vec_q, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
         else if (bn == 128)
@@ -649,6 +674,9 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
     h->skpart_elems = (int64_t)h->slots * 2 * 128 * 256;
     ok = h->alloc(h->skpart, (size_t)h->skpart_elems);
   }
+  if (ok) {
+    ok = h->alloc(h->zeros, 1024) && hipMemset(h->zeros, 0, 1024 * sizeof(float)) == hipSuccess;
+  }
   if (!ok) {
     (void)hipGetLastError();
     h->release();
@@ -658,6 +686,17 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
   }
   bool attr_ok =
       hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholLds) == hipSuccess;
+  for (int bn = 64; bn <= 256; bn *= 2) {
+    const void* fs = bn == 256 ? (const void*)k_gemm_sample_side_dma<256>
+                     : bn == 128 ? (const void*)k_gemm_sample_side_dma<128> : (const void*)k_gemm_sample_side_dma<64>;
+    const void* fp = bn == 256 ? (const void*)k_gemm_param_side_dma<256>
+                     : bn == 128 ? (const void*)k_gemm_param_side_dma<128> : (const void*)k_gemm_param_side_dma<64>;
+    attr_ok = attr_ok &&
+              hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_dma_lds(false, bn)) ==
+                  hipSuccess &&
+              hipFuncSetAttribute(fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_dma_lds(true, bn)) ==
+                  hipSuccess;
+  }
   for (int k = 64; k <= rp; k += 64)
     attr_ok = attr_ok && hipFuncSetAttribute(wssr_ctx::jacobi_fn(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)jacobi_lds(k)) == hipSuccess;

@@ -90,6 +90,29 @@ def test_param_side_many_tiles(ws_wide, n, m, r):
     assert row_err.max() < 1e-5
 
 
+# Shapes whose rows are 16-byte aligned (M and r multiples of 4), so both
+# products take their direct-to-LDS form, for each column-tile width (64, 128,
+# 256), with ragged N, a ragged last parameter tile, partial column tiles, and
+# (parameter side) more tiles than one round of workgroups.
+DMA_SHAPES = [(333, 2048, 32), (500, 3000, 100), (257, 4100, 128), (500, 70_000, 200), (96, 100_000, 256),
+              (511, 6_000, 256)]
+
+
+@pytest.mark.parametrize("n,m,r", DMA_SHAPES)
+def test_products_aligned(ws_wide, n, m, r):
+    o, _, v = _inputs(n, m, r, seed=7 * n + r, ld_pad=0)
+    y = ws_wide.sample_side(o, v).cpu().numpy()
+    ref = orc.gemm_sample_side(o.double().cpu().numpy(), v.double().cpu().numpy())
+    assert rel(y, ref) < 2e-6
+    x = torch.randn(n, r, device="cuda", dtype=torch.float32)
+    x -= x.mean(0, keepdim=True)
+    z = ws_wide.param_side(o, x).cpu().numpy()
+    ref = orc.gemm_param_side(o.double().cpu().numpy(), x.double().cpu().numpy())
+    assert rel(z, ref) < 2e-6
+    row_err = np.abs(z - ref).max(1) / (np.abs(ref).max() + 1e-30)
+    assert row_err.max() < 1e-5
+
+
 @pytest.mark.parametrize("rows,r", [(100, 1), (333, 7), (1000, 64), (4000, 65), (4096, 130), (2500, 192),
                                     (3000, 512)])
 def test_cholqr2(ws, ws512, rows, r):
