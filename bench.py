@@ -12,6 +12,9 @@ both sides), Rayleigh-Ritz, signs and the Woodbury apply.
 --compare-f32 1 times the FP32 form on the same instance beside it.
 --config batch16_mixed times the batched form (16 uneven problems per
 wssr_step_batched call) beside the same problems run one after another.
+--sweep 1 times the two product kernels alone on the precision-form shape
+(N=16384, M=1e6) over a range of ranks, FP32 and BF16, and reports each
+against both rooflines (HBM and MFMA): the small ranks are memory-bound.
 
 Prints one JSON line.  `--gpus` above 1 is not supported (single-GPU build).
 """
@@ -72,6 +75,10 @@ def parse():
     ap.add_argument("--plain-inputs", type=int, default=0,
                     help="draw O, E_L and V_0 i.i.d. Gaussian (no QR factorisation in the generator); "
                          "for hardware-counter runs, whose byte counts do not depend on the values")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="time the product kernels alone over a range of ranks (roofline sweep)")
+    ap.add_argument("--sweep-n", type=int, default=16384)
+    ap.add_argument("--sweep-m", type=int, default=1_000_000)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run one elementwise copy of this many MiB before timing, as the reference "
                          "point that scales the HBM byte counters of a counter-collection run")
@@ -146,6 +153,18 @@ def time_form(form, o_ring, e_ring, v_start, cfg, args, dev):
                 diag=diag, v=v)
 
 
+def product_kernel(form, side, cfg):
+    """Name of the product kernel the library launches for this form and
+    side: the FP32 products take their direct-to-LDS form when the rows of O
+    and of the skinny operand are 16-byte aligned (the inputs here are
+    contiguous torch tensors, so that is r % 4 == 0, plus M % 4 == 0 on the
+    sample side)."""
+    if form != "f32":
+        return "k_gemm16_" + side
+    aligned = cfg.r % 4 == 0 and (cfg.m % 4 == 0 or side == "param_side")
+    return "k_gemm_" + side + ("_dma" if aligned else "")
+
+
 def roofline_of(form, prof, cfg):
     n, m, r = cfg.n, cfg.m, cfg.r
     flops_gemm = 2.0 * n * m * r * PRODUCTS[form]     # MFMA flops of one product launch
@@ -159,11 +178,72 @@ def roofline_of(form, prof, cfg):
     achieved = kern[dom]["tflops"]
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": recorded_traffic("k_gemm_" + dom) if form == "f32" else None,
-            "kernel": "k_gemm_" + dom if form == "f32" else "k_gemm16_" + dom, "avg_ms": round(kern[dom]["avg_ms"], 4),
+            "traffic": recorded_traffic(product_kernel(form, dom, cfg)) if form == "f32" else None,
+            "kernel": product_kernel(form, dom, cfg), "avg_ms": round(kern[dom]["avg_ms"], 4),
             "flops_per_launch": flops_gemm, "products": PRODUCTS[form],
             "other": {k: {"avg_ms": round(v_["avg_ms"], 4), "tflops": round(v_["tflops"], 2)}
                       for k, v_ in kern.items() if k != dom}}
+
+
+PEAK_HBM_GBS = 8000.0
+SWEEP_RANKS = {"f32": [8, 16, 32, 64, 128, 256], "bf16": [16, 32, 64, 128, 256, 512]}
+
+
+def run_sweep(args):
+    """The two products alone on an N x M O (i.i.d. Gaussian values; the
+    kernels' work does not depend on them), for each rank of SWEEP_RANKS:
+    the kernel time (HIP events around each product launch, read back from
+    the library), its algorithmic bytes and flops, and the fraction of the
+    roofline it reaches, roofline time = max(bytes / HBM peak, flops / MFMA
+    peak).  Algorithmic bytes of a product: one read of O, one of the skinny
+    operand, one write of the output (FP32)."""
+    import torch
+
+    from paper_2512_05749_amd import Wssr
+
+    n, m = args.sweep_n, args.sweep_m
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    gen = torch.Generator(device=dev).manual_seed(11)
+    rows = []
+    for form in ("f32", "bf16"):
+        dt = torch.float32 if form == "f32" else torch.bfloat16
+        o = torch.randn(n, m, device=dev, dtype=dt, generator=gen)
+        b_o = 4 if form == "f32" else 2
+        peak = PEAK_FP32_TFLOPS if form == "f32" else PEAK_BF16_TFLOPS
+        for r in SWEEP_RANKS[form]:
+            h = Wssr(n_max=n, m_max=m, r_max=r, q_max=2, device=dev, dtype=form)
+            v = torch.randn(m, r, device=dev, dtype=torch.float32, generator=gen)
+            x = torch.randn(n, r, device=dev, dtype=torch.float32, generator=gen)
+            h.sample_side(o, v)
+            h.param_side(o, x)
+            torch.cuda.synchronize()
+            h.profile(True)
+            for _ in range(3):
+                h.sample_side(o, v)
+                h.param_side(o, x)
+            torch.cuda.synchronize()
+            prof = h.profile_read()
+            h.profile(False)
+            h.close()
+            del v, x
+            flops = 2.0 * n * m * r
+            for side in ("sample_side", "param_side"):
+                ms_, cnt = prof[side]
+                avg = ms_ / max(cnt, 1)
+                nbytes = n * m * b_o + 4.0 * (m * r + n * r)
+                t_hbm, t_mfma = nbytes / (PEAK_HBM_GBS * 1e9), flops / (peak * 1e12)
+                bound = "hbm" if t_hbm >= t_mfma else "mfma"
+                row = {"form": form, "r": r, "side": side, "kernel": product_kernel(form, side, type("C", (), {"m": m, "r": r})),
+                       "ms": round(avg, 4), "GB/s": round(nbytes / (avg * 1e-3) / 1e9, 1),
+                       "TFLOP/s": round(flops / (avg * 1e-3) / 1e12, 1), "bound": bound,
+                       "frac_of_bound": round(max(t_hbm, t_mfma) / (avg * 1e-3), 4)}
+                rows.append(row)
+                log(f"[sweep] {row}")
+        del o
+        torch.cuda.empty_cache()
+    print(json.dumps({"sweep": "product kernels alone", "n": n, "m": m, "peaks": {"hbm_GBs": PEAK_HBM_GBS,
+                      "fp32_TFs": PEAK_FP32_TFLOPS, "bf16_TFs": PEAK_BF16_TFLOPS}, "rows": rows}))
 
 
 def run_batched(args):
@@ -265,6 +345,8 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        return run_sweep(args)
     if args.config == "batch16_mixed":
         # the lanes and their second streams need their own hardware queues to
         # run side by side (HIP maps streams onto this many queues; set before

@@ -60,8 +60,8 @@ __global__ void k_gradient16_partial(const unsigned short* O, int64_t ld, int64_
 // PA planes of O, PB planes of the skinny operand, which k_split_skinny has
 // split into BF16 planes laid out [k / 16][column][k % 16] (plane stride in
 // elements).
-__global__ void k_split_skinny(const float* S, int64_t K, int r, unsigned short* out, int64_t pstride, int planes,
-                               const DevStatus* st);
+__global__ void k_split_skinny(const float* S, int64_t K, int r, int sw, unsigned short* out, int64_t pstride,
+                               int planes, const DevStatus* st);
 template <int BN, int BK, int PA, int PB>
 __global__ void k_gemm16_sample_side(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
                                      const unsigned short* Vs, int64_t vstride, int r, float* ypart, int64_t kchunk,

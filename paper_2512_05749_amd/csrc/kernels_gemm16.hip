@@ -116,7 +116,7 @@ struct SUnit {
 };
 
 template <int BN, int BK, int PB, int PT>
-__device__ __forceinline__ void s_load(u32x4 (&rs)[PB][PT], const u16* __restrict__ Ss, int64_t pstride, int r,
+__device__ __forceinline__ void s_load(u32x4 (&rs)[PB][PT], const u16* __restrict__ Ss, int64_t pstride, int sw,
                                        int64_t kblocks, int j0, int64_t k0, bool fast, int t) {
 #pragma unroll
   for (int q = 0; q < PB; ++q)
@@ -129,8 +129,8 @@ __device__ __forceinline__ void s_load(u32x4 (&rs)[PB][PT], const u16* __restric
       const int kb = unit / (2 * BN), c = (unit % (2 * BN)) >> 1, h8 = unit & 1;
       const int64_t blk = k0 / 16 + kb;
       const int j = j0 + c;
-      const u16* src = Ss + q * pstride + (blk * r + j) * 16 + h8 * 8;
-      if (fast || (j < r && blk < kblocks))
+      const u16* src = Ss + q * pstride + (blk * sw + j) * 16 + h8 * 8;
+      if (fast || blk < kblocks)
         rs[q][u] = *reinterpret_cast<const u32x4*>(src);
       else
         rs[q][u] = u32x4{0, 0, 0, 0};
@@ -154,24 +154,26 @@ __device__ __forceinline__ void s_store(const u32x4 (&rs)[PB][PT], u16* __restri
 
 // ---------------------------------------------------------------------------
 // S (K x r FP32, row-major) -> BF16 planes hi (and lo when two planes) in the
-// K-blocked layout [kb][j][k % 16], zero for k >= K.  One thread per (kb, j):
+// K-blocked layout [kb][j][k % 16] with sw >= r columns (a whole number of
+// product column tiles), zero for k >= K and for j >= r, so that the product
+// kernels read whole tiles of S unguarded.  One thread per (kb, j):
 // 16 loads that are coalesced across threads (consecutive j), two 32-byte
 // stores per plane.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_split_skinny(const float* __restrict__ S, int64_t K, int r,
+__global__ __launch_bounds__(256) void k_split_skinny(const float* __restrict__ S, int64_t K, int r, int sw,
                                                       u16* __restrict__ out, int64_t pstride, int planes,
                                                       const DevStatus* st) {
   if (failed(st)) return;
   const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t kblocks = (K + 15) / 16;
-  if (id >= kblocks * r) return;
-  const int64_t kb = id / r;
-  const int j = (int)(id % r);
+  if (id >= kblocks * sw) return;
+  const int64_t kb = id / sw;
+  const int j = (int)(id % sw);
   u16 hi[16], lo[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int64_t k = kb * 16 + e;
-    const float x = (k < K) ? S[k * r + j] : 0.0f;
+    const float x = (k < K && j < r) ? S[k * r + j] : 0.0f;
     split_bf16(x, hi[e], lo[e]);
   }
   u16* dst = out + id * 16;
@@ -205,6 +207,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
                                                                bool xcd_groups) {
   if (failed(st)) return;
   using G = Geo<BN, BK, PA, PB, false>;
+  const int sw = tj * BN;                         // column width of the split planes of V
   constexpr int AU = BM * BK / 8;                 // 16-byte A units per plane
   constexpr int APT = (AU + 255) / 256;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem16[];
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
   constexpr int SPT = SUnit<BN, BK>::PER_T;
   u32x4 rs[PB][SPT];
   const int64_t kblocks = (m + 15) / 16;
-  const bool inner = vec_o && (n0 + BM <= n) && (j0 + BN <= r);
+  const bool inner = vec_o && (n0 + BM <= n);
   auto gload = [&](int64_t k0) __attribute__((always_inline)) {
     const bool fast = inner && k0 + BK <= ke;
 #pragma unroll
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side(const u16* __rest
           ra[p][u] = u32x4{pack2(e8[0], e8[1]), pack2(e8[2], e8[3]), pack2(e8[4], e8[5]), pack2(e8[6], e8[7])};
         }
       }
-    s_load<BN, BK, PB, SPT>(rs, Vs, vstride, r, kblocks, j0, k0, fast, t);
+    s_load<BN, BK, PB, SPT>(rs, Vs, vstride, sw, kblocks, j0, k0, fast, t);
   };
   auto sstore = [&](int buf) __attribute__((always_inline)) {
     u16* S = lds + buf * G::STAGE;
@@ -324,6 +327,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
                                                               int sk_wgs, float* __restrict__ part) {
   if (failed(st)) return;
   using G = Geo<BN, BK, PA, PB, true>;
+  const int sw = tiles_j * BN;                    // column width of the split planes of Q
   constexpr int AU = BK * (BM / 8);                // 16-byte units (8 parameters of one K-row) per plane
   constexpr int APT = (AU + 255) / 256;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem16[];
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
           ro[p][u] = u32x4{pack2(e8[0], e8[1]), pack2(e8[2], e8[3]), pack2(e8[4], e8[5]), pack2(e8[6], e8[7])};
         }
       }
-    s_load<BN, BK, PB, SPT>(rs, Qs, qstride, r, kblocks, j0, k0, fast, t);
+    s_load<BN, BK, PB, SPT>(rs, Qs, qstride, sw, kblocks, j0, k0, fast, t);
   };
   auto sstore = [&](int buf) __attribute__((always_inline)) {
     u16* S = lds + buf * G::STAGE;
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
   auto run = [&](int64_t tile, int64_t kb, int64_t ke) __attribute__((always_inline)) {
     m0 = (tile / tiles_j) * BM;
     j0 = (int)(tile % tiles_j) * BN;
-    inner = vec_o && (m0 + BM <= m) && (j0 + BN <= r);
+    inner = vec_o && (m0 + BM <= m);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll

@@ -261,10 +261,12 @@ struct wssr_ctx {
   int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
 
   // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
-  // when pb = 2), K-blocked; returns the plane stride in elements
-  int64_t split_skinny(const float* S, int64_t K, int r, int pb) {
-    const int64_t kblocks = cdiv(K, 16), ps = kblocks * 16 * r;
-    hipLaunchKernelGGL(k_split_skinny, dim3(cdiv(kblocks * r, 256)), dim3(256), 0, stream, S, K, r, s16, ps, pb,
+  // when pb = 2), K-blocked, r padded with zero columns to the product's
+  // column tiles (bn); returns the plane stride in elements
+  int64_t split_skinny(const float* S, int64_t K, int r, int pb, int bn) {
+    const int sw = (int)rup(r, bn);
+    const int64_t kblocks = cdiv(K, 16), ps = kblocks * 16 * sw;
+    hipLaunchKernelGGL(k_split_skinny, dim3(cdiv(kblocks * sw, 256)), dim3(256), 0, stream, S, K, r, sw, s16, ps, pb,
                        (const DevStatus*)st);
     return ps;
   }
@@ -329,7 +331,7 @@ struct wssr_ctx {
       const int64_t ps = n * ld;
       const bool vec_o = (ld % 8 == 0) && ((uintptr_t)O % 16 == 0);
       const unsigned lds = (unsigned)gemm16_lds(bn, bk, pa, pb);
-      const int64_t vs = split_skinny(V, m, r, pb);
+      const int64_t vs = split_skinny(V, m, r, pb, bn);
       timed(0, [&] {
 #define WSSR_S16(BN, BK, PA, PB)                                                                                     \
   hipLaunchKernelGGL((k_gemm16_sample_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,          \
@@ -374,7 +376,7 @@ struct wssr_ctx {
       }
     }
     const dim3 grid(full + skw);
-    const int64_t qs = b16 ? split_skinny(Q, n, r, pb) : 0;
+    const int64_t qs = b16 ? split_skinny(Q, n, r, pb, bn) : 0;
     timed(1, [&] {
       if (!b16) {
         const float* O = static_cast<const float*>(Ov);
@@ -669,7 +671,8 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
   // when a parameter-side product can have more tiles than one round holds
   // (capacity for 2 slots per CU at 128 x 256 or 1 slot per CU at 128 x 512)
   const int64_t ptiles = cdiv(m, 128);
-  if (ok && cfg->o_dtype != WSSR_F32) ok = h->alloc(h->s16, (size_t)2 * cdiv(rows, 16) * 16 * r);
+  if (ok && cfg->o_dtype != WSSR_F32)
+    ok = h->alloc(h->s16, (size_t)2 * cdiv(rows, 16) * 16 * rup(r, wssr_ctx::bn_for(r, true)));
   if (ok && ptiles > h->slots / 2) {
     h->skpart_elems = (int64_t)h->slots * 2 * 128 * 256;
     ok = h->alloc(h->skpart, (size_t)h->skpart_elems);
