@@ -72,6 +72,18 @@ __global__ void k_gemm16_param_side(const unsigned short* O, int64_t ld, int64_t
                                     bool vec_o, const DevStatus* st, int tiles_j, int full_tiles, int64_t sk_units,
                                     int sk_wgs, float* part);
 size_t gemm16_lds(int bn, int bk, int pa, int pb);
+template <int BN, int BK, int PA, int PB>
+__global__ void k_gemm16_sample_side_dma(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
+                                         const unsigned short* Vs, int64_t vstride, int r, float* ypart,
+                                         int64_t kchunk, const unsigned short* zeros, const DevStatus* st, int tn,
+                                         int tj, bool xcd_groups);
+template <int BN, int BK, int PA, int PB>
+__global__ void k_gemm16_param_side_dma(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
+                                        const unsigned short* Qs, int64_t qstride, int r, float scale, float* Z,
+                                        const unsigned short* zeros, const DevStatus* st, int tiles_j, int full_tiles,
+                                        int64_t sk_units, int sk_wgs, float* part);
+// dynamic LDS bytes of the direct-to-LDS BF16 product kernels
+size_t gemm16_dma_lds(int bn, int bk, int pa, int pb);
 
 template <typename T>
 __global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,

@@ -444,6 +444,350 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_param_side(const u16* __restr
   if (u < uend) segment(1);
 }
 
+// ---------------------------------------------------------------------------
+// Direct-to-LDS forms of the BF16 products (used when the rows of O are
+// 16-byte aligned and M is a multiple of 8).  As in the FP32 products,
+// global_load_lds_dwordx4 fills a ring of three K-steps in LDS without
+// passing through registers; a step's copies are waited for with an explicit
+// vmcnt and published by a bare s_barrier.
+//
+// LDS layouts of one ring slot (per plane):
+//   S (split skinny operand): the K-blocked global layout [k-block][j][16]
+//     of the tile's columns, copied as is; a B fragment (8 K-values of one
+//     column) is one 16-byte read, 32 bytes apart across lanes.
+//   sample-side O (rows K-contiguous): CPR = BK/8 chunks of 16 bytes per row,
+//     chunk c of row i at slot CPR*i + (c ^ swz(i)), swz(i) = (i >> 2) & 3
+//     when CPR = 4; an A fragment is one 16-byte read.
+//   parameter-side O (rows are the K index): four K-rows of 128 parameters
+//     per copy instruction; chunk c (8 parameters) of the instruction's row
+//     rho at slot 16 rho + (c ^ 2 rho).  An A fragment (8 K-values of one
+//     parameter) is two ds_read_b64_tr_b16: in a group of 16 lanes, lane
+//     4 rho + q points at parameters 4q..4q+3 of K-row rho, and lane j gets
+//     K-rows 0..3 of parameter j (the swizzle keeps the group's four rows
+//     in different banks).
+// ---------------------------------------------------------------------------
+namespace {
+#define WSSR_LDS16(p) ((__attribute__((address_space(3))) void*)(p))
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+constexpr int kStages16 = 3;
+
+template <int BN, int BK, int PA, int PB, bool PARAM>
+struct G16 {
+  static constexpr int TB = BN / 64;                  // 32-column MFMA tiles per wave
+  static constexpr int KB = BK / 16;                  // MFMA K-blocks per step
+  static constexpr int A_PLANE = BM * BK * 2;         // bytes
+  static constexpr int S_PLANE = BN * BK * 2;
+  static constexpr int STAGE = PA * A_PLANE + PB * S_PLANE;
+  static constexpr int A_INSTR = A_PLANE / 1024;      // copy instructions per plane and step
+  static constexpr int S_INSTR = S_PLANE / 1024;
+  static constexpr int PER_STEP = (PA * A_INSTR + PB * S_INSTR) / 4;   // per wave
+  static_assert((PA * A_INSTR) % 4 == 0 && (PB * S_INSTR) % 4 == 0, "copies split evenly over four waves");
+};
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt16() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// copies of one step of the split skinny operand: k-blocks kb0.. of columns
+// j0..j0+BN of each plane (plane stride pstride elements, sw columns)
+template <int BN, int BK, int PB>
+__device__ __forceinline__ void dma16_s(const u16* __restrict__ Ss, int64_t pstride, int sw, int64_t kblocks,
+                                        int64_t kb0, int j0, const u16* __restrict__ zeros, unsigned char* dst,
+                                        int w, int lane) {
+  constexpr int PER_KB = BN * 32 / 1024;   // instructions per k-block and plane
+  constexpr int TOT = PB * (BK / 16) * PER_KB;
+#pragma unroll
+  for (int q = 0; q < TOT / 4; ++q) {
+    const int ins = w * (TOT / 4) + q;
+    const int pl = ins / ((BK / 16) * PER_KB), rem = ins % ((BK / 16) * PER_KB);
+    const int kb = rem / PER_KB, part = rem % PER_KB;
+    const int64_t blk = kb0 + kb;
+    const int64_t e = (blk * sw + j0) * 16 + (int64_t)part * 512 + lane * 8;   // 8 elements per lane
+    const u16* src = blk < kblocks ? Ss + pl * pstride + e : zeros;
+    __builtin_amdgcn_global_load_lds((const void*)src,
+                                     WSSR_LDS16(dst + pl * (BN * BK * 2) + kb * (BN * 32) + part * 1024), 16, 0, 0);
+  }
+}
+
+// MFMAs of one ring slot: acc[a][b] += sum over products of A_p B_q
+template <int BN, int BK, int PA, int PB, bool PARAM>
+__device__ __forceinline__ void mma16_slot(f32x16 (&acc)[2][BN / 64], const unsigned char* S, int wm, int wn,
+                                           int lane) {
+  using G = G16<BN, BK, PA, PB, PARAM>;
+  const int x = lane & 31, hh = lane >> 5;
+#pragma unroll
+  for (int kb = 0; kb < G::KB; ++kb) {
+    u32x4 av[PA][2], bv[PB][G::TB];
+#pragma unroll
+    for (int p = 0; p < PA; ++p)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const unsigned char* A = S + p * G::A_PLANE;
+        if constexpr (!PARAM) {
+          constexpr int CPR = BK / 8;
+          const int row = wm * 64 + a * 32 + x;
+          const int c = 2 * kb + hh;
+          const int swz = CPR == 4 ? ((row >> 2) & 3) : 0;
+          av[p][a] = *reinterpret_cast<const u32x4*>(A + (row * CPR + (c ^ swz)) * 16);
+        } else {
+          // group g = lane / 16: parameters mbase..mbase+15, K-rows kbase.. (+4s)
+          const int g = lane >> 4, i = lane & 15;
+          const int rho = i >> 2, q = i & 3;
+          const int mbase = wm * 64 + a * 32 + 16 * (g & 1);
+          const int c = (mbase >> 3) + (q >> 1);
+          v4i16 part[2];
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int k = 16 * kb + 8 * (g >> 1) + 4 * s2 + rho;   // this lane's K-row
+            const unsigned char* src = A + (k >> 2) * 1024 + rho * 256 + ((c ^ (2 * rho)) * 16) + (q & 1) * 8;
+            part[s2] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) v4i16*)src);
+          }
+          const unsigned lo0 = (unsigned)(unsigned short)part[0][0] | ((unsigned)(unsigned short)part[0][1] << 16);
+          const unsigned lo1 = (unsigned)(unsigned short)part[0][2] | ((unsigned)(unsigned short)part[0][3] << 16);
+          const unsigned hi0 = (unsigned)(unsigned short)part[1][0] | ((unsigned)(unsigned short)part[1][1] << 16);
+          const unsigned hi1 = (unsigned)(unsigned short)part[1][2] | ((unsigned)(unsigned short)part[1][3] << 16);
+          av[p][a] = u32x4{lo0, lo1, hi0, hi1};
+        }
+      }
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+#pragma unroll
+      for (int b = 0; b < G::TB; ++b)
+        bv[q][b] = *reinterpret_cast<const u32x4*>(S + PA * G::A_PLANE + q * G::S_PLANE + kb * (BN * 32) +
+                                                   (wn * (BN / 2) + b * 32 + x) * 32 + hh * 16);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < G::TB; ++b) {
+        acc[a][b] = mfma_bf16(av[0][a], bv[0][b], acc[a][b]);
+        if constexpr (PB == 2) acc[a][b] = mfma_bf16(av[0][a], bv[1][b], acc[a][b]);
+        if constexpr (PA == 2) acc[a][b] = mfma_bf16(av[1][a], bv[0][b], acc[a][b]);
+      }
+  }
+}
+}  // namespace
+
+// Sample side, direct-to-LDS form (arguments as k_gemm16_sample_side, plus a
+// zero buffer of at least 16 bytes).
+template <int BN, int BK, int PA, int PB>
+__global__ __launch_bounds__(256, 1) void k_gemm16_sample_side_dma(const u16* __restrict__ O, int64_t ld,
+                                                                   int64_t pstride, int64_t n, int64_t m,
+                                                                   const u16* __restrict__ Vs, int64_t vstride, int r,
+                                                                   float* __restrict__ ypart, int64_t kchunk,
+                                                                   const u16* __restrict__ zeros,
+                                                                   const DevStatus* st, int tn, int tj,
+                                                                   bool xcd_groups) {
+  if (failed(st)) return;
+  using G = G16<BN, BK, PA, PB, false>;
+  constexpr int CPR = BK / 8;
+  extern __shared__ __attribute__((aligned(16))) unsigned char sm16[];
+  const int sw = tj * BN;
+  int bx, by, bz;
+  {
+    const int id = blockIdx.x;
+    int grp, i;
+    if (xcd_groups) {
+      const int xcd = id & 7, local = id >> 3;
+      grp = (local / tn) * 8 + xcd;
+      i = local % tn;
+    } else {
+      grp = id / tn;
+      i = id % tn;
+    }
+    bx = i;
+    by = grp % tj;
+    bz = grp / tj;
+  }
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int x = lane & 31, hh = lane >> 5;
+  const int64_t n0 = (int64_t)bx * BM;
+  const int j0 = by * BN;
+  const int64_t kb = (int64_t)bz * kchunk;
+  const int64_t ke = min(m, kb + kchunk);
+  const int64_t kblocks = (m + 15) / 16;
+  float* out = ypart + (int64_t)bz * n * r;
+
+  f32x16 acc[2][G::TB];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < G::TB; ++b) acc[a][b] = f32x16{0};
+
+  auto issue = [&](int64_t k0, int slot) __attribute__((always_inline)) {
+    unsigned char* base = sm16 + slot * G::STAGE;
+#pragma unroll
+    for (int q = 0; q < PA * G::A_INSTR / 4; ++q) {
+      const int ins = w * (PA * G::A_INSTR / 4) + q;
+      const int pl = ins / G::A_INSTR, pi = ins % G::A_INSTR;
+      const int slotid = pi * 64 + lane;                // 16-byte slot of the plane
+      const int row = slotid / CPR;
+      const int c = (slotid % CPR) ^ (CPR == 4 ? ((row >> 2) & 3) : 0);
+      const int64_t gr = min(n0 + row, n - 1);
+      const int64_t gk = k0 + 8 * c;
+      const u16* src = gk < ke ? O + pl * pstride + gr * ld + gk : zeros;
+      __builtin_amdgcn_global_load_lds((const void*)src, WSSR_LDS16(base + pl * G::A_PLANE + pi * 1024), 16, 0, 0);
+    }
+    dma16_s<BN, BK, PB>(Vs, vstride, sw, kblocks, k0 / 16, j0, zeros, base + PA * G::A_PLANE, w, lane);
+  };
+
+  const int64_t ns = (ke - kb + BK - 1) / BK;
+  if (ns > 0) issue(kb, 0);
+  if (ns > 1) issue(kb + BK, 1);
+  int slot = 0;
+  for (int64_t it = 0; it < ns; ++it) {
+    if (it + 1 < ns)
+      wait_vmcnt16<G::PER_STEP>();
+    else
+      wait_vmcnt16<0>();
+    __builtin_amdgcn_s_barrier();
+    if (it + 2 < ns) issue(kb + (it + 2) * BK, slot == 0 ? 2 : slot - 1);
+    mma16_slot<BN, BK, PA, PB, false>(acc, sm16 + slot * G::STAGE, wm, wn, lane);
+    slot = slot == 2 ? 0 : slot + 1;
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < G::TB; ++b) {
+      const int col = j0 + wn * (BN / 2) + b * 32 + x;
+      if (col >= r) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = n0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * hh + (v & 3);
+        if (row < n) out[row * r + col] = acc[a][b][v];
+      }
+    }
+}
+
+// Parameter side, direct-to-LDS form (arguments as k_gemm16_param_side, plus
+// a zero buffer of at least 16 bytes).
+template <int BN, int BK, int PA, int PB>
+__global__ __launch_bounds__(256, 1) void k_gemm16_param_side_dma(const u16* __restrict__ O, int64_t ld,
+                                                                  int64_t pstride, int64_t n, int64_t m,
+                                                                  const u16* __restrict__ Qs, int64_t qstride, int r,
+                                                                  float scale, float* __restrict__ Z,
+                                                                  const u16* __restrict__ zeros, const DevStatus* st,
+                                                                  int tiles_j, int full_tiles, int64_t sk_units,
+                                                                  int sk_wgs, float* __restrict__ part) {
+  if (failed(st)) return;
+  using G = G16<BN, BK, PA, PB, true>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char sm16[];
+  const int sw = tiles_j * BN;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int x = lane & 31, hh = lane >> 5;
+  const int64_t kblocks = (n + 15) / 16;
+  const int64_t mlast = ((m - 1) / 8) * 8;   // first parameter of the last 16-byte chunk of a row
+  int64_t m0 = 0;
+  int j0 = 0;
+  f32x16 acc[2][G::TB];
+
+  auto issue = [&](int64_t ks, int slot) __attribute__((always_inline)) {
+    unsigned char* base = sm16 + slot * G::STAGE;
+    const int64_t k0 = ks * BK;
+#pragma unroll
+    for (int q = 0; q < PA * G::A_INSTR / 4; ++q) {
+      const int ins = w * (PA * G::A_INSTR / 4) + q;
+      const int pl = ins / G::A_INSTR, pi = ins % G::A_INSTR;   // K-rows 4 pi .. 4 pi + 3
+      const int rho = lane >> 4, c = (lane & 15) ^ (2 * rho);
+      const int64_t k = min(k0 + 4 * pi + rho, n - 1);
+      const int64_t mm = min(m0 + 8 * c, mlast);
+      __builtin_amdgcn_global_load_lds((const void*)(O + pl * pstride + k * ld + mm),
+                                       WSSR_LDS16(base + pl * G::A_PLANE + pi * 1024), 16, 0, 0);
+    }
+    dma16_s<BN, BK, PB>(Qs, qstride, sw, kblocks, k0 / 16, j0, zeros, base + PA * G::A_PLANE, w, lane);
+  };
+  auto run = [&](int64_t tile, int64_t kb, int64_t ke) __attribute__((always_inline)) {
+    m0 = (tile / tiles_j) * BM;
+    j0 = (int)(tile % tiles_j) * BN;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < G::TB; ++b) acc[a][b] = f32x16{0};
+    const int64_t ns = ke - kb;
+    wait_vmcnt16<0>();
+    if (ns > 0) issue(kb, 0);
+    if (ns > 1) issue(kb + 1, 1);
+    int slot = 0;
+    for (int64_t it = 0; it < ns; ++it) {
+      if (it + 1 < ns)
+        wait_vmcnt16<G::PER_STEP>();
+      else
+        wait_vmcnt16<0>();
+      __builtin_amdgcn_s_barrier();
+      if (it + 2 < ns) issue(kb + it + 2, slot == 0 ? 2 : slot - 1);
+      mma16_slot<BN, BK, PA, PB, true>(acc, sm16 + slot * G::STAGE, wm, wn, lane);
+      slot = slot == 2 ? 0 : slot + 1;
+    }
+    __syncthreads();
+  };
+
+  const int64_t nk = (n + BK - 1) / BK;
+  if ((int)blockIdx.x < full_tiles) {
+    run(blockIdx.x, 0, nk);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < G::TB; ++b) {
+        const int col = j0 + wn * (BN / 2) + b * 32 + x;
+        if (col >= r) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = m0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * hh + (v & 3);
+          if (row < m) Z[row * r + col] = acc[a][b][v] * scale;
+        }
+      }
+    return;
+  }
+  const int64_t wg = (int64_t)blockIdx.x - full_tiles;
+  int64_t u = wg * sk_units / sk_wgs;
+  const int64_t uend = (wg + 1) * sk_units / sk_wgs;
+  auto segment = [&](int seg) __attribute__((always_inline)) {
+    const int64_t tl = u / nk, kb = u - tl * nk, ke = min(nk, kb + (uend - u));
+    run(full_tiles + tl, kb, ke);
+    float* outp = part + (wg * 2 + seg) * (int64_t)(BM * BN);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < G::TB; ++b) {
+        const int col = wn * (BN / 2) + b * 32 + x;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * hh + (v & 3);
+          outp[row * BN + col] = acc[a][b][v];
+        }
+      }
+    u += ke - kb;
+  };
+  if (u < uend) segment(0);
+  if (u < uend) segment(1);
+}
+
+// dynamic LDS bytes of a direct-to-LDS BF16 product kernel
+size_t gemm16_dma_lds(int bn, int bk, int pa, int pb) {
+  return (size_t)kStages16 * ((size_t)pa * BM * bk * 2 + (size_t)pb * bn * bk * 2);
+}
+
+#define WSSR_GEMM16_DMA_INST(BN, BK, PA, PB)                                                                         \
+  template __global__ void k_gemm16_sample_side_dma<BN, BK, PA, PB>(                                                \
+      const u16*, int64_t, int64_t, int64_t, int64_t, const u16*, int64_t, int, float*, int64_t, const u16*,        \
+      const DevStatus*, int, int, bool);                                                                            \
+  template __global__ void k_gemm16_param_side_dma<BN, BK, PA, PB>(                                                 \
+      const u16*, int64_t, int64_t, int64_t, int64_t, const u16*, int64_t, int, float, float*, const u16*,          \
+      const DevStatus*, int, int, int64_t, int, float*);
+WSSR_GEMM16_DMA_INST(128, 32, 1, 1)
+WSSR_GEMM16_DMA_INST(128, 32, 1, 2)
+WSSR_GEMM16_DMA_INST(128, 32, 2, 2)
+WSSR_GEMM16_DMA_INST(256, 32, 1, 1)
+WSSR_GEMM16_DMA_INST(256, 32, 1, 2)
+WSSR_GEMM16_DMA_INST(256, 32, 2, 2)
+WSSR_GEMM16_DMA_INST(512, 32, 1, 1)
+WSSR_GEMM16_DMA_INST(512, 16, 1, 2)
+WSSR_GEMM16_DMA_INST(512, 16, 2, 2)
+
 // dynamic LDS bytes of a BF16 product kernel
 size_t gemm16_lds(int bn, int bk, int pa, int pb) {
   const size_t a_k = (size_t)BM * (bk + 8), a_t = (size_t)bk * (BM + 8);

@@ -17,6 +17,8 @@ using namespace wssr;
 
 namespace {
 
+// K-step of a direct-to-LDS BF16 product kernel instantiation (wssr_ctx::bk_dma)
+#define BKD(BN, PA, PB) ((BN) == 512 && ((PA) > 1 || (PB) > 1) ? 16 : 32)
 constexpr int kS1Max = 32;      // split-K ranges of the sample-side product
 constexpr int kGSplitMax = 16;  // row splits of the gradient
 constexpr int kVecChunkMax = 1024;
@@ -238,9 +240,20 @@ struct wssr_ctx {
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, (size_t)lds) != hipSuccess || per < 1) per = 1;
       out = per * cus;
     };
+    auto oned = [&](const void* fn, int bn, int bk, int pa, int pb, int& out) {
+      const int lds = (int)gemm16_dma_lds(bn, bk, pa, pb);
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) ok = false;
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, (size_t)lds) != hipSuccess || per < 1) per = 1;
+      out = per * cus;
+    };
 #define WSSR_SETUP16(BN, BK, PA, PB)                                                                                 \
   one((const void*)k_gemm16_sample_side<BN, BK, PA, PB>, BN, BK, PA, PB, slots16s[v16(BN, PA, PB)]);                 \
-  one((const void*)k_gemm16_param_side<BN, BK, PA, PB>, BN, BK, PA, PB, slots16p[v16(BN, PA, PB)]);
+  one((const void*)k_gemm16_param_side<BN, BK, PA, PB>, BN, BK, PA, PB, slots16p[v16(BN, PA, PB)]);                  \
+  oned((const void*)k_gemm16_sample_side_dma<BN, BKD(BN, PA, PB), PA, PB>, BN, BKD(BN, PA, PB), PA, PB,              \
+       slots16sd[v16(BN, PA, PB)]);                                                                                 \
+  oned((const void*)k_gemm16_param_side_dma<BN, BKD(BN, PA, PB), PA, PB>, BN, BKD(BN, PA, PB), PA, PB,               \
+       slots16pd[v16(BN, PA, PB)]);
     WSSR_SETUP16(128, 32, 1, 1) WSSR_SETUP16(128, 32, 1, 2) WSSR_SETUP16(128, 32, 2, 2)
     WSSR_SETUP16(256, 32, 1, 1) WSSR_SETUP16(256, 32, 1, 2) WSSR_SETUP16(256, 32, 2, 2)
     WSSR_SETUP16(512, 16, 1, 1) WSSR_SETUP16(512, 16, 1, 2) WSSR_SETUP16(512, 16, 2, 2)
@@ -248,6 +261,10 @@ struct wssr_ctx {
     (void)hipGetLastError();
     return ok;
   }
+
+  // K-step of a direct-to-LDS BF16 product: 32, or 16 where three ring
+  // slots of 32 would not fit in LDS (BN = 512 with a second plane)
+  static constexpr int bk_dma(int bn, int pa, int pb) { return bn == 512 && (pa > 1 || pb > 1) ? 16 : 32; }
 
   // ---- storage precision of O
   bool bf16() const { return cfg.o_dtype != WSSR_F32; }
@@ -259,6 +276,7 @@ struct wssr_ctx {
   // index of a BF16 product variant: (BN, PA, PB) with BN in {128, 256, 512}
   static int v16(int bn, int pa, int pb) { return (bn == 128 ? 0 : bn == 256 ? 1 : 2) * 3 + (pa == 2 ? 2 : pb - 1); }
   int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
+  int slots16sd[9] = {0}, slots16pd[9] = {0}; // the same for the direct-to-LDS variants
 
   // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
   // when pb = 2), K-blocked, r padded with zero columns to the product's
@@ -288,10 +306,14 @@ struct wssr_ctx {
 
   void gemm_sample_side(const void* Ov, int64_t ld, int64_t n, int64_t m, const float* V, int r) {
     const bool b16 = bf16();
-    const int bn = bn_for(r, b16), bk = b16 ? (bn == 512 ? 16 : 32) : 16;
+    const int bn = bn_for(r, b16);
     const int pa = o_planes(), pb = s_planes();
     const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
-    const int sl = std::max(1, (b16 ? slots16s[v16(bn, pa, pb)] : slots) / slot_div);
+    // BF16 direct-to-LDS form: 16-byte aligned rows of O, whole 16-byte chunks of its rows
+    const bool dma16 = b16 && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0) && (m % 8 == 0);
+    const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
+    const int sl =
+        std::max(1, (b16 ? (dma16 ? slots16sd : slots16s)[v16(bn, pa, pb)] : slots) / slot_div);
     // about one round of resident workgroups; split K = M into s1 ranges
     int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(sl, tn * tj)));
     int64_t kchunk = rup(cdiv(m, s1), bk);
@@ -330,13 +352,19 @@ struct wssr_ctx {
       const auto* O = static_cast<const unsigned short*>(Ov);
       const int64_t ps = n * ld;
       const bool vec_o = (ld % 8 == 0) && ((uintptr_t)O % 16 == 0);
-      const unsigned lds = (unsigned)gemm16_lds(bn, bk, pa, pb);
+      const unsigned lds = (unsigned)(dma16 ? gemm16_dma_lds(bn, bk, pa, pb) : gemm16_lds(bn, bk, pa, pb));
       const int64_t vs = split_skinny(V, m, r, pb, bn);
       timed(0, [&] {
 #define WSSR_S16(BN, BK, PA, PB)                                                                                     \
-  hipLaunchKernelGGL((k_gemm16_sample_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,          \
-                     (const unsigned short*)s16, vs, r, ypart, kchunk, vec_o, (const DevStatus*)st, (int)tn,          \
-                     (int)tj, xcd)
+  if (dma16)                                                                                                         \
+    hipLaunchKernelGGL((k_gemm16_sample_side_dma<BN, BKD(BN, PA, PB), PA, PB>), grid, dim3(256), lds, stream, O, ld, \
+                       ps, n, m,                                                                                    \
+                       (const unsigned short*)s16, vs, r, ypart, kchunk, (const unsigned short*)zeros,              \
+                       (const DevStatus*)st, (int)tn, (int)tj, xcd);                                                \
+  else                                                                                                               \
+    hipLaunchKernelGGL((k_gemm16_sample_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,        \
+                       (const unsigned short*)s16, vs, r, ypart, kchunk, vec_o, (const DevStatus*)st, (int)tn,        \
+                       (int)tj, xcd)
         switch (v16(bn, pa, pb)) {
           case 0: WSSR_S16(128, 32, 1, 1); break;
           case 1: WSSR_S16(128, 32, 1, 2); break;
@@ -356,11 +384,15 @@ struct wssr_ctx {
 
   void gemm_param_side(const void* Ov, int64_t ld, int64_t n, int64_t m, const float* Q, int r, float* Z) {
     const bool b16 = bf16();
-    const int bn = bn_for(r, b16), bk = b16 ? (bn == 512 ? 16 : 32) : 16;
+    const int bn = bn_for(r, b16);
     const int pa = o_planes(), pb = s_planes();
     const bool vec_q = (r % 4 == 0) && ((uintptr_t)Q % 16 == 0);
     const float scale = (float)(1.0 / std::sqrt((double)n));
-    const int sl = std::max(1, (b16 ? slots16p[v16(bn, pa, pb)] : slots) / slot_div);
+    // BF16 direct-to-LDS form: 16-byte aligned rows of O
+    const bool dma16 = b16 && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0);
+    const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
+    const int sl =
+        std::max(1, (b16 ? (dma16 ? slots16pd : slots16p)[v16(bn, pa, pb)] : slots) / slot_div);
     const int64_t tj = cdiv(r, bn), tiles = cdiv(m, 128) * tj, nk = cdiv(n, bk);
     // whole tiles for every full round of resident workgroups; the leftover
     // tiles' K-steps shared evenly by one more round (stream-K) unless the
@@ -405,11 +437,17 @@ struct wssr_ctx {
         const auto* O = static_cast<const unsigned short*>(Ov);
         const int64_t ps = n * ld;
         const bool vec_o = (ld % 8 == 0) && ((uintptr_t)O % 16 == 0);
-        const unsigned lds = (unsigned)gemm16_lds(bn, bk, pa, pb);
+        const unsigned lds = (unsigned)(dma16 ? gemm16_dma_lds(bn, bk, pa, pb) : gemm16_lds(bn, bk, pa, pb));
 #define WSSR_P16(BN, BK, PA, PB)                                                                                     \
-  hipLaunchKernelGGL((k_gemm16_param_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,           \
-                     (const unsigned short*)s16, qs, r, scale, Z, vec_o, (const DevStatus*)st, (int)tj, full, units,  \
-                     skw, skpart)
+  if (dma16)                                                                                                         \
+    hipLaunchKernelGGL((k_gemm16_param_side_dma<BN, BKD(BN, PA, PB), PA, PB>), grid, dim3(256), lds, stream, O, ld,  \
+                       ps, n, m,                                                                                    \
+                       (const unsigned short*)s16, qs, r, scale, Z, (const unsigned short*)zeros,                   \
+                       (const DevStatus*)st, (int)tj, full, units, skw, skpart);                                    \
+  else                                                                                                               \
+    hipLaunchKernelGGL((k_gemm16_param_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,         \
+                       (const unsigned short*)s16, qs, r, scale, Z, vec_o, (const DevStatus*)st, (int)tj, full,       \
+                       units, skw, skpart)
         switch (v16(bn, pa, pb)) {
           case 0: WSSR_P16(128, 32, 1, 1); break;
           case 1: WSSR_P16(128, 32, 1, 2); break;

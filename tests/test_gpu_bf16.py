@@ -57,7 +57,10 @@ def handles():
         h.close()
 
 
-SHAPES = [(257, 777, 7), (300, 1001, 40), (1000, 2999, 130), (520, 4096, 256), (1100, 3001, 300), (700, 2048, 512)]
+# ragged shapes (guarded loads) and shapes whose O rows are whole 16-byte
+# chunks (the direct-to-LDS kernels), for each column-tile width
+SHAPES = [(257, 777, 7), (300, 1001, 40), (1000, 2999, 130), (520, 4096, 256), (1100, 3001, 300), (700, 2048, 512),
+          (333, 2048, 100), (1000, 3000, 64)]
 
 
 @pytest.mark.parametrize("form", FORMS)
