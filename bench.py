@@ -160,7 +160,8 @@ def product_kernel(form, side, cfg):
     contiguous torch tensors, so that is r % 4 == 0, plus M % 4 == 0 on the
     sample side)."""
     if form != "f32":
-        return "k_gemm16_" + side
+        # BF16: O's rows are whole 16-byte chunks (8 elements)
+        return "k_gemm16_" + side + ("_dma" if cfg.m % 8 == 0 else "")
     aligned = cfg.r % 4 == 0 and (cfg.m % 4 == 0 or side == "param_side")
     return "k_gemm_" + side + ("_dma" if aligned else "")
 
