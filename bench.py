@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--plain-inputs", type=int, default=0,
                     help="draw O, E_L and V_0 i.i.d. Gaussian (no QR factorisation in the generator); "
                          "for hardware-counter runs, whose byte counts do not depend on the values")
+    ap.add_argument("--m", type=int, default=0,
+                    help="override the workload's M (number of parameters), e.g. the FP32 comparison of the "
+                         "largest instance at M=2e6")
     ap.add_argument("--sweep", type=int, default=0,
                     help="time the product kernels alone over a range of ranks (roofline sweep)")
     ap.add_argument("--sweep-n", type=int, default=16384)
@@ -359,6 +362,9 @@ def main():
     from workloads import CONFIGS, Workload, to_storage
 
     cfg = CONFIGS[args.config]
+    if args.m:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, m=args.m)
     form = args.form
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -379,8 +385,14 @@ def main():
     else:
         wl = Workload(cfg, device=dev, gen_dtype=torch.float32)
         for t in range(1, ring + 1):
-            o = wl.o(t)
             es.append(wl.e_l(t))
+            if form in ("bf16", "bf16_split") and not keep_f32:
+                # straight to BF16, block by block (the same rounding as
+                # to_storage, without the FP32 copy of O)
+                ost.append(wl.o(t, dtype=torch.bfloat16))
+                o32.append(None)
+                continue
+            o = wl.o(t)
             if form != "f32":
                 ost.append(to_storage(o, form))
             o32.append(o if keep_f32 else None)

@@ -111,20 +111,39 @@ def _orthonormal(x):
     Cholesky QR in float64 (a Gaussian matrix that tall is well conditioned,
     so this reaches the same unique Q as Householder QR, to rounding)."""
     if x.numel() > _BIG:
-        # Gram on the device, its Cholesky factor and the inverse of that
-        # (k x k) on the host, then one plain product on the device
-        dt = x.dtype
-        y = x.double()
+        # Gram on the device (FP64, accumulated over row blocks, so that no
+        # FP64 copy of x is held), its Cholesky factor and the inverse of that
+        # (k x k) on the host, then the product applied block by block in place
+        y = x.contiguous()
+        rows = max(1, (1 << 26) // y.shape[1])
         for _ in range(2):
-            gram = (y.T @ y).cpu().numpy()
-            low = np.linalg.cholesky(gram)
-            rinv = np.linalg.inv(low.T)
-            y = y @ torch.from_numpy(np.ascontiguousarray(rinv)).to(y.device)
-        return y.to(dt).contiguous()
+            gram = torch.zeros(y.shape[1], y.shape[1], dtype=torch.float64, device=y.device)
+            for i in range(0, y.shape[0], rows):
+                b = y[i:i + rows].double()
+                gram += b.T @ b
+                del b
+            low = np.linalg.cholesky(gram.cpu().numpy())
+            rinv = torch.from_numpy(np.ascontiguousarray(np.linalg.inv(low.T))).to(y.device)
+            for i in range(0, y.shape[0], rows):
+                y[i:i + rows] = (y[i:i + rows].double() @ rinv).to(y.dtype)
+        return y
     q, r = torch.linalg.qr(x)
     d = torch.sign(torch.diagonal(r))
     d[d == 0] = 1
     return (q * d).contiguous()
+
+
+def _rotate_pairs_inplace(x, perm, angle, chunk=1 << 16):
+    """Rotate rows (perm[2i], perm[2i+1]) of x by angle, in place, a chunk of
+    pairs at a time (for factors too large to copy)."""
+    npair = perm.numel() // 2
+    c, s = math.cos(angle), math.sin(angle)
+    for i in range(0, npair, chunk):
+        a = perm[2 * i:2 * min(npair, i + chunk):2]
+        b = perm[2 * i + 1:2 * min(npair, i + chunk):2]
+        xa, xb = x[a].clone(), x[b].clone()
+        x[a] = c * xa - s * xb
+        x[b] = s * xa + c * xb
 
 
 def _rotate_pairs(x, perm, angle):
@@ -159,14 +178,24 @@ class Workload:
         self.perm_n = torch.randperm(self.n, generator=_gen(dev, sd, "perm_n"), device=dev)
         self.perm_m = torch.randperm(self.m, generator=_gen(dev, sd, "perm_m"), device=dev)
         self.spectrum = torch.arange(1, k + 1, device=dev, dtype=gen_dtype) ** (-cfg.alpha)
+        # W_t of the large instances is rotated in place (W_0 is not kept):
+        # the angle it currently stands at
+        self._w_angle = 0.0
 
     def o(self, t, dtype=torch.float32):
         """O_t (N x M) in the given dtype.  Instances of more than 2^28
-        elements are built in blocks of 1024 rows (noise drawn block by block
-        from the same generator), which bounds the temporaries."""
+        elements are built in blocks of rows (at most 1024, and at most 2^30
+        elements; noise drawn block by block from the same generator), which
+        bounds the temporaries."""
         cfg, dev = self.cfg, self.device
         ut = _rotate_pairs(self.u0, self.perm_n, t * cfg.theta)
-        wt = _rotate_pairs(self.w0, self.perm_m, t * cfg.theta)
+        if self.w0.numel() > _BIG:
+            # pair rotations compose by adding angles
+            _rotate_pairs_inplace(self.w0, self.perm_m, t * cfg.theta - self._w_angle)
+            self._w_angle = t * cfg.theta
+            wt = self.w0
+        else:
+            wt = _rotate_pairs(self.w0, self.perm_m, t * cfg.theta)
         left = math.sqrt(self.n) * ut * self.spectrum[None, :]
         del ut
         gen = _gen(dev, cfg.seed, "noise", t)
@@ -176,10 +205,11 @@ class Workload:
             o.add_(noise, alpha=cfg.eta)
             return o.to(dtype).contiguous()
         out = torch.empty(self.n, self.m, device=dev, dtype=dtype)
-        for i in range(0, self.n, 1024):
-            blk = left[i:i + 1024] @ wt.T
+        rows = max(64, min(1024, (1 << 30) // self.m))
+        for i in range(0, self.n, rows):
+            blk = left[i:i + rows] @ wt.T
             blk.add_(torch.randn(blk.shape, generator=gen, device=dev, dtype=self.gen_dtype), alpha=cfg.eta)
-            out[i:i + 1024] = blk.to(dtype)
+            out[i:i + rows] = blk.to(dtype)
             del blk
         return out
 
