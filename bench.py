@@ -169,6 +169,13 @@ def product_kernel(form, side, cfg):
     return "k_gemm_" + side + ("_dma" if aligned else "")
 
 
+def column_tile(form, r):
+    """Column-tile width of the product kernels for rank r (aligned inputs)."""
+    if form == "f32":
+        return 32 if r <= 32 else 64 if r <= 64 else 128 if r <= 128 else 256
+    return 128 if r <= 128 else 256 if r <= 256 else 512
+
+
 def roofline_of(form, prof, cfg):
     n, m, r = cfg.n, cfg.m, cfg.r
     flops_gemm = 2.0 * n * m * r * PRODUCTS[form]     # MFMA flops of one product launch
@@ -239,6 +246,7 @@ def run_sweep(args):
                 t_hbm, t_mfma = nbytes / (PEAK_HBM_GBS * 1e9), flops / (peak * 1e12)
                 bound = "hbm" if t_hbm >= t_mfma else "mfma"
                 row = {"form": form, "r": r, "side": side, "kernel": product_kernel(form, side, type("C", (), {"m": m, "r": r})),
+                       "tile_cols": column_tile(form, r),
                        "ms": round(avg, 4), "GB/s": round(nbytes / (avg * 1e-3) / 1e9, 1),
                        "TFLOP/s": round(flops / (avg * 1e-3) / 1e12, 1), "bound": bound,
                        "frac_of_bound": round(max(t_hbm, t_mfma) / (avg * 1e-3), 4)}

@@ -399,11 +399,21 @@ constexpr int kSampleA = BM * BK * 4;   // bytes of the sample-side O tile (swiz
 template <int BN>
 struct DmaS {
   static constexpr int RPI = 256 / BN;                                  // K-rows per copy instruction
-  static constexpr int PITCH = 1024 + (RPI == 1 ? 16 : RPI == 2 ? 32 : 64);
+  static constexpr int PITCH = 1024 + (RPI == 1 ? 16 : RPI == 2 ? 32 : RPI == 4 ? 64 : 128);
   static constexpr int INSTR = BK / RPI;                                // copy instructions per step
   static constexpr int BYTES = INSTR * PITCH;
   // byte offset of element (k, j) of the skinny tile
   __device__ static __forceinline__ int off(int k, int j) { return (k / RPI) * PITCH + (k % RPI) * (BN * 4) + j * 4; }
+};
+
+// wave layout of a BN-column tile: WN waves across the columns, WM along the
+// 128 rows; each wave owns TA x TB MFMA tiles of 32 x 32
+template <int BN>
+struct WaveL {
+  static constexpr int WN = BN >= 64 ? 2 : 1;
+  static constexpr int WM = 4 / WN;
+  static constexpr int TA = BM / WM / 32;
+  static constexpr int TB = BN / WN / 32;
 };
 
 // vmcnt wait with lgkmcnt / expcnt left alone
@@ -413,16 +423,36 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Wait before K-step `it` of `ns` for wave w: its copies per K-step are two
+// of the O tile and its share of the skinny tile (with fewer than four skinny
+// instructions, the first waves take one each); all but the next step's
+// copies must have landed, or all of them before the last step.
+template <int BN>
+__device__ __forceinline__ void wait_step(int w, bool last) {
+  constexpr int I = DmaS<BN>::INSTR;
+  if (last) {
+    wait_vmcnt<0>();
+  } else if constexpr (I >= 4) {
+    wait_vmcnt<2 + I / 4>();
+  } else {
+    if (w < I)
+      wait_vmcnt<3>();
+    else
+      wait_vmcnt<2>();
+  }
+}
+
 // copy instructions of one K-step of the skinny tile (rows k0.., columns j0..)
 // issued by wave w into `dst`
 template <int BN>
 __device__ __forceinline__ void dma_skinny(const float* __restrict__ S, int r, int64_t k0, int64_t kend, int j0,
                                            const float* __restrict__ zeros, unsigned char* dst, int w, int lane) {
   using D = DmaS<BN>;
-  constexpr int PER_W = D::INSTR / 4;
+  constexpr int PER_W = D::INSTR >= 4 ? D::INSTR / 4 : 1;
 #pragma unroll
   for (int q = 0; q < PER_W; ++q) {
-    const int ins = w * PER_W + q;
+    const int ins = D::INSTR >= 4 ? w * PER_W + q : w;
+    if (ins >= D::INSTR) break;
     const int kr = ins * D::RPI + (lane * 4) / BN;
     const int j = j0 + (lane * 4) % BN;
     const int64_t k = k0 + kr;
@@ -443,9 +473,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __
                                                                  bool xcd_groups) {
   if (failed(st)) return;
   using D = DmaS<BN>;
-  constexpr int TB = BN / 64;
+  using L = WaveL<BN>;
+  constexpr int TA = L::TA, TB = L::TB;
   constexpr int STAGE = kSampleA + D::BYTES;
-  constexpr int PER_STEP = 2 + D::INSTR / 4;    // copy instructions per wave per K-step
   extern __shared__ __attribute__((aligned(16))) unsigned char smd[];
   int bx, by, bz;
   {
@@ -464,7 +494,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __
     bz = grp / tj;
   }
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / L::WN, wn = w % L::WN;
   const int x = lane & 31, h = lane >> 5;
   const int64_t n0 = (int64_t)bx * BM;
   const int j0 = by * BN;
@@ -472,9 +502,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __
   const int64_t ke = min(m, kb + kchunk);
   float* out = ypart + (int64_t)bz * n * r;
 
-  f32x16 acc[2][TB];
+  f32x16 acc[TA][TB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TA; ++a)
 #pragma unroll
     for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
 
@@ -498,19 +528,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __
   if (ns > 1) issue(kb + BK, 1);
   int slot = 0;
   for (int64_t it = 0; it < ns; ++it) {
-    if (it + 1 < ns)
-      wait_vmcnt<PER_STEP>();
-    else
-      wait_vmcnt<0>();
+    wait_step<BN>(w, it + 1 >= ns);
     __builtin_amdgcn_s_barrier();
     if (it + 2 < ns) issue(kb + (it + 2) * BK, slot == 0 ? 2 : slot - 1);
     const unsigned char* S = smd + slot * STAGE;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      f32x4 av[2];
+      f32x4 av[TA];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int row = wm * 64 + a * 32 + x;
+      for (int a = 0; a < TA; ++a) {
+        const int row = wm * (BM / L::WM) + a * 32 + x;
         const int c = 2 * h + half;
         av[a] = *reinterpret_cast<const f32x4*>(S + (row * 4 + (c ^ ((row >> 2) & 3))) * 16);
       }
@@ -520,9 +547,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __
         float bv[TB];
 #pragma unroll
         for (int b = 0; b < TB; ++b)
-          bv[b] = *reinterpret_cast<const float*>(S + kSampleA + D::off(k, wn * (BN / 2) + b * 32 + x));
+          bv[b] = *reinterpret_cast<const float*>(S + kSampleA + D::off(k, wn * (BN / L::WN) + b * 32 + x));
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < TA; ++a)
 #pragma unroll
           for (int b = 0; b < TB; ++b) acc[a][b] = mfma32x32x2(av[a][e], bv[b], acc[a][b]);
       }
@@ -531,14 +558,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __
   }
 
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TA; ++a)
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
-      const int col = j0 + wn * (BN / 2) + b * 32 + x;
+      const int col = j0 + wn * (BN / L::WN) + b * 32 + x;
       if (col >= r) continue;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t row = n0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int64_t row = n0 + wm * (BM / L::WM) + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         if (row < n) out[row * r + col] = acc[a][b][v];
       }
     }
@@ -555,17 +582,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
                                                                 int sk_wgs, float* __restrict__ part) {
   if (failed(st)) return;
   using D = DmaS<BN>;
-  constexpr int TB = BN / 64;
+  using L = WaveL<BN>;
+  constexpr int TA = L::TA, TB = L::TB;
   constexpr int SO = 8 * kPairPitch;
   constexpr int STAGE = SO + D::BYTES;
-  constexpr int PER_STEP = 2 + D::INSTR / 4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smd[];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = w >> 1, wj = w & 1;
+  const int wm = w / L::WN, wj = w % L::WN;
   const int x = lane & 31, h = lane >> 5;
   int64_t m0 = 0;
   int j0 = 0;
-  f32x16 acc[2][TB];
+  f32x16 acc[TA][TB];
   const int64_t mlast = ((m - 1) / 4) * 4;      // last 16-byte chunk of a row of O
 
   auto issue = [&](int64_t ks, int slot) __attribute__((always_inline)) {
@@ -585,7 +612,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
     m0 = (tile / tiles_j) * BM;
     j0 = (int)(tile % tiles_j) * BN;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TA; ++a)
 #pragma unroll
       for (int b = 0; b < TB; ++b) acc[a][b] = f32x16{0};
     const int64_t ns = ke - kb;
@@ -594,26 +621,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
     if (ns > 1) issue(kb + 1, 1);
     int slot = 0;
     for (int64_t it = 0; it < ns; ++it) {
-      if (it + 1 < ns)
-        wait_vmcnt<PER_STEP>();
-      else
-        wait_vmcnt<0>();
+      wait_step<BN>(w, it + 1 >= ns);
       __builtin_amdgcn_s_barrier();
       if (it + 2 < ns) issue(kb + it + 2, slot == 0 ? 2 : slot - 1);
       const unsigned char* S = smd + slot * STAGE;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int k = s + 8 * h;
-        float av[2], bv[TB];
+        float av[TA], bv[TB];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < TA; ++a)
           av[a] = *reinterpret_cast<const float*>(S + (k >> 1) * kPairPitch + (k & 1) * 512 +
-                                                  (wm * 64 + a * 32 + x) * 4);
+                                                  (wm * (BM / L::WM) + a * 32 + x) * 4);
 #pragma unroll
         for (int b = 0; b < TB; ++b)
-          bv[b] = *reinterpret_cast<const float*>(S + SO + D::off(k, wj * (BN / 2) + b * 32 + x));
+          bv[b] = *reinterpret_cast<const float*>(S + SO + D::off(k, wj * (BN / L::WN) + b * 32 + x));
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < TA; ++a)
 #pragma unroll
           for (int b = 0; b < TB; ++b) acc[a][b] = mfma32x32x2(av[a], bv[b], acc[a][b]);
       }
@@ -626,14 +650,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
   if ((int)blockIdx.x < full_tiles) {
     run(blockIdx.x, 0, nk);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TA; ++a)
 #pragma unroll
       for (int b = 0; b < TB; ++b) {
-        const int col = j0 + wj * (BN / 2) + b * 32 + x;
+        const int col = j0 + wj * (BN / L::WN) + b * 32 + x;
         if (col >= r) continue;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int64_t row = m0 + wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int64_t row = m0 + wm * (BM / L::WM) + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
           if (row < m) Z[row * r + col] = acc[a][b][v] * scale;
         }
       }
@@ -648,13 +672,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
     run(full_tiles + tl, kb, ke);
     float* outp = part + (wg * 2 + seg) * (int64_t)(BM * BN);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TA; ++a)
 #pragma unroll
       for (int b = 0; b < TB; ++b) {
-        const int col = wj * (BN / 2) + b * 32 + x;
+        const int col = wj * (BN / L::WN) + b * 32 + x;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int row = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int row = wm * (BM / L::WM) + a * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
           outp[row * BN + col] = acc[a][b][v];
         }
       }
@@ -666,7 +690,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
 
 size_t gemm_dma_lds(bool param_side, int bn) {
   const size_t a = param_side ? (size_t)8 * kPairPitch : (size_t)kSampleA;
-  const size_t b = bn == 256 ? DmaS<256>::BYTES : bn == 128 ? DmaS<128>::BYTES : DmaS<64>::BYTES;
+  const size_t b = bn == 256   ? DmaS<256>::BYTES
+                   : bn == 128 ? DmaS<128>::BYTES
+                   : bn == 64  ? DmaS<64>::BYTES
+                               : DmaS<32>::BYTES;
   return kDmaStages * (a + b);
 }
 
@@ -677,6 +704,7 @@ size_t gemm_dma_lds(bool param_side, int bn) {
   template __global__ void k_gemm_param_side_dma<BN>(const float*, int64_t, int64_t, int64_t, const float*, int,    \
                                                      float, float*, const float*, const DevStatus*, int, int,       \
                                                      int64_t, int, float*);
+WSSR_GEMM_DMA_INST(32)
 WSSR_GEMM_DMA_INST(64)
 WSSR_GEMM_DMA_INST(128)
 WSSR_GEMM_DMA_INST(256)
@@ -693,6 +721,8 @@ template __global__ void k_gemm_param_side<128>(const float*, int64_t, int64_t, 
                                                 float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
 template __global__ void k_gemm_param_side<256>(const float*, int64_t, int64_t, int64_t, const float*, int, float,
                                                 float*, bool, bool, const DevStatus*, int, int, int64_t, int, float*);
+template __global__ void k_streamk_fixup<32>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
+                                             int, const DevStatus*);
 template __global__ void k_streamk_fixup<64>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,
                                              int, const DevStatus*);
 template __global__ void k_streamk_fixup<128>(const float*, float*, int64_t, int, float, int, int, int64_t, int64_t,

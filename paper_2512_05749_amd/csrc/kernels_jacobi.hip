@@ -72,8 +72,18 @@ __global__ __launch_bounds__(JT) void k_jacobi_coop(double* __restrict__ Bc, dou
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = rp / JB, nwg = nb / 2, wg = blockIdx.x;
   const int li = lane & 15, lk = lane >> 4;
-  const double floor = 4.93e-32 * scal[0];                 // (eps ||C||_F)^2
-  const double absfloor = 64.0 * 2.220446049250313e-16 * scal[0];
+  // ||C||_F^2 from the column sums of squares k_jacobi_prep left in scal[1..rp]
+  __shared__ double fro2;
+  if (tid < 64) {
+    double s2 = 0.0;
+    for (int j = tid; j < rp; j += 64) s2 += scal[1 + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+    if (tid == 0) fro2 = s2;
+  }
+  __syncthreads();
+  const double floor = 4.93e-32 * fro2;                    // (eps ||C||_F)^2
+  const double absfloor = 64.0 * 2.220446049250313e-16 * fro2;
   unsigned bars = 0;
   double last_cos = 0.0;
   int sweeps_done = 0, converged = 0;

@@ -478,63 +478,67 @@ template __global__ void k_trinv<8>(const double*, int, const double*, double*, 
 // Rayleigh-Ritz SVD of C (r x r) by block one-sided Jacobi (the sweeps are
 // k_jacobi_coop in kernels_jacobi.hip).
 //   prep: Bc (column-major C, i.e. column j contiguous) <- C with zero padding,
-//         Pc <- I, scal[0] <- ||C||_F^2, and the grid-barrier words of the
+//         Pc <- I, scal[1 + j] <- ||c_j||^2 (the sweep kernel sums them to
+//         ||C||_F^2), and the grid-barrier words of the
 //         sweep kernel.  C is given as its transpose Ct (rp x rp row-major, so
 //         row j of Ct is column j of C).
 //   A column pair counts as orthogonal when its cosine is <= tol or its Gram
 //   entry is <= 64 eps ||C||_F^2.
 //   final: sigma_j = ||c_j||, sorted descending (stable), P permuted to match.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_jacobi_prep(const double* __restrict__ Ct, int rp, int r,
+__global__ __launch_bounds__(256) void k_jacobi_prep(const double* __restrict__ Ct, int rp, int r,
                                                      double* __restrict__ Bc, double* __restrict__ Pc,
                                                      double* __restrict__ scal, unsigned* __restrict__ sync,
                                                      DevStatus* st) {
+  // grid: rp / 4 workgroups, one column per wavefront (lanes stride the rows)
   const bool skip = failed(st);
-  if (threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     sync[0] = 0u;
     sync[1] = 0u;
     sync[2] = skip ? 1u : 0u;
+    if (!skip) {
+      st->jacobi_done = 0;
+      st->jacobi_sweeps = 0;
+      st->jacobi_cosine = 0;
+    }
   }
   if (skip) return;
-  __shared__ double red[NTH];
-  double s = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)rp * rp; e += NTH) {
-    const int j = (int)(e / rp), i = (int)(e % rp);
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= rp) return;
+  double sq = 0.0;
+  for (int i = lane; i < rp; i += 64) {
+    const int64_t e = (int64_t)j * rp + i;
     const double v = (j < r && i < r) ? Ct[e] : 0.0;
     Bc[e] = v;
     Pc[e] = (i == j) ? 1.0 : 0.0;
-    s += v * v;
+    sq += v * v;
   }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = NTH / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    scal[0] = red[0];
-    st->jacobi_done = 0;
-    st->jacobi_sweeps = 0;
-    st->jacobi_cosine = 0;
-  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+  if (lane == 0) scal[1 + j] = sq;   // column sums of squares; the sweep kernel adds them up
 }
 
 // sigma_j = ||c_j|| sorted descending (ties keep index order); Ps (rp x rp
-// row-major) holds the matching columns of P.  One workgroup.
+// row-major) holds the matching columns of P.  One workgroup: the column
+// norms one column per wavefront at a time (lanes stride the rows), the
+// ranks one thread per column, then the permuted copy.
 __global__ __launch_bounds__(NTH) void k_jacobi_final(const double* __restrict__ Bc, const double* __restrict__ Pc,
                                                       int rp, int r, double* __restrict__ sig,
                                                       double* __restrict__ Ps, DevStatus* st) {
   if (failed(st)) return;
   __shared__ double nrm[512];
-  __shared__ int rank[512];
-  const int tid = threadIdx.x;
-  for (int j = tid; j < rp; j += NTH) {
+  __shared__ int src[512];   // src[k] = the column of P that becomes column k of Ps
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j = wv; j < rp; j += NTH / 64) {
     double s = 0.0;
-    for (int i = 0; i < rp; ++i) {
+    for (int i = lane; i < rp; i += 64) {
       const double v = Bc[(int64_t)j * rp + i];
       s += v * v;
     }
-    nrm[j] = sqrt(s);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) nrm[j] = sqrt(s);
   }
   __syncthreads();
   for (int j = tid; j < rp; j += NTH) {
@@ -544,13 +548,15 @@ __global__ __launch_bounds__(NTH) void k_jacobi_final(const double* __restrict__
       const double si = nrm[i];
       k += (si > sj) || (si == sj && i < j);
     }
-    rank[j] = k;
+    src[k] = j;
     sig[k] = sj;
   }
   __syncthreads();
+  // Ps[i][k] = P[i][src[k]] = Pc[src[k]][i]: consecutive threads write
+  // consecutive k of a row
   for (int64_t e = tid; e < (int64_t)rp * rp; e += NTH) {
-    const int j = (int)(e / rp), i = (int)(e % rp);   // P[i][j] = Pc[j][i]
-    Ps[(int64_t)i * rp + rank[j]] = Pc[e];
+    const int i = (int)(e / rp), k = (int)(e % rp);
+    Ps[e] = Pc[(int64_t)src[k] * rp + i];
   }
   if (tid == 0 && st->code == 0 && !st->jacobi_done) st->code = ST_WARN_NOT_CONVERGED;
 }

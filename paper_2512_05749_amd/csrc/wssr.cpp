@@ -277,6 +277,7 @@ struct wssr_ctx {
   static int v16(int bn, int pa, int pb) { return (bn == 128 ? 0 : bn == 256 ? 1 : 2) * 3 + (pa == 2 ? 2 : pb - 1); }
   int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
   int slots16sd[9] = {0}, slots16pd[9] = {0}; // the same for the direct-to-LDS variants
+  int slots32s = 0, slots32p = 0;             // the same for the FP32 32-column direct-to-LDS kernels
 
   // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
   // when pb = 2), K-blocked, r padded with zero columns to the product's
@@ -306,30 +307,33 @@ struct wssr_ctx {
 
   void gemm_sample_side(const void* Ov, int64_t ld, int64_t n, int64_t m, const float* V, int r) {
     const bool b16 = bf16();
-    const int bn = bn_for(r, b16);
+    const bool vec_v = (r % 4 == 0) && ((uintptr_t)V % 16 == 0);
+    // FP32 direct-to-LDS form: 16-byte aligned rows of O and V, whole 16-byte
+    // chunks of O's rows; with it, r <= 32 takes the 32-column tile
+    const bool dma = !b16 && vec_v && (ld % 4 == 0) && ((uintptr_t)Ov % 16 == 0) && (m % 4 == 0);
+    const int bn = dma && r <= 32 ? 32 : bn_for(r, b16);
     const int pa = o_planes(), pb = s_planes();
     const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
     // BF16 direct-to-LDS form: 16-byte aligned rows of O, whole 16-byte chunks of its rows
     const bool dma16 = b16 && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0) && (m % 8 == 0);
     const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
     const int sl =
-        std::max(1, (b16 ? (dma16 ? slots16sd : slots16s)[v16(bn, pa, pb)] : slots) / slot_div);
+        std::max(1, (b16 ? (dma16 ? slots16sd : slots16s)[v16(bn, pa, pb)] : bn == 32 ? slots32s : slots) / slot_div);
     // about one round of resident workgroups; split K = M into s1 ranges
     int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(sl, tn * tj)));
     int64_t kchunk = rup(cdiv(m, s1), bk);
     s1 = (int)cdiv(m, kchunk);
-    const bool vec_v = (r % 4 == 0) && ((uintptr_t)V % 16 == 0);
     const bool xcd = ((int64_t)s1 * tj) % 8 == 0;
     const dim3 grid((unsigned)(tn * tj * s1));
     if (!b16) {
       const float* O = static_cast<const float*>(Ov);
       const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
-      // direct-to-LDS form: 16-byte aligned rows of O and V, whole 16-byte
-      // chunks of O's rows
-      const bool dma = vec_o && vec_v && (m % 4 == 0);
       const unsigned dl = (unsigned)gemm_dma_lds(false, bn);
       timed(0, [&] {
-        if (dma && bn == 256)
+        if (bn == 32)
+          hipLaunchKernelGGL(k_gemm_sample_side_dma<32>, grid, dim3(256), dl, stream, O, ld, n, m, V, r, ypart,
+                             kchunk, (const float*)zeros, (const DevStatus*)st, (int)tn, (int)tj, xcd);
+        else if (dma && bn == 256)
           hipLaunchKernelGGL(k_gemm_sample_side_dma<256>, grid, dim3(256), dl, stream, O, ld, n, m, V, r, ypart,
                              kchunk, (const float*)zeros, (const DevStatus*)st, (int)tn, (int)tj, xcd);
         else if (dma && bn == 128)
@@ -384,15 +388,18 @@ struct wssr_ctx {
 
   void gemm_param_side(const void* Ov, int64_t ld, int64_t n, int64_t m, const float* Q, int r, float* Z) {
     const bool b16 = bf16();
-    const int bn = bn_for(r, b16);
     const int pa = o_planes(), pb = s_planes();
     const bool vec_q = (r % 4 == 0) && ((uintptr_t)Q % 16 == 0);
+    // FP32 direct-to-LDS form: 16-byte aligned rows of O and Q; with it,
+    // r <= 32 takes the 32-column tile
+    const bool dma = !b16 && vec_q && (ld % 4 == 0) && ((uintptr_t)Ov % 16 == 0);
+    const int bn = dma && r <= 32 ? 32 : bn_for(r, b16);
     const float scale = (float)(1.0 / std::sqrt((double)n));
     // BF16 direct-to-LDS form: 16-byte aligned rows of O
     const bool dma16 = b16 && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0);
     const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
     const int sl =
-        std::max(1, (b16 ? (dma16 ? slots16pd : slots16p)[v16(bn, pa, pb)] : slots) / slot_div);
+        std::max(1, (b16 ? (dma16 ? slots16pd : slots16p)[v16(bn, pa, pb)] : bn == 32 ? slots32p : slots) / slot_div);
     const int64_t tj = cdiv(r, bn), tiles = cdiv(m, 128) * tj, nk = cdiv(n, bk);
     // whole tiles for every full round of resident workgroups; the leftover
     // tiles' K-steps shared evenly by one more round (stream-K) unless the
@@ -413,9 +420,11 @@ struct wssr_ctx {
       if (!b16) {
         const float* O = static_cast<const float*>(Ov);
         const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
-        const bool dma = vec_o && vec_q;   // direct-to-LDS form: 16-byte aligned rows of O and Q
         const unsigned dl = (unsigned)gemm_dma_lds(true, bn);
-        if (dma && bn == 256)
+        if (bn == 32)
+          hipLaunchKernelGGL(k_gemm_param_side_dma<32>, grid, dim3(256), dl, stream, O, ld, n, m, Q, r, scale, Z,
+                             (const float*)zeros, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        else if (dma && bn == 256)
           hipLaunchKernelGGL(k_gemm_param_side_dma<256>, grid, dim3(256), dl, stream, O, ld, n, m, Q, r, scale, Z,
                              (const float*)zeros, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
         else if (dma && bn == 128)
@@ -471,6 +480,9 @@ struct wssr_ctx {
                              (int)tj, full, nk, units, skw, (const DevStatus*)st);
         else if (bn == 128)
           hipLaunchKernelGGL(k_streamk_fixup<128>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
+                             (int)tj, full, nk, units, skw, (const DevStatus*)st);
+        else if (bn == 32)
+          hipLaunchKernelGGL(k_streamk_fixup<32>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
                              (int)tj, full, nk, units, skw, (const DevStatus*)st);
         else
           hipLaunchKernelGGL(k_streamk_fixup<64>, fg, dim3(256), 0, stream, (const float*)skpart, Z, m, r, scale,
@@ -592,7 +604,7 @@ struct wssr_ctx {
   // singular values into sig[0..rp), right singular vectors into Ps (rp x rp).
   void small_svd(const double* Ct, int r) {
     int rp = (int)rup(r, 64);
-    hipLaunchKernelGGL(k_jacobi_prep, dim3(1), dim3(1024), 0, stream, Ct, rp, r, Bc, Pc, scal, jsync, st);
+    hipLaunchKernelGGL(k_jacobi_prep, dim3(rp / 4), dim3(256), 0, stream, Ct, rp, r, Bc, Pc, scal, jsync, st);
     // all sweeps in one cooperative launch: rp/32 workgroups, one per block
     // pair of 32 columns, meeting at grid barriers between rounds
     double tol = kJacobiTol;
@@ -699,7 +711,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
             h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
             h->alloc(h->Pc, (size_t)rp * rp) && h->alloc(h->Ps, (size_t)rp * rp) && h->alloc(h->T, (size_t)rp * rp) &&
-            h->alloc(h->scal, 4) && h->alloc(h->sig, rp) && h->alloc(h->cosbuf, (size_t)rp * rp / 64) &&
+            h->alloc(h->scal, (size_t)rp + 1) && h->alloc(h->sig, rp) && h->alloc(h->cosbuf, (size_t)rp * rp / 64) &&
             h->alloc(h->cw, rp) && h->alloc(h->vpart, (size_t)kVecChunkMax * r) &&
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
             h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
@@ -727,16 +739,34 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
   }
   bool attr_ok =
       hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholLds) == hipSuccess;
-  for (int bn = 64; bn <= 256; bn *= 2) {
-    const void* fs = bn == 256 ? (const void*)k_gemm_sample_side_dma<256>
-                     : bn == 128 ? (const void*)k_gemm_sample_side_dma<128> : (const void*)k_gemm_sample_side_dma<64>;
-    const void* fp = bn == 256 ? (const void*)k_gemm_param_side_dma<256>
-                     : bn == 128 ? (const void*)k_gemm_param_side_dma<128> : (const void*)k_gemm_param_side_dma<64>;
+  for (int bn = 32; bn <= 256; bn *= 2) {
+    const void* fs = bn == 256   ? (const void*)k_gemm_sample_side_dma<256>
+                     : bn == 128 ? (const void*)k_gemm_sample_side_dma<128>
+                     : bn == 64  ? (const void*)k_gemm_sample_side_dma<64>
+                                 : (const void*)k_gemm_sample_side_dma<32>;
+    const void* fp = bn == 256   ? (const void*)k_gemm_param_side_dma<256>
+                     : bn == 128 ? (const void*)k_gemm_param_side_dma<128>
+                     : bn == 64  ? (const void*)k_gemm_param_side_dma<64>
+                                 : (const void*)k_gemm_param_side_dma<32>;
     attr_ok = attr_ok &&
               hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_dma_lds(false, bn)) ==
                   hipSuccess &&
               hipFuncSetAttribute(fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_dma_lds(true, bn)) ==
                   hipSuccess;
+  }
+  // the 32-column kernels hold little LDS and few registers: more of them
+  // are resident per compute unit than of the wider tiles
+  {
+    const int cus = std::max(1, h->slots / 2);
+    int ps = 0, pp = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&ps, (const void*)k_gemm_sample_side_dma<32>, 256,
+                                                     gemm_dma_lds(false, 32)) != hipSuccess || ps < 1)
+      ps = 2;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pp, (const void*)k_gemm_param_side_dma<32>, 256,
+                                                     gemm_dma_lds(true, 32)) != hipSuccess || pp < 1)
+      pp = 2;
+    h->slots32s = std::min(ps, 4) * cus;
+    h->slots32p = std::min(pp, 4) * cus;
   }
   for (int k = 64; k <= rp; k += 64)
     attr_ok = attr_ok && hipFuncSetAttribute(wssr_ctx::jacobi_fn(k), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -95,7 +95,10 @@ def test_param_side_many_tiles(ws_wide, n, m, r):
 # 256), with ragged N, a ragged last parameter tile, partial column tiles, and
 # (parameter side) more tiles than one round of workgroups.
 DMA_SHAPES = [(333, 2048, 32), (500, 3000, 100), (257, 4100, 128), (500, 70_000, 200), (96, 100_000, 256),
-              (511, 6_000, 256)]
+              (511, 6_000, 256),
+              # r <= 32: the 32-column tile, ragged rows and columns, and a
+              # parameter side with more tiles than one round (stream-K)
+              (257, 4100, 4), (100, 6_000, 20), (512, 3000, 32), (500, 140_000, 8), (77, 140_000, 28)]
 
 
 @pytest.mark.parametrize("n,m,r", DMA_SHAPES)
