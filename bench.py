@@ -166,6 +166,8 @@ def product_kernel(form, side, cfg):
         # BF16: O's rows are whole 16-byte chunks (8 elements)
         return "k_gemm16_" + side + ("_dma" if cfg.m % 8 == 0 else "")
     aligned = cfg.r % 4 == 0 and (cfg.m % 4 == 0 or side == "param_side")
+    if aligned and side == "param_side" and cfg.r <= 32:
+        return "k_gemm_param_side_narrow"      # 32-column tile, O staged through registers
     return "k_gemm_" + side + ("_dma" if aligned else "")
 
 

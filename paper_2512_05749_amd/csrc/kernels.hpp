@@ -44,6 +44,10 @@ __global__ void k_gemm_param_side_dma(const float* O, int64_t ld, int64_t n, int
                                       int full_tiles, int64_t sk_units, int sk_wgs, float* part);
 // dynamic LDS bytes of the direct-to-LDS product kernels
 size_t gemm_dma_lds(bool param_side, int bn);
+// narrow parameter side (one 32-column tile, O staged through registers, static LDS)
+__global__ void k_gemm_param_side_narrow(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
+                                         float scale, float* Z, const float* zeros, const DevStatus* st, int tiles_j,
+                                         int full_tiles, int64_t sk_units, int sk_wgs, float* part);
 template <int BN>
 __global__ void k_gemm_param_side(const float* O, int64_t ld, int64_t n, int64_t m, const float* Q, int r,
                                   float scale, float* Z, bool vec_o, bool vec_q, const DevStatus* st, int tiles_j,

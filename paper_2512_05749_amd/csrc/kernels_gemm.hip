@@ -688,6 +688,143 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
   if (u < uend) segment(1);
 }
 
+// ---------------------------------------------------------------------------
+// Narrow form of the FP32 parameter-side product (r <= 32: one 32-column
+// tile).  At that width the product does 2r flops per 4-byte element of O and
+// is bound by HBM, so what sets its speed is how many bytes of O each compute
+// unit keeps in flight.  A direct-to-LDS copy holds a slot of LDS for every
+// byte in flight; here O and the skinny tile go through registers instead,
+// kAhead K-steps ahead of the MFMAs, and LDS holds only the two stages the
+// MFMAs alternate between (written at step s, read after the barrier of step
+// s; stage s & 1 is rewritten at step s + 2, after every wave has passed the
+// barrier of step s + 1 and so finished step s).  The LDS layouts are those
+// of the direct-to-LDS kernel, so the MFMA side is the same.  (The sample
+// side reads 64-byte pieces of 128 rows per K-step; staged through registers
+// it ran slower than its direct-to-LDS 32-column form, which it keeps.)
+namespace {
+constexpr int kAhead = 4;     // K-steps in flight (even: step s uses stage s & 1 = d & 1)
+using NS = DmaS<32>;
+
+// LDS waits for this wave's LDS writes only (vmcnt left at its maximum)
+__device__ __forceinline__ void wait_lgkm0() {
+  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4) | (0 << 8));
+}
+}  // namespace
+
+// Parameter side, narrow form.  Arguments as k_gemm_param_side_dma.
+__global__ __launch_bounds__(256, 4) void k_gemm_param_side_narrow(const float* __restrict__ O, int64_t ld, int64_t n,
+                                                                int64_t m, const float* __restrict__ Q, int r,
+                                                                float scale, float* __restrict__ Z,
+                                                                const float* __restrict__ zeros, const DevStatus* st,
+                                                                int tiles_j, int full_tiles, int64_t sk_units,
+                                                                int sk_wgs, float* __restrict__ part) {
+  if (failed(st)) return;
+  constexpr int SO = 8 * kPairPitch;
+  constexpr int STAGE = SO + NS::BYTES;
+  __shared__ __attribute__((aligned(16))) unsigned char sm[2 * STAGE];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int x = lane & 31, h = lane >> 5;
+  const int64_t mlast = ((m - 1) / 4) * 4;      // last 16-byte chunk of a row of O
+
+  // this thread's share of a K-step: the 16-byte chunk at column mc of
+  // K-rows kr[q] (pairs 2w, 2w + 1), two values of row ks of Q
+  const int mc = (lane & 31) * 4;
+  int kr[2], aoff[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = 2 * w + q;
+    kr[q] = 2 * p + h;
+    aoff[q] = p * kPairPitch + h * 512 + (lane & 31) * 16;
+  }
+  const int ks = t >> 4, js = (t & 15) * 2;
+  const int qoff = SO + NS::off(ks, js);
+
+  int64_t m0 = 0;
+  int j0 = 0;
+  f32x16 acc;
+  f32x4 ra[kAhead][2];
+  f32x2 rv[kAhead];
+  auto load = [&](int64_t kstep, f32x4* a, f32x2& v) __attribute__((always_inline)) {
+    const int64_t k0 = kstep * BK;
+    const int64_t mm = min(m0 + mc, mlast);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int64_t k = min(k0 + kr[q], n - 1);
+      a[q] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(O + k * ld + mm));
+    }
+    const int64_t kk = k0 + ks;
+    v = *reinterpret_cast<const f32x2*>((kk < n && j0 + js < r) ? Q + kk * r + j0 + js : zeros);
+  };
+  // acc = the product of tile `tile` over K-steps [kb, ke)
+  auto run = [&](int64_t tile, int64_t kb, int64_t ke) __attribute__((always_inline)) {
+    m0 = (tile / tiles_j) * BM;
+    j0 = (int)(tile % tiles_j) * 32;
+    acc = f32x16{0};
+    auto step = [&](int d, bool refill, int64_t next) __attribute__((always_inline)) {
+      unsigned char* S = sm + (d & 1) * STAGE;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) *reinterpret_cast<f32x4*>(S + aoff[q]) = ra[d][q];
+      *reinterpret_cast<f32x2*>(S + qoff) = rv[d];
+      if (refill) load(next, ra[d], rv[d]);
+      wait_lgkm0();
+      __builtin_amdgcn_s_barrier();
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int k = s8 + 8 * h;
+        const float av =
+            *reinterpret_cast<const float*>(S + (k >> 1) * kPairPitch + (k & 1) * 512 + (w * 32 + x) * 4);
+        const float bv = *reinterpret_cast<const float*>(S + SO + NS::off(k, x));
+        acc = mfma32x32x2(av, bv, acc);
+      }
+    };
+    // loads past the K range read clamped rows and the zero buffer (never
+    // used), so every group of kAhead steps issues the same loads
+    const int64_t ns = ke - kb;
+#pragma unroll
+    for (int d = 0; d < kAhead; ++d) load(kb + d, ra[d], rv[d]);
+    int64_t it = 0;
+    for (; it + kAhead <= ns; it += kAhead) {
+#pragma unroll
+      for (int d = 0; d < kAhead; ++d) step(d, true, kb + it + d + kAhead);
+    }
+#pragma unroll
+    for (int d = 0; d < kAhead - 1; ++d)
+      if (it + d < ns) step(d, false, 0);
+    __syncthreads();        // every wave is done with both stages before they are rewritten
+  };
+
+  const int64_t nk = (n + BK - 1) / BK;
+  if ((int)blockIdx.x < full_tiles) {
+    run(blockIdx.x, 0, nk);
+    const int col = j0 + x;
+    if (col < r) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = m0 + w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < m) Z[row * r + col] = acc[v] * scale;
+      }
+    }
+    return;
+  }
+  // stream-K: at most two tiles per workgroup, written out without a loop
+  const int64_t wg = (int64_t)blockIdx.x - full_tiles;
+  int64_t u = wg * sk_units / sk_wgs;
+  const int64_t uend = (wg + 1) * sk_units / sk_wgs;
+  auto segment = [&](int seg) __attribute__((always_inline)) {
+    const int64_t tl = u / nk, kb = u - tl * nk, ke = min(nk, kb + (uend - u));
+    run(full_tiles + tl, kb, ke);
+    float* outp = part + (wg * 2 + seg) * (int64_t)(BM * 32);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = w * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+      outp[row * 32 + x] = acc[v];
+    }
+    u += ke - kb;
+  };
+  if (u < uend) segment(0);
+  if (u < uend) segment(1);
+}
+
 size_t gemm_dma_lds(bool param_side, int bn) {
   const size_t a = param_side ? (size_t)8 * kPairPitch : (size_t)kSampleA;
   const size_t b = bn == 256   ? DmaS<256>::BYTES
@@ -704,7 +841,8 @@ size_t gemm_dma_lds(bool param_side, int bn) {
   template __global__ void k_gemm_param_side_dma<BN>(const float*, int64_t, int64_t, int64_t, const float*, int,    \
                                                      float, float*, const float*, const DevStatus*, int, int,       \
                                                      int64_t, int, float*);
-WSSR_GEMM_DMA_INST(32)
+template __global__ void k_gemm_sample_side_dma<32>(const float*, int64_t, int64_t, int64_t, const float*, int, float*,
+                                                    int64_t, const float*, const DevStatus*, int, int, bool);
 WSSR_GEMM_DMA_INST(64)
 WSSR_GEMM_DMA_INST(128)
 WSSR_GEMM_DMA_INST(256)

@@ -277,7 +277,7 @@ struct wssr_ctx {
   static int v16(int bn, int pa, int pb) { return (bn == 128 ? 0 : bn == 256 ? 1 : 2) * 3 + (pa == 2 ? 2 : pb - 1); }
   int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
   int slots16sd[9] = {0}, slots16pd[9] = {0}; // the same for the direct-to-LDS variants
-  int slots32s = 0, slots32p = 0;             // the same for the FP32 32-column direct-to-LDS kernels
+  int slots32s = 0, slots32p = 0;             // the same for the FP32 32-column kernels
 
   // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
   // when pb = 2), K-blocked, r padded with zero columns to the product's
@@ -422,7 +422,7 @@ struct wssr_ctx {
         const bool vec_o = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
         const unsigned dl = (unsigned)gemm_dma_lds(true, bn);
         if (bn == 32)
-          hipLaunchKernelGGL(k_gemm_param_side_dma<32>, grid, dim3(256), dl, stream, O, ld, n, m, Q, r, scale, Z,
+          hipLaunchKernelGGL(k_gemm_param_side_narrow, grid, dim3(256), 0, stream, O, ld, n, m, Q, r, scale, Z,
                              (const float*)zeros, (const DevStatus*)st, (int)tj, full, units, skw, skpart);
         else if (dma && bn == 256)
           hipLaunchKernelGGL(k_gemm_param_side_dma<256>, grid, dim3(256), dl, stream, O, ld, n, m, Q, r, scale, Z,
@@ -744,29 +744,30 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
                      : bn == 128 ? (const void*)k_gemm_sample_side_dma<128>
                      : bn == 64  ? (const void*)k_gemm_sample_side_dma<64>
                                  : (const void*)k_gemm_sample_side_dma<32>;
-    const void* fp = bn == 256   ? (const void*)k_gemm_param_side_dma<256>
-                     : bn == 128 ? (const void*)k_gemm_param_side_dma<128>
-                     : bn == 64  ? (const void*)k_gemm_param_side_dma<64>
-                                 : (const void*)k_gemm_param_side_dma<32>;
     attr_ok = attr_ok &&
               hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_dma_lds(false, bn)) ==
-                  hipSuccess &&
+                  hipSuccess;
+    if (bn == 32) continue;   // the 32-column parameter side is the narrow kernel (static LDS)
+    const void* fp = bn == 256   ? (const void*)k_gemm_param_side_dma<256>
+                     : bn == 128 ? (const void*)k_gemm_param_side_dma<128>
+                                 : (const void*)k_gemm_param_side_dma<64>;
+    attr_ok = attr_ok &&
               hipFuncSetAttribute(fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_dma_lds(true, bn)) ==
                   hipSuccess;
   }
-  // the 32-column kernels hold little LDS and few registers: more of them
-  // are resident per compute unit than of the wider tiles
+  // the 32-column kernels hold little LDS: more of them are resident per
+  // compute unit than of the wider tiles
   {
     const int cus = std::max(1, h->slots / 2);
     int ps = 0, pp = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&ps, (const void*)k_gemm_sample_side_dma<32>, 256,
                                                      gemm_dma_lds(false, 32)) != hipSuccess || ps < 1)
       ps = 2;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pp, (const void*)k_gemm_param_side_dma<32>, 256,
-                                                     gemm_dma_lds(true, 32)) != hipSuccess || pp < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pp, (const void*)k_gemm_param_side_narrow, 256, 0) !=
+            hipSuccess || pp < 1)
       pp = 2;
-    h->slots32s = std::min(ps, 4) * cus;
-    h->slots32p = std::min(pp, 4) * cus;
+    h->slots32s = ps * cus;
+    h->slots32p = pp * cus;
   }
   for (int k = 64; k <= rp; k += 64)
     attr_ok = attr_ok && hipFuncSetAttribute(wssr_ctx::jacobi_fn(k), hipFuncAttributeMaxDynamicSharedMemorySize,
