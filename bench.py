@@ -171,10 +171,13 @@ def product_kernel(form, side, cfg):
     return "k_gemm_" + side + ("_dma" if aligned else "")
 
 
-def column_tile(form, r):
-    """Column-tile width of the product kernels for rank r (aligned inputs)."""
+def column_tile(form, r, side):
+    """Column-tile width of the product kernels for rank r (aligned inputs;
+    BF16 with one plane of each operand)."""
     if form == "f32":
         return 32 if r <= 32 else 64 if r <= 64 else 128 if r <= 128 else 256
+    if side == "param_side" and r > 256:
+        return 256              # two 256-column tiles per row block
     return 128 if r <= 128 else 256 if r <= 256 else 512
 
 
@@ -248,7 +251,7 @@ def run_sweep(args):
                 t_hbm, t_mfma = nbytes / (PEAK_HBM_GBS * 1e9), flops / (peak * 1e12)
                 bound = "hbm" if t_hbm >= t_mfma else "mfma"
                 row = {"form": form, "r": r, "side": side, "kernel": product_kernel(form, side, type("C", (), {"m": m, "r": r})),
-                       "tile_cols": column_tile(form, r),
+                       "tile_cols": column_tile(form, r, side),
                        "ms": round(avg, 4), "GB/s": round(nbytes / (avg * 1e-3) / 1e9, 1),
                        "TFLOP/s": round(flops / (avg * 1e-3) / 1e12, 1), "bound": bound,
                        "frac_of_bound": round(max(t_hbm, t_mfma) / (avg * 1e-3), 4)}

@@ -663,9 +663,12 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side_dma(const u16* __
 }
 
 // Parameter side, direct-to-LDS form (arguments as k_gemm16_param_side, plus
-// a zero buffer of at least 16 bytes).
+// a zero buffer of at least 16 bytes).  Below 512 columns the register budget
+// is held to two waves per SIMD (two workgroups per compute unit where LDS
+// allows); at one wave per SIMD the 256-column form waited on its copies
+// most of the time.
 template <int BN, int BK, int PA, int PB>
-__global__ __launch_bounds__(256, 1) void k_gemm16_param_side_dma(const u16* __restrict__ O, int64_t ld,
+__global__ __launch_bounds__(256, BN == 512 ? 1 : 2) void k_gemm16_param_side_dma(const u16* __restrict__ O, int64_t ld,
                                                                   int64_t pstride, int64_t n, int64_t m,
                                                                   const u16* __restrict__ Qs, int64_t qstride, int r,
                                                                   float scale, float* __restrict__ Z,

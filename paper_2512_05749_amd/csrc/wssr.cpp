@@ -393,10 +393,14 @@ struct wssr_ctx {
     // FP32 direct-to-LDS form: 16-byte aligned rows of O and Q; with it,
     // r <= 32 takes the 32-column tile
     const bool dma = !b16 && vec_q && (ld % 4 == 0) && ((uintptr_t)Ov % 16 == 0);
-    const int bn = dma && r <= 32 ? 32 : bn_for(r, b16);
-    const float scale = (float)(1.0 / std::sqrt((double)n));
     // BF16 direct-to-LDS form: 16-byte aligned rows of O
     const bool dma16 = b16 && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0);
+    // BF16 with one plane of each operand and r > 256: two 256-column tiles
+    // (two workgroups per compute unit) in place of one 512-column tile (one)
+    const int bn = dma && r <= 32                                 ? 32
+                   : dma16 && pa == 1 && pb == 1 && r > 256 ? 256
+                                                                  : bn_for(r, b16);
+    const float scale = (float)(1.0 / std::sqrt((double)n));
     const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
     const int sl =
         std::max(1, (b16 ? (dma16 ? slots16pd : slots16p)[v16(bn, pa, pb)] : bn == 32 ? slots32p : slots) / slot_div);
