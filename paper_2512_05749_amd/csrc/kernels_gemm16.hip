@@ -781,6 +781,9 @@ size_t gemm16_dma_lds(int bn, int bk, int pa, int pb) {
   template __global__ void k_gemm16_param_side_dma<BN, BK, PA, PB>(                                                 \
       const u16*, int64_t, int64_t, int64_t, int64_t, const u16*, int64_t, int, float, float*, const u16*,          \
       const DevStatus*, int, int, int64_t, int, float*);
+WSSR_GEMM16_DMA_INST(64, 32, 1, 1)
+WSSR_GEMM16_DMA_INST(64, 32, 1, 2)
+WSSR_GEMM16_DMA_INST(64, 32, 2, 2)
 WSSR_GEMM16_DMA_INST(128, 32, 1, 1)
 WSSR_GEMM16_DMA_INST(128, 32, 1, 2)
 WSSR_GEMM16_DMA_INST(128, 32, 2, 2)

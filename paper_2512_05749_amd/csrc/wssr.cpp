@@ -254,6 +254,17 @@ struct wssr_ctx {
        slots16sd[v16(BN, PA, PB)]);                                                                                 \
   oned((const void*)k_gemm16_param_side_dma<BN, BKD(BN, PA, PB), PA, PB>, BN, BKD(BN, PA, PB), PA, PB,               \
        slots16pd[v16(BN, PA, PB)]);
+    for (int pp = 0; pp < 3; ++pp) {
+      const int pa = pp == 2 ? 2 : 1, pb = pp == 0 ? 1 : 2;
+      const void* fs = pp == 0   ? (const void*)k_gemm16_sample_side_dma<64, 32, 1, 1>
+                       : pp == 1 ? (const void*)k_gemm16_sample_side_dma<64, 32, 1, 2>
+                                 : (const void*)k_gemm16_sample_side_dma<64, 32, 2, 2>;
+      const void* fp = pp == 0   ? (const void*)k_gemm16_param_side_dma<64, 32, 1, 1>
+                       : pp == 1 ? (const void*)k_gemm16_param_side_dma<64, 32, 1, 2>
+                                 : (const void*)k_gemm16_param_side_dma<64, 32, 2, 2>;
+      oned(fs, 64, 32, pa, pb, slots16sd[v16(64, pa, pb)]);
+      oned(fp, 64, 32, pa, pb, slots16pd[v16(64, pa, pb)]);
+    }
     WSSR_SETUP16(128, 32, 1, 1) WSSR_SETUP16(128, 32, 1, 2) WSSR_SETUP16(128, 32, 2, 2)
     WSSR_SETUP16(256, 32, 1, 1) WSSR_SETUP16(256, 32, 1, 2) WSSR_SETUP16(256, 32, 2, 2)
     WSSR_SETUP16(512, 16, 1, 1) WSSR_SETUP16(512, 16, 1, 2) WSSR_SETUP16(512, 16, 2, 2)
@@ -273,10 +284,13 @@ struct wssr_ctx {
   static int bn_for(int r, bool b16) {
     return r <= 64 && !b16 ? 64 : r <= 128 ? 128 : (r <= 256 || !b16 ? 256 : 512);
   }
-  // index of a BF16 product variant: (BN, PA, PB) with BN in {128, 256, 512}
-  static int v16(int bn, int pa, int pb) { return (bn == 128 ? 0 : bn == 256 ? 1 : 2) * 3 + (pa == 2 ? 2 : pb - 1); }
-  int slots16s[9] = {0}, slots16p[9] = {0};   // resident workgroups per variant (sample, parameter side)
-  int slots16sd[9] = {0}, slots16pd[9] = {0}; // the same for the direct-to-LDS variants
+  // index of a BF16 product variant: (BN, PA, PB) with BN in {64, 128, 256, 512}
+  // (BN = 64 exists only in the direct-to-LDS form)
+  static int v16(int bn, int pa, int pb) {
+    return (bn == 64 ? 0 : bn == 128 ? 1 : bn == 256 ? 2 : 3) * 3 + (pa == 2 ? 2 : pb - 1);
+  }
+  int slots16s[12] = {0}, slots16p[12] = {0};   // resident workgroups per variant (sample, parameter side)
+  int slots16sd[12] = {0}, slots16pd[12] = {0}; // the same for the direct-to-LDS variants
   int slots32s = 0, slots32p = 0;             // the same for the FP32 32-column kernels
 
   // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
@@ -311,11 +325,12 @@ struct wssr_ctx {
     // FP32 direct-to-LDS form: 16-byte aligned rows of O and V, whole 16-byte
     // chunks of O's rows; with it, r <= 32 takes the 32-column tile
     const bool dma = !b16 && vec_v && (ld % 4 == 0) && ((uintptr_t)Ov % 16 == 0) && (m % 4 == 0);
-    const int bn = dma && r <= 32 ? 32 : bn_for(r, b16);
-    const int pa = o_planes(), pb = s_planes();
-    const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
     // BF16 direct-to-LDS form: 16-byte aligned rows of O, whole 16-byte chunks of its rows
     const bool dma16 = b16 && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0) && (m % 8 == 0);
+    // narrow column tiles where r allows: FP32 32 (direct form), BF16 64
+    const int bn = dma && r <= 32 ? 32 : dma16 && r <= 64 ? 64 : bn_for(r, b16);
+    const int pa = o_planes(), pb = s_planes();
+    const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
     const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
     const int sl =
         std::max(1, (b16 ? (dma16 ? slots16sd : slots16s)[v16(bn, pa, pb)] : bn == 32 ? slots32s : slots) / slot_div);
@@ -369,17 +384,25 @@ struct wssr_ctx {
     hipLaunchKernelGGL((k_gemm16_sample_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,        \
                        (const unsigned short*)s16, vs, r, ypart, kchunk, vec_o, (const DevStatus*)st, (int)tn,        \
                        (int)tj, xcd)
+#define WSSR_S16D(PA, PB)                                                                                            \
+  hipLaunchKernelGGL((k_gemm16_sample_side_dma<64, 32, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,        \
+                     (const unsigned short*)s16, vs, r, ypart, kchunk, (const unsigned short*)zeros,                  \
+                     (const DevStatus*)st, (int)tn, (int)tj, xcd)
         switch (v16(bn, pa, pb)) {
-          case 0: WSSR_S16(128, 32, 1, 1); break;
-          case 1: WSSR_S16(128, 32, 1, 2); break;
-          case 2: WSSR_S16(128, 32, 2, 2); break;
-          case 3: WSSR_S16(256, 32, 1, 1); break;
-          case 4: WSSR_S16(256, 32, 1, 2); break;
-          case 5: WSSR_S16(256, 32, 2, 2); break;
-          case 6: WSSR_S16(512, 16, 1, 1); break;
-          case 7: WSSR_S16(512, 16, 1, 2); break;
+          case 0: WSSR_S16D(1, 1); break;
+          case 1: WSSR_S16D(1, 2); break;
+          case 2: WSSR_S16D(2, 2); break;
+          case 3: WSSR_S16(128, 32, 1, 1); break;
+          case 4: WSSR_S16(128, 32, 1, 2); break;
+          case 5: WSSR_S16(128, 32, 2, 2); break;
+          case 6: WSSR_S16(256, 32, 1, 1); break;
+          case 7: WSSR_S16(256, 32, 1, 2); break;
+          case 8: WSSR_S16(256, 32, 2, 2); break;
+          case 9: WSSR_S16(512, 16, 1, 1); break;
+          case 10: WSSR_S16(512, 16, 1, 2); break;
           default: WSSR_S16(512, 16, 2, 2); break;
         }
+#undef WSSR_S16D
 #undef WSSR_S16
       });
     }
@@ -398,6 +421,7 @@ struct wssr_ctx {
     // BF16 with one plane of each operand and r > 256: two 256-column tiles
     // (two workgroups per compute unit) in place of one 512-column tile (one)
     const int bn = dma && r <= 32                                 ? 32
+                   : dma16 && r <= 64                             ? 64
                    : dma16 && pa == 1 && pb == 1 && r > 256 ? 256
                                                                   : bn_for(r, b16);
     const float scale = (float)(1.0 / std::sqrt((double)n));
@@ -461,17 +485,25 @@ struct wssr_ctx {
     hipLaunchKernelGGL((k_gemm16_param_side<BN, BK, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,         \
                        (const unsigned short*)s16, qs, r, scale, Z, vec_o, (const DevStatus*)st, (int)tj, full,       \
                        units, skw, skpart)
+#define WSSR_P16D(PA, PB)                                                                                            \
+  hipLaunchKernelGGL((k_gemm16_param_side_dma<64, 32, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,         \
+                     (const unsigned short*)s16, qs, r, scale, Z, (const unsigned short*)zeros, (const DevStatus*)st, \
+                     (int)tj, full, units, skw, skpart)
         switch (v16(bn, pa, pb)) {
-          case 0: WSSR_P16(128, 32, 1, 1); break;
-          case 1: WSSR_P16(128, 32, 1, 2); break;
-          case 2: WSSR_P16(128, 32, 2, 2); break;
-          case 3: WSSR_P16(256, 32, 1, 1); break;
-          case 4: WSSR_P16(256, 32, 1, 2); break;
-          case 5: WSSR_P16(256, 32, 2, 2); break;
-          case 6: WSSR_P16(512, 16, 1, 1); break;
-          case 7: WSSR_P16(512, 16, 1, 2); break;
+          case 0: WSSR_P16D(1, 1); break;
+          case 1: WSSR_P16D(1, 2); break;
+          case 2: WSSR_P16D(2, 2); break;
+          case 3: WSSR_P16(128, 32, 1, 1); break;
+          case 4: WSSR_P16(128, 32, 1, 2); break;
+          case 5: WSSR_P16(128, 32, 2, 2); break;
+          case 6: WSSR_P16(256, 32, 1, 1); break;
+          case 7: WSSR_P16(256, 32, 1, 2); break;
+          case 8: WSSR_P16(256, 32, 2, 2); break;
+          case 9: WSSR_P16(512, 16, 1, 1); break;
+          case 10: WSSR_P16(512, 16, 1, 2); break;
           default: WSSR_P16(512, 16, 2, 2); break;
         }
+#undef WSSR_P16D
 #undef WSSR_P16
       }
       if (skw) {

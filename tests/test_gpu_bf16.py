@@ -60,7 +60,7 @@ def handles():
 # ragged shapes (guarded loads) and shapes whose O rows are whole 16-byte
 # chunks (the direct-to-LDS kernels), for each column-tile width
 SHAPES = [(257, 777, 7), (300, 1001, 40), (1000, 2999, 130), (520, 4096, 256), (1100, 3001, 300), (700, 2048, 512),
-          (333, 2048, 100), (1000, 3000, 64)]
+          (333, 2048, 100), (1000, 3000, 64), (520, 4096, 24), (700, 2048, 8)]
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -81,6 +81,27 @@ def test_products(handles, form, n, m, r):
     assert rel(z, _expected(lambda o_, x_: o_.T @ x_ / np.sqrt(n), planes, x, form)) < TOL_PRODUCT
     g = h.gradient(os_, e).cpu().numpy()
     assert rel(g, orc.gradient(stored_values(os_).cpu().numpy(), _np(e))) < 1e-12
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_products_streamk_narrow(form):
+    """64-column tiles with more parameter-side tiles than one round of
+    resident workgroups holds (stream-K), ragged N."""
+    from paper_2512_05749_amd import Wssr
+    n, m, r = 77, 140_000, 40
+    h = Wssr(n_max=n, m_max=m, r_max=r, q_max=2, dtype=form)
+    try:
+        o, _, v = random_problem(n, m, r, seed=5, device="cuda")
+        os_ = to_storage(o, form)
+        planes = [p.double().cpu().numpy() for p in (os_ if os_.dim() == 3 else [os_])]
+        y = h.sample_side(os_, v).cpu().numpy()
+        assert rel(y, _expected(orc.gemm_sample_side, planes, v, form)) < TOL_PRODUCT
+        x = torch.randn(n, r, device="cuda")
+        x -= x.mean(0, keepdim=True)
+        z = h.param_side(os_, x).cpu().numpy()
+        assert rel(z, _expected(lambda o_, x_: o_.T @ x_ / np.sqrt(n), planes, x, form)) < TOL_PRODUCT
+    finally:
+        h.close()
 
 
 @pytest.mark.parametrize("form", FORMS)
