@@ -511,10 +511,13 @@ __device__ __forceinline__ void dma16_s(const u16* __restrict__ Ss, int64_t pstr
   }
 }
 
-// MFMAs of one ring slot: acc[a][b] += sum over products of A_p B_q
-template <int BN, int BK, int PA, int PB, bool PARAM>
+// MFMAs of one ring slot: acc[a][b] += sum over products of A_p B_q.
+// mid() runs once, right after the first K-block's MFMAs are issued: the
+// copies for a later ring slot go out while those MFMAs execute instead of
+// ahead of them.
+template <int BN, int BK, int PA, int PB, bool PARAM, class Mid>
 __device__ __forceinline__ void mma16_slot(f32x16 (&acc)[2][BN / 64], const unsigned char* S, int wm, int wn,
-                                           int lane) {
+                                           int lane, Mid&& mid) {
   using G = G16<BN, BK, PA, PB, PARAM>;
   const int x = lane & 31, hh = lane >> 5;
 #pragma unroll
@@ -565,6 +568,7 @@ __device__ __forceinline__ void mma16_slot(f32x16 (&acc)[2][BN / 64], const unsi
         if constexpr (PB == 2) acc[a][b] = mfma_bf16(av[0][a], bv[1][b], acc[a][b]);
         if constexpr (PA == 2) acc[a][b] = mfma_bf16(av[1][a], bv[0][b], acc[a][b]);
       }
+    if (kb == 0) mid();
   }
 }
 }  // namespace
@@ -643,8 +647,9 @@ __global__ __launch_bounds__(256, 1) void k_gemm16_sample_side_dma(const u16* __
     else
       wait_vmcnt16<0>();
     __builtin_amdgcn_s_barrier();
-    if (it + 2 < ns) issue(kb + (it + 2) * BK, slot == 0 ? 2 : slot - 1);
-    mma16_slot<BN, BK, PA, PB, false>(acc, sm16 + slot * G::STAGE, wm, wn, lane);
+    mma16_slot<BN, BK, PA, PB, false>(acc, sm16 + slot * G::STAGE, wm, wn, lane, [&] {
+      if (it + 2 < ns) issue(kb + (it + 2) * BK, slot == 0 ? 2 : slot - 1);
+    });
     slot = slot == 2 ? 0 : slot + 1;
   }
 
@@ -721,8 +726,9 @@ __global__ __launch_bounds__(256, BN == 512 ? 1 : 2) void k_gemm16_param_side_dm
       else
         wait_vmcnt16<0>();
       __builtin_amdgcn_s_barrier();
-      if (it + 2 < ns) issue(kb + it + 2, slot == 0 ? 2 : slot - 1);
-      mma16_slot<BN, BK, PA, PB, true>(acc, sm16 + slot * G::STAGE, wm, wn, lane);
+      mma16_slot<BN, BK, PA, PB, true>(acc, sm16 + slot * G::STAGE, wm, wn, lane, [&] {
+        if (it + 2 < ns) issue(kb + it + 2, slot == 0 ? 2 : slot - 1);
+      });
       slot = slot == 2 ? 0 : slot + 1;
     }
     __syncthreads();
