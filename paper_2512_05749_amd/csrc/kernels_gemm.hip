@@ -530,10 +530,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sample_side_dma(const float* __
   for (int64_t it = 0; it < ns; ++it) {
     wait_step<BN>(w, it + 1 >= ns);
     __builtin_amdgcn_s_barrier();
-    if (it + 2 < ns) issue(kb + (it + 2) * BK, slot == 0 ? 2 : slot - 1);
     const unsigned char* S = smd + slot * STAGE;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
+      // the copies for step it + 2 go out once the first half's MFMAs are
+      // issued, so that they overlap MFMA work instead of preceding it
+      if (half == 1 && it + 2 < ns) issue(kb + (it + 2) * BK, slot == 0 ? 2 : slot - 1);
       f32x4 av[TA];
 #pragma unroll
       for (int a = 0; a < TA; ++a) {
@@ -623,10 +625,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_param_side_dma(const float* __r
     for (int64_t it = 0; it < ns; ++it) {
       wait_step<BN>(w, it + 1 >= ns);
       __builtin_amdgcn_s_barrier();
-      if (it + 2 < ns) issue(kb + it + 2, slot == 0 ? 2 : slot - 1);
       const unsigned char* S = smd + slot * STAGE;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
+        // copies for step it + 2 after the first half of the MFMAs
+        if (s == 4 && it + 2 < ns) issue(kb + it + 2, slot == 0 ? 2 : slot - 1);
         const int k = s + 8 * h;
         float av[TA], bv[TB];
 #pragma unroll
