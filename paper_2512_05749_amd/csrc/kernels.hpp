@@ -56,8 +56,9 @@ template <int BN>
 __global__ void k_streamk_fixup(const float* part, float* Z, int64_t m, int r, float scale, int tiles_j,
                                 int full_tiles, int64_t nk, int64_t sk_units, int sk_wgs, const DevStatus* st);
 
-__global__ void k_gradient16_partial(const unsigned short* O, int64_t ld, int64_t pstride, int planes, int64_t n,
-                                     int64_t m, const double* eps, int64_t rows_per_split, double* part, bool vec,
+template <int PL, int CPT>
+__global__ void k_gradient16_partial(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
+                                     const double* eps, int64_t rows_per_split, double* part, bool vec,
                                      const DevStatus* st);
 
 // BF16 products (kernels_gemm16.hip): BN output columns per tile, BK K-step,

@@ -75,42 +75,74 @@ __global__ __launch_bounds__(256) void k_gradient_partial(const float* __restric
   if (c0 + 3 < m) p[c0 + 3] = a3;
 }
 
-// The same partial sums with O in BF16 (planes = 1) or as BF16 hi and lo
-// planes (planes = 2, O = hi + lo, plane stride pstride elements).
+// The same partial sums with O in BF16 (PL = 1) or as BF16 hi and lo planes
+// (PL = 2, O = hi + lo, plane stride pstride elements).  Each thread sums CPT
+// adjacent columns: 8 with 16-byte loads (rows of O 16-byte aligned) or 4
+// with 8-byte loads (8-byte aligned); vec says which alignment holds.  Other
+// threads, and the ragged last columns, load element by element.
+template <int PL, int CPT>
 __global__ __launch_bounds__(256) void k_gradient16_partial(const unsigned short* __restrict__ O, int64_t ld,
-                                                            int64_t pstride, int planes, int64_t n, int64_t m,
+                                                            int64_t pstride, int64_t n, int64_t m,
                                                             const double* __restrict__ eps, int64_t rows_per_split,
                                                             double* __restrict__ part, bool vec, const DevStatus* st) {
   if (failed(st)) return;
-  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * CPT;
   if (c0 >= m) return;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r1 = min(n, r0 + rows_per_split);
-  auto val = [](unsigned short b) { return (double)(float)__builtin_bit_cast(__bf16, b); };
-  double a[4] = {0, 0, 0, 0};
-#pragma unroll 4
-  for (int64_t i = r0; i < r1; ++i) {
-    const double e = eps[i];
-    for (int p = 0; p < planes; ++p) {
-      const unsigned short* row = O + p * pstride + i * ld + c0;
-      if (vec && c0 + 3 < m) {
-        const uint2 w = *reinterpret_cast<const uint2*>(row);
-        a[0] += val((unsigned short)(w.x & 0xffffu)) * e;
-        a[1] += val((unsigned short)(w.x >> 16)) * e;
-        a[2] += val((unsigned short)(w.y & 0xffffu)) * e;
-        a[3] += val((unsigned short)(w.y >> 16)) * e;
-      } else {
+  // a BF16 value is the upper half of an FP32 one
+  auto lo = [](unsigned w) { return (double)__builtin_bit_cast(float, w << 16); };
+  auto hi = [](unsigned w) { return (double)__builtin_bit_cast(float, w & 0xffff0000u); };
+  double a[CPT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (c0 + q < m) a[q] += val(row[q]) * e;
+  for (int q = 0; q < CPT; ++q) a[q] = 0.0;
+  if (vec && c0 + CPT <= m) {
+#pragma unroll 8
+    for (int64_t i = r0; i < r1; ++i) {
+      const double e = eps[i];
+#pragma unroll
+      for (int p = 0; p < PL; ++p) {
+        const unsigned short* row = O + p * pstride + i * ld + c0;
+        unsigned w[CPT / 2];
+        if constexpr (CPT == 8) {
+          const uint4 v = *reinterpret_cast<const uint4*>(row);
+          w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
+        } else {
+          const uint2 v = *reinterpret_cast<const uint2*>(row);
+          w[0] = v.x, w[1] = v.y;
+        }
+#pragma unroll
+        for (int q = 0; q < CPT / 2; ++q) {
+          a[2 * q] += lo(w[q]) * e;
+          a[2 * q + 1] += hi(w[q]) * e;
+        }
+      }
+    }
+  } else {
+    for (int64_t i = r0; i < r1; ++i) {
+      const double e = eps[i];
+#pragma unroll
+      for (int p = 0; p < PL; ++p) {
+        const unsigned short* row = O + p * pstride + i * ld + c0;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+          if (c0 + q < m) a[q] += lo(row[q]) * e;
       }
     }
   }
   double* pp = part + (int64_t)blockIdx.y * m;
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < CPT; ++q)
     if (c0 + q < m) pp[c0 + q] = a[q];
 }
+template __global__ void k_gradient16_partial<1, 4>(const unsigned short*, int64_t, int64_t, int64_t, int64_t,
+                                                    const double*, int64_t, double*, bool, const DevStatus*);
+template __global__ void k_gradient16_partial<1, 8>(const unsigned short*, int64_t, int64_t, int64_t, int64_t,
+                                                    const double*, int64_t, double*, bool, const DevStatus*);
+template __global__ void k_gradient16_partial<2, 4>(const unsigned short*, int64_t, int64_t, int64_t, int64_t,
+                                                    const double*, int64_t, double*, bool, const DevStatus*);
+template __global__ void k_gradient16_partial<2, 8>(const unsigned short*, int64_t, int64_t, int64_t, int64_t,
+                                                    const double*, int64_t, double*, bool, const DevStatus*);
 
 __global__ __launch_bounds__(256) void k_gradient_reduce(const double* __restrict__ part, int nsplit, int64_t m,
                                                          double inv_n, double* __restrict__ g,

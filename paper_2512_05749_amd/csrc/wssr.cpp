@@ -533,7 +533,9 @@ struct wssr_ctx {
                 hipStream_t on = nullptr, bool lean = false) {
     hipStream_t stream = on ? on : this->stream;
     hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, eps, st);
-    const int64_t cb = cdiv(m, 1024);
+    // BF16 rows that are whole 16-byte chunks: 8 columns per thread
+    const bool vec8 = bf16() && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0);
+    const int64_t cb = cdiv(m, vec8 ? 2048 : 1024);
     const int64_t want = lean ? std::max<int64_t>(1, slots / 2 / cb) : cdiv(2048, cb);
     const int gs = (int)std::min<int64_t>(kGSplitMax, std::max<int64_t>(1, std::min<int64_t>(want, n)));
     const int64_t rows = cdiv(n, gs);
@@ -544,9 +546,14 @@ struct wssr_ctx {
                          rows, gpart, vec, (const DevStatus*)st);
     } else {
       const auto* O = static_cast<const unsigned short*>(Ov);
-      const bool vec = (ld % 4 == 0) && ((uintptr_t)O % 8 == 0);
-      hipLaunchKernelGGL(k_gradient16_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n * ld, o_planes(), n, m,
-                         (const double*)eps, rows, gpart, vec, (const DevStatus*)st);
+      const bool vec = vec8 || ((ld % 4 == 0) && ((uintptr_t)O % 8 == 0));
+      const dim3 grid((unsigned)cb, (unsigned)gs);
+      if (o_planes() == 2)
+        hipLaunchKernelGGL((vec8 ? k_gradient16_partial<2, 8> : k_gradient16_partial<2, 4>), grid, dim3(256), 0,
+                           stream, O, ld, n * ld, n, m, (const double*)eps, rows, gpart, vec, (const DevStatus*)st);
+      else
+        hipLaunchKernelGGL((vec8 ? k_gradient16_partial<1, 8> : k_gradient16_partial<1, 4>), grid, dim3(256), 0,
+                           stream, O, ld, n * ld, n, m, (const double*)eps, rows, gpart, vec, (const DevStatus*)st);
     }
     hipLaunchKernelGGL(k_gradient_reduce, dim3(cdiv(m, 256)), dim3(256), 0, stream, (const double*)gpart, gs, m,
                        1.0 / (double)n, gout, (const DevStatus*)st);
