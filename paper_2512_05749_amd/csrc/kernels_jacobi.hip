@@ -126,24 +126,26 @@ __global__ __launch_bounds__(JT) void k_jacobi_coop(double* __restrict__ Bc, dou
     return proceed != 0;
   };
 
-  // rotation of the pair (p, q) of H that zeroes H[p][q]; false when the
-  // pair is already orthogonal (cosine <= tol or entries at rounding level).
-  // The angle comes from hardware reciprocal and square-root estimates (a
-  // rough angle only slows the iteration; what it leaves is measured and
-  // removed later); c and s satisfy c^2 + s^2 = 1 to FP64 rounding.
-  auto rot = [&](const double (*H)[JC + 1], int p, int q, double& c, double& s) -> bool {
-    const double a = H[p][p], d = H[q][q], b = H[p][q];
-    c = 1.0;
-    s = 0.0;
-    if (!(a > floor && d > floor && fabs(b) > absfloor && b * b > tol * tol * (a * d))) return false;
+  // rotation of the pair (p, q) of H, with a = H[p][p], d = H[q][q],
+  // b = H[p][q], that zeroes H[p][q]; c = 1, s = 0 and false when the pair is
+  // already orthogonal (cosine <= tol or entries at rounding level).  The
+  // angle comes from hardware reciprocal and square-root estimates (a rough
+  // angle only slows the iteration; what it leaves is measured and removed
+  // later); c and s satisfy c^2 + s^2 = 1 to FP64 rounding.  Branch-free:
+  // the formula runs on every pair and a select keeps (1, 0) where it does
+  // not apply (it may produce NaN there, which the select drops), so that
+  // both rotations of a thread and all of its LDS reads overlap.
+  auto rot = [&](double a, double d, double b, double& c, double& s) -> bool {
+    const bool act = a > floor && d > floor && fabs(b) > absfloor && b * b > tol * tol * (a * d);
     const double dm = d - a;
     const double h2 = dm * dm + 4.0 * b * b;
     const double hy = h2 * __builtin_amdgcn_rsq(h2);
     const double sg = ((dm >= 0.0) == (b >= 0.0)) ? 2.0 : -2.0;
     const double t = sg * fabs(b) * __builtin_amdgcn_rcp(fabs(dm) + hy);
-    c = rsq_nr_j(1.0 + t * t);
-    s = c * t;
-    return true;
+    const double cc = rsq_nr_j(1.0 + t * t);
+    c = act ? cc : 1.0;
+    s = act ? cc * t : 0.0;
+    return act;
   };
 
   for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
@@ -213,35 +215,43 @@ __global__ __launch_bounds__(JT) void k_jacobi_coop(double* __restrict__ Bc, dou
         // by the owner of each block.
         const int ra = tid >> 4, rb = tid & 15;
         int cur = 0;
+        // this thread's pairs in rotation round 0; each round reads the next
+        // round's from the (constant) table while its own reads are in flight
+        int pa = ptab[0][ra][0], qa = ptab[0][ra][1];
+        int pb = ptab[0][rb][0], qb = ptab[0][rb][1];
         for (int isw = 0; isw < inner_sweeps; ++isw) {
           int myrot = 0;
           for (int ird = 0; ird < JC - 1; ++ird) {
             const double(*Hc)[JC + 1] = cur ? H1 : H0;
             double(*Hn)[JC + 1] = cur ? H0 : H1;
-            const int pa = ptab[ird][ra][0], qa = ptab[ird][ra][1];
-            const int pb = ptab[ird][rb][0], qb = ptab[ird][rb][1];
-            double ca, sa, cb, sb;
-            myrot |= (int)rot(Hc, pa, qa, ca, sa);
-            rot(Hc, pb, qb, cb, sb);
+            const double aa = Hc[pa][pa], da = Hc[qa][qa], ba = Hc[pa][qa];
+            const double ab = Hc[pb][pb], db = Hc[qb][qb], bb = Hc[pb][qb];
             const double x11 = Hc[pa][pb], x12 = Hc[pa][qb], x21 = Hc[qa][pb], x22 = Hc[qa][qb];
-            // H <- R_a^T H R_b on the block; J <- J R_b on the block
+            const double j11 = J[pa][pb], j12 = J[pa][qb], j21 = J[qa][pb], j22 = J[qa][qb];
+            const int nr = ird + 1 < JC - 1 ? ird + 1 : 0;
+            const int pa2 = ptab[nr][ra][0], qa2 = ptab[nr][ra][1];
+            const int pb2 = ptab[nr][rb][0], qb2 = ptab[nr][rb][1];
+            double ca, sa, cb, sb;
+            myrot |= (int)rot(aa, da, ba, ca, sa);
+            rot(ab, db, bb, cb, sb);
+            // H <- R_a^T H R_b on the block; J <- J R_b on the block (the
+            // identity where the pair b does not rotate)
             const double y11 = ca * x11 - sa * x21, y12 = ca * x12 - sa * x22;
             const double y21 = sa * x11 + ca * x21, y22 = sa * x12 + ca * x22;
-            double z11 = cb * y11 - sb * y12, z12 = sb * y11 + cb * y12;
-            double z21 = cb * y21 - sb * y22, z22 = sb * y21 + cb * y22;
-            if (ra == rb && sa != 0.0) z12 = z21 = 0.0;
+            const double z11 = cb * y11 - sb * y12, z22 = sb * y21 + cb * y22;
+            const bool zero_off = ra == rb && sa != 0.0;
+            const double z12 = zero_off ? 0.0 : sb * y11 + cb * y12;
+            const double z21 = zero_off ? 0.0 : cb * y21 - sb * y22;
             Hn[pa][pb] = z11;
             Hn[pa][qb] = z12;
             Hn[qa][pb] = z21;
             Hn[qa][qb] = z22;
-            if (sb != 0.0) {
-              const double j11 = J[pa][pb], j12 = J[pa][qb], j21 = J[qa][pb], j22 = J[qa][qb];
-              J[pa][pb] = cb * j11 - sb * j12;
-              J[pa][qb] = sb * j11 + cb * j12;
-              J[qa][pb] = cb * j21 - sb * j22;
-              J[qa][qb] = sb * j21 + cb * j22;
-            }
+            J[pa][pb] = cb * j11 - sb * j12;
+            J[pa][qb] = sb * j11 + cb * j12;
+            J[qa][pb] = cb * j21 - sb * j22;
+            J[qa][qb] = sb * j21 + cb * j22;
             cur ^= 1;
+            pa = pa2, qa = qa2, pb = pb2, qb = qb2;
             __syncthreads();
           }
           if (!__syncthreads_or(myrot)) break;
