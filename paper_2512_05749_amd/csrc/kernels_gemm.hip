@@ -1,10 +1,19 @@
 // The two tall-skinny products of each subspace-iteration pass (Alg. 1), in
-// FP32 on the 32x32x2 FP32 MFMA with LDS-staged, double-buffered tiles.
+// FP32 on the 32x32x2 FP32 MFMA.
 //
 //   sample side    Ypart[s] = O[:, Ks] V[Ks, :]     (N x r, K = M split into S ranges)
 //   parameter side Z = O^T Q * scale                 (M x r, K = N)
 //
-// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; output tile
+// Three forms, chosen by the host:
+//   - register-staged (k_gemm_*_side<BN>, described first below): any
+//     alignment of O and of the skinny operand;
+//   - direct-to-LDS (k_gemm_*_side_dma<BN>): 16-byte aligned rows, a
+//     three-slot LDS ring filled by global_load_lds; BN = 32 (sample side,
+//     r <= 32) to 256;
+//   - narrow parameter side (k_gemm_param_side_narrow): aligned rows and
+//     r <= 32, O staged through registers four K-steps ahead.
+//
+// Register-staged workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; output tile
 // 128 rows x BN columns (BN = 64, 128 or 256 over the rank dimension); each
 // wave owns a 64 x (BN/2) sub-tile = 2 x (BN/64) MFMA tiles of 32 x 32, i.e.
 // 8 FP32 accumulator tiles at BN = 256.  K advances 16 at a time with one barrier per
