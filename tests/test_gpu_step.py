@@ -69,7 +69,9 @@ def test_small_workload_ten_steps(ws):
 
 
 @pytest.mark.parametrize("n,m,r,q", [(257, 1001, 7, 2), (500, 3000, 65, 3), (130, 200, 129, 2),
-                                     (64, 4999, 1, 1), (2048, 4096, 192, 2)])
+                                     (64, 4999, 1, 1), (2048, 4096, 192, 2),
+                                     # aligned rows and r <= 32: the 32-column product kernels
+                                     (1000, 4000, 32, 2), (333, 4096, 12, 3)])
 def test_ragged_shapes(ws, n, m, r, q):
     o, e, v = random_problem(n, m, r, seed=n * 7 + r, device="cuda", alpha=1.0)
     v_in = v.clone()
