@@ -512,6 +512,12 @@ __device__ __forceinline__ void dma16_s(const u16* __restrict__ Ss, int64_t pstr
 }
 
 // MFMAs of one ring slot: acc[a][b] += sum over products of A_p B_q.
+// On the parameter side the fragments of K-block kb + 1 are read from LDS
+// before the MFMAs of K-block kb are issued, so that the latency of their
+// transposing reads hides behind those MFMAs (on the sample side a second set
+// of fragment registers measured no gain; the 256-column tile with two O
+// planes has no registers for it, and the 512-column tiles take one K-block
+// per step).
 // mid() runs once, right after the first K-block's MFMAs are issued: the
 // copies for a later ring slot go out while those MFMAs execute instead of
 // ahead of them.
@@ -520,9 +526,7 @@ __device__ __forceinline__ void mma16_slot(f32x16 (&acc)[2][BN / 64], const unsi
                                            int lane, Mid&& mid) {
   using G = G16<BN, BK, PA, PB, PARAM>;
   const int x = lane & 31, hh = lane >> 5;
-#pragma unroll
-  for (int kb = 0; kb < G::KB; ++kb) {
-    u32x4 av[PA][2], bv[PB][G::TB];
+  auto frags = [&](int kb, u32x4 (&av)[PA][2], u32x4 (&bv)[PB][G::TB]) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < PA; ++p)
 #pragma unroll
@@ -560,13 +564,25 @@ __device__ __forceinline__ void mma16_slot(f32x16 (&acc)[2][BN / 64], const unsi
       for (int b = 0; b < G::TB; ++b)
         bv[q][b] = *reinterpret_cast<const u32x4*>(S + PA * G::A_PLANE + q * G::S_PLANE + kb * (BN * 32) +
                                                    (wn * (BN / 2) + b * 32 + x) * 32 + hh * 16);
+  };
+  constexpr bool PF = PARAM && BN <= 256 && !(BN == 256 && PA == 2);
+  u32x4 av[2][PA][2], bv[2][PB][G::TB];
+  if constexpr (PF) frags(0, av[0], bv[0]);
+#pragma unroll
+  for (int kb = 0; kb < G::KB; ++kb) {
+    if constexpr (PF) {
+      if (kb + 1 < G::KB) frags(kb + 1, av[(kb + 1) & 1], bv[(kb + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      frags(kb, av[kb & 1], bv[kb & 1]);
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < G::TB; ++b) {
-        acc[a][b] = mfma_bf16(av[0][a], bv[0][b], acc[a][b]);
-        if constexpr (PB == 2) acc[a][b] = mfma_bf16(av[0][a], bv[1][b], acc[a][b]);
-        if constexpr (PA == 2) acc[a][b] = mfma_bf16(av[1][a], bv[0][b], acc[a][b]);
+        acc[a][b] = mfma_bf16(av[kb & 1][0][a], bv[kb & 1][0][b], acc[a][b]);
+        if constexpr (PB == 2) acc[a][b] = mfma_bf16(av[kb & 1][0][a], bv[kb & 1][1][b], acc[a][b]);
+        if constexpr (PA == 2) acc[a][b] = mfma_bf16(av[kb & 1][1][a], bv[kb & 1][0][b], acc[a][b]);
       }
     if (kb == 0) mid();
   }
