@@ -60,7 +60,9 @@ def handles():
 # ragged shapes (guarded loads) and shapes whose O rows are whole 16-byte
 # chunks (the direct-to-LDS kernels), for each column-tile width
 SHAPES = [(257, 777, 7), (300, 1001, 40), (1000, 2999, 130), (520, 4096, 256), (1100, 3001, 300), (700, 2048, 512),
-          (333, 2048, 100), (1000, 3000, 64), (520, 4096, 24), (700, 2048, 8)]
+          (333, 2048, 100), (1000, 3000, 64), (520, 4096, 24), (700, 2048, 8),
+          # fewer samples than one K-step of the parameter side
+          (8, 4096, 16), (20, 2048, 300)]
 
 
 @pytest.mark.parametrize("form", FORMS)

@@ -98,7 +98,9 @@ DMA_SHAPES = [(333, 2048, 32), (500, 3000, 100), (257, 4100, 128), (500, 70_000,
               (511, 6_000, 256),
               # r <= 32: the 32-column tile, ragged rows and columns, and a
               # parameter side with more tiles than one round (stream-K)
-              (257, 4100, 4), (100, 6_000, 20), (512, 3000, 32), (500, 140_000, 8), (77, 140_000, 28)]
+              (257, 4100, 4), (100, 6_000, 20), (512, 3000, 32), (500, 140_000, 8), (77, 140_000, 28),
+              # fewer samples than one K-step of the parameter side
+              (8, 4096, 8), (16, 5000, 24), (5, 2000, 64)]
 
 
 @pytest.mark.parametrize("n,m,r", DMA_SHAPES)
