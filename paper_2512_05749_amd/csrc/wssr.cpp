@@ -418,12 +418,14 @@ struct wssr_ctx {
     const bool dma = !b16 && vec_q && (ld % 4 == 0) && ((uintptr_t)Ov % 16 == 0);
     // BF16 direct-to-LDS form: 16-byte aligned rows of O
     const bool dma16 = b16 && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0);
-    // BF16 with one plane of each operand and r > 256: two 256-column tiles
-    // (two workgroups per compute unit) in place of one 512-column tile (one)
-    const int bn = dma && r <= 32                                 ? 32
-                   : dma16 && r <= 64                             ? 64
+    // narrow column tiles where r allows (FP32 32: the narrow kernel; BF16
+    // 64); BF16 with one plane of each operand and r > 256: two 256-column
+    // tiles (two workgroups per compute unit) in place of one 512-column tile
+    // (one)
+    const int bn = dma && r <= 32                           ? 32
+                   : dma16 && r <= 64                       ? 64
                    : dma16 && pa == 1 && pb == 1 && r > 256 ? 256
-                                                                  : bn_for(r, b16);
+                                                            : bn_for(r, b16);
     const float scale = (float)(1.0 / std::sqrt((double)n));
     const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
     const int sl =
