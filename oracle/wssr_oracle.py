@@ -320,11 +320,8 @@ def wssr_step(o, e_l, v_in, lam, r, q, precond="damped"):
 def sr_direct(o, e_l, lam):
     """delta_full = (S + lam I)^{-1} g with S = A^T A formed (M x M), Cholesky solve
     (eq. param:update2 with the diagonal shift of Sec. 3.2)."""
-    a = scaled_centered(o)
-    n = o.shape[0]
-    g = a.T @ center_energies(e_l) / np.sqrt(n)
-    s = a.T @ a
-    return spd_solve(s + lam * np.eye(s.shape[0]), g)
+    s = s_matrix(o)
+    return spd_solve(s + lam * np.eye(s.shape[0]), gradient(o, e_l))
 
 
 def sr_pushthrough(o, e_l, lam):

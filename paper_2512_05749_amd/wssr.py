@@ -105,7 +105,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _need(t, name, dtype, device, shape=None):
+def _need(t, name, dtype, device, shape=None, contiguous=False):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.dtype != dtype:
@@ -114,6 +114,9 @@ def _need(t, name, dtype, device, shape=None):
         raise ValueError(f"{name} must be on {device}, got {t.device}")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if contiguous and not t.is_contiguous():
+        # the library reads and writes packed arrays at the tensor's data pointer
+        raise ValueError(f"{name} must be contiguous")
 
 
 class Wssr:
@@ -165,6 +168,21 @@ class Wssr:
         _need(O, "O", torch.float32 if self.dtype == "f32" else torch.bfloat16, self.device)
         return O.shape[0], O.shape[1], O.stride(0)
 
+    def _operand(self, t):
+        """t itself when contiguous; otherwise a packed copy whose memory the
+        caching allocator keeps until the work queued on the handle's stream
+        so far has finished (the library may still be reading it after this
+        call returns, when that stream is not torch's current one)."""
+        if t.is_contiguous():
+            return t
+        c = t.contiguous()
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            # the copy was queued on torch's current stream
+            self.stream.wait_stream(cur)
+        c.record_stream(self.stream)
+        return c
+
     def close(self):
         if getattr(self, "_h", None):
             lib().wssr_destroy(self._h)
@@ -191,8 +209,8 @@ class Wssr:
             delta = torch.empty(m, dtype=torch.float64, device=self.device)
         if sigma is None:
             sigma = torch.empty(r, dtype=torch.float64, device=self.device)
-        _need(delta, "delta", torch.float64, self.device, (m,))
-        _need(sigma, "sigma", torch.float64, self.device, (r,))
+        _need(delta, "delta", torch.float64, self.device, (m,), contiguous=True)
+        _need(sigma, "sigma", torch.float64, self.device, (r,), contiguous=True)
         self._check(lib().wssr_step(self._h, n, m, _ptr(O), ld, _ptr(e_l), _ptr(V), float(lam), r, int(q),
                                     _ptr(delta), _ptr(sigma)))
         return delta, sigma
@@ -222,9 +240,9 @@ class Wssr:
                 delta = torch.empty(m, dtype=torch.float64, device=self.device)
             if sigma is None:
                 sigma = torch.empty(r, dtype=torch.float64, device=self.device)
-            _need(delta, "delta", torch.float64, self.device, (m,))
-            _need(sigma, "sigma", torch.float64, self.device, (r,))
-            e_c = e_l.contiguous()
+            _need(delta, "delta", torch.float64, self.device, (m,), contiguous=True)
+            _need(sigma, "sigma", torch.float64, self.device, (r,), contiguous=True)
+            e_c = self._operand(e_l)
             arr[i] = Problem(n, m, ld, O.data_ptr(), e_c.data_ptr(), V.data_ptr(), float(pb["lam"]),
                              r, int(pb.get("q", 2)), delta.data_ptr(), sigma.data_ptr())
             outs.append((delta, sigma))
@@ -278,7 +296,7 @@ class Wssr:
         r = V.shape[1]
         _need(V, "V", torch.float32, self.device, (m, r))
         y = torch.empty(n, r, dtype=torch.float64, device=self.device)
-        self._check(lib().wssr_dbg_sample_side(self._h, n, m, _ptr(O), ld, _ptr(V.contiguous()), r, _ptr(y)))
+        self._check(lib().wssr_dbg_sample_side(self._h, n, m, _ptr(O), ld, _ptr(self._operand(V)), r, _ptr(y)))
         return y
 
     def param_side(self, O, X):
@@ -286,20 +304,20 @@ class Wssr:
         r = X.shape[1]
         _need(X, "X", torch.float32, self.device, (n, r))
         z = torch.empty(m, r, dtype=torch.float32, device=self.device)
-        self._check(lib().wssr_dbg_param_side(self._h, n, m, _ptr(O), ld, _ptr(X.contiguous()), r, _ptr(z)))
+        self._check(lib().wssr_dbg_param_side(self._h, n, m, _ptr(O), ld, _ptr(self._operand(X)), r, _ptr(z)))
         return z
 
     def gradient(self, O, e_l):
         n, m, ld = self._o(O)
         _need(e_l, "e_l", torch.float64, self.device, (n,))
         g = torch.empty(m, dtype=torch.float64, device=self.device)
-        self._check(lib().wssr_dbg_gradient(self._h, n, m, _ptr(O), ld, _ptr(e_l.contiguous()), _ptr(g)))
+        self._check(lib().wssr_dbg_gradient(self._h, n, m, _ptr(O), ld, _ptr(self._operand(e_l)), _ptr(g)))
         return g
 
     def cholqr2(self, X):
         rows, r = X.shape
         _need(X, "X", torch.float32, self.device)
-        X = X.contiguous()
+        X = self._operand(X)
         Q = torch.empty(rows, r, dtype=torch.float32, device=self.device)
         R = torch.empty(r, r, dtype=torch.float64, device=self.device)
         self._check(lib().wssr_dbg_cholqr2(self._h, rows, _ptr(X), r, _ptr(Q), _ptr(R)))
@@ -308,7 +326,7 @@ class Wssr:
     def small_svd(self, C):
         r = C.shape[0]
         _need(C, "C", torch.float64, self.device, (r, r))
-        C = C.contiguous()
+        C = self._operand(C)
         s = torch.empty(r, dtype=torch.float64, device=self.device)
         P = torch.empty(r, r, dtype=torch.float64, device=self.device)
         self._check(lib().wssr_dbg_small_svd(self._h, _ptr(C), r, _ptr(s), _ptr(P)))

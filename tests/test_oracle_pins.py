@@ -58,6 +58,19 @@ def test_golden_hand_examples():
         np.testing.assert_allclose(res["v"], sub["V"], atol=1e-12)
 
 
+def test_s_matrix_hand_values_and_loop_sum():
+    """S = O_bar^T O_bar / N (eq. SN with the 1/N of eq. Osrn): the hand-derived
+    S of both golden cases, and an element-by-element loop over samples."""
+    for c in json.loads((GOLDEN / "hand_examples.json").read_text())["cases"]:
+        np.testing.assert_allclose(orc.s_matrix(np.array(c["O"], float)), c["S"], atol=1e-15)
+    o, _ = _problem(7, 5, seed=21)
+    n, m = o.shape
+    mu = [sum(o[k, j] for k in range(n)) / n for j in range(m)]
+    loop = np.array([[sum((o[k, i] - mu[i]) * (o[k, j] - mu[j]) for k in range(n)) / n for j in range(m)]
+                     for i in range(m)])
+    np.testing.assert_allclose(orc.s_matrix(o), loop, rtol=1e-13, atol=1e-15)
+
+
 # --------------------------------------------------------------- building blocks
 
 @pytest.mark.parametrize("n", [1, 2, 7, 30])
