@@ -147,6 +147,48 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
                       const double* e_l, float* V, double lambda, int32_t r, int32_t q,
                       double* delta, double* sigma);
 
+/* One WSSR step with a gradient the caller supplies: the same step as
+ * wssr_step, except that g (device, double[m]) is used as the gradient of
+ * eq. barg and the step makes no gradient pass over O (E_L is not needed).
+ * This is how the BF16 forms use a gradient formed from the unrounded O by
+ * wssr_ingest: BF16 storage of O perturbs g by about 2^-9 relative, and the
+ * damping 1/lambda of the update amplifies that into delta, while the
+ * subspace iteration tolerates it.  g is read only. */
+wssr_status wssr_step_g(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* g,
+                        float* V, double lambda, int32_t r, int32_t q, double* delta, double* sigma);
+
+/* Ingest of O: one pass over a block of rows of the unrounded FP32 matrix
+ * that writes them in the handle's storage form and forms, from the unrounded
+ * values, the gradient g = O_bar^T eps / n (Sec. 4.1 eq. barg; eps = E_L -
+ * mean(E_L), Sec. 3.1 eq. Lbarn) and the column means mu of O (eq. Osr).
+ *   n, m      the whole matrix: n rows (samples), m columns; n <= n_max, m <= m_max
+ *   row0, rows  this block: rows row0 .. row0 + rows - 1.  The block with
+ *             row0 = 0 centres e_l and starts the sums (overwriting g and
+ *             colmean); the following calls must continue from the next row,
+ *             without gaps, with the same n and m (checked: WSSR_ERR_INVALID_ARG),
+ *             and after the block that ends at row n, g and colmean hold their
+ *             final values.  A block may be the whole matrix.
+ *   O32, ld32 device, float, the block's rows (row i of the block at O32 + i * ld32), ld32 >= m
+ *   e_l       device, double[n]: all n energies (the same array for every block)
+ *   mu        device, double[m] or NULL: when given, the stored values are
+ *             x - mu[j] (explicit centring before rounding, for data whose
+ *             column means are large against its spread; pass the colmean of a
+ *             first pass with O_out = NULL).  g and colmean always use x.
+ *   O_out, ld_o  device, the whole stored matrix (row 0), row stride ld_o >= m, in
+ *             the handle's dtype: float (WSSR_F32), BF16 (WSSR_BF16, WSSR_BF16_SPLIT),
+ *             or the hi plane with the lo plane at O_out + n * ld_o (WSSR_BF16X2);
+ *             rows row0 .. row0 + rows - 1 are written.  BF16 values are
+ *             round-to-nearest-even: hi = RNE(x), lo = RNE(x - hi).  NULL: nothing
+ *             is stored (a statistics pass).
+ *   g         device, double[m] or NULL: out, sum_i O[i, j] eps_i / n
+ *   colmean   device, double[m] or NULL: out, the column means of O; must not alias mu
+ * Numerical status (a non-finite value of O or E_L: WSSR_ERR_NONFINITE) is
+ * read with wssr_status_sync after the last block; the next step resets it.
+ * Cost: one read of the FP32 block and one write of its stored form (HBM-bound). */
+wssr_status wssr_ingest(wssr_handle h, int64_t n, int64_t m, int64_t row0, int64_t rows, const float* O32,
+                        int64_t ld32, const double* e_l, const double* mu, void* O_out, int64_t ld_o, double* g,
+                        double* colmean);
+
 /* Batched form: `count` independent steps (1 <= count <= 1024), each with its
  * own sizes, lambda, r and q within the handle's capacities, in the handle's
  * dtype.  The problems are spread over the handle's lanes (longest first onto

@@ -119,6 +119,16 @@ __global__ void k_jacobi_final(const double* Bc, const double* Pc, int rp, int r
                                DevStatus* st);
 
 __global__ void k_transpose_pad(const double* C, int r, int rp, double* Ct);
+// ingest of O (kernels_ingest.hip): storage form plus gradient and column sums
+// from the unrounded values
+template <int PL, bool OUT_F32>
+__global__ void k_ingest_partial(const float* O32, int64_t ld32, int64_t rows, int64_t m, const double* eps,
+                                 const double* mu, void* out, int64_t ld_out, int64_t pstride,
+                                 int64_t rows_per_split, double* gpart, double* cpart, bool vec, bool vec_out,
+                                 DevStatus* st);
+__global__ void k_ingest_reduce(const double* gpart, const double* cpart, int nsplit, int64_t m, double inv_n,
+                                bool first, double* g, double* mu);
+
 
 // dynamic LDS sizes (bytes)
 constexpr size_t kCholLds = 4 * 64 * 65 * sizeof(double);

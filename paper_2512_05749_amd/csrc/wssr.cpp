@@ -166,9 +166,13 @@ struct wssr_ctx {
   hipError_t last() { return hipGetLastError(); }
 
   // Enqueue one step on this context's stream (arguments already checked).
+  // g_ext (nullable): a gradient the caller formed (wssr_step_g); the step
+  // then makes no gradient pass and does not read e_l.
   wssr_status enqueue(int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, float* V,
-                      double lambda, int32_t r, int32_t q, double* delta, double* sigma) {
+                      double lambda, int32_t r, int32_t q, double* delta, double* sigma,
+                      const double* g_ext = nullptr) {
     wssr_ctx* h = this;
+    const double* gv = g_ext ? g_ext : h->g;
     const int rp = (int)rup(r, 64);
     const DevStatus* cst = h->st;
     hipStream_t stream = h->stream;
@@ -189,10 +193,12 @@ struct wssr_ctx {
       } else {
         // the gradient (one HBM-bound pass over O) runs on the second stream
         // while this stream works through the few-workgroup Jacobi launches
-        (void)hipEventRecord(h->ev_fork, stream);
-        (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
-        h->gradient(O, ld_o, n, m, e_l, h->g, h->side, true);
-        (void)hipEventRecord(h->ev_join, h->side);
+        if (!g_ext) {
+          (void)hipEventRecord(h->ev_fork, stream);
+          (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+          h->gradient(O, ld_o, n, m, e_l, h->g, h->side, true);
+          (void)hipEventRecord(h->ev_join, h->side);
+        }
         // Rayleigh-Ritz: C = Q_Y^T A Q_Z = R_Z^T;  C = G diag(sigma) P^T
         h->small_svd(h->Rz, r);
         // V = Q_Z P = Z (Tq P)
@@ -200,7 +206,7 @@ struct wssr_ctx {
         h->apply((const float*)h->z, m, r, r, h->T, rp, r, h->vw, r, false);
       }
     }
-    (void)hipStreamWaitEvent(stream, h->ev_join, 0);
+    if (!g_ext) (void)hipStreamWaitEvent(stream, h->ev_join, 0);
     if (h->coop_err != hipSuccess)
       return h->fail(WSSR_ERR_HIP, "cooperative launch of the SVD kernel failed: %s", hipGetErrorString(h->coop_err));
     // output signs, then V <- signed vw
@@ -218,10 +224,10 @@ struct wssr_ctx {
                          (const float*)h->sgn, tot, r, V, cst);
       // Woodbury
       hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
-                         (const double*)h->g, m, r, rpc, h->vpart, cst);
+                         gv, m, r, rpc, h->vpart, cst);
       hipLaunchKernelGGL(k_vtg_final, dim3(r), dim3(256), 0, stream, (const double*)h->vpart, nch, r,
                          (const double*)h->sig, lambda, (h->cfg.flags & WSSR_FLOOR_PRECOND) ? 1 : 0, h->cw, sigma, cst);
-      hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, (const double*)h->g,
+      hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, gv,
                          (const double*)h->cw, m, r, 1.0 / lambda, delta, cst);
     }
     if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
@@ -559,6 +565,44 @@ struct wssr_ctx {
     }
     hipLaunchKernelGGL(k_gradient_reduce, dim3(cdiv(m, 256)), dim3(256), 0, stream, (const double*)gpart, gs, m,
                        1.0 / (double)n, gout, (const DevStatus*)st);
+  }
+
+  // Ingest of a block of rows of FP32 O (see wssr_ingest).  The first block
+  // (row0 == 0) centres the energies and starts the sums.
+  int64_t ingest_next = -1, ingest_n = 0, ingest_m = 0;
+  void ingest(int64_t n, int64_t m, int64_t row0, int64_t rows, const float* O32, int64_t ld32,
+              const double* e_l, const double* mu, void* out, int64_t ld_o, double* gout, double* mout) {
+    const bool first = row0 == 0;
+    if (first) {
+      hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, st);
+      hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, eps, st);
+    }
+    const int64_t cb = cdiv(m, 2048);
+    const int gs = (int)std::min<int64_t>(kGSplitMax / 2, std::max<int64_t>(1, std::min(cdiv(2048, cb), rows)));
+    const int64_t rps = cdiv(rows, gs);
+    const int nsplit = (int)cdiv(rows, rps);
+    double* gp = gpart;
+    double* cp = gpart + (int64_t)(kGSplitMax / 2) * m;
+    const bool vec = (ld32 % 4 == 0) && ((uintptr_t)O32 % 16 == 0);
+    const dim3 grid((unsigned)cb, (unsigned)nsplit);
+    const double* e = eps + row0;
+    if (!bf16()) {
+      float* o = out ? static_cast<float*>(out) + row0 * ld_o : nullptr;
+      const bool vo = (ld_o % 4 == 0) && ((uintptr_t)out % 16 == 0);
+      hipLaunchKernelGGL((k_ingest_partial<1, true>), grid, dim3(256), 0, stream, O32, ld32, rows, m, e, mu,
+                         (void*)o, ld_o, n * ld_o, rps, gp, cp, vec, vo, st);
+    } else {
+      unsigned short* o = out ? static_cast<unsigned short*>(out) + row0 * ld_o : nullptr;
+      const bool vo = (ld_o % 8 == 0) && ((uintptr_t)out % 16 == 0);
+      if (o_planes() == 2)
+        hipLaunchKernelGGL((k_ingest_partial<2, false>), grid, dim3(256), 0, stream, O32, ld32, rows, m, e, mu,
+                           (void*)o, ld_o, n * ld_o, rps, gp, cp, vec, vo, st);
+      else
+        hipLaunchKernelGGL((k_ingest_partial<1, false>), grid, dim3(256), 0, stream, O32, ld32, rows, m, e, mu,
+                           (void*)o, ld_o, n * ld_o, rps, gp, cp, vec, vo, st);
+    }
+    hipLaunchKernelGGL(k_ingest_reduce, dim3(cdiv(m, 256)), dim3(256), 0, stream, (const double*)gp,
+                       (const double*)cp, nsplit, m, 1.0 / (double)n, first, gout, mout);
   }
 
   // row chunks of the Gram partials: about 512 workgroups, at least 256 rows
@@ -944,6 +988,42 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
   if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
 
   return h->enqueue(n, m, O, ld_o, e_l, V, lambda, r, q, delta, sigma);
+}
+
+wssr_status wssr_step_g(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* g,
+                        float* V, double lambda, int32_t r, int32_t q, double* delta, double* sigma) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!g) return h->fail(WSSR_ERR_INVALID_ARG, "g is NULL");
+  // e_l is not read: any non-null pointer passes the common check
+  wssr_status s = check_step(h, n, m, O, ld_o, g, V, lambda, r, q, delta, sigma);
+  if (s != WSSR_OK) return s;
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+  return h->enqueue(n, m, O, ld_o, nullptr, V, lambda, r, q, delta, sigma, g);
+}
+
+wssr_status wssr_ingest(wssr_handle h, int64_t n, int64_t m, int64_t row0, int64_t rows, const float* O32,
+                        int64_t ld32, const double* e_l, const double* mu, void* O_out, int64_t ld_o, double* g,
+                        double* colmean) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!O32 || !e_l) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (n < 2 || n > h->cfg.n_max) return h->fail(WSSR_ERR_INVALID_ARG, "n=%lld outside [2, n_max]", (long long)n);
+  if (m < 1 || m > h->cfg.m_max) return h->fail(WSSR_ERR_INVALID_ARG, "m=%lld outside [1, m_max]", (long long)m);
+  if (rows < 1 || row0 < 0 || row0 + rows > n)
+    return h->fail(WSSR_ERR_INVALID_ARG, "rows [%lld, %lld) outside [0, n)", (long long)row0, (long long)(row0 + rows));
+  if (ld32 < m) return h->fail(WSSR_ERR_INVALID_ARG, "ld32 < m");
+  if (O_out && ld_o < m) return h->fail(WSSR_ERR_INVALID_ARG, "ld_o < m");
+  if (mu && mu == colmean) return h->fail(WSSR_ERR_INVALID_ARG, "colmean must not alias mu");
+  if (row0 != 0 && (row0 != h->ingest_next || n != h->ingest_n || m != h->ingest_m))
+    return h->fail(WSSR_ERR_INVALID_ARG,
+                   "blocks must follow each other from row 0 without gaps (expected row0=%lld for n=%lld, m=%lld)",
+                   (long long)h->ingest_next, (long long)h->ingest_n, (long long)h->ingest_m);
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+  h->ingest(n, m, row0, rows, O32, ld32, e_l, mu, O_out, ld_o, g, colmean);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  h->ingest_n = n;
+  h->ingest_m = m;
+  h->ingest_next = row0 + rows == n ? -1 : row0 + rows;
+  return WSSR_OK;
 }
 
 namespace {

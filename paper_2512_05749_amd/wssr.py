@@ -64,6 +64,8 @@ _SIGS = {
     "wssr_create": ([ctypes.POINTER(Config), ctypes.POINTER(_P)], ctypes.c_int),
     "wssr_destroy": ([_P], ctypes.c_int),
     "wssr_step": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
+    "wssr_step_g": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
+    "wssr_ingest": ([_P, _I64, _I64, _I64, _I64, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
     "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
     "wssr_batched_status": ([_P, _I32, ctypes.POINTER(_I32)], ctypes.c_int),
@@ -195,25 +197,75 @@ class Wssr:
             pass
 
     # ------------------------------------------------------------------ step
-    def step(self, O, e_l, V, lam, q=2, delta=None, sigma=None):
-        """One WSSR step.  V (m x r, float32) is updated in place; returns (delta, sigma)."""
+    def step(self, O, e_l, V, lam, q=2, delta=None, sigma=None, g=None):
+        """One WSSR step.  V (m x r, float32) is updated in place; returns (delta, sigma).
+        With g (float64 [m], e.g. from ingest) the step uses that gradient
+        (wssr_step_g) and e_l may be None."""
         n, m, ld = self._o(O)
         if V.dim() != 2 or not V.is_contiguous():
             raise ValueError("V must be a contiguous m x r tensor")
         r = V.shape[1]
         _need(V, "V", torch.float32, self.device, (m, r))
-        _need(e_l, "e_l", torch.float64, self.device, (n,))
-        if not e_l.is_contiguous():
-            raise ValueError("e_l must be contiguous")
+        if g is None:
+            _need(e_l, "e_l", torch.float64, self.device, (n,), contiguous=True)
+        else:
+            _need(g, "g", torch.float64, self.device, (m,), contiguous=True)
         if delta is None:
             delta = torch.empty(m, dtype=torch.float64, device=self.device)
         if sigma is None:
             sigma = torch.empty(r, dtype=torch.float64, device=self.device)
         _need(delta, "delta", torch.float64, self.device, (m,), contiguous=True)
         _need(sigma, "sigma", torch.float64, self.device, (r,), contiguous=True)
-        self._check(lib().wssr_step(self._h, n, m, _ptr(O), ld, _ptr(e_l), _ptr(V), float(lam), r, int(q),
-                                    _ptr(delta), _ptr(sigma)))
+        if g is None:
+            self._check(lib().wssr_step(self._h, n, m, _ptr(O), ld, _ptr(e_l), _ptr(V), float(lam), r, int(q),
+                                        _ptr(delta), _ptr(sigma)))
+        else:
+            self._check(lib().wssr_step_g(self._h, n, m, _ptr(O), ld, _ptr(g), _ptr(V), float(lam), r, int(q),
+                                          _ptr(delta), _ptr(sigma)))
         return delta, sigma
+
+    def storage_like(self, n, m):
+        """An empty O buffer in this handle's storage form: (n, m) float32 or
+        bfloat16, or (2, n, m) bfloat16 planes for bf16x2."""
+        if self.dtype == "f32":
+            return torch.empty(n, m, dtype=torch.float32, device=self.device)
+        if self.dtype == "bf16x2":
+            return torch.empty(2, n, m, dtype=torch.bfloat16, device=self.device)
+        return torch.empty(n, m, dtype=torch.bfloat16, device=self.device)
+
+    def ingest(self, block, e_l, row0, out=None, g=None, colmean=None, mu=None, n=None):
+        """wssr_ingest: write rows row0 .. row0 + block.shape[0] - 1 of the
+        float32 block into `out` (this handle's storage form, see
+        storage_like; None: statistics only) and form g = O_bar^T eps / n and
+        the column means from the unrounded values.  Blocks follow each other
+        from row 0; g and colmean are final after the last one.  mu (float64
+        [m]) is subtracted before storing.  Returns (g, colmean)."""
+        if block.dim() != 2 or block.stride(1) != 1 or block.stride(0) < block.shape[1]:
+            raise ValueError("block must be 2-D, row-major with unit column stride")
+        _need(block, "block", torch.float32, self.device)
+        rows, m = block.shape
+        if out is not None:
+            on, om, ld = self._o(out)
+            if om != m:
+                raise ValueError("out has a different column count")
+            n = on
+        elif n is None:
+            raise ValueError("n (total rows) is needed when out is None")
+        else:
+            ld = m
+        _need(e_l, "e_l", torch.float64, self.device, (n,), contiguous=True)
+        if g is None:
+            g = torch.empty(m, dtype=torch.float64, device=self.device)
+        _need(g, "g", torch.float64, self.device, (m,), contiguous=True)
+        if colmean is not None:
+            _need(colmean, "colmean", torch.float64, self.device, (m,), contiguous=True)
+        if mu is not None:
+            _need(mu, "mu", torch.float64, self.device, (m,), contiguous=True)
+        self._check(lib().wssr_ingest(self._h, n, m, int(row0), rows, _ptr(block), block.stride(0), _ptr(e_l),
+                                      _ptr(mu) if mu is not None else None,
+                                      _ptr(out) if out is not None else None, ld, _ptr(g),
+                                      _ptr(colmean) if colmean is not None else None))
+        return g, colmean
 
     def step_batched(self, problems):
         """One batched step.  problems: list of dicts with keys O, e_l, V, lam and
@@ -331,3 +383,4 @@ class Wssr:
         P = torch.empty(r, r, dtype=torch.float64, device=self.device)
         self._check(lib().wssr_dbg_small_svd(self._h, _ptr(C), r, _ptr(s), _ptr(P)))
         return s, P
+
