@@ -280,6 +280,26 @@ wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_
  * by block one-sided Jacobi.  s double[r] descending; P double[r x r] row-major. */
 wssr_status wssr_dbg_small_svd(wssr_handle h, const double* C, int32_t r, double* s, double* P);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the r x r
+ * SVD of wssr_dbg_small_svd without a handle and without any allocation.
+ * Its working arrays live in a fixed device array of about 8.4 MB that the
+ * library holds on each device it runs on until the process ends.
+ *   C       device, double[r x r] row-major, read only
+ *   r       1 <= r <= 512 (larger: WSSR_ERR_INVALID_ARG, nothing enqueued)
+ *   s       device, double[r], out: singular values, descending
+ *   P       device, double[r x r] row-major, out: right singular vectors (C = G diag(s) P^T)
+ *   status  device, int32 or NULL: out, the numerical status (WSSR_OK,
+ *           WSSR_WARN_NOT_CONVERGED, WSSR_ERR_NONFINITE, WSSR_ERR_TIMEOUT)
+ *   stream  hipStream_t the work is enqueued on (NULL: the null stream)
+ * Runs on the current HIP device.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (other streams,
+ * other threads) race and must not be issued.  Returns WSSR_ERR_NO_DEVICE or
+ * WSSR_ERR_HIP when the set-up (first call on a device) or a launch fails. */
+wssr_status wssr_small_svd_noalloc(const double* C, int32_t r, double* s, double* P, int32_t* status,
+                                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

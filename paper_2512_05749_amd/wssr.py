@@ -81,6 +81,7 @@ _SIGS = {
     "wssr_dbg_gradient": ([_P, _I64, _I64, _P, _I64, _P, _P], ctypes.c_int),
     "wssr_dbg_cholqr2": ([_P, _I64, _P, _I32, _P, _P], ctypes.c_int),
     "wssr_dbg_small_svd": ([_P, _P, _I32, _P, _P], ctypes.c_int),
+    "wssr_small_svd_noalloc": ([_P, _I32, _P, _P, _P, _P], ctypes.c_int),
 }
 
 
@@ -384,3 +385,29 @@ class Wssr:
         self._check(lib().wssr_dbg_small_svd(self._h, _ptr(C), r, _ptr(s), _ptr(P)))
         return s, P
 
+
+def small_svd_noalloc(C, s=None, P=None, status=None, stream=None):
+    """wssr_small_svd_noalloc: C = G diag(s) P^T for an r x r float64 matrix on
+    the current device, with no handle and no allocation inside the library
+    (the outputs are allocated here when not given).  Returns (s, P, status)."""
+    if C.dim() != 2 or C.shape[0] != C.shape[1]:
+        raise ValueError("C must be square")
+    r = C.shape[0]
+    dev = C.device
+    _need(C, "C", torch.float64, dev, (r, r), contiguous=True)
+    if s is None:
+        s = torch.empty(r, dtype=torch.float64, device=dev)
+    if P is None:
+        P = torch.empty(r, r, dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+    _need(s, "s", torch.float64, dev, (r,), contiguous=True)
+    _need(P, "P", torch.float64, dev, (r, r), contiguous=True)
+    _need(status, "status", torch.int32, dev, (1,), contiguous=True)
+    with torch.cuda.device(dev):
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        code = lib().wssr_small_svd_noalloc(_ptr(C), r, _ptr(s), _ptr(P), _ptr(status),
+                                            ctypes.c_void_p(st.cuda_stream))
+    if code != OK:
+        raise WssrError(code, "wssr_small_svd_noalloc failed")
+    return s, P, status
