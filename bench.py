@@ -1,20 +1,25 @@
 """Benchmark: SR steps/s of the warm-started SR step on one MI355X.
 
-Default workload: the FP32 form, N=8192 samples, M=100000 parameters, rank
-r=256, q=2 passes, lambda=1e-3, synthetic O with a k^-1.2 spectrum rotating by
-0.01 per step (workloads.CONFIGS["f32_n8192_m100k_r256"]).  Inputs are
-generated on the GPU and resident in HBM before timing.  A step is one whole
-call of wssr_step: centring, gradient, q passes (two products, CholeskyQR2 of
-both sides), Rayleigh-Ritz, signs and the Woodbury apply.
+Default workload: the largest single-GPU instance, N=16384 samples,
+M=4,000,000 parameters, rank r=512, q=3 passes, lambda=1e-3, synthetic O with
+a k^-1.3 spectrum rotating by 0.005 per step (workloads.CONFIGS
+["bf16_n16384_m4m_r512_q3"]), stored in BF16 (131 GB) and run in the BF16
+form with the split correction of the skinny operand (two products).  The
+FP32 row blocks of O are generated on the GPU and stored through the
+library's ingest, which also forms the gradient from the unrounded values; O
+is resident in HBM before timing.  A step is one whole call of wssr_step_g:
+q passes (two products, CholeskyQR2 of both sides), Rayleigh-Ritz, signs and
+the Woodbury apply.  Beside it, in the same JSON line: the FP32 form on the
+same recipe at M=2e6 (its FP32 O is 131 GB), the FP32 benchmark workload
+f32_n8192_m100k_r256 as a secondary record, the FP64 oracle on a column
+sample (CPU baseline and the accuracy of the form against it), and the
+ingest time.
 
---form bf16 | bf16_split | bf16x2 times a BF16 precision form instead
-(--config bf16_n16384_m1m_r512 for the precision-form instance), and
---compare-f32 1 times the FP32 form on the same instance beside it.
---config batch16_mixed times the batched form (16 uneven problems per
-wssr_step_batched call) beside the same problems run one after another.
---sweep 1 times the two product kernels alone on the precision-form shape
-(N=16384, M=1e6) over a range of ranks, FP32 and BF16, and reports each
-against both rooflines (HBM and MFMA): the small ranks are memory-bound.
+--config picks another workload (f32_n8192_m100k_r256, bf16_n16384_m1m_r512,
+or batch16_mixed for the batched form beside the same problems one after
+another); --form another precision form.  --sweep 1 times the two product
+kernels alone on N=16384, M=1e6 over a range of ranks, FP32 and BF16, against
+both rooflines (HBM and MFMA): the small ranks are memory-bound.
 
 Prints one JSON line.  `--gpus` above 1 is not supported (single-GPU build).
 """
@@ -59,17 +64,21 @@ def recorded_traffic(kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (0: the workload's own count, 10 for the "
+                                                                 "largest instance, 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="f32_n8192_m100k_r256",
+    ap.add_argument("--config", default="bf16_n16384_m4m_r512_q3",
                     help="workload name (workloads.CONFIGS), or batch16_mixed for the batched form")
     ap.add_argument("--ring", type=int, default=0,
                     help="distinct O_t held in HBM and cycled (0: 4, or 1 above 2^30 elements)")
-    ap.add_argument("--form", default="f32", choices=["f32", "bf16", "bf16_split", "bf16x2"],
-                    help="storage and product precision of O")
+    ap.add_argument("--form", default=None, choices=["f32", "bf16", "bf16_split", "bf16x2"],
+                    help="storage and product precision of O (default: the workload's own form)")
     ap.add_argument("--lanes", type=int, default=4, help="batched workload: concurrent lanes of the handle")
-    ap.add_argument("--compare-f32", type=int, default=0,
-                    help="also time the FP32 form on the same instance and report the ratio")
+    ap.add_argument("--compare-f32", type=int, default=-1,
+                    help="BF16 forms: also time the FP32 form (1: the same instance; -1: the workload's own "
+                         "comparison, FP32 at M=2e6 for the largest instance; 0: none)")
+    ap.add_argument("--secondary", type=int, default=1,
+                    help="also time the FP32 benchmark workload f32_n8192_m100k_r256 as a secondary record")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-cols", type=int, default=0, help="columns of the oracle sample (0: auto)")
     ap.add_argument("--plain-inputs", type=int, default=0,
@@ -96,26 +105,32 @@ PEAK_BF16_TFLOPS = 2516.6
 PRODUCTS = {"f32": 1, "bf16": 1, "bf16_split": 2, "bf16x2": 3}
 
 
-def time_form(form, o_ring, e_ring, v_start, cfg, args, dev):
-    """Cold step, warm-up and timed steps of one precision form; returns the
-    timings, the product-kernel profile and the last status."""
+def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev):
+    """Cold step, warm-up and timed steps of one precision form on handle h;
+    returns the timings, the product-kernel profile and the last status.  The
+    BF16 forms use the gradient their ingest formed from the unrounded O
+    (g_ring); the FP32 form forms it inside the step."""
     import numpy as np
     import torch
 
-    from paper_2512_05749_amd import Wssr
-
-    n, m, r, q, lam = cfg.n, cfg.m, cfg.r, cfg.q, cfg.lam
+    m, r, q, lam = cfg.m, cfg.r, cfg.q, cfg.lam
     ring = len(o_ring)
     v = v_start.clone()
-    h = Wssr(n_max=n, m_max=m, r_max=r, q_max=8, device=dev, dtype=form)
     delta = torch.empty(m, dtype=torch.float64, device=dev)
     sigma = torch.empty(r, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    def one(t, qq):
+        k = t % ring
+        if g_ring is None:
+            h.step(o_ring[k], e_ring[k], v, lam, q=qq, delta=delta, sigma=sigma)
+        else:
+            h.step(o_ring[k], None, v, lam, q=qq, delta=delta, sigma=sigma, g=g_ring[k])
+
     # step 1: cold start (8 passes from V_0), reported separately
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    h.step(o_ring[0], e_ring[0], v, lam, q=8, delta=delta, sigma=sigma)
+    one(0, 8)
     e1.record(stream)
     code, diag = h.status()
     cold_ms = e0.elapsed_time(e1)
@@ -125,7 +140,7 @@ def time_form(form, o_ring, e_ring, v_start, cfg, args, dev):
 
     t = 1
     for _ in range(args.warmup):
-        h.step(o_ring[t % ring], e_ring[t % ring], v, lam, q=q, delta=delta, sigma=sigma)
+        one(t, q)
         t += 1
     torch.cuda.synchronize()
     log(f"[{form}] warmup done")
@@ -137,7 +152,7 @@ def time_form(form, o_ring, e_ring, v_start, cfg, args, dev):
     wall0 = time.perf_counter()
     for k in range(args.steps):
         starts[k].record(stream)
-        h.step(o_ring[t % ring], e_ring[t % ring], v, lam, q=q, delta=delta, sigma=sigma)
+        one(t, q)
         ends[k].record(stream)
         t += 1
     torch.cuda.synchronize()
@@ -145,15 +160,15 @@ def time_form(form, o_ring, e_ring, v_start, cfg, args, dev):
     prof = h.profile_read()
     h.profile(False)
     code, diag = h.status()
-    h.close()
     per_step = [s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)]
     ms_per_step = wall * 1e3 / args.steps
     log(f"[{form}] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall), median event "
         f"{np.median(per_step):.3f} ms, status {code}, diag {diag}")
     if code < 0:
         raise SystemExit(f"timed steps failed with status {code}")
-    return dict(ms_per_step=ms_per_step, median_ms=float(np.median(per_step)), cold_ms=cold_ms, prof=prof,
-                diag=diag, v=v)
+    return dict(ms_per_step=ms_per_step, median_ms=float(np.median(per_step)),
+                p10_ms=float(np.percentile(per_step, 10)), p90_ms=float(np.percentile(per_step, 90)),
+                cold_ms=cold_ms, prof=prof, diag=diag, v=v)
 
 
 def product_kernel(form, side, cfg):
@@ -194,7 +209,8 @@ def roofline_of(form, prof, cfg):
     achieved = kern[dom]["tflops"]
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": recorded_traffic(product_kernel(form, dom, cfg)) if form == "f32" else None,
+            "traffic": (recorded_traffic(product_kernel(form, dom, cfg))
+                        if form == "f32" and (cfg.name, cfg.m) == ("f32_n8192_m100k_r256", 100_000) else None),
             "kernel": product_kernel(form, dom, cfg), "avg_ms": round(kern[dom]["avg_ms"], 4),
             "flops_per_launch": flops_gemm, "products": PRODUCTS[form],
             "other": {k: {"avg_ms": round(v_["avg_ms"], 4), "tflops": round(v_["tflops"], 2)}
@@ -357,64 +373,136 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
-        sys.exit(2)
-    if args.sweep:
-        return run_sweep(args)
-    if args.config == "batch16_mixed":
-        # the lanes and their second streams need their own hardware queues to
-        # run side by side (HIP maps streams onto this many queues; set before
-        # the runtime starts)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, 2 * args.lanes + 2)))
-        return run_batched(args)
+def env_info(dev):
+    """ROCm version, gfx target and current clocks (best effort)."""
+    import subprocess
+
+    import torch
+    info = {"gfx": torch.cuda.get_device_properties(dev).gcnArchName, "torch": torch.__version__}
+    try:
+        info["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        info["rocm"] = None
+    try:
+        res = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        js = json.loads(res.stdout) if res.returncode == 0 else {}
+        card = next(iter(js.values()), {}) if js else {}
+        info["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower() and ("sclk" in k or "mclk" in k
+                                                                                   or "fclk" in k)}
+    except Exception:
+        info["clocks"] = None
+    return info
+
+
+# form and FP32 comparison of each workload: the precision-form instance runs
+# its single-product BF16 form beside FP32 on the same instance; the largest
+# instance runs BF16 with the split correction, beside FP32 at M = 2e6 (its
+# FP32 O at the full M would be 262 GB)
+DEFAULT_FORM = {"bf16_n16384_m1m_r512": "bf16", "bf16_n16384_m4m_r512_q3": "bf16_split"}
+COMPARE_F32_M = {"bf16_n16384_m1m_r512": 0, "bf16_n16384_m4m_r512_q3": 2_000_000}
+
+
+def oracle_cols(args, cfg):
+    """Columns of the oracle's sample: about 10-30 s of oracle work on the
+    box's cores."""
+    n, m, r, q = cfg.n, cfg.m, cfg.r, cfg.q
+    return args.cpu_cols or min(m, max(4 * r, m // 8, 1), max(4 * r, int(1.3e12 / (8.0 * n * r * q))))
+
+
+def generate(h, cfg, form, ring, dev, args, sample_cols=0):
+    """Draw `ring` steps' inputs of cfg into HBM.  FP32: O itself.  BF16
+    forms: the library's ingest stores each FP32 row block in the form and
+    forms g from the unrounded values (the FP32 matrix is never held whole).
+    Returns O list, E_L list, g list (None for FP32), V_0, the first columns
+    of step 1's unrounded O (for the oracle's sample), and the ingest time."""
     import torch
 
-    from workloads import CONFIGS, Workload, to_storage
-
-    cfg = CONFIGS[args.config]
-    if args.m:
-        import dataclasses
-        cfg = dataclasses.replace(cfg, m=args.m)
-    form = args.form
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    ring = args.ring or (4 if cfg.n * cfg.m <= (1 << 30) else 1)
-    keep_f32 = form == "f32" or args.compare_f32 or args.cpu_baseline
+    from workloads import Workload
     t0 = time.time()
-    o32, ost, es = [], [], []
+    os_, es, gs = [], [], []
+    sample = None
+    ingest_ms = 0.0
+    stream = torch.cuda.current_stream(dev)
     if args.plain_inputs:
         gen = torch.Generator(device=dev).manual_seed(cfg.seed)
-        for _ in range(ring):
-            o = torch.randn(cfg.n, cfg.m, generator=gen, device=dev)
-            es.append(cfg.el_mean + cfg.el_std * torch.randn(cfg.n, generator=gen, device=dev, dtype=torch.float64))
-            if form != "f32":
-                ost.append(to_storage(o, form))
-            o32.append(o if keep_f32 else None)
-            del o
-        v = torch.randn(cfg.m, cfg.r, generator=gen, device=dev) / math.sqrt(cfg.m)
+
+        def blocks(t):
+            rows = max(64, min(cfg.n, (1 << 30) // cfg.m))
+            for i in range(0, cfg.n, rows):
+                yield i, torch.randn(min(rows, cfg.n - i), cfg.m, generator=gen, device=dev)
+        el = lambda t: cfg.el_mean + cfg.el_std * torch.randn(cfg.n, generator=gen, device=dev,  # noqa: E731
+                                                              dtype=torch.float64)
+        v0 = lambda: torch.randn(cfg.m, cfg.r, generator=gen, device=dev) / math.sqrt(cfg.m)  # noqa: E731
+        wl = None
     else:
         wl = Workload(cfg, device=dev, gen_dtype=torch.float32)
-        for t in range(1, ring + 1):
-            es.append(wl.e_l(t))
-            if form in ("bf16", "bf16_split") and not keep_f32:
-                # straight to BF16, block by block (the same rounding as
-                # to_storage, without the FP32 copy of O)
-                ost.append(wl.o(t, dtype=torch.bfloat16))
-                o32.append(None)
-                continue
-            o = wl.o(t)
-            if form != "f32":
-                ost.append(to_storage(o, form))
-            o32.append(o if keep_f32 else None)
-            del o
-        v = wl.v0()
-        del wl
+        blocks, el, v0 = wl.o_blocks, wl.e_l, wl.v0
+    for t in range(1, ring + 1):
+        e = el(t)
+        es.append(e)
+        if form == "f32":
+            o = torch.empty(cfg.n, cfg.m, dtype=torch.float32, device=dev)
+            for i, blk in blocks(t):
+                o[i:i + blk.shape[0]] = blk
+            os_.append(o)
+            if t == 1 and sample_cols:
+                sample = o[:, :sample_cols].clone()
+            gs = None
+            continue
+        st = h.storage_like(cfg.n, cfg.m)
+        g = torch.empty(cfg.m, dtype=torch.float64, device=dev)
+        if t == 1 and sample_cols:
+            sample = torch.empty(cfg.n, sample_cols, dtype=torch.float32, device=dev)
+        for i, blk in blocks(t):
+            a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a_.record(stream)
+            h.ingest(blk, e, i, out=st, g=g)
+            b_.record(stream)
+            b_.synchronize()
+            ingest_ms += a_.elapsed_time(b_)
+            if sample is not None and t == 1:
+                sample[i:i + blk.shape[0]] = blk[:, :sample_cols]
+            del blk
+        code, _ = h.status()
+        if code != 0:
+            raise SystemExit(f"ingest of step {t} failed with status {code}")
+        os_.append(st)
+        gs.append(g)
+    v = v0()
+    del wl
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log(f"generated {ring} x O ({cfg.n}x{cfg.m}, form {form}) in {time.time() - t0:.1f}s")
+    log(f"generated {ring} x O ({cfg.n}x{cfg.m}, form {form}) in {time.time() - t0:.1f}s"
+        + (f", ingest {ingest_ms / ring:.1f} ms per O" if form != "f32" else ""))
+    return os_, es, gs, v, sample, ingest_ms / ring
+
+
+def hbm_of(form, prof, cfg, res):
+    """Achieved HBM rates: the dominant product kernel (its algorithmic bytes:
+    one read of O, one of the skinny operand, one write of its FP32 output),
+    and the whole step (2q reads of O plus the skinny traffic of about 24 q M r
+    bytes; the BF16 forms make no gradient pass, the FP32 form one)."""
+    n, m, r, q = cfg.n, cfg.m, cfg.r, cfg.q
+    b_o = 4 if form == "f32" else (4 if form == "bf16x2" else 2)
+    per = {}
+    for side, (ms, cnt) in prof.items():
+        avg = ms / max(cnt, 1)
+        nbytes = n * m * b_o + 4.0 * (m * r + n * r) + (4.0 * m * r if side == "param_side" else 8.0 * n * r)
+        per[side] = {"GB/s": round(nbytes / (avg * 1e-3) / 1e9, 1), "bytes_per_launch": nbytes}
+    step_bytes = 2.0 * q * n * m * b_o + 24.0 * q * m * r + (n * m * b_o if form == "f32" else 0.0)
+    return {"kernels": per, "step_GB/s": round(step_bytes / (res["ms_per_step"] * 1e-3) / 1e9, 1),
+            "step_bytes": step_bytes, "peak_GB/s": PEAK_HBM_GBS}
+
+
+def run_single(args, cfg, form, dev, sample_cols=0, ring=0):
+    """Generate, time and release one workload in one form; returns the
+    result record, the step-1 sample columns and V (for the accuracy leg)."""
+    import torch
+
+    from paper_2512_05749_amd import Wssr
+    ring = ring or args.ring or (4 if cfg.n * cfg.m <= (1 << 30) else 1)
+    h = Wssr(n_max=cfg.n, m_max=cfg.m, r_max=cfg.r, q_max=8, device=dev, dtype=form)
+    os_, es, gs, v, sample, ingest_ms = generate(h, cfg, form, ring, dev, args, sample_cols)
     if args.copy_calibration:
         # one elementwise kernel reading and writing exactly copy_calibration MiB
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
@@ -423,108 +511,273 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration} MiB read + written by one neg kernel")
         del src, dst
+    res = time_form(h, form, os_, es, gs, v, cfg, args, dev)
+    h.close()
+    e1 = es[0]
+    del os_, gs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    rec = {"value": round(1e3 / res["ms_per_step"], 3), "ms_per_step": round(res["ms_per_step"], 4),
+           "step_ms_events": {"median": round(res["median_ms"], 4), "p10": round(res["p10_ms"], 4),
+                              "p90": round(res["p90_ms"], 4)},
+           "cold_step_ms": round(res["cold_ms"], 3),
+           "roofline": roofline_of(form, res["prof"], cfg),
+           "hbm": hbm_of(form, res["prof"], cfg, res),
+           "diag": res["diag"]}
+    if form != "f32":
+        rec["ingest_ms_per_O"] = round(ingest_ms, 3)
+    return rec, sample, e1, res["v"]
 
-    n, m, r, q, lam = cfg.n, cfg.m, cfg.r, cfg.q, cfg.lam
-    res = time_form(form, o32 if form == "f32" else ost, es, v, cfg, args, dev)
+
+def describe(cfg, form):
+    return (f"{cfg.name}: WSSR step, O {form}, N={cfg.n} M={cfg.m} r={cfg.r} q={cfg.q} lambda={cfg.lam}, "
+            f"spectrum k^-{cfg.alpha}, rotation {cfg.theta}/step")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; --gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.sweep:
+        return run_sweep(args)
+    if args.config == "batch16_mixed":
+        args.steps = args.steps or 20
+        # the lanes and their second streams need their own hardware queues to
+        # run side by side (HIP maps streams onto this many queues; set before
+        # the runtime starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, 2 * args.lanes + 2)))
+        return run_batched(args)
+    import dataclasses
+
+    import torch
+
+    from workloads import CONFIGS
+
+    cfg = CONFIGS[args.config]
+    if args.m:
+        cfg = dataclasses.replace(cfg, m=args.m)
+    form = args.form or DEFAULT_FORM.get(cfg.name, "f32")
+    steps_default = cfg.steps if cfg.name in DEFAULT_FORM else 20
+    if args.steps <= 0:
+        args.steps = steps_default
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cols = oracle_cols(args, cfg) if args.cpu_baseline else 0
+    cols_wide = min(cfg.m, OracleSample.WIDE * cols)
+    rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols_wide)
     out = {
         "metric": METRIC,
-        "value": round(1e3 / res["ms_per_step"], 3),
+        "value": rec["value"],
         "unit": "SR steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(res["ms_per_step"], 4),
+        "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if form == "f32" else "bf16",
         "data": "synthetic, i.i.d. Gaussian O (counter run)" if args.plain_inputs else "synthetic",
-        "config": {"workload": f"{cfg.name}: WSSR step, O {form}, N={n} M={m} r={r} q={q} lambda={lam}, "
-                               f"spectrum k^-{cfg.alpha}, rotation {cfg.theta}/step",
-                   "n": n, "m": m, "r": r, "q": q, "lambda": lam, "form": form},
-        "cold_step_ms": round(res["cold_ms"], 3),
-        "step_ms_median_events": round(res["median_ms"], 4),
-        "roofline": roofline_of(form, res["prof"], cfg),
+        "config": {"workload": describe(cfg, form), "n": cfg.n, "m": cfg.m, "r": cfg.r, "q": cfg.q,
+                   "lambda": cfg.lam, "form": form},
+        "cold_step_ms": rec["cold_step_ms"],
+        "step_ms_events": rec["step_ms_events"],
+        "roofline": rec["roofline"],
+        "hbm": rec["hbm"],
     }
-    if form != "f32" and args.compare_f32:
-        ref = time_form("f32", o32, es, v, cfg, args, dev)
-        out["fp32_same_instance"] = {"ms_per_step": round(ref["ms_per_step"], 4),
-                                     "value": round(1e3 / ref["ms_per_step"], 3),
-                                     "roofline": roofline_of("f32", ref["prof"], cfg)}
-        out["vs_fp32_same_instance"] = round(ref["ms_per_step"] / res["ms_per_step"], 3)
-    if args.cpu_baseline:
-        out["cpu_baseline"], acc = cpu_baseline(args, cfg, o32[min(1, ring - 1)], es[min(1, ring - 1)], v, form)
-        out["accuracy_vs_oracle"] = acc
+    if form != "f32":
+        out["ingest_ms_per_O"] = rec["ingest_ms_per_O"]
+    oracle = OracleSample(args, cfg, sample, e1, v_end[:cols_wide], form, cols) if args.cpu_baseline else None
+    del sample, v_end
+    torch.cuda.empty_cache()
+    # the FP32 form beside it: the same instance, or the same recipe at the M
+    # whose FP32 O fits
+    if args.compare_f32 == 1:
+        cmp_m = cfg.m
+    elif args.compare_f32 < 0:
+        cmp_m = COMPARE_F32_M.get(cfg.name) or cfg.m
+    else:
+        cmp_m = 0
+    if form != "f32" and cmp_m:
+        cfg32 = dataclasses.replace(cfg, m=cmp_m)
+        r32, _, _, _ = run_single(args, cfg32, "f32", dev)
+        key = "fp32_same_instance" if cmp_m == cfg.m else f"fp32_same_recipe_m{cmp_m}"
+        out[key] = {"workload": describe(cfg32, "f32"), **{k: r32[k] for k in
+                    ("value", "ms_per_step", "step_ms_events", "cold_step_ms", "roofline", "hbm")}}
+        out["vs_fp32"] = {"steps_per_s_ratio": round(rec["value"] / r32["value"], 3),
+                          "parameters_per_s_ratio": round(rec["value"] * cfg.m / (r32["value"] * cmp_m), 3)}
+    if args.secondary and cfg.name != "f32_n8192_m100k_r256":
+        c2 = CONFIGS["f32_n8192_m100k_r256"]
+        steps = args.steps
+        args.steps = 20
+        r2, _, _, _ = run_single(args, c2, "f32", dev)
+        args.steps = steps
+        out["secondary"] = {"f32_n8192_m100k_r256": {"workload": describe(c2, "f32"), "steps": 20,
+                                                     **{k: r2[k] for k in ("value", "ms_per_step", "step_ms_events",
+                                                                           "roofline", "hbm")}}}
+    if oracle is not None:
+        out["cpu_baseline"], out["accuracy_vs_oracle"] = oracle.finish()
+    out["env"] = env_info(dev)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(args, cfg, o_dev, e_dev, v_dev, form="f32"):
-    """Time the FP64 oracle on a column sample of the same workload (the first
-    `cols` parameters of one step's O, same E_L, the matching rows of V as the
-    warm start) and scale the per-step time by M / cols to a full step.  Every
-    stage of the step is linear in M except the N x r and r x r ones, which the
-    scaling counts M / cols times over, so the reported rate is a slight
-    underestimate of the oracle's full-size rate.  The GPU path is run on the
-    same sample instance, in the benchmarked precision form, to report its
-    errors against the oracle: on the values O holds in storage (the
-    implementation error) and, for the BF16 forms, also on the unrounded O
-    (the end-to-end error of the form)."""
+def _oracle_job(o32, e_np, v32, cols, lam, r, q, threads, queue):
+    """Child process (spawned, so that it shares nothing with the parent's
+    GPU runtime): the FP64 oracle step on the first `cols` columns of the
+    sample (the accuracy reference), timed, and when the sample is wider, the
+    same step on all of its columns, timed: a second point of time against
+    columns."""
+    sys.path.insert(0, ROOT)
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=threads)
+    except Exception:
+        limiter = None
     import numpy as np
-    import torch
 
     from oracle import wssr_oracle as orc
-    from tests.metrics import rel, sigma_rel_gated
-
-    n, m, r, q, lam = cfg.n, cfg.m, cfg.r, cfg.q, cfg.lam
-    # about 10-30 s of oracle work on the box's cores at the benchmark shape
-    cols = args.cpu_cols or min(m, max(4 * r, m // 8, 1), max(4 * r, int(1.3e12 / (8.0 * n * r * q))))
-    o_s = o_dev[:, :cols].contiguous()
-    v_s = v_dev[:cols].contiguous()
-    o_np = o_s.double().cpu().numpy()
-    e_np = e_dev.cpu().numpy()
-    v_np = v_s.double().cpu().numpy()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    try:
-        from threadpoolctl import threadpool_info
-        info = threadpool_info()
-        if info:
-            threads = max(int(i.get("num_threads", threads)) for i in info)
-    except Exception:
-        pass
-    log(f"oracle on a {n}x{cols} column sample, {threads} threads ...")
+    o_np = np.asarray(o32[:, :cols], dtype=np.float64)
+    v_np = np.asarray(v32[:cols], dtype=np.float64)
     t0 = time.perf_counter()
     ref = orc.wssr_step(o_np, e_np, v_np, lam, r, q)
-    dt = time.perf_counter() - t0
-    full_s = dt * m / cols
-    log(f"oracle sample step {dt:.1f}s -> {full_s:.1f}s per full step")
+    res = {"delta": ref["delta"], "sigma": ref["sigma"], "v": ref["v"], "g": ref["g"],
+           "seconds": time.perf_counter() - t0}
+    del o_np, v_np, ref
+    if o32.shape[1] > cols:
+        o2 = np.asarray(o32, dtype=np.float64)
+        v2 = np.asarray(v32, dtype=np.float64)
+        t0 = time.perf_counter()
+        orc.wssr_step(o2, e_np, v2, lam, r, q)
+        res["seconds_wide"] = time.perf_counter() - t0
+        del o2, v2
+    queue.put(res)
+    del limiter
 
-    # GPU on the same sample instance
-    from paper_2512_05749_amd import Wssr
-    from workloads import stored_values, to_storage
-    hs = Wssr(n_max=n, m_max=cols, r_max=r, q_max=q, dtype=form)
-    o_in = to_storage(o_s, form)
-    vv = v_s.clone()
-    d, s = hs.step(o_in, e_dev, vv, lam, q=q)
-    code, _ = hs.status()
-    hs.close()
-    acc = {"sample": f"N={n}, first {cols} of M={m} columns, warm start = matching rows of V",
-           "status": code, "form": form,
-           "delta_rel_err": rel(d.cpu().numpy(), ref["delta"]),
-           "sigma_rel_err_gated": sigma_rel_gated(s.cpu().numpy(), ref["sigma"], lam),
-           "v_orth_err": float(np.abs(vv.double().cpu().numpy().T @ vv.double().cpu().numpy()
-                                      - np.eye(r)).max())}
-    if form != "f32":
-        # the oracle on the values O holds in storage
-        ref_s = orc.wssr_step(stored_values(o_in).cpu().numpy(), e_np, v_np, lam, r, q)
-        acc["vs_unrounded_O"] = {"delta_rel_err": acc.pop("delta_rel_err"),
-                                 "sigma_rel_err_gated": acc.pop("sigma_rel_err_gated")}
-        acc["vs_stored_O"] = {"delta_rel_err": rel(d.cpu().numpy(), ref_s["delta"]),
-                              "sigma_rel_err_gated": sigma_rel_gated(s.cpu().numpy(), ref_s["sigma"], lam)}
-    log(f"accuracy on the sample: {acc}")
-    base = {"value": round(1.0 / full_s, 6), "unit": "SR steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one step of the FP64 oracle on N={n} x {cols} columns (of M={m}), r={r}, q={q}: "
-                      f"{dt:.2f}s, scaled by M/{cols} to a full step"}
-    return base, acc
+
+class OracleSample:
+    """The accuracy leg and the CPU baseline on a column sample of the
+    workload: the first `cols` parameters of step 1's unrounded O, the same
+    E_L, and the matching rows of the V the timed steps ended with as the warm
+    start.  The GPU runs that sample instance in the benchmarked form, the
+    way the benchmark feeds it (BF16 forms: the library's ingest of the FP32
+    sample, then the step with the ingested g).  The FP64 oracle then runs in
+    child processes on the host cores while the GPU goes on with other work:
+    on the unrounded O (the end-to-end error of the form, where the BF16 bar
+    applies) and, for the BF16 forms, on the values O holds in storage (the
+    implementation error).  The CPU baseline times the oracle on the sample
+    and on a sample `wide` times wider (the first wide * cols columns): the
+    step's time is linear in the column count (every stage but the N x r and
+    r x r ones grows with M, those do not), so the two points give the time
+    of a full step, a + b M."""
+
+    WIDE = 3
+
+    def __init__(self, args, cfg, o_sample, e_dev, v_sample, form, cols):
+        import multiprocessing as mp
+
+        from paper_2512_05749_amd import Wssr
+        from workloads import stored_values
+
+        self.cfg, self.form = cfg, form
+        n, r, q, lam = cfg.n, cfg.r, cfg.q, cfg.lam
+        self.cols = cols
+        self.cols_wide = o_sample.shape[1]
+        o32 = o_sample.cpu().numpy()
+        e_np = e_dev.cpu().numpy()
+        v32 = v_sample.cpu().numpy()
+        o_acc = o_sample[:, :cols].contiguous()
+        hs = Wssr(n_max=n, m_max=cols, r_max=r, q_max=q, dtype=form)
+        vv = v_sample[:cols].clone().contiguous()
+        stored = None
+        if form == "f32":
+            d, s_ = hs.step(o_acc, e_dev, vv, lam, q=q)
+        else:
+            st = hs.storage_like(n, cols)
+            g, _ = hs.ingest(o_acc, e_dev, 0, out=st)
+            d, s_ = hs.step(st, None, vv, lam, q=q, g=g)
+            stored = stored_values(st).float().cpu().numpy()
+        self.code, _ = hs.status()
+        hs.close()
+        del o_acc
+        self.d, self.s, self.v = d.cpu().numpy(), s_.cpu().numpy(), vv.double().cpu().numpy()
+        ncpu = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # the timed run gets most of the cores; the second one little (its
+        # time is not reported)
+        self.threads = max(1, ncpu - 2) if stored is not None else ncpu
+        ctx = mp.get_context("spawn")
+        self.q_main, self.q_stored = ctx.Queue(), ctx.Queue()
+        self.p_main = ctx.Process(target=_oracle_job,
+                                  args=(o32, e_np, v32, cols, lam, r, q, self.threads, self.q_main))
+        self.p_main.start()
+        self.p_stored = None
+        if stored is not None:
+            # the stored values are exact in FP32 (BF16, or the sum of two
+            # BF16 planes, which FP32 holds to the plane's 17 bits)
+            self.p_stored = ctx.Process(target=_oracle_job,
+                                        args=(stored, e_np, v32[:cols], cols, lam, r, q,
+                                              max(1, ncpu - self.threads), self.q_stored))
+            self.p_stored.start()
+        log(f"oracle on {n}x{cols} and {n}x{self.cols_wide} column samples started ({self.threads} threads)")
+
+    @staticmethod
+    def _wait(queue, proc):
+        import queue as _q
+        t0 = time.time()
+        while True:
+            try:
+                res = queue.get(timeout=30)
+                break
+            except _q.Empty:
+                if not proc.is_alive():
+                    raise SystemExit("oracle process ended without a result")
+                log(f"waiting for the oracle ({time.time() - t0:.0f}s)")
+        proc.join()
+        return res
+
+    def finish(self):
+        import numpy as np
+
+        from tests.metrics import orth_err, rel, sigma_rel_gated
+        cfg, form = self.cfg, self.form
+        lam = cfg.lam
+        ref = self._wait(self.q_main, self.p_main)
+        dt = ref["seconds"]
+        dt2 = ref.get("seconds_wide", dt)
+        # time against columns through the two points; where the step is
+        # cheaper in the wider sample (run-to-run noise in the r x r part),
+        # the whole narrow-sample time is scaled by M / cols instead
+        b = (dt2 - dt) / (self.cols_wide - self.cols) if self.cols_wide > self.cols else 0.0
+        a = dt - b * self.cols
+        fit = b > 0 and a >= 0
+        full_s = a + b * cfg.m if fit else dt * cfg.m / self.cols
+        log(f"oracle sample steps {dt:.1f}s ({self.cols} columns), {dt2:.1f}s ({self.cols_wide} columns) -> "
+            f"{full_s:.1f}s per full step")
+        err = {"delta_rel_err": rel(self.d, ref["delta"]),
+               "delta_max_err_rel_to_max": float(np.abs(self.d - ref["delta"]).max() / np.abs(ref["delta"]).max()),
+               "sigma_rel_err_gated": sigma_rel_gated(self.s, ref["sigma"], lam)}
+        acc = {"sample": f"N={cfg.n}, first {self.cols} of M={cfg.m} columns, warm start = matching rows of the "
+                         f"timed steps' V", "status": self.code, "form": form, "v_orth_err": orth_err(self.v)}
+        if form == "f32":
+            acc.update(err)
+        else:
+            acc["vs_unrounded_O"] = err
+            ref_s = self._wait(self.q_stored, self.p_stored)
+            # the oracle's subspace and singular values on the stored values,
+            # applied to the gradient of the unrounded O (the one the library's
+            # ingest forms): the implementation error of the BF16 path
+            from oracle import wssr_oracle as orc
+            d_s = orc.woodbury_apply(ref_s["v"], ref_s["sigma"], ref["g"], lam)
+            acc["vs_stored_O"] = {"delta_rel_err": rel(self.d, d_s),
+                                  "sigma_rel_err_gated": sigma_rel_gated(self.s, ref_s["sigma"], lam),
+                                  "gradient": "of the unrounded O in both"}
+        log(f"accuracy on the sample: {acc}")
+        base = {"value": round(1.0 / full_s, 6), "unit": "SR steps/s", "cores": self.threads, "kind": "oracle",
+                "sample": (f"one step of the FP64 oracle (r={cfg.r}, q={cfg.q}) on N={cfg.n} x {self.cols} columns "
+                           f"of M={cfg.m}: {dt:.2f}s, and on {self.cols_wide} columns: {dt2:.2f}s; "
+                           + (f"a full step from the line through the two points, {a:.1f}s + {b * 1e3:.3f}ms "
+                              f"per column" if fit else f"the first time scaled by M/{self.cols}"))}
+        return base, acc
 
 
 if __name__ == "__main__":

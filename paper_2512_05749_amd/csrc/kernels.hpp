@@ -89,6 +89,27 @@ __global__ void k_gemm16_param_side_dma(const unsigned short* O, int64_t ld, int
                                         int64_t sk_units, int sk_wgs, float* part);
 // dynamic LDS bytes of the direct-to-LDS BF16 product kernels
 size_t gemm16_dma_lds(int bn, int bk, int pa, int pb);
+// K-steps of the skinny operand in flight in the register-streamed BF16
+// sample-side product (O: one more), per plane count of the skinny operand
+#ifndef WSSR_RS1_DB
+#define WSSR_RS1_DB 2
+#endif
+#ifndef WSSR_RS2_DB
+#define WSSR_RS2_DB 2
+#endif
+// BF16 sample side with the skinny operand streamed into registers
+// (kernels_gemm16_rs.hip): one O plane, BN columns per workgroup, DB K-steps
+// of the skinny operand in flight
+template <int BN, int PB, int DB>
+__global__ void k_gemm16_param_side_rs(const unsigned short* O, int64_t ld, int64_t n, int64_t m,
+                                       const unsigned short* Qs, int64_t qstride, int r, float scale, float* Z,
+                                       const unsigned short* zeros, const DevStatus* st, int tiles_j, int full_tiles,
+                                       int64_t sk_units, int sk_wgs, float* part);
+template <int BN, int PB, int DB>
+__global__ void k_gemm16_sample_side_rs(const unsigned short* O, int64_t ld, int64_t n, int64_t m,
+                                        const unsigned short* Vs, int64_t vstride, int r, float* ypart,
+                                        int64_t kchunk, const unsigned short* zeros, const DevStatus* st, int tn,
+                                        int tj, bool xcd_groups);
 
 template <typename T>
 __global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,

@@ -28,6 +28,15 @@ constexpr double kJacobiTol = 1e-8;
 constexpr double kKappaRound2 = 1e4;
 constexpr int kBatchMax = 1024;     // problems per batched step
 constexpr int kLanesMax = 16;       // concurrent batch lanes
+#ifndef WSSR_RS_ROUNDS
+#define WSSR_RS_ROUNDS 4
+#endif
+constexpr int kRsRounds = WSSR_RS_ROUNDS;
+#ifdef WSSR_RS_OFF
+constexpr bool kUseRs = false;
+#else
+constexpr bool kUseRs = true;
+#endif
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -275,6 +284,18 @@ struct wssr_ctx {
     WSSR_SETUP16(256, 32, 1, 1) WSSR_SETUP16(256, 32, 1, 2) WSSR_SETUP16(256, 32, 2, 2)
     WSSR_SETUP16(512, 16, 1, 1) WSSR_SETUP16(512, 16, 1, 2) WSSR_SETUP16(512, 16, 2, 2)
 #undef WSSR_SETUP16
+    for (int pb = 1; pb <= 2; ++pb) {
+      const void* f = pb == 1 ? (const void*)k_gemm16_sample_side_rs<512, 1, WSSR_RS1_DB>
+                              : (const void*)k_gemm16_sample_side_rs<512, 2, WSSR_RS2_DB>;
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 256, 0) != hipSuccess || per < 1) per = 1;
+      slots16rs[pb - 1] = per * cus;
+      const void* fp = pb == 1 ? (const void*)k_gemm16_param_side_rs<512, 1, WSSR_RS1_DB>
+                               : (const void*)k_gemm16_param_side_rs<512, 2, WSSR_RS2_DB>;
+      per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fp, 256, 0) != hipSuccess || per < 1) per = 1;
+      slots16rsp[pb - 1] = per * cus;
+    }
     (void)hipGetLastError();
     return ok;
   }
@@ -298,6 +319,8 @@ struct wssr_ctx {
   int slots16s[12] = {0}, slots16p[12] = {0};   // resident workgroups per variant (sample, parameter side)
   int slots16sd[12] = {0}, slots16pd[12] = {0}; // the same for the direct-to-LDS variants
   int slots32s = 0, slots32p = 0;             // the same for the FP32 32-column kernels
+  int slots16rs[2] = {0, 0};                   // register-streamed 512-column sample side, PB = 1, 2
+  int slots16rsp[2] = {0, 0};                  // the same for the parameter side
 
   // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
   // when pb = 2), K-blocked, r padded with zero columns to the product's
@@ -336,12 +359,18 @@ struct wssr_ctx {
     // narrow column tiles where r allows: FP32 32 (direct form), BF16 64
     const int bn = dma && r <= 32 ? 32 : dma16 && r <= 64 ? 64 : bn_for(r, b16);
     const int pa = o_planes(), pb = s_planes();
+    // 512-column tiles with one O plane: the skinny operand streamed into registers
+    const bool rs = kUseRs && dma16 && bn == 512 && pa == 1;
     const int64_t tn = cdiv(n, 128), tj = cdiv(r, bn);
-    const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
-    const int sl =
-        std::max(1, (b16 ? (dma16 ? slots16sd : slots16s)[v16(bn, pa, pb)] : bn == 32 ? slots32s : slots) / slot_div);
-    // about one round of resident workgroups; split K = M into s1 ranges
-    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv(sl, tn * tj)));
+    const int bk = !b16 ? 16 : rs ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
+    const int sl = std::max(
+        1, (rs ? slots16rs[pb - 1]
+               : b16 ? (dma16 ? slots16sd : slots16s)[v16(bn, pa, pb)]
+                     : bn == 32 ? slots32s : slots) / slot_div);
+    // about one round of resident workgroups; split K = M into s1 ranges (the
+    // register-streamed kernel: several rounds, whose later workgroups fill
+    // the compute units that finish first)
+    int s1 = (int)std::min<int64_t>(kS1Max, std::max<int64_t>(1, cdiv((int64_t)sl * (rs ? kRsRounds : 1), tn * tj)));
     int64_t kchunk = rup(cdiv(m, s1), bk);
     s1 = (int)cdiv(m, kchunk);
     const bool xcd = ((int64_t)s1 * tj) % 8 == 0;
@@ -394,7 +423,16 @@ struct wssr_ctx {
   hipLaunchKernelGGL((k_gemm16_sample_side_dma<64, 32, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,        \
                      (const unsigned short*)s16, vs, r, ypart, kchunk, (const unsigned short*)zeros,                  \
                      (const DevStatus*)st, (int)tn, (int)tj, xcd)
-        switch (v16(bn, pa, pb)) {
+        if (rs) {
+          if (pb == 1)
+            hipLaunchKernelGGL((k_gemm16_sample_side_rs<512, 1, WSSR_RS1_DB>), grid, dim3(256), 0, stream, O, ld, n, m,
+                               (const unsigned short*)s16, vs, r, ypart, kchunk, (const unsigned short*)zeros,
+                               (const DevStatus*)st, (int)tn, (int)tj, xcd);
+          else
+            hipLaunchKernelGGL((k_gemm16_sample_side_rs<512, 2, WSSR_RS2_DB>), grid, dim3(256), 0, stream, O, ld, n, m,
+                               (const unsigned short*)s16, vs, r, ypart, kchunk, (const unsigned short*)zeros,
+                               (const DevStatus*)st, (int)tn, (int)tj, xcd);
+        } else switch (v16(bn, pa, pb)) {
           case 0: WSSR_S16D(1, 1); break;
           case 1: WSSR_S16D(1, 2); break;
           case 2: WSSR_S16D(2, 2); break;
@@ -428,14 +466,20 @@ struct wssr_ctx {
     // 64); BF16 with one plane of each operand and r > 256: two 256-column
     // tiles (two workgroups per compute unit) in place of one 512-column tile
     // (one)
+    // one O plane and r > 256: one 512-column tile with the skinny operand
+    // streamed into registers
+    const bool rs = kUseRs && dma16 && pa == 1 && r > 256;
     const int bn = dma && r <= 32                           ? 32
                    : dma16 && r <= 64                       ? 64
+                   : rs                                     ? 512
                    : dma16 && pa == 1 && pb == 1 && r > 256 ? 256
                                                             : bn_for(r, b16);
     const float scale = (float)(1.0 / std::sqrt((double)n));
-    const int bk = !b16 ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
-    const int sl =
-        std::max(1, (b16 ? (dma16 ? slots16pd : slots16p)[v16(bn, pa, pb)] : bn == 32 ? slots32p : slots) / slot_div);
+    const int bk = !b16 ? 16 : rs ? 16 : dma16 ? bk_dma(bn, pa, pb) : (bn == 512 ? 16 : 32);
+    const int sl = std::max(
+        1, (rs ? slots16rsp[pb - 1]
+               : b16 ? (dma16 ? slots16pd : slots16p)[v16(bn, pa, pb)]
+                     : bn == 32 ? slots32p : slots) / slot_div);
     const int64_t tj = cdiv(r, bn), tiles = cdiv(m, 128) * tj, nk = cdiv(n, bk);
     // whole tiles for every full round of resident workgroups; the leftover
     // tiles' K-steps shared evenly by one more round (stream-K) unless the
@@ -497,7 +541,16 @@ struct wssr_ctx {
   hipLaunchKernelGGL((k_gemm16_param_side_dma<64, 32, PA, PB>), grid, dim3(256), lds, stream, O, ld, ps, n, m,         \
                      (const unsigned short*)s16, qs, r, scale, Z, (const unsigned short*)zeros, (const DevStatus*)st, \
                      (int)tj, full, units, skw, skpart)
-        switch (v16(bn, pa, pb)) {
+        if (rs) {
+          if (pb == 1)
+            hipLaunchKernelGGL((k_gemm16_param_side_rs<512, 1, WSSR_RS1_DB>), grid, dim3(256), 0, stream, O, ld, n, m,
+                               (const unsigned short*)s16, qs, r, scale, Z, (const unsigned short*)zeros,
+                               (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+          else
+            hipLaunchKernelGGL((k_gemm16_param_side_rs<512, 2, WSSR_RS2_DB>), grid, dim3(256), 0, stream, O, ld, n, m,
+                               (const unsigned short*)s16, qs, r, scale, Z, (const unsigned short*)zeros,
+                               (const DevStatus*)st, (int)tj, full, units, skw, skpart);
+        } else switch (v16(bn, pa, pb)) {
           case 0: WSSR_P16D(1, 1); break;
           case 1: WSSR_P16D(1, 2); break;
           case 2: WSSR_P16D(2, 2); break;

@@ -182,11 +182,12 @@ class Workload:
         # the angle it currently stands at
         self._w_angle = 0.0
 
-    def o(self, t, dtype=torch.float32):
-        """O_t (N x M) in the given dtype.  Instances of more than 2^28
-        elements are built in blocks of rows (at most 1024, and at most 2^30
-        elements; noise drawn block by block from the same generator), which
-        bounds the temporaries."""
+    def o_blocks(self, t):
+        """O_t as consecutive blocks of rows: yields (first row, float32 block).
+        Instances of more than 2^28 elements come in blocks of at most 1024
+        rows and 2^30 elements (noise drawn block by block from the step's
+        generator), so that no full-size temporary is held; smaller ones come
+        as one block.  The values are those of o(t)."""
         cfg, dev = self.cfg, self.device
         ut = _rotate_pairs(self.u0, self.perm_n, t * cfg.theta)
         if self.w0.numel() > _BIG:
@@ -203,14 +204,25 @@ class Workload:
             o = left @ wt.T
             noise = torch.randn(self.n, self.m, generator=gen, device=dev, dtype=self.gen_dtype)
             o.add_(noise, alpha=cfg.eta)
-            return o.to(dtype).contiguous()
-        out = torch.empty(self.n, self.m, device=dev, dtype=dtype)
+            del noise
+            yield 0, o.float().contiguous()
+            return
         rows = max(64, min(1024, (1 << 30) // self.m))
         for i in range(0, self.n, rows):
             blk = left[i:i + rows] @ wt.T
             blk.add_(torch.randn(blk.shape, generator=gen, device=dev, dtype=self.gen_dtype), alpha=cfg.eta)
-            out[i:i + rows] = blk.to(dtype)
+            yield i, blk.float().contiguous()
             del blk
+
+    def o(self, t, dtype=torch.float32):
+        """O_t (N x M) in the given dtype (converted from float32 block by
+        block for the large instances)."""
+        if self.n * self.m <= _BIG:
+            (_, o), = list(self.o_blocks(t))
+            return o.to(dtype).contiguous()
+        out = torch.empty(self.n, self.m, device=self.device, dtype=dtype)
+        for i, blk in self.o_blocks(t):
+            out[i:i + blk.shape[0]] = blk.to(dtype)
         return out
 
     def e_l(self, t):
