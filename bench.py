@@ -178,8 +178,14 @@ def product_kernel(form, side, cfg):
     contiguous torch tensors, so that is r % 4 == 0, plus M % 4 == 0 on the
     sample side)."""
     if form != "f32":
-        # BF16: O's rows are whole 16-byte chunks (8 elements)
-        return "k_gemm16_" + side + ("_dma" if cfg.m % 8 == 0 else "")
+        # BF16: O's rows are whole 16-byte chunks (8 elements); one O plane and
+        # r > 256 (r = 512 on the sample side): the skinny operand streamed
+        # into registers
+        if cfg.m % 8 != 0:
+            return "k_gemm16_" + side
+        if form != "bf16x2" and (cfg.r > 256 if side == "param_side" else cfg.r > 256):
+            return "k_gemm16_" + side + "_rs"
+        return "k_gemm16_" + side + "_dma"
     aligned = cfg.r % 4 == 0 and (cfg.m % 4 == 0 or side == "param_side")
     if aligned and side == "param_side" and cfg.r <= 32:
         return "k_gemm_param_side_narrow"      # 32-column tile, O staged through registers
