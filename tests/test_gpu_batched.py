@@ -155,3 +155,41 @@ def test_batch_errors_stay_per_problem(batch):
     with pytest.raises(WssrError):
         h.step_batched(bad)
     h.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_at_the_batched_workload_ranks():
+    """Lanes with problems at the batched workload's ranks and sample counts
+    (r in {64, 128, 256}, N in {2048, 4096}), with M reduced so that the
+    oracle runs in seconds: per-problem status, parity with the oracle at the
+    FP32 bars, and bit-identity with single steps."""
+    from paper_2512_05749_amd import Wssr
+    shapes = [(2048, 5000, 64), (4096, 3000, 128), (2048, 6000, 256), (4096, 4500, 64), (2048, 2500, 128),
+              (4096, 5000, 256)]
+    rng = np.random.default_rng(77)
+    probs = []
+    for j, (n, m, r) in enumerate(shapes):
+        a = float(rng.uniform(1.0, 1.5))
+        lam = float(10 ** rng.uniform(-4, -2))
+        o, e, v = random_problem(n, m, r, seed=900 + j, alpha=a, eta=1e-4, el_mean=-10.0, el_std=0.5,
+                                 device="cuda")
+        probs.append(dict(O=o, e_l=e, V=v, lam=lam, q=2))
+    v_in = [p["V"].clone() for p in probs]
+    h = Wssr(n_max=4096, m_max=6000, r_max=256, q_max=2, lanes=4)
+    work = _copy(probs)
+    outs = h.step_batched(work)
+    codes = h.batched_status(len(work))
+    h.close()
+    assert codes == [0] * len(work)
+    hs = Wssr(n_max=4096, m_max=6000, r_max=256, q_max=2)
+    for j, (p, (d, s)) in enumerate(zip(work, outs)):
+        vv = v_in[j].clone()
+        d1, s1 = hs.step(p["O"], p["e_l"], vv, p["lam"], q=2)
+        assert hs.status()[0] == 0
+        assert torch.equal(d, d1) and torch.equal(s, s1) and torch.equal(p["V"], vv), j
+        ref = orc.wssr_step(_np(p["O"]), _np(p["e_l"]), _np(v_in[j]), p["lam"], p["V"].shape[1], 2)
+        assert rel(_np(d), ref["delta"]) <= 1e-4, j
+        assert float(np.abs(_np(d) - ref["delta"]).max() / np.abs(ref["delta"]).max()) <= 1e-4, j
+        assert sigma_rel_gated(_np(s), ref["sigma"], p["lam"]) <= 1e-4, j
+        assert orth_err(_np(p["V"])) <= 1e-5, j
+    hs.close()

@@ -25,6 +25,9 @@ def _np(t):
 def _check_against_oracle(o, e, v_in, v_out, delta, sigma, lam, q, precond="damped"):
     ref = orc.wssr_step(_np(o), _np(e), _np(v_in), lam, v_in.shape[1], q, precond=precond)
     d_err = rel(_np(delta), ref["delta"])
+    # element by element too: the largest deviation against the largest entry
+    d_max = float(np.abs(_np(delta) - ref["delta"]).max() / np.abs(ref["delta"]).max())
+    assert d_max <= TOL_DELTA, d_max
     s_err = sigma_rel_gated(_np(sigma), ref["sigma"], lam)
     o_err = orth_err(_np(v_out))
     w_g = orc.woodbury_weights(_np(sigma), lam, precond)
