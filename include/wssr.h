@@ -52,14 +52,18 @@ typedef struct wssr_ctx* wssr_handle;
 
 typedef enum {
   WSSR_OK = 0,
+  WSSR_WARN_RANK_DEFICIENT = 1,  /* a basis of the iteration lost rank (r exceeds the rank of the
+                                    centred O, e.g. repeated samples); the basis was completed with
+                                    directions from rounding and the extra singular values are at
+                                    rounding level, so delta is unaffected; results usable */
   WSSR_WARN_NOT_CONVERGED = 2,   /* Rayleigh-Ritz Jacobi hit its sweep limit; results usable */
   WSSR_ERR_INVALID_ARG = -1,
   WSSR_ERR_NO_DEVICE = -2,
   WSSR_ERR_OOM = -3,
   WSSR_ERR_HIP = -4,
   WSSR_ERR_NONFINITE = -5,       /* NaN/Inf in E_L, or reached the Gram matrices from O or V */
-  WSSR_ERR_BREAKDOWN = -6,       /* a Cholesky pivot of a Gram matrix was not positive:
-                                    the iterated basis lost rank */
+  WSSR_ERR_BREAKDOWN = -6,       /* the iterated basis lost rank and could not be completed (a zero
+                                    column, or a second CholeskyQR round that broke down) */
   WSSR_ERR_TIMEOUT = -7          /* internal: a bounded wait between the workgroups of the
                                     Rayleigh-Ritz SVD expired; outputs untouched */
 } wssr_status;
@@ -271,7 +275,10 @@ wssr_status wssr_dbg_gradient(wssr_handle h, int64_t n, int64_t m, const void* O
 /* CholeskyQR of a tall matrix X (rows x r, float): X = Q R with Q^T Q = I,
  * R upper triangular with positive diagonal (Alg. 1 "QR decomposition").  The
  * Gram matrix and the factors are FP64; a second round (CholeskyQR2) runs when
- * the first round's condition bound exceeds 1e4, as in wssr_step.
+ * the first round's condition bound exceeds 1e4, as in wssr_step.  A
+ * rank-deficient X is completed as in wssr_step (WSSR_WARN_RANK_DEFICIENT is
+ * not raised here; Q R then equals X up to sqrt(r eps) max_j |x_j| in each
+ * completed column).
  * Q float[rows x r]; R double[r x r] row-major.  rows <= max(n_max, m_max). */
 wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_t r,
                              float* Q, double* R);

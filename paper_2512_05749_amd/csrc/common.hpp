@@ -23,10 +23,19 @@ struct DevStatus {
   int round2;             // set by a first-round Cholesky when a second CholeskyQR round is needed
   double kappa_max;       // largest condition bound ||R D^-1||_F ||D R^-1||_F seen
   int round2_count;       // second rounds actually run
+  int rank_def;           // pivots of first-round Cholesky factorizations replaced in this step
+  int repl;               // set by a first-round Cholesky that replaced a pivot; forces its second round
   int pad;
 };
 
-enum : int { ST_OK = 0, ST_WARN_NOT_CONVERGED = 2, ST_NONFINITE = -5, ST_BREAKDOWN = -6, ST_TIMEOUT = -7 };
+enum : int {
+  ST_OK = 0,
+  ST_WARN_RANK_DEFICIENT = 1,
+  ST_WARN_NOT_CONVERGED = 2,
+  ST_NONFINITE = -5,
+  ST_BREAKDOWN = -6,
+  ST_TIMEOUT = -7
+};
 
 __device__ __forceinline__ void raise_error(DevStatus* st, int code) {
   atomicCAS(&st->code, 0, code);

@@ -123,8 +123,11 @@ __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const dou
 constexpr int kF64Tile = 128;
 constexpr size_t kGramPartBytes = (size_t)64 << 20;
 
-__global__ void k_chol(double* G, int rp, double* R, double* Rt, double* gdiag, double* invdiag, DevStatus* st,
-                       bool gated);
+__global__ void k_chol(double* G, int rp, int r, double* R, double* Rt, double* gdiag, double* invdiag, int* repcol,
+                       DevStatus* st, bool gated);
+template <typename T>
+__global__ void k_complete(T* X, int64_t rows, int r, const double* R, int rp, const int* repcol,
+                           const DevStatus* st);
 template <int RPL>
 __global__ void k_trinv(const double* Rt, int rp, const double* invdiag, double* Ri, const DevStatus* st, bool gated);
 __global__ void k_kappa(const double* gdiag, const double* R, const double* Ri, int rp, int r, double kappa_round2,

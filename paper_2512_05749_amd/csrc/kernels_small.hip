@@ -96,8 +96,21 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // multiple of 64 (padding rows/columns of G are identity).  One workgroup of
 // 1024 threads; G is overwritten (trailing updates).  Writes R and its
 // transpose Rt (so that columns of R can be read contiguously) and the
-// reciprocals of its diagonal (invdiag).  A pivot d_k
-// with !(d_k > rp * eps * G_kk) is a breakdown (NaN: non-finite input).
+// reciprocals of its diagonal (invdiag).  A pivot d_k with
+// !(d_k > rp * eps * G_kk) means column k of the input depends on the columns
+// before it (NaN: non-finite input).  In a first round (gated = false) such a
+// pivot, when G_kk > 0, is replaced by rp * eps * max_j G_jj (j < r: the
+// scale of the whole input, so that R^{-1} stays below about
+// 1 / sqrt(rp eps) of it and X R^{-1} keeps its accuracy) and counted
+// (st->rank_def; st->repl forces the second round): the factor still
+// satisfies X = Q1 R with Q1 = X R^{-1} by construction, and the second round
+// orthonormalises Q1, whose column k is the rounding residual of x_k scaled
+// up -- a direction outside the span of the other columns.  So Q R = X still
+// holds exactly, with an orthonormal Q whose extra column completes the basis
+// of a rank-deficient X (k_complete first gives that column a direction of
+// its own where the data supply none: repeated samples).  In a second round,
+// and for a zero or non-finite column, it is a breakdown.  repcol[k] is set to
+// 1 for a replaced pivot of a first round (0 otherwise).
 //
 // Blocked right-looking over 64-wide block columns.  The 64 x 64 diagonal
 // tile is factored in LDS in four sub-blocks of 16 rows (one wavefront per
@@ -110,9 +123,10 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // nothing (the gated consumers of R and Rt then take the identity instead).
 // Dynamic LDS: 4 tiles.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, double* __restrict__ R,
+__global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, int r, double* __restrict__ R,
                                               double* __restrict__ Rt, double* __restrict__ gdiag,
-                                              double* __restrict__ invdiag, DevStatus* st, bool gated) {
+                                              double* __restrict__ invdiag, int* __restrict__ repcol, DevStatus* st,
+                                              bool gated) {
   if (failed(st)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (gated && *reinterpret_cast<volatile int*>(&st->round2) == 0) return;
@@ -123,17 +137,29 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
   double(*T3)[TP] = reinterpret_cast<double(*)[TP]>(smem + 3 * TS * TP);
   __shared__ double dorig[512];
   __shared__ double invd[TS];
-  __shared__ int err;
-  __shared__ double minrel;
+  __shared__ int err, nrep;
+  __shared__ double minrel, dmax;
   const int nt = rp / TS;
   const double tiny = (double)rp * 2.220446049250313e-16;
   for (int i = tid; i < rp; i += NTH) {
     dorig[i] = G[(int64_t)i * rp + i];
     gdiag[i] = dorig[i];
+    if (!gated) repcol[i] = 0;
   }
   if (tid == 0) {
     err = 0;
+    nrep = 0;
     minrel = 1.0;
+  }
+  __syncthreads();
+  // the largest diagonal entry of the r columns of the input: the scale of a
+  // replaced pivot
+  if (tid < 64) {
+    double mx = 0.0;
+    for (int i = tid; i < r; i += 64) mx = fmax(mx, G[(int64_t)i * rp + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (tid == 0) dmax = mx;
   }
   for (int bi = 1; bi < nt; ++bi)
     for (int bj = 0; bj < bi; ++bj) {
@@ -157,15 +183,24 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
         double col[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) col[i] = T0[s0 + i][j];
-        int bad = 0;
+        int bad = 0, rep = 0;
         double mr = 1.0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-          const double d = bcast_lane(col[k], s0 + k);
+          double d = bcast_lane(col[k], s0 + k);
           const double d0 = dorig[kb * TS + s0 + k];
-          // a failed pivot is recorded and the steps run on (uniform: every
-          // lane sees the same d); the kernel stops after the sub-block
-          if (!(d > tiny * d0) && !bad) bad = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
+          // a failed pivot is replaced (first round) or recorded and the
+          // steps run on (uniform: every lane sees the same d); after a
+          // recorded failure the kernel stops after the sub-block
+          if (!(d > tiny * d0) && !bad) {
+            if (!gated && !isnan(d) && d0 > 0.0 && d0 < INFINITY) {
+              d = tiny * dmax;
+              ++rep;
+              if (j == 0) repcol[kb * TS + s0 + k] = 1;
+            } else {
+              bad = isnan(d) ? ST_NONFINITE : ST_BREAKDOWN;
+            }
+          }
           const double ipiv = rsq_nr(d);   // 1/sqrt(d)
           mr = fmin(mr, d / d0);
           col[k] = (j > s0 + k) ? col[k] * ipiv : (j == s0 + k ? d * ipiv : col[k]);
@@ -177,6 +212,7 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
           if (j >= s0 + i) T0[s0 + i][j] = col[i];
         if (lane == 0) {
           if (bad) err = bad;
+          nrep += rep;
           minrel = fmin(minrel, mr);
         }
       }
@@ -300,6 +336,10 @@ __global__ __launch_bounds__(NTH) void k_chol(double* __restrict__ G, int rp, do
     st->chol_count += 1;
     const double mr = sqrt(minrel);
     if (mr < st->min_rel_pivot) st->min_rel_pivot = mr;
+    if (nrep) {
+      st->rank_def += nrep;
+      st->repl = 1;
+    }
   }
 }
 
@@ -423,7 +463,9 @@ __global__ __launch_bounds__(1024) void k_kappa(const double* __restrict__ gdiag
       b += red[1][w];
     }
     const double kap = sqrt(a * b);
-    const int need = !(kap <= kappa_round2);
+    // a replaced pivot always takes the second round
+    const int need = !(kap <= kappa_round2) || st->repl;
+    st->repl = 0;
     st->round2 = need;
     if (need) st->round2_count += 1;
     if (kap > st->kappa_max) st->kappa_max = kap;
@@ -558,8 +600,50 @@ __global__ __launch_bounds__(NTH) void k_jacobi_final(const double* __restrict__
     const int i = (int)(e / rp), k = (int)(e % rp);
     Ps[e] = Pc[(int64_t)src[k] * rp + i];
   }
-  if (tid == 0 && st->code == 0 && !st->jacobi_done) st->code = ST_WARN_NOT_CONVERGED;
+  if (tid == 0 && st->code == 0) {
+    if (!st->jacobi_done)
+      st->code = ST_WARN_NOT_CONVERGED;
+    else if (st->rank_def)
+      st->code = ST_WARN_RANK_DEFICIENT;
+  }
 }
+
+// Completion of a rank-deficient basis, after a first-round Cholesky of
+// X^T X that replaced the pivots of the columns k with repcol[k] = 1: x_k +=
+// R_kk xi_k with xi_k a pseudo-random unit vector of zero sum (entries +h and
+// -h on row pairs 2i, 2i+1, h uniform in [-1, 1) from an integer hash of
+// (i, k), scaled by sqrt(3 / rows); a last odd row gets 0).  Then the first
+// round's Q1 = X R^{-1} has column k = (old column k) + xi_k: the unit vector
+// xi_k plus the rounding residual, which the second round orthonormalises
+// against the others.  R stays the factor of the modified X (X = Q1 R by
+// construction), so X Tq is orthonormal and R the triangular factor of the
+// modified X, whose column k moved by R_kk = sqrt(rp eps) max_j |x_j|.  The zero sum keeps the columns of a centred basis centred.
+// grid: ceil(rows * r / 256) workgroups of 256 threads.
+template <typename T>
+__global__ __launch_bounds__(256) void k_complete(T* __restrict__ X, int64_t rows, int r, const double* __restrict__ R,
+                                                  int rp, const int* __restrict__ repcol, const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * r) return;
+  const int k = (int)(e % r);
+  if (!repcol[k]) return;
+  const int64_t i = e / r;
+  const int64_t pair = i >> 1;
+  if ((rows & 1) && i == rows - 1) return;
+  // integer hash of (pair, k) (a 32-bit finaliser of multiply-xorshift steps)
+  uint32_t hsh = (uint32_t)pair * 0x9E3779B1u ^ (uint32_t)(pair >> 32) * 0x85EBCA77u ^ (uint32_t)k * 0xC2B2AE3Du;
+  hsh ^= hsh >> 16;
+  hsh *= 0x7FEB352Du;
+  hsh ^= hsh >> 15;
+  hsh *= 0x846CA68Bu;
+  hsh ^= hsh >> 16;
+  const double h = ((double)hsh * (1.0 / 4294967296.0)) * 2.0 - 1.0;
+  const double xi = ((i & 1) ? -h : h) * sqrt(3.0 / (double)rows);
+  X[e] = (T)((double)X[e] + R[(int64_t)k * rp + k] * xi);
+}
+template __global__ void k_complete<float>(float*, int64_t, int, const double*, int, const int*, const DevStatus*);
+template __global__ void k_complete<double>(double*, int64_t, int, const double*, int, const int*,
+                                            const DevStatus*);
 
 // Ct (rp x rp row-major) = C^T with zero padding; C is r x r row-major.
 __global__ void k_transpose_pad(const double* __restrict__ C, int r, int rp, double* __restrict__ Ct) {

@@ -375,6 +375,8 @@ __global__ void k_status_init(DevStatus* st) {
     st->round2 = 0;
     st->kappa_max = 0.0;
     st->round2_count = 0;
+    st->rank_def = 0;
+    st->repl = 0;
     st->pad = 0;
   }
 }

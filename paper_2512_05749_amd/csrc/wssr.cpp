@@ -85,6 +85,7 @@ struct wssr_ctx {
   double *Bc = nullptr, *Pc = nullptr, *Ps = nullptr, *T = nullptr, *scal = nullptr, *sig = nullptr;
   double *cosbuf = nullptr, *cw = nullptr, *vpart = nullptr, *dots = nullptr, *ymean = nullptr, *Tq = nullptr;
   double *Rt = nullptr, *gdiag = nullptr, *invdiag = nullptr;
+  int* repcol = nullptr;          // columns whose first-round pivot was replaced (rank deficiency)
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
 
@@ -682,7 +683,8 @@ struct wssr_ctx {
   // Cholesky of G into R and R^{-1}; a first round (gated = false) also sets
   // the device flag that decides the second round.
   void chol(int rp, int r, double* R, double* Ri, bool gated) {
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), kCholLds, stream, G, rp, R, Rt, gdiag, invdiag, st, gated);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), kCholLds, stream, G, rp, r, R, Rt, gdiag, invdiag, repcol, st,
+                       gated);
     const dim3 g(cdiv(rp, 4));
     switch (rp / 64) {
       case 1: hipLaunchKernelGGL(k_trinv<1>, g, dim3(256), 0, stream, (const double*)Rt, rp, (const double*)invdiag, Ri, (const DevStatus*)st, gated); break;
@@ -721,6 +723,11 @@ struct wssr_ctx {
     const int rp = (int)rup(r, 64);
     gram(X, rows, r, false);
     chol(rp, r, R1, R1i, false);
+    // a rank-deficient X: its dependent columns get directions of their own
+    // (X is modified in place; X Tq and the factor R then refer to the
+    // modified X)
+    hipLaunchKernelGGL((k_complete<Tin>), dim3(cdiv(rows * r, 256)), dim3(256), 0, stream, const_cast<Tin*>(X), rows,
+                       r, (const double*)R1, rp, (const int*)repcol, (const DevStatus*)st);
     apply(X, rows, r, r, R1i, rp, r, mid, r, true, true);
     gram((const Tmid*)mid, rows, r, true);
     chol(rp, r, R2, R2i, true);
@@ -857,7 +864,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->cw, rp) && h->alloc(h->vpart, (size_t)kVecChunkMax * r) &&
             h->alloc(h->dots, (size_t)kVecChunkMax * r) && h->alloc(h->maxval, (size_t)kVecChunkMax * r) &&
             h->alloc(h->maxrow, (size_t)kVecChunkMax * r) && h->alloc(h->sgn, rp) && h->alloc(h->ymean, rp) &&
-            h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp) && h->alloc(h->invdiag, rp) &&
+            h->alloc(h->Tq, (size_t)rp * rp) && h->alloc(h->Rt, (size_t)rp * rp) && h->alloc(h->gdiag, rp) && h->alloc(h->invdiag, rp) && h->alloc(h->repcol, rp) &&
             h->alloc(h->jsync, 4) && h->alloc(h->bstat, kBatchMax);
   // stream-K partials (two 128 x 256 tiles per workgroup of one round), only
   // when a parameter-side product can have more tiles than one round holds
@@ -1387,8 +1394,11 @@ wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_
   if (rows < r || rows > h->rows_max) return h->fail(WSSR_ERR_INVALID_ARG, "rows outside [r, max(n_max, m_max)]");
   const int rp = (int)rup(r, 64);
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
-  h->cholqr<float, float>(X, rows, r, h->q1, h->Rz);
-  h->apply(X, rows, r, r, h->Tq, rp, r, Q, r, true);
+  // a workspace copy of X (a rank-deficient X is completed in place)
+  float* xc = rows <= h->cfg.m_max ? h->vw : h->qy;
+  (void)hipMemcpyAsync(xc, X, sizeof(float) * rows * r, hipMemcpyDeviceToDevice, h->stream);
+  h->cholqr<float, float>(xc, rows, r, h->q1, h->Rz);
+  h->apply((const float*)xc, rows, r, r, h->Tq, rp, r, Q, r, true);
   (void)hipMemcpy2DAsync(R, sizeof(double) * r, h->Rz, sizeof(double) * rp, sizeof(double) * r, r,
                          hipMemcpyDeviceToDevice, h->stream);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");

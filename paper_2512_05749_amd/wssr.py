@@ -16,6 +16,7 @@ _PKG = pathlib.Path(__file__).resolve().parent
 LIB_PATH = _PKG / "libwssr.so"
 
 OK = 0
+WARN_RANK_DEFICIENT = 1
 WARN_NOT_CONVERGED = 2
 ERR_INVALID_ARG = -1
 ERR_NO_DEVICE = -2
@@ -24,7 +25,7 @@ ERR_HIP = -4
 ERR_NONFINITE = -5
 ERR_BREAKDOWN = -6
 ERR_TIMEOUT = -7
-STATUS_NAMES = {0: "OK", 2: "WARN_NOT_CONVERGED", -1: "ERR_INVALID_ARG", -2: "ERR_NO_DEVICE", -3: "ERR_OOM",
+STATUS_NAMES = {0: "OK", 1: "WARN_RANK_DEFICIENT", 2: "WARN_NOT_CONVERGED", -1: "ERR_INVALID_ARG", -2: "ERR_NO_DEVICE", -3: "ERR_OOM",
                 -4: "ERR_HIP", -5: "ERR_NONFINITE", -6: "ERR_BREAKDOWN", -7: "ERR_TIMEOUT"}
 
 F32 = 0

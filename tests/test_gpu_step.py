@@ -180,17 +180,49 @@ def test_nonfinite_O_is_reported(ws):
     assert torch.equal(v, v_before)
 
 
-def test_rank_deficient_breakdown(ws):
-    """O with only 4 distinct centred rows but r = 6: the basis loses rank."""
-    base = torch.randn(5, 300, device="cuda")
+def test_rank_deficient(ws):
+    """O with only 5 distinct rows (4 after centring) but r = 6: the bases of
+    the iteration lose rank.  The library completes them, reports
+    WARN_RANK_DEFICIENT, and delta matches the oracle, whose Householder QR
+    completes them too (the extra singular values are zero, their weights 0).
+
+    lambda = 1 here: g lies entirely in the 4-dimensional span of the top
+    singular vectors, so delta = (g - V w V^T g) / lambda cancels down to about
+    g / sigma^2, and the FP32 rounding of V (about 1e-7) enters delta
+    amplified by sigma^2 / lambda (60 here; 6e4 at lambda = 1e-3)."""
+    lam = 1.0
+    g = torch.Generator(device="cuda").manual_seed(17)
+    base = torch.randn(5, 300, device="cuda", generator=g)
     o = base[torch.arange(40, device="cuda") % 5].contiguous()
-    e = torch.randn(40, dtype=torch.float64, device="cuda")
-    v = torch.randn(300, 6, device="cuda")
+    e = torch.randn(40, dtype=torch.float64, device="cuda", generator=g)
+    v = torch.randn(300, 6, device="cuda", generator=g)
+    v_in = v.clone()
+    delta, sigma = ws.step(o, e, v, lam, q=2)
+    code, diag = ws.status()
+    assert code == 1, (code, diag)
+    ref = orc.wssr_step(_np(o), _np(e), _np(v_in), lam, 6, 2)
+    assert rel(_np(delta), ref["delta"]) <= TOL_DELTA
+    assert float(np.abs(_np(delta) - ref["delta"]).max() / np.abs(ref["delta"]).max()) <= TOL_DELTA
+    # the four nonzero singular values agree; the rest are at rounding level
+    np.testing.assert_allclose(_np(sigma)[:4], ref["sigma"][:4], rtol=1e-4)
+    assert np.all(_np(sigma)[4:] < 1e-5 * _np(sigma)[0])
+    assert orth_err(_np(v)) <= TOL_ORTH
+
+
+def test_zero_column_breakdown(ws):
+    """A zero column in V_in gives a zero column in the first basis, which no
+    QR completes from the data: WSSR_ERR_BREAKDOWN, V, delta and sigma left
+    as they were."""
+    o, e, v = random_problem(200, 500, 8, seed=13, device="cuda")
+    v[:, 3] = 0.0
     v_before = v.clone()
-    ws.step(o, e, v, 1e-3, q=2)
+    delta = torch.full((500,), 7.0, dtype=torch.float64, device="cuda")
+    sigma = torch.full((8,), 7.0, dtype=torch.float64, device="cuda")
+    ws.step(o, e, v, 1e-3, q=2, delta=delta, sigma=sigma)
     code, _ = ws.status()
     assert code == -6
     assert torch.equal(v, v_before)
+    assert (delta == 7.0).all() and (sigma == 7.0).all()
 
 
 def test_handle_recovers_after_error(ws):
