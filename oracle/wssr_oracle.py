@@ -31,6 +31,12 @@ design notes):
   * output signs: column j of V_out has a non-negative inner product with
     column j of V_in; if that product is below 1e-8 in magnitude, the entry of
     largest magnitude (lowest index on ties) is made positive.
+  * averaged state (Sec. 4.1): the stored matrix is kept as its factors, the
+    orthonormal U of the previous step and sigma (Obar = U diag(sigma)); the
+    initial state is zero as the paper sets it, so the first step's Sbar is
+    (1 - avg) S_N rather than the S_N that the plain averaging scheme (eq.
+    ave_s) starts from; the sample-side singular factor V of eq. svd:det is the
+    last pass's Q_Y G, signed like its parameter-side partner.
 """
 from __future__ import annotations
 
@@ -253,9 +259,9 @@ def ssi_svd(a, v_in, q):
         qy, ry = qr_positive(y)
         qz, rz = qr_positive(z)
         c = qy.T @ (a @ qz)
-        _g, s, p = jacobi_svd(c)
+        gl, s, p = jacobi_svd(c)
         v = qz @ p
-        last = dict(y=y, z=z, qy=qy, ry=ry, qz=qz, rz=rz, c=c, s=s, p=p)
+        last = dict(y=y, z=z, qy=qy, ry=ry, qz=qz, rz=rz, c=c, gl=gl, s=s, p=p)
     v = fix_signs(v, v_in)
     return v, last["s"].copy(), last
 
@@ -311,6 +317,78 @@ def wssr_step(o, e_l, v_in, lam, r, q, precond="damped"):
     v, sigma, last = ssi_svd(a, np.asarray(v_in, dtype=np.float64)[:, :r], q)
     delta = woodbury_apply(v, sigma, g, lam, precond)
     return dict(delta=delta, v=v, sigma=sigma, g=g, eps=eps, last=last)
+
+
+def stack_averaged(a, lbar, state, avg):
+    """The averaged matrix and vector of eqs. Ohat and Lhat, transposed into this
+    module's orientation (rows are samples).
+
+    The paper stacks the stored matrix Obar^(k-1) (M x r_s) beside the new
+    centred, scaled samples; transposed, the new sample rows sqrt(1-avg) A come
+    first and the r_s history rows sqrt(avg) diag(sigma_s) U_s^T last (the order
+    of rows changes no singular value or parameter-side vector; Lhat is stacked
+    in the same order).  With state None (k = 0: Obar and Lbar are zero) there
+    are no history rows."""
+    w_new, w_old = np.sqrt(1.0 - avg), np.sqrt(avg)
+    if state is None:
+        return w_new * a, w_new * lbar
+    u_s = np.asarray(state["v"], dtype=np.float64)
+    s_s = np.asarray(state["sigma"], dtype=np.float64)
+    l_s = np.asarray(state["l"], dtype=np.float64)
+    hist = w_old * (s_s[:, None] * u_s.T)
+    return np.concatenate([w_new * a, hist], axis=0), np.concatenate([w_new * lbar, w_old * l_s])
+
+
+def state_l(last, sgn, lhat):
+    """L^(k) = (sample-side singular vectors)^T Lhat (eq. Lbar).
+
+    The sample-side singular vectors of the last pass are Q_Y G, with G the
+    left singular vectors of the Rayleigh-Ritz matrix C; each column carries
+    the sign its parameter-side partner was given."""
+    w = last["qy"] @ last["gl"]
+    return sgn * (w.T @ lhat)
+
+
+def averaged_step(o, e_l, v_in, state, lam, r, q, avg, precond="damped"):
+    """One WSSR step with the averaged state (Sec. 4.1: eqs. Ohat, Lhat,
+    svd:det, Obar, Lbar, barg, barS and updated_sr_1; Alg. 2).
+
+    state: None for the initial state (Obar^(0) = 0, Lbar^(0) = 0), else a dict
+    with v (M x r_s, the orthonormal parameter-side factor U of the previous
+    step), sigma (r_s,) and l (r_s,): the stored matrix is Obar = U diag(sigma)
+    (eq. Obar) and the stored vector is l (eq. Lbar).  avg is the averaging
+    weight delta of eq. Ohat, 0 <= avg < 1.  v_in (M x r) is the warm start of
+    the subspace iteration (Alg. 2 uses U of the previous step).
+
+    Steps, in the paper's order: stack (eqs. Ohat, Lhat); rank-r truncated SVD
+    of the stacked matrix by the subspace iteration (eq. svd:det, Alg. 1 with
+    the two-sided Rayleigh-Ritz reading); new state Obar = U Sigma (eq. Obar),
+    L = V Lhat (eq. Lbar); averaged gradient gbar = Ohat Lhat (eq. barg); the
+    update direction with Sbar = Obar Obar^T (eq. barS) in place of S.
+    Returns dict(delta, v, sigma, l, gbar, g, eps, last)."""
+    o = np.asarray(o, dtype=np.float64)
+    n, m = o.shape
+    if not 0.0 <= avg < 1.0:
+        raise ValueError("averaging weight out of range")
+    r_s = 0 if state is None else np.asarray(state["sigma"]).shape[0]
+    if not (1 <= r <= min(n - 1 + r_s, m)):
+        raise ValueError("rank out of range")
+    if q < 1 or not lam > 0:
+        raise ValueError("bad q or lambda")
+    if not (np.isfinite(o).all() and np.isfinite(e_l).all() and np.isfinite(v_in).all()):
+        raise FloatingPointError("non-finite input")
+    eps = center_energies(e_l)
+    a = scaled_centered(o)
+    lbar = eps / np.sqrt(n)                       # eq. Lbarn with the 1/sqrt(N) of eq. Osrn
+    ahat, lhat = stack_averaged(a, lbar, state, avg)
+    v_in = np.asarray(v_in, dtype=np.float64)[:, :r]
+    v, sigma, last = ssi_svd(ahat, v_in, q)
+    sgn = np.where(np.einsum("ij,ij->j", v, last["qz"] @ last["p"]) >= 0, 1.0, -1.0)
+    l_new = state_l(last, sgn, lhat)
+    gbar = ahat.T @ lhat                          # eq. barg
+    delta = woodbury_apply(v, sigma, gbar, lam, precond)
+    g = a.T @ lbar
+    return dict(delta=delta, v=v, sigma=sigma, l=l_new, gbar=gbar, g=g, eps=eps, last=last)
 
 
 # ----------------------------------------------------------------------------

@@ -392,3 +392,154 @@ def test_planted_mistakes_are_caught(monkeypatch):
     assert not pins_pass()
     monkeypatch.setattr(orc, "scaled_centered", real_scaled)
     assert pins_pass()
+
+
+# --------------------------------------------------------------- averaged state (Sec. 4.1)
+
+def _avg_problem(n, m, seed):
+    o, e = _problem(n, m, seed, spectrum=np.linspace(1.0, 0.3, min(n, m)), noise=0.05)
+    return o, e
+
+
+def _avg_chain(n, m, avg, ranks, seed, lam=0.3, q=2):
+    """Run averaged steps with the given rank per step; yield each step's
+    inputs and result."""
+    rng = rng0(seed)
+    state = None
+    for k, r in enumerate(ranks):
+        o, e = _avg_problem(n, m, seed + 1 + k)
+        v_in = rng.standard_normal((m, r))
+        res = orc.averaged_step(o, e, v_in, state, lam, r, q, avg)
+        yield o, e, res
+        state = dict(v=res["v"], sigma=res["sigma"], l=res["l"])
+
+
+@pytest.mark.parametrize("avg", [0.3, 0.7, 0.95])
+def test_averaged_exact_svd_is_the_running_average(avg):
+    """The remark after eq. barS: with an SVD that truncates nothing (rank r
+    equal to the rank of the stacked matrix), Sbar^(k) = avg Sbar^(k-1) +
+    (1-avg) S_N and gbar^(k) = avg gbar^(k-1) + (1-avg) g_N, from zero.  The
+    gradient recursion holds only if the stored vector L reproduces the old
+    gradient through the stored matrix (Obar L = Ohat Lhat), so it pins eq.
+    Lbar, the singular-vector signs and the stacking weights."""
+    n, m, lam = 5, 9, 0.3
+    ranks = [4, 8, 9, 9]            # rank of the stacked matrix: min(k (N-1), M)
+    s_prev, g_prev = np.zeros((m, m)), np.zeros(m)
+    for o, e, res in _avg_chain(n, m, avg, ranks, seed=700, lam=lam):
+        s_bar = (res["v"] * res["sigma"] ** 2) @ res["v"].T
+        s_want = avg * s_prev + (1 - avg) * orc.s_matrix(o)
+        g_want = avg * g_prev + (1 - avg) * orc.gradient(o, e)
+        assert _rel(s_bar, s_want) < 1e-11
+        assert _rel(res["gbar"], g_want) < 1e-11
+        # the stored pair reproduces the averaged gradient: Obar L = gbar
+        assert _rel(res["v"] @ (res["sigma"] * res["l"]), g_want) < 1e-10
+        # the step direction: a dense solve with the averaged matrices
+        assert _rel(res["delta"], np.linalg.solve(s_want + lam * np.eye(m), g_want)) < 1e-10
+        s_prev, g_prev = s_want, g_want
+
+
+def test_averaged_weight_zero_is_the_plain_step():
+    """avg = 0 discards the history rows: the step equals the plain step."""
+    n, m, r = 12, 30, 5
+    o0, e0 = _avg_problem(n, m, 801)
+    st = orc.averaged_step(o0, e0, rng0(1).standard_normal((m, r)), None, 0.1, r, 3, 0.5)
+    state = dict(v=st["v"], sigma=st["sigma"], l=st["l"])
+    o, e = _avg_problem(n, m, 802)
+    v_in = rng0(2).standard_normal((m, r))
+    got = orc.averaged_step(o, e, v_in, state, 1e-2, r, 3, 0.0)
+    want = orc.wssr_step(o, e, v_in, 1e-2, r, 3)
+    assert _rel(got["delta"], want["delta"]) < 1e-10
+    assert _rel(got["sigma"], want["sigma"]) < 1e-12
+    assert np.abs(got["v"] - want["v"]).max() < 1e-10
+    assert _rel(got["gbar"], want["g"]) < 1e-13
+
+
+def test_averaged_truncated_against_the_averaged_gram():
+    """Truncated (r below the stacked rank), converged: sigma^2 and the span of
+    V are the top-r eigenpairs of the averaged Gram avg U_s diag(sigma_s^2) U_s^T
+    + (1-avg) S_N, formed here directly and decomposed by LAPACK; L is the
+    projection of gbar on V scaled by 1/sigma (a converged singular triplet
+    has sample-side vector Ohat^T v / sigma)."""
+    n, m, r, avg = 40, 60, 6, 0.8
+    rng = rng0(901)
+    # a gap after the sixth value, so that 60 passes converge
+    spec = np.r_[np.linspace(1.0, 0.6, r), 0.2 * np.linspace(1.0, 0.3, n - r)]
+    o0, e0 = _problem(n, m, 902, spectrum=spec, noise=0.01)
+    st = orc.averaged_step(o0, e0, rng.standard_normal((m, r)), None, 0.1, r, 60, avg)
+    o = o0 + 0.02 * rng.standard_normal((n, m))     # the next step's samples: a nearby state
+    e = e0 + 0.01 * rng.standard_normal(n)
+    state = dict(v=st["v"], sigma=st["sigma"], l=st["l"])
+    res = orc.averaged_step(o, e, st["v"], state, 0.1, r, 60, avg)
+    gram = avg * (st["v"] * st["sigma"] ** 2) @ st["v"].T + (1 - avg) * orc.s_matrix(o)
+    w, u = np.linalg.eigh(gram)
+    w, u = w[::-1][:r], u[:, ::-1][:, :r]
+    assert _rel(res["sigma"] ** 2, w) < 1e-10
+    assert orc.subspace_distance(res["v"], u) < 1e-7      # the distance is a sine: floor ~sqrt(eps)
+    g_want = avg * st["v"] @ (st["sigma"] * st["l"]) + (1 - avg) * orc.gradient(o, e)
+    assert _rel(res["gbar"], g_want) < 1e-12
+    assert _rel(res["l"], (res["v"].T @ g_want) / res["sigma"]) < 1e-8
+
+
+def test_averaged_one_pass_projection_identity():
+    """At any pass count the stored pair satisfies Obar L = P_V Ohat P_Y Lhat:
+    with C = Q_Y^T Ohat^T Q_Z = G diag(s) P^T the Rayleigh-Ritz matrix, V =
+    Q_Z P and L = G^T Q_Y^T Lhat give V diag(s) L = Q_Z C^T Q_Y^T Lhat.  At
+    q = 1 the sample-side space is span(Ohat^T orth(V_in)), built here with
+    LAPACK's QR from the stacked matrix written out."""
+    n, m, r, avg = 30, 50, 5, 0.6
+    rng = rng0(951)
+    o0, e0 = _avg_problem(n, m, 952)
+    st = orc.averaged_step(o0, e0, rng.standard_normal((m, r)), None, 0.1, r, 1, avg)
+    o, e = _avg_problem(n, m, 953)
+    v_in = rng.standard_normal((m, r))
+    state = dict(v=st["v"], sigma=st["sigma"], l=st["l"])
+    res = orc.averaged_step(o, e, v_in, state, 0.1, r, 1, avg)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    eps = e - e.mean()
+    ahat = np.vstack([np.sqrt(1 - avg) * a, np.sqrt(avg) * (st["sigma"][:, None] * st["v"].T)])
+    lhat = np.concatenate([np.sqrt(1 - avg) * eps / np.sqrt(n), np.sqrt(avg) * st["l"]])
+    qy = np.linalg.qr(ahat @ np.linalg.qr(v_in)[0])[0]
+    v = res["v"]
+    want = v @ (v.T @ (ahat.T @ (qy @ (qy.T @ lhat))))
+    assert _rel(v @ (res["sigma"] * res["l"]), want) < 1e-12
+
+
+def test_averaged_rejects_bad_arguments():
+    o, e = _avg_problem(6, 10, 5)
+    v = np.ones((10, 3))
+    for bad in (-0.1, 1.0):
+        with pytest.raises(ValueError):
+            orc.averaged_step(o, e, v, None, 0.1, 3, 1, bad)
+    with pytest.raises(ValueError):
+        orc.averaged_step(o, e, np.ones((10, 6)), None, 0.1, 6, 1, 0.5)   # r > N - 1 without history
+
+
+def test_averaged_planted_mistakes_are_caught(monkeypatch):
+    """Swapped stacking weights, L taken from the parameter-side rotation, and
+    L without the output signs each fail the averaged pins."""
+    def pins_pass():
+        try:
+            for avg in (0.3, 0.7):
+                test_averaged_exact_svd_is_the_running_average(avg)
+            test_averaged_truncated_against_the_averaged_gram()
+            test_averaged_one_pass_projection_identity()
+        except AssertionError:
+            return False
+        return True
+
+    assert pins_pass()
+    real_stack, real_l = orc.stack_averaged, orc.state_l
+
+    def swapped(a, lbar, state, avg):
+        return real_stack(a, lbar, state, 1.0 - avg) if state is not None else real_stack(a, lbar, state, avg)
+
+    def l_from_p(last, sgn, lhat):
+        return sgn * ((last["qy"] @ last["p"]).T @ lhat)
+
+    def l_unsigned(last, sgn, lhat):
+        return real_l(last, np.ones_like(sgn), lhat)
+
+    for name, fn in (("stack_averaged", swapped), ("state_l", l_from_p), ("state_l", l_unsigned)):
+        monkeypatch.setattr(orc, name, fn)
+        assert not pins_pass(), (name, fn.__name__)
+        monkeypatch.undo()
