@@ -79,6 +79,8 @@ def parse():
                          "comparison, FP32 at M=2e6 for the largest instance; 0: none)")
     ap.add_argument("--secondary", type=int, default=1,
                     help="also time the FP32 benchmark workload f32_n8192_m100k_r256 as a secondary record")
+    ap.add_argument("--averaged", type=float, default=0.95,
+                    help="also time the averaged-state step with this weight on the same data (0: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-cols", type=int, default=0, help="columns of the oracle sample (0: auto)")
     ap.add_argument("--plain-inputs", type=int, default=0,
@@ -105,11 +107,12 @@ PEAK_BF16_TFLOPS = 2516.6
 PRODUCTS = {"f32": 1, "bf16": 1, "bf16_split": 2, "bf16x2": 3}
 
 
-def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev):
+def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev, avg=None):
     """Cold step, warm-up and timed steps of one precision form on handle h;
     returns the timings, the product-kernel profile and the last status.  The
     BF16 forms use the gradient their ingest formed from the unrounded O
-    (g_ring); the FP32 form forms it inside the step."""
+    (g_ring); the FP32 form forms it inside the step.  avg: the averaged-state
+    step with that weight, from the zero state."""
     import numpy as np
     import torch
 
@@ -117,15 +120,20 @@ def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev):
     ring = len(o_ring)
     v = v_start.clone()
     delta = torch.empty(m, dtype=torch.float64, device=dev)
-    sigma = torch.empty(r, dtype=torch.float64, device=dev)
+    sigma = torch.zeros(r, dtype=torch.float64, device=dev)
+    l_state = torch.zeros(r, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
+    tag = form if avg is None else f"{form}, averaged {avg}"
 
     def one(t, qq):
         k = t % ring
-        if g_ring is None:
+        g = None if g_ring is None else g_ring[k]
+        if avg is not None:
+            h.step_avg(o_ring[k], e_ring[k], v, lam, avg, sigma, l_state, q=qq, delta=delta, g=g)
+        elif g is None:
             h.step(o_ring[k], e_ring[k], v, lam, q=qq, delta=delta, sigma=sigma)
         else:
-            h.step(o_ring[k], None, v, lam, q=qq, delta=delta, sigma=sigma, g=g_ring[k])
+            h.step(o_ring[k], None, v, lam, q=qq, delta=delta, sigma=sigma, g=g)
 
     # step 1: cold start (8 passes from V_0), reported separately
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -134,7 +142,7 @@ def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev):
     e1.record(stream)
     code, diag = h.status()
     cold_ms = e0.elapsed_time(e1)
-    log(f"[{form}] cold step (q=8): {cold_ms:.2f} ms, status {code}, diag {diag}")
+    log(f"[{tag}] cold step (q=8): {cold_ms:.2f} ms, status {code}, diag {diag}")
     if code < 0:
         raise SystemExit(f"cold step failed with status {code}")
 
@@ -143,7 +151,7 @@ def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev):
         one(t, q)
         t += 1
     torch.cuda.synchronize()
-    log(f"[{form}] warmup done")
+    log(f"[{tag}] warmup done")
 
     h.profile(True)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -162,7 +170,7 @@ def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev):
     code, diag = h.status()
     per_step = [s_.elapsed_time(e_) for s_, e_ in zip(starts, ends)]
     ms_per_step = wall * 1e3 / args.steps
-    log(f"[{form}] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall), median event "
+    log(f"[{tag}] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall), median event "
         f"{np.median(per_step):.3f} ms, status {code}, diag {diag}")
     if code < 0:
         raise SystemExit(f"timed steps failed with status {code}")
@@ -500,7 +508,7 @@ def hbm_of(form, prof, cfg, res):
             "step_bytes": step_bytes, "peak_GB/s": PEAK_HBM_GBS}
 
 
-def run_single(args, cfg, form, dev, sample_cols=0, ring=0):
+def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0):
     """Generate, time and release one workload in one form; returns the
     result record, the step-1 sample columns and V (for the accuracy leg)."""
     import torch
@@ -518,6 +526,10 @@ def run_single(args, cfg, form, dev, sample_cols=0, ring=0):
         log(f"copy calibration: {args.copy_calibration} MiB read + written by one neg kernel")
         del src, dst
     res = time_form(h, form, os_, es, gs, v, cfg, args, dev)
+    res_avg = None
+    if averaged > 0:
+        # the averaged-state step on the same data and handle
+        res_avg = time_form(h, form, os_, es, gs, v, cfg, args, dev, avg=averaged)
     h.close()
     e1 = es[0]
     del os_, gs
@@ -532,6 +544,15 @@ def run_single(args, cfg, form, dev, sample_cols=0, ring=0):
            "diag": res["diag"]}
     if form != "f32":
         rec["ingest_ms_per_O"] = round(ingest_ms, 3)
+    if res_avg is not None:
+        rec["averaged"] = {"weight": averaged, "value": round(1e3 / res_avg["ms_per_step"], 3),
+                           "ms_per_step": round(res_avg["ms_per_step"], 4),
+                           "step_ms_events": {"median": round(res_avg["median_ms"], 4),
+                                              "p10": round(res_avg["p10_ms"], 4),
+                                              "p90": round(res_avg["p90_ms"], 4)},
+                           "cold_step_ms": round(res_avg["cold_ms"], 3),
+                           "time_vs_plain_step": round(res_avg["ms_per_step"] / res["ms_per_step"], 4),
+                           "diag": res_avg["diag"]}
     return rec, sample, e1, res["v"]
 
 
@@ -571,7 +592,7 @@ def main():
     torch.cuda.set_device(dev)
     cols = oracle_cols(args, cfg) if args.cpu_baseline else 0
     cols_wide = min(cfg.m, OracleSample.WIDE * cols)
-    rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols_wide)
+    rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols_wide, averaged=args.averaged)
     out = {
         "metric": METRIC,
         "value": rec["value"],
@@ -594,6 +615,8 @@ def main():
     }
     if form != "f32":
         out["ingest_ms_per_O"] = rec["ingest_ms_per_O"]
+    if "averaged" in rec:
+        out["averaged_state_step"] = rec["averaged"]
     oracle = OracleSample(args, cfg, sample, e1, v_end[:cols_wide], form, cols) if args.cpu_baseline else None
     del sample, v_end
     torch.cuda.empty_cache()

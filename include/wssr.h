@@ -161,6 +161,40 @@ wssr_status wssr_step(wssr_handle h, int64_t n, int64_t m, const void* O, int64_
 wssr_status wssr_step_g(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* g,
                         float* V, double lambda, int32_t r, int32_t q, double* delta, double* sigma);
 
+/* One WSSR step with the averaged state (Sec. 4.1: eqs. Ohat, Lhat, svd:det,
+ * Obar, Lbar, barg, barS; Alg. 2).  The state of the previous step is the
+ * stored matrix Obar = V_in diag(sig_state) (parameters x r) and the stored
+ * vector l_state (r); the step
+ *   - stacks them with the new samples, weights sqrt(avg) and sqrt(1 - avg)
+ *     (eqs. Ohat, Lhat), and runs q passes of the subspace iteration on the
+ *     stacked matrix (n + r rows in this library's orientation), warm-started
+ *     from V_in;
+ *   - returns its rank-r right singular vectors in V and its singular values
+ *     in sig_state: the new Obar = V diag(sig_state) (eq. Obar);
+ *   - sets l_state to the sample-side singular vectors applied to the
+ *     stacked vector (eq. Lbar), signed like the columns of V;
+ *   - forms the averaged gradient gbar = (1 - avg) g + avg V_in (sig o l)
+ *     (eq. barg) and the direction delta = (V diag(sig^2) V^T + lambda I)^{-1}
+ *     gbar (the floor form with WSSR_FLOOR_PRECOND), i.e. with Sbar of eq.
+ *     barS in place of S.
+ * Arguments as for wssr_step, and:
+ *   e_l        device, double[n]: read always (the stacked vector needs eps)
+ *   g          device, double[m] or NULL: a gradient formed by wssr_ingest; NULL:
+ *              the step forms g from O and e_l
+ *   V          in: the U of the previous averaged step (the state's basis and the
+ *              warm start); for the first step any basis, with sig_state = 0
+ *   avg        averaging weight, 0 <= avg < 1 (0: the plain step; the state is
+ *              then ignored but must be finite)
+ *   sig_state  device, double[r], in/out, finite; zero for the initial state
+ *   l_state    device, double[r], in/out, finite; zero for the initial state
+ *   g_bar      device, double[m] or NULL: out, the averaged gradient
+ * The history rows are weighted by sqrt(avg / (1 - avg)) relative to the
+ * samples; the cost beyond wssr_step is one Gram of V_in (m x r), one
+ * accumulating apply V_in B (m x r times r x r) per pass, and r x r work. */
+wssr_status wssr_step_avg(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                          const double* g, float* V, double lambda, int32_t r, int32_t q, double avg,
+                          double* sig_state, double* l_state, double* delta, double* g_bar);
+
 /* Ingest of O: one pass over a block of rows of the unrounded FP32 matrix
  * that writes them in the handle's storage form and forms, from the unrounded
  * values, the gradient g = O_bar^T eps / n (Sec. 4.1 eq. barg; eps = E_L -

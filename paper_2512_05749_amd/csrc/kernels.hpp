@@ -118,7 +118,12 @@ __global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, 
                               const DevStatus* st, bool gated);
 template <typename Tin, typename Tout>
 __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
-                        Tout* Out, int ldo, bool upper, bool vec, const DevStatus* st, bool gated);
+                        Tout* Out, int ldo, bool upper, bool vec, bool acc, const DevStatus* st, bool gated);
+template <typename TX, typename TW>
+__global__ void k_cross_partial(const TX* X, const TW* W, int64_t rows, int r, int ntile, int64_t rows_per_chunk,
+                                double* part, bool vec, const DevStatus* st);
+__global__ void k_cross_reduce(const double* part, int nchunk, int ntile, int r, int rp, double* H,
+                               const DevStatus* st);
 // tile of the Gram and apply kernels, and the Gram partial-buffer budget
 constexpr int kF64Tile = 128;
 constexpr size_t kGramPartBytes = (size_t)64 << 20;
@@ -153,6 +158,16 @@ __global__ void k_ingest_partial(const float* O32, int64_t ld32, int64_t rows, i
 __global__ void k_ingest_reduce(const double* gpart, const double* cpart, int nsplit, int64_t m, double inv_n,
                                 bool first, double* g, double* mu);
 
+// averaged-state step (kernels_avg.hip)
+__global__ void k_hist_rows(double* yh, int r, const double* sig, const double* H, int ldh, double c,
+                            const DevStatus* st);
+__global__ void k_hist_b(const float* qtop, int r, const double* sig, double c, double* B, int rp,
+                         const DevStatus* st);
+__global__ void k_gbar_w(const double* sig, const double* l, int r, double coef, double* cw, const DevStatus* st);
+__global__ void k_lhat(const double* eps, int64_t n, const double* l, int r, double a_new, double a_old,
+                       double* lhat, const DevStatus* st);
+__global__ void k_state_l(const double* Rz, const double* Ps, int rp, int r, const double* t, const float* sgn,
+                          double* sig, double wscale, double* l_out, const DevStatus* st);
 
 // dynamic LDS sizes (bytes)
 constexpr size_t kCholLds = 4 * 64 * 65 * sizeof(double);

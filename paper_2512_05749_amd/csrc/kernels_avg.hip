@@ -1,0 +1,86 @@
+// Small kernels of the averaged-state step (Sec. 4.1, eqs. Ohat, Lhat, Obar,
+// Lbar, barg).  The stored matrix of the previous step, U diag(sigma), enters
+// the subspace iteration as r extra rows of the sample-side block; these
+// kernels build those rows and the r x r factors that carry them through the
+// parameter-side product, the averaged gradient, and the new stored vector.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace wssr {
+
+// History rows of the sample-side block: Yh[i][j] = c sigma_i H[i][j]
+// (i, j < r; Yh has row stride r, H row stride ldh).  c = 0 writes zeros
+// without reading H.
+__global__ __launch_bounds__(256) void k_hist_rows(double* __restrict__ yh, int r, const double* __restrict__ sig,
+                                                   const double* __restrict__ H, int ldh, double c,
+                                                   const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e / r), j = (int)(e % r);
+  yh[e] = c == 0.0 ? 0.0 : c * sig[i] * H[(int64_t)i * ldh + j];
+}
+
+// Factor of the history term of the parameter-side product:
+// B[i][j] = c sigma_i Qtop[i][j] for i, j < r, zero elsewhere in rp x rp
+// (Qtop: the r history rows of the orthonormal sample-side block, stride r).
+__global__ __launch_bounds__(256) void k_hist_b(const float* __restrict__ qtop, int r, const double* __restrict__ sig,
+                                                double c, double* __restrict__ B, int rp, const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rp * rp) return;
+  const int i = (int)(e / rp), j = (int)(e % rp);
+  B[e] = (i < r && j < r) ? c * sig[i] * (double)qtop[(int64_t)i * r + j] : 0.0;
+}
+
+// Weights of the averaged gradient's history term: cw_j = coef sigma_j l_j.
+__global__ __launch_bounds__(256) void k_gbar_w(const double* __restrict__ sig, const double* __restrict__ l, int r,
+                                                double coef, double* __restrict__ cw, const DevStatus* st) {
+  if (failed(st)) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < r) cw[j] = coef * sig[j] * l[j];
+}
+
+// The stacked vector of eq. Lhat in the row order of the sample-side block:
+// lhat[i] = a_new eps_i (i < n), lhat[n + i] = a_old l_i (i < r).
+__global__ __launch_bounds__(256) void k_lhat(const double* __restrict__ eps, int64_t n, const double* __restrict__ l,
+                                              int r, double a_new, double a_old, double* __restrict__ lhat,
+                                              const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n)
+    lhat[e] = a_new * eps[e];
+  else if (e < n + r)
+    lhat[e] = a_old * l[e - n];
+}
+
+// New stored vector (eq. Lbar) and singular values.  With the Rayleigh-Ritz
+// matrix C = R_Z^T = G diag(s) P^T, the sample-side singular vectors are
+// Q_Y G and G^T = diag(1/s) P^T R_Z, so L = sgn * diag(1/s) P^T (R_Z t) with
+// t = Q_Y^T Lhat.  A zero singular value gives L_j = 0.  The singular values
+// are then scaled in place by `wscale` (those of the block the iteration ran
+// on are 1/wscale times those of the stacked matrix).  One workgroup.
+__global__ __launch_bounds__(512) void k_state_l(const double* __restrict__ Rz, const double* __restrict__ Ps, int rp,
+                                                 int r, const double* __restrict__ t, const float* __restrict__ sgn,
+                                                 double* __restrict__ sig, double wscale, double* __restrict__ l_out,
+                                                 const DevStatus* st) {
+  if (failed(st)) return;
+  __shared__ double ts[512], us[512];
+  for (int k = threadIdx.x; k < r; k += blockDim.x) ts[k] = t[k];
+  __syncthreads();
+  for (int i = threadIdx.x; i < r; i += blockDim.x) {
+    double a = 0.0;
+    for (int k = i; k < r; ++k) a += Rz[(int64_t)i * rp + k] * ts[k];
+    us[i] = a;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    double a = 0.0;
+    for (int k = 0; k < r; ++k) a += Ps[(int64_t)k * rp + j] * us[k];
+    const double s = sig[j];
+    l_out[j] = s > 0.0 ? (double)sgn[j] * a / s : 0.0;
+    sig[j] = wscale * s;
+  }
+}
+
+}  // namespace wssr

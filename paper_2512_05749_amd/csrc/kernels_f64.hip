@@ -183,16 +183,17 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Apply: Out[rows x ldo] = X[rows x ldx] * Tm[0:kdim, 0:ncol] (Tm rp x rp
-// row-major, FP64).  grid (row tiles of 128, column tiles of 128); 4 waves of
-// 64 x 64 as in the Gram kernel.  When `upper`, Tm is upper triangular and
-// K-steps below the column tile are skipped.  The next K-step's tiles are
-// loaded into registers while the current ones are multiplied.
+// row-major, FP64), or Out += X * Tm when `acc`.  grid (row tiles of 128,
+// column tiles of 128); 4 waves of 64 x 64 as in the Gram kernel.  When
+// `upper`, Tm is upper triangular and K-steps below the column tile are
+// skipped.  The next K-step's tiles are loaded into registers while the
+// current ones are multiplied.
 // ---------------------------------------------------------------------------
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int64_t rows, int ldx, int kdim,
                                                   const double* __restrict__ Tm, int rp, int ncol,
                                                   Tout* __restrict__ Out, int ldo, bool upper, bool vec,
-                                                  const DevStatus* st, bool gated) {
+                                                  bool acc, const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
   __shared__ double Xs[GK][GS];   // [k][row]
   __shared__ double Ts[GK][GS];   // [k][col]
@@ -203,11 +204,11 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
   const int col0 = blockIdx.y * GT;
   const int kend = upper ? min(kdim, col0 + GT) : kdim;
 
-  f64x4 acc[4][4];
+  f64x4 acc_v[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0};
+    for (int b = 0; b < 4; ++b) acc_v[a][b] = f64x4{0};
 
   // X: thread -> (row, 4 K-values), two units; T: thread -> (K-row, 2 columns), four units
   f64x4 px[2];
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc_v[a][b] = mfma16x16x4d(av[a], bv[b], acc_v[a][b]);
     }
     __syncthreads();
   }
@@ -277,8 +278,119 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
       for (int v = 0; v < 4; ++v) {
         const int64_t i = row0 + qi * 64 + a * 16 + 4 * v + lk;
         const int j = col0 + qj * 64 + b * 16 + li;
-        if (i < rows && j < ncol) Out[i * ldo + j] = (Tout)acc[a][b][v];
+        if (i < rows && j < ncol)
+          Out[i * ldo + j] = acc ? (Tout)(acc_v[a][b][v] + (double)Out[i * ldo + j]) : (Tout)acc_v[a][b][v];
       }
+}
+
+// ---------------------------------------------------------------------------
+// Cross products H = X^T W of two tall blocks (rows x r, row stride r each,
+// X and W of possibly different element types), as partials over row chunks:
+// grid.x enumerates all ntile x ntile tiles of 128 x 128 (I, J), grid.y the
+// row chunks; the waves, K-steps and staging are those of the Gram kernel.
+// part[(chunk * ntile^2 + I * ntile + J) * 16384 + i * 128 + j].
+// ---------------------------------------------------------------------------
+template <typename TX, typename TW>
+__global__ __launch_bounds__(256, 2) void k_cross_partial(const TX* __restrict__ X, const TW* __restrict__ W,
+                                                          int64_t rows, int r, int ntile, int64_t rows_per_chunk,
+                                                          double* __restrict__ part, bool vec, const DevStatus* st) {
+  if (failed(st)) return;
+  __shared__ double XI[GK][GS];
+  __shared__ double WJ[GK][GS];
+  const int I = blockIdx.x / ntile, J = blockIdx.x % ntile;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int qi = w >> 1, qj = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t rbeg = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t rend = min(rows, rbeg + rows_per_chunk);
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0};
+
+  f64x4 pi[2], pj[2];
+  auto load = [&](int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = t + 256 * e;
+      const int64_t gr = k0 + (idx >> 5);
+      const int c4 = (idx & 31) * 4;
+      const int ci = I * GT + c4, cj = J * GT + c4;
+      const bool row_ok = gr < rend;
+      pi[e] = load4d(X + gr * r + ci, row_ok ? min(4, r - ci) : 0, vec);
+      pj[e] = load4d(W + gr * r + cj, row_ok ? min(4, r - cj) : 0, vec);
+    }
+  };
+  auto store = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = t + 256 * e;
+      const int kr = idx >> 5, c4 = (idx & 31) * 4;
+      *reinterpret_cast<f64x2*>(&XI[kr][c4]) = f64x2{pi[e][0], pi[e][1]};
+      *reinterpret_cast<f64x2*>(&XI[kr][c4 + 2]) = f64x2{pi[e][2], pi[e][3]};
+      *reinterpret_cast<f64x2*>(&WJ[kr][c4]) = f64x2{pj[e][0], pj[e][1]};
+      *reinterpret_cast<f64x2*>(&WJ[kr][c4 + 2]) = f64x2{pj[e][2], pj[e][3]};
+    }
+  };
+  if (rbeg < rend) load(rbeg);
+  for (int64_t k0 = rbeg; k0 < rend; k0 += GK) {
+    store();
+    __syncthreads();
+    if (k0 + GK < rend) load(k0 + GK);
+#pragma unroll
+    for (int kk = 0; kk < GK / 4; ++kk) {
+      const int k = kk * 4 + lk;
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = XI[k][qi * 64 + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = WJ[k][qj * 64 + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* out = part + ((int64_t)blockIdx.y * ntile * ntile + blockIdx.x) * (GT * GT);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = qi * 64 + a * 16 + 4 * v + lk;
+        const int j = qj * 64 + b * 16 + li;
+        out[i * GT + j] = acc[a][b][v];
+      }
+}
+
+// Sum the cross partials in chunk order into H (rp x rp row-major, zero
+// outside r x r).  grid (ntile^2, 64), one entry per thread.
+__global__ __launch_bounds__(256) void k_cross_reduce(const double* __restrict__ part, int nchunk, int ntile, int r,
+                                                      int rp, double* __restrict__ H, const DevStatus* st) {
+  if (failed(st)) return;
+  const int I = blockIdx.x / ntile, J = blockIdx.x % ntile;
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  const int i = e / GT, j = e % GT;
+  const int gi = I * GT + i, gj = J * GT + j;
+  if (gi >= rp || gj >= rp) return;
+  double s = 0.0;
+  if (gi < r && gj < r) {
+    const double* p = part + (int64_t)blockIdx.x * (GT * GT) + e;
+    const int64_t stride = (int64_t)ntile * ntile * (GT * GT);
+    double a0 = 0.0, a1 = 0.0;
+    int c = 0;
+    for (; c + 1 < nchunk; c += 2) {
+      a0 += p[(c + 0) * stride];
+      a1 += p[(c + 1) * stride];
+    }
+    if (c < nchunk) a0 += p[c * stride];
+    s = a0 + a1;
+  }
+  H[(int64_t)gi * rp + gj] = s;
 }
 
 // explicit instantiations used by the host runtime
@@ -286,11 +398,13 @@ template __global__ void k_gram_partial<float>(const float*, int64_t, int, int, 
                                                const DevStatus*, bool);
 template __global__ void k_gram_partial<double>(const double*, int64_t, int, int, int64_t, double*, bool,
                                                 const DevStatus*, bool);
+template __global__ void k_cross_partial<double, float>(const double*, const float*, int64_t, int, int, int64_t,
+                                                        double*, bool, const DevStatus*);
 template __global__ void k_apply<float, float>(const float*, int64_t, int, int, const double*, int, int, float*, int,
-                                               bool, bool, const DevStatus*, bool);
+                                               bool, bool, bool, const DevStatus*, bool);
 template __global__ void k_apply<double, float>(const double*, int64_t, int, int, const double*, int, int, float*,
-                                                int, bool, bool, const DevStatus*, bool);
+                                                int, bool, bool, bool, const DevStatus*, bool);
 template __global__ void k_apply<double, double>(const double*, int64_t, int, int, const double*, int, int, double*,
-                                                 int, bool, bool, const DevStatus*, bool);
+                                                 int, bool, bool, bool, const DevStatus*, bool);
 
 }  // namespace wssr

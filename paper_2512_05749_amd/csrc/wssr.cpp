@@ -86,6 +86,13 @@ struct wssr_ctx {
   double *cosbuf = nullptr, *cw = nullptr, *vpart = nullptr, *dots = nullptr, *ymean = nullptr, *Tq = nullptr;
   double *Rt = nullptr, *gdiag = nullptr, *invdiag = nullptr;
   int* repcol = nullptr;          // columns whose first-round pivot was replaced (rank deficiency)
+  // averaged-state step: the first pass's sample-side block, the cross
+  // products that carry the history rows through later passes, the factor of
+  // the parameter-side history term, the averaged gradient, the stacked
+  // vector Lhat and its projection
+  double *y1 = nullptr, *Hc = nullptr, *Hn = nullptr, *Bm = nullptr, *gbar = nullptr, *lhat = nullptr;
+  double* tvec = nullptr;
+  int64_t gram_part_elems = 0;
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
 
@@ -175,12 +182,31 @@ struct wssr_ctx {
   // ---------------------------------------------------------------- kernels
   hipError_t last() { return hipGetLastError(); }
 
+  // Averaged state of a step (wssr_step_avg): the stored matrix of the
+  // previous step is V_in diag(sig_state) and its vector l_state.
+  struct AvgArgs {
+    double avg;           // averaging weight, 0 <= avg < 1
+    double* sig_state;    // r: in, the stored singular values; out, the new ones
+    double* l_state;      // r: in, the stored vector; out, the new one
+    double* gbar_out;     // m (nullable): the averaged gradient
+  };
+
   // Enqueue one step on this context's stream (arguments already checked).
   // g_ext (nullable): a gradient the caller formed (wssr_step_g); the step
-  // then makes no gradient pass and does not read e_l.
+  // then makes no gradient pass and, without averaging, does not read e_l.
+  // av (nullable): the averaged-state step.  The iteration then runs on the
+  // block [A ; c diag(sig_state) V_in^T] (n + r rows, c = sqrt(avg/(1-avg))),
+  // which is the stacked matrix of eq. Ohat divided by sqrt(1 - avg):
+  //  * pass 1's history rows are c diag(sig) V_in^T V_in (a Gram of V_in);
+  //  * later passes' are c diag(sig) V_in^T V_p with V_p = Z Tq of the pass
+  //    before, and V_in^T Z = Y_1^T Q_Y (Y_1 = pass 1's block, Z its product
+  //    with Q_Y), so no further product over the M rows of V_in is needed;
+  //  * the parameter-side product gains V_in B, B = c diag(sig) Q_Y[n:n+r];
+  //  * the Rayleigh-Ritz step is unchanged (C = R_Z^T), and the singular
+  //    values are scaled back by sqrt(1 - avg) at the end.
   wssr_status enqueue(int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, float* V,
                       double lambda, int32_t r, int32_t q, double* delta, double* sigma,
-                      const double* g_ext = nullptr) {
+                      const double* g_ext = nullptr, const AvgArgs* av = nullptr) {
     wssr_ctx* h = this;
     const double* gv = g_ext ? g_ext : h->g;
     const int rp = (int)rup(r, 64);
@@ -188,16 +214,42 @@ struct wssr_ctx {
     hipStream_t stream = h->stream;
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
 
+    const double c_hist = av ? std::sqrt(av->avg / (1.0 - av->avg)) : 0.0;
+    const bool hist = av && c_hist > 0.0;          // history rows that are not all zero
+    const int64_t ny = av ? n + r : n;             // rows of the sample-side block
+    double* yh = h->y64 + n * r;                   // its history rows
+    if (av && g_ext) hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, h->eps, h->st);
+    // pass 1's history rows come from the Gram of V_in
+    if (hist) h->gram(V, m, r, false);
+
     const float* vcur = V;
     for (int p = 1; p <= q; ++p) {
       // sample side: Y = A V (FP64), then its QR: Q_Y = Y Tq (float)
       h->gemm_sample_side(O, ld_o, n, m, vcur, r);
-      h->cholqr<double, double>(h->y64, n, r, h->yq1, nullptr);
-      h->apply((const double*)h->y64, n, r, r, h->Tq, rp, r, h->qy, r, true);
-      // parameter side: Z = A^T Q_Y, then its QR: Q_Z = Z Tq, R_Z
+      if (av) {
+        hipLaunchKernelGGL(k_hist_rows, dim3(cdiv((int64_t)r * r, 256)), dim3(256), 0, stream, yh, r,
+                           (const double*)av->sig_state, (const double*)(p == 1 ? h->G : h->Hn), rp, c_hist, cst);
+        if (hist && p == 1 && q > 1)
+          (void)hipMemcpyAsync(h->y1, h->y64, sizeof(double) * ny * r, hipMemcpyDeviceToDevice, stream);
+      }
+      h->cholqr<double, double>(h->y64, ny, r, h->yq1, nullptr);
+      h->apply((const double*)h->y64, ny, r, r, h->Tq, rp, r, h->qy, r, true);
+      // parameter side: Z = A^T Q_Y (+ V_in B), then its QR: Q_Z = Z Tq, R_Z
       h->gemm_param_side(O, ld_o, n, m, h->qy, r, h->z);
+      if (hist) {
+        hipLaunchKernelGGL(k_hist_b, dim3(cdiv((int64_t)rp * rp, 256)), dim3(256), 0, stream,
+                           (const float*)(h->qy + n * r), r, (const double*)av->sig_state, c_hist, h->Bm, rp, cst);
+        h->apply((const float*)V, m, r, r, h->Bm, rp, r, h->z, r, false, false, true);
+      }
       h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
       if (p < q) {
+        if (av) {
+          // V_in^T V_{p+1} = (Y_1^T Q_Y) Tq for the next pass's history rows
+          if (hist) {
+            h->cross(h->y1, h->qy, ny, r, h->Hc);
+            h->smallgemm(h->Hc, h->Tq, rp, h->Hn, false, false);
+          }
+        }
         h->apply((const float*)h->z, m, r, r, h->Tq, rp, r, h->vw, r, true);
         vcur = h->vw;
       } else {
@@ -219,16 +271,43 @@ struct wssr_ctx {
     if (!g_ext) (void)hipStreamWaitEvent(stream, h->ev_join, 0);
     if (h->coop_err != hipSuccess)
       return h->fail(WSSR_ERR_HIP, "cooperative launch of the SVD kernel failed: %s", hipGetErrorString(h->coop_err));
+    // row chunks: as many as the partial buffers hold (enough blocks to cover
+    // every compute unit several times), at least 64 rows each
+    const int64_t rpc = std::max<int64_t>(64, cdiv(m, kVecChunkMax));
+    const int nch = (int)cdiv(m, rpc);
+    if (av) {
+      // averaged gradient (eq. barg): gbar = (1-avg) g + avg V_in (sig o l),
+      // read before V and the state are overwritten
+      const double a = av->avg;
+      double* gb = av->gbar_out ? av->gbar_out : h->gbar;
+      hipLaunchKernelGGL(k_gbar_w, dim3(cdiv(r, 256)), dim3(256), 0, stream, (const double*)av->sig_state,
+                         (const double*)av->l_state, r, -a / (1.0 - a), h->cw, cst);
+      hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, gv, (const double*)h->cw,
+                         m, r, 1.0 - a, gb, cst);
+      gv = gb;
+      // t = Q_Y^T Lhat (eq. Lhat in the block's row order)
+      const int64_t rpy = std::max<int64_t>(64, cdiv(ny, kVecChunkMax));
+      const int nchy = (int)cdiv(ny, rpy);
+      hipLaunchKernelGGL(k_lhat, dim3(cdiv(ny, 256)), dim3(256), 0, stream, (const double*)h->eps, n,
+                         (const double*)av->l_state, r, std::sqrt((1.0 - a) / (double)n), std::sqrt(a), h->lhat,
+                         cst);
+      hipLaunchKernelGGL(k_vtg_partial, dim3(nchy, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->qy,
+                         (const double*)h->lhat, ny, r, rpy, h->vpart, cst);
+      hipLaunchKernelGGL(k_colreduce, dim3(r), dim3(256), 0, stream, (const double*)h->vpart, nchy, r, 1.0, h->tvec,
+                         cst);
+    }
     // output signs, then V <- signed vw
     {
-      // row chunks: as many as the partial buffers hold (enough blocks to cover
-      // every compute unit several times), at least 64 rows each
-      const int64_t rpc = std::max<int64_t>(64, cdiv(m, kVecChunkMax));
-      const int nch = (int)cdiv(m, rpc);
       hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->vw,
                          (const float*)V, m, r, rpc, h->dots, h->maxval, h->maxrow, cst);
       hipLaunchKernelGGL(k_sign_final, dim3(r), dim3(256), 0, stream, (const double*)h->dots, (const float*)h->maxval,
                          (const int64_t*)h->maxrow, nch, r, h->sgn, cst);
+      if (av)
+        // new stored vector (eq. Lbar) with the output signs; singular values
+        // of the stacked matrix
+        hipLaunchKernelGGL(k_state_l, dim3(1), dim3(512), 0, stream, (const double*)h->Rz, (const double*)h->Ps, rp, r,
+                           (const double*)h->tvec, (const float*)h->sgn, h->sig, std::sqrt(1.0 - av->avg),
+                           av->l_state, cst);
       const int64_t tot = m * r;
       hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)h->vw,
                          (const float*)h->sgn, tot, r, V, cst);
@@ -707,10 +786,25 @@ struct wssr_ctx {
 
   template <typename Tin, typename Tout>
   void apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol, Tout* out, int ldo,
-             bool upper, bool gated = false) {
+             bool upper, bool gated = false, bool acc = false) {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
     hipLaunchKernelGGL((k_apply<Tin, Tout>), dim3(cdiv(rows, kF64Tile), cdiv(ncol, kF64Tile)), dim3(256), 0, stream,
-                       X, rows, ldx, kdim, Tm, rp, ncol, out, ldo, upper, vec, (const DevStatus*)st, gated);
+                       X, rows, ldx, kdim, Tm, rp, ncol, out, ldo, upper, vec, acc, (const DevStatus*)st, gated);
+  }
+
+  // H = X^T W (rp x rp, zero outside r x r) for two rows x r blocks
+  void cross(const double* X, const float* W, int64_t rows, int r, double* H) {
+    const int rp = (int)rup(r, 64), nt = (int)cdiv(r, kF64Tile), tiles = nt * nt;
+    const int64_t per = (int64_t)tiles * kF64Tile * kF64Tile;
+    const int64_t cap = std::max<int64_t>(1, gram_part_elems / per);
+    int nch = (int)std::max<int64_t>(1, std::min(std::min<int64_t>(cdiv(512, tiles), cdiv(rows, 256)), cap));
+    const int64_t rpc = std::max<int64_t>(16, rup(cdiv(rows, nch), 16));
+    nch = (int)std::max<int64_t>(1, cdiv(rows, rpc));
+    const bool vec = (r % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((uintptr_t)W % 16 == 0);
+    hipLaunchKernelGGL((k_cross_partial<double, float>), dim3(tiles, nch), dim3(256), 0, stream, X, W, rows, r, nt,
+                       rpc, gram_part, vec, (const DevStatus*)st);
+    hipLaunchKernelGGL(k_cross_reduce, dim3(tiles, kF64Tile * kF64Tile / 256), dim3(256), 0, stream,
+                       (const double*)gram_part, nch, nt, r, rp, H, (const DevStatus*)st);
   }
 
   // CholeskyQR of X (rows x r) with a second round when the first round's
@@ -849,13 +943,19 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
   h->rp_max = rp;
   h->rows_max = std::max(n, m);
   const int64_t rows = h->rows_max;
+  // Gram partials: the largest block is the parameter side (m rows) or the
+  // averaged step's sample side (n + r rows)
+  h->gram_part_elems =
+      (int64_t)wssr_ctx::gram_chunks(std::max(n + r, m), npairs) * npairs * kF64Tile * kF64Tile;
   bool ok = h->alloc(h->st, 1) && h->alloc(h->eps, n) && h->alloc(h->g, m) &&
             h->alloc(h->gpart, (size_t)kGSplitMax * m) && h->alloc(h->ypart, (size_t)kS1Max * n * r) &&
-            h->alloc(h->y64, (size_t)n * r) && h->alloc(h->yq1, (size_t)n * r) &&
-            h->alloc(h->colpart, (size_t)cdiv(n, 128) * r) && h->alloc(h->qy, (size_t)n * r) &&
+            h->alloc(h->y64, (size_t)(n + r) * r) && h->alloc(h->yq1, (size_t)(n + r) * r) &&
+            h->alloc(h->colpart, (size_t)cdiv(n, 128) * r) && h->alloc(h->qy, (size_t)(n + r) * r) &&
             h->alloc(h->z, (size_t)m * r) && h->alloc(h->q1, (size_t)rows * r) && h->alloc(h->vw, (size_t)m * r) &&
-            h->alloc(h->gram_part,
-                     (size_t)wssr_ctx::gram_chunks(std::max(n, m), npairs) * npairs * kF64Tile * kF64Tile) &&
+            h->alloc(h->gram_part, (size_t)h->gram_part_elems) &&
+            h->alloc(h->y1, (size_t)(n + r) * r) && h->alloc(h->Hc, (size_t)rp * rp) &&
+            h->alloc(h->Hn, (size_t)rp * rp) && h->alloc(h->Bm, (size_t)rp * rp) && h->alloc(h->gbar, m) &&
+            h->alloc(h->lhat, (size_t)(n + r)) && h->alloc(h->tvec, rp) &&
             h->alloc(h->G, (size_t)rp * rp) &&
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
             h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
@@ -1059,6 +1159,19 @@ wssr_status wssr_step_g(wssr_handle h, int64_t n, int64_t m, const void* O, int6
   if (s != WSSR_OK) return s;
   if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
   return h->enqueue(n, m, O, ld_o, nullptr, V, lambda, r, q, delta, sigma, g);
+}
+
+wssr_status wssr_step_avg(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                          const double* g, float* V, double lambda, int32_t r, int32_t q, double avg,
+                          double* sig_state, double* l_state, double* delta, double* g_bar) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  wssr_status s = check_step(h, n, m, O, ld_o, e_l, V, lambda, r, q, delta, sig_state);
+  if (s != WSSR_OK) return s;
+  if (!l_state) return h->fail(WSSR_ERR_INVALID_ARG, "l_state is NULL");
+  if (!(avg >= 0.0 && avg < 1.0)) return h->fail(WSSR_ERR_INVALID_ARG, "avg must be in [0, 1)");
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+  wssr_ctx::AvgArgs av{avg, sig_state, l_state, g_bar};
+  return h->enqueue(n, m, O, ld_o, e_l, V, lambda, r, q, delta, sig_state, g, &av);
 }
 
 wssr_status wssr_ingest(wssr_handle h, int64_t n, int64_t m, int64_t row0, int64_t rows, const float* O32,

@@ -66,6 +66,7 @@ _SIGS = {
     "wssr_destroy": ([_P], ctypes.c_int),
     "wssr_step": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
     "wssr_step_g": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
+    "wssr_step_avg": ([_P, _I64, _I64, _P, _I64, _P, _P, _P, _D, _I32, _I32, _D, _P, _P, _P, _P], ctypes.c_int),
     "wssr_ingest": ([_P, _I64, _I64, _I64, _I64, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
     "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
@@ -225,6 +226,34 @@ class Wssr:
             self._check(lib().wssr_step_g(self._h, n, m, _ptr(O), ld, _ptr(g), _ptr(V), float(lam), r, int(q),
                                           _ptr(delta), _ptr(sigma)))
         return delta, sigma
+
+    def step_avg(self, O, e_l, V, lam, avg, sig_state, l_state, q=2, delta=None, g=None, g_bar=None):
+        """One WSSR step with the averaged state (wssr_step_avg).  V (m x r,
+        float32), sig_state and l_state (float64 [r]) are updated in place:
+        the state in is V diag(sig_state) and l_state of the previous step
+        (zeros for the first), out the new one.  g: a gradient from ingest
+        (optional); g_bar: where to write the averaged gradient (optional).
+        Returns delta."""
+        n, m, ld = self._o(O)
+        if V.dim() != 2 or not V.is_contiguous():
+            raise ValueError("V must be a contiguous m x r tensor")
+        r = V.shape[1]
+        _need(V, "V", torch.float32, self.device, (m, r))
+        _need(e_l, "e_l", torch.float64, self.device, (n,), contiguous=True)
+        _need(sig_state, "sig_state", torch.float64, self.device, (r,), contiguous=True)
+        _need(l_state, "l_state", torch.float64, self.device, (r,), contiguous=True)
+        if g is not None:
+            _need(g, "g", torch.float64, self.device, (m,), contiguous=True)
+        if g_bar is not None:
+            _need(g_bar, "g_bar", torch.float64, self.device, (m,), contiguous=True)
+        if delta is None:
+            delta = torch.empty(m, dtype=torch.float64, device=self.device)
+        _need(delta, "delta", torch.float64, self.device, (m,), contiguous=True)
+        nul = ctypes.c_void_p(None)
+        self._check(lib().wssr_step_avg(self._h, n, m, _ptr(O), ld, _ptr(e_l), _ptr(g) if g is not None else nul,
+                                        _ptr(V), float(lam), r, int(q), float(avg), _ptr(sig_state),
+                                        _ptr(l_state), _ptr(delta), _ptr(g_bar) if g_bar is not None else nul))
+        return delta
 
     def storage_like(self, n, m):
         """An empty O buffer in this handle's storage form: (n, m) float32 or

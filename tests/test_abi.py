@@ -57,5 +57,7 @@ def test_null_handle_calls_are_rejected():
     lib = wssr.lib()
     assert lib.wssr_destroy(None) == wssr.ERR_INVALID_ARG
     assert lib.wssr_step(None, 10, 10, None, 10, None, None, 1.0, 1, 1, None, None) == wssr.ERR_INVALID_ARG
+    assert lib.wssr_step_avg(None, 10, 10, None, 10, None, None, None, 1.0, 1, 1, 0.5, None, None, None,
+                             None) == wssr.ERR_INVALID_ARG
     code = ctypes.c_int32()
     assert lib.wssr_status_sync(None, ctypes.byref(code), None) == wssr.ERR_INVALID_ARG
