@@ -36,7 +36,11 @@ design notes):
     initial state is zero as the paper sets it, so the first step's Sbar is
     (1 - avg) S_N rather than the S_N that the plain averaging scheme (eq.
     ave_s) starts from; the sample-side singular factor V of eq. svd:det is the
-    last pass's Q_Y G, signed like its parameter-side partner.
+    last pass's Q_Y G, signed like its parameter-side partner;
+  * randomized sketch (App. A): the random block multiplies the sample side, so
+    it is N x (r + p) (the paper prints the parameter count as its row count),
+    and it is an input; the rank-r result has no warm start to sign against,
+    so each column's entry of largest magnitude is made positive.
 """
 from __future__ import annotations
 
@@ -389,6 +393,50 @@ def averaged_step(o, e_l, v_in, state, lam, r, q, avg, precond="damped"):
     delta = woodbury_apply(v, sigma, gbar, lam, precond)
     g = a.T @ lbar
     return dict(delta=delta, v=v, sigma=sigma, l=l_new, gbar=gbar, g=g, eps=eps, last=last)
+
+
+def randomized_svd(a, omega, r):
+    """Rank-r SVD of A by randomized sketching (App. A, eq. randsvd).
+
+    In the paper's orientation the matrix is A^T (parameters x samples) and the
+    sketch multiplies it by a random sample-side block: Y = A^T Omega (M x
+    (r+p)), Q = orth(Y), B = Q^T A^T ((r+p) x N), B = U_B Sigma V_B, and the
+    parameter-side factor is Q U_B.  Omega is N x (r+p), drawn by the caller
+    (the paper prints it with the parameter count as its row count; the product
+    needs the sample count).  The SVD of B is taken from its transpose A Q
+    (N x (r+p)), whose right singular vectors are the left ones of B.
+    Returns V (M x r), sigma (r,)."""
+    omega = np.asarray(omega, dtype=np.float64)
+    q = qr_positive(a.T @ omega)[0]
+    _u, s, p = jacobi_svd(a @ q)
+    return q @ p[:, :r], s[:r].copy()
+
+
+def sketch_step(o, e_l, omega, lam, r, precond="damped"):
+    """One SR step whose rank-r SVD comes from the randomized sketch (the RSSR
+    variant of the remark on randomized sketching in Sec. 4.1; App. A): no
+    warm start, the oversampling p = omega's column count minus r.  Signs:
+    no reference basis, so the entry of largest magnitude of each column is
+    positive (the tie rule of the plain step).
+    Returns dict(delta, v, sigma, g, eps)."""
+    o = np.asarray(o, dtype=np.float64)
+    n, m = o.shape
+    omega = np.asarray(omega, dtype=np.float64)
+    if omega.shape[0] != n or omega.shape[1] < r:
+        raise ValueError("omega must be N x (r + p), p >= 0")
+    if not (1 <= omega.shape[1] <= min(n - 1, m)) or r < 1:
+        raise ValueError("rank out of range")
+    if not lam > 0:
+        raise ValueError("bad lambda")
+    if not (np.isfinite(o).all() and np.isfinite(e_l).all() and np.isfinite(omega).all()):
+        raise FloatingPointError("non-finite input")
+    eps = center_energies(e_l)
+    a = scaled_centered(o)
+    g = a.T @ eps / np.sqrt(n)
+    v, sigma = randomized_svd(a, omega, r)
+    v = fix_signs(v, np.zeros((m, 0)))
+    delta = woodbury_apply(v, sigma, g, lam, precond)
+    return dict(delta=delta, v=v, sigma=sigma, g=g, eps=eps)
 
 
 # ----------------------------------------------------------------------------

@@ -543,3 +543,96 @@ def test_averaged_planted_mistakes_are_caught(monkeypatch):
         monkeypatch.setattr(orc, name, fn)
         assert not pins_pass(), (name, fn.__name__)
         monkeypatch.undo()
+
+
+# --------------------------------------------------------------- randomized sketch (App. A)
+
+def _sketch_problem(n, m, rank, seed, noise=0.0):
+    rng = rng0(seed)
+    u = np.linalg.qr(rng.standard_normal((n, rank)))[0]
+    w = np.linalg.qr(rng.standard_normal((m, rank)))[0]
+    s = np.geomspace(1.0, 0.05, rank)
+    o = np.sqrt(n) * (u * s) @ w.T + noise * rng.standard_normal((n, m)) + rng.standard_normal(m)[None, :]
+    return o, -1.0 + 0.1 * rng.standard_normal(n)
+
+
+def test_sketch_exact_when_the_rank_fits():
+    """A of rank at most r + p: Q spans its row space, so the rank-r result
+    is the exact truncated SVD (LAPACK) and delta the exact-subspace Woodbury
+    (against a dense solve with the rank-r S)."""
+    n, m, rank, r, p = 40, 70, 9, 6, 4
+    o, e = _sketch_problem(n, m, rank, 11)
+    omega = rng0(12).standard_normal((n, r + p))
+    res = orc.sketch_step(o, e, omega, 1e-2, r)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    _, s_ref, wt = np.linalg.svd(a)
+    assert _rel(res["sigma"], s_ref[:r]) < 1e-12
+    assert orc.subspace_distance(res["v"], wt[:r].T) < 1e-7
+    s_r = (wt[:r].T * s_ref[:r] ** 2) @ wt[:r]
+    g = a.T @ (e - e.mean()) / np.sqrt(n)
+    assert _rel(res["delta"], np.linalg.solve(s_r + 1e-2 * np.eye(m), g)) < 1e-10
+
+
+def test_sketch_within_the_randomized_bound():
+    """Halko, Martinsson and Tropp's bounds (the source App. A follows): for a
+    Gaussian Omega with p >= 2, the sketch's span satisfies ||A (I - Q Q^T)||
+    <= (1 + 9 sqrt(r + p) sqrt(min(N, M))) sigma_{r+1} except with probability
+    at most 6 p^-p (p = 8 here), and truncating to rank r adds at most
+    sigma_{r+1}.  Checked on the oracle's rank-r V: ||A - A V V^T||_2 within
+    the sum, against LAPACK's singular values."""
+    n, m, r, p = 60, 120, 5, 8
+    o, e = _sketch_problem(n, m, 30, 21, noise=1e-3)
+    omega = rng0(22).standard_normal((n, r + p))
+    res = orc.sketch_step(o, e, omega, 1e-2, r)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    s_ref = np.linalg.svd(a, compute_uv=False)
+    v = res["v"]
+    resid = np.linalg.norm(a - (a @ v) @ v.T, 2)
+    assert resid <= (2 + 9 * np.sqrt(r + p) * np.sqrt(min(n, m))) * s_ref[r]
+    assert resid >= s_ref[r] * (1 - 1e-12)          # no rank-r approximation does better
+    # sigma are the singular values of A V, which never exceed the exact ones
+    assert _rel(res["sigma"], np.linalg.svd(a @ v, compute_uv=False)) < 1e-12
+    assert np.all(res["sigma"] <= s_ref[:r] * (1 + 1e-12))
+    # output signs: the entry of largest magnitude of each column is positive
+    k = np.argmax(np.abs(v), axis=0)
+    assert np.all(v[k, np.arange(r)] > 0)
+
+
+def test_sketch_rejects_bad_arguments():
+    o, e = _sketch_problem(10, 20, 5, 31)
+    with pytest.raises(ValueError):
+        orc.sketch_step(o, e, np.ones((9, 6)), 0.1, 4)          # wrong row count
+    with pytest.raises(ValueError):
+        orc.sketch_step(o, e, np.ones((10, 3)), 0.1, 4)         # fewer columns than r
+    with pytest.raises(ValueError):
+        orc.sketch_step(o, e, np.ones((10, 10)), 0.1, 4)        # r + p > N - 1
+
+
+def test_sketch_planted_mistakes_are_caught(monkeypatch):
+    """Dropping Q from the parameter-side factor, or taking the singular
+    vectors from the wrong side of A Q, fails the exactness pin."""
+    def pin_passes():
+        try:
+            test_sketch_exact_when_the_rank_fits()
+        except (AssertionError, ValueError):
+            return False
+        return True
+
+    assert pin_passes()
+    real_svd = orc.jacobi_svd
+
+    def left_side(c, *a, **k):
+        u, s, p = real_svd(c, *a, **k)
+        return u, s, u[: p.shape[0], : p.shape[1]]
+
+    def no_q(a, omega, r):
+        q = orc.qr_positive(a.T @ np.asarray(omega, float))[0]
+        _u, s, p = real_svd(a @ q)
+        return np.vstack([p[:, :r], np.zeros((a.shape[1] - p.shape[0], r))]), s[:r].copy()
+
+    monkeypatch.setattr(orc, "jacobi_svd", left_side)
+    assert not pin_passes()
+    monkeypatch.undo()
+    monkeypatch.setattr(orc, "randomized_svd", no_q)
+    assert not pin_passes()
+    monkeypatch.undo()
