@@ -412,12 +412,15 @@ def randomized_svd(a, omega, r):
     return q @ p[:, :r], s[:r].copy()
 
 
-def sketch_step(o, e_l, omega, lam, r, precond="damped"):
+def sketch_step(o, e_l, omega, lam, r, q=0, precond="damped"):
     """One SR step whose rank-r SVD comes from the randomized sketch (the RSSR
     variant of the remark on randomized sketching in Sec. 4.1; App. A): no
-    warm start, the oversampling p = omega's column count minus r.  Signs:
-    no reference basis, so the entry of largest magnitude of each column is
-    positive (the tie rule of the plain step).
+    warm start, the oversampling p = omega's column count minus r.  q > 0:
+    the power scheme of the same randomized range finder (Halko et al.), that
+    is q passes of the subspace iteration at rank r + p started from
+    orth(A^T Omega), then truncation to r.  Signs: no reference basis, so the
+    entry of largest magnitude of each column is positive (the tie rule of the
+    plain step).
     Returns dict(delta, v, sigma, g, eps)."""
     o = np.asarray(o, dtype=np.float64)
     n, m = o.shape
@@ -426,14 +429,19 @@ def sketch_step(o, e_l, omega, lam, r, precond="damped"):
         raise ValueError("omega must be N x (r + p), p >= 0")
     if not (1 <= omega.shape[1] <= min(n - 1, m)) or r < 1:
         raise ValueError("rank out of range")
-    if not lam > 0:
-        raise ValueError("bad lambda")
+    if not lam > 0 or q < 0:
+        raise ValueError("bad lambda or q")
     if not (np.isfinite(o).all() and np.isfinite(e_l).all() and np.isfinite(omega).all()):
         raise FloatingPointError("non-finite input")
     eps = center_energies(e_l)
     a = scaled_centered(o)
     g = a.T @ eps / np.sqrt(n)
-    v, sigma = randomized_svd(a, omega, r)
+    if q == 0:
+        v, sigma = randomized_svd(a, omega, r)
+    else:
+        v0 = qr_positive(a.T @ omega)[0]
+        v, sigma, _last = ssi_svd(a, v0, q)
+        v, sigma = v[:, :r], sigma[:r].copy()
     v = fix_signs(v, np.zeros((m, 0)))
     delta = woodbury_apply(v, sigma, g, lam, precond)
     return dict(delta=delta, v=v, sigma=sigma, g=g, eps=eps)

@@ -556,14 +556,15 @@ def _sketch_problem(n, m, rank, seed, noise=0.0):
     return o, -1.0 + 0.1 * rng.standard_normal(n)
 
 
-def test_sketch_exact_when_the_rank_fits():
+@pytest.mark.parametrize("q", [0, 1])
+def test_sketch_exact_when_the_rank_fits(q):
     """A of rank at most r + p: Q spans its row space, so the rank-r result
     is the exact truncated SVD (LAPACK) and delta the exact-subspace Woodbury
-    (against a dense solve with the rank-r S)."""
+    (against a dense solve with the rank-r S), with or without power passes."""
     n, m, rank, r, p = 40, 70, 9, 6, 4
     o, e = _sketch_problem(n, m, rank, 11)
     omega = rng0(12).standard_normal((n, r + p))
-    res = orc.sketch_step(o, e, omega, 1e-2, r)
+    res = orc.sketch_step(o, e, omega, 1e-2, r, q=q)
     a = (o - o.mean(axis=0)) / np.sqrt(n)
     _, s_ref, wt = np.linalg.svd(a)
     assert _rel(res["sigma"], s_ref[:r]) < 1e-12
@@ -598,6 +599,26 @@ def test_sketch_within_the_randomized_bound():
     assert np.all(v[k, np.arange(r)] > 0)
 
 
+def test_sketch_power_passes_converge():
+    """The power scheme tightens the randomized bound to the 1/(2q+1) power of
+    its factor (Halko et al.): with q = 20 at this decaying spectrum the
+    rank-r result is the exact truncated SVD (LAPACK), and no power pass
+    increases ||A - A V V^T||."""
+    n, m, r, p = 60, 120, 5, 5
+    o, e = _sketch_problem(n, m, 30, 41, noise=1e-3)
+    omega = rng0(42).standard_normal((n, r + p))
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    _, s_ref, wt = np.linalg.svd(a)
+    prev = np.inf
+    for q in range(0, 21):
+        res = orc.sketch_step(o, e, omega, 1e-2, r, q=q)
+        resid = np.linalg.norm(a - (a @ res["v"]) @ res["v"].T, 2)
+        assert resid <= prev * (1 + 1e-12)
+        prev = resid
+    assert _rel(res["sigma"], s_ref[:r]) < 1e-10
+    assert orc.subspace_distance(res["v"], wt[:r].T) < 1e-7
+
+
 def test_sketch_rejects_bad_arguments():
     o, e = _sketch_problem(10, 20, 5, 31)
     with pytest.raises(ValueError):
@@ -613,7 +634,7 @@ def test_sketch_planted_mistakes_are_caught(monkeypatch):
     vectors from the wrong side of A Q, fails the exactness pin."""
     def pin_passes():
         try:
-            test_sketch_exact_when_the_rank_fits()
+            test_sketch_exact_when_the_rank_fits(0)
         except (AssertionError, ValueError):
             return False
         return True
