@@ -195,6 +195,31 @@ wssr_status wssr_step_avg(wssr_handle h, int64_t n, int64_t m, const void* O, in
                           const double* g, float* V, double lambda, int32_t r, int32_t q, double avg,
                           double* sig_state, double* l_state, double* delta, double* g_bar);
 
+/* One SR step whose rank-r SVD comes from a randomized sketch (App. A, eq.
+ * randsvd; the RSSR variant of the remark on randomized sketching in Sec.
+ * 4.1), for a cold start or in place of the warm-started iteration: with the
+ * random sample-side block Omega (n x (r + p)), Q = orth(A^T Omega) (the
+ * paper's Y = Ohat Omega), the SVD of B = Q^T A^T (through A Q = Q_W R_W and
+ * the SVD of R_W), V = Q U_B truncated to r columns, and the Woodbury
+ * direction as in wssr_step.  Two products over O at rank r + p.  With q > 0
+ * the power scheme of the same randomized range finder: q passes of the
+ * subspace iteration at rank r + p start from Q and end in the Rayleigh-Ritz
+ * step of wssr_step (1 + 2q products); that makes the result far less
+ * sensitive to perturbations of O such as BF16 storage.
+ *   e_l, g     as in wssr_step / wssr_step_g: g (device, double[m]) may be
+ *              NULL, then e_l is read and g formed; e_l may be NULL when g is given
+ *   omega      device, float[n x (r + p)] row-major: the random block (e.g.
+ *              Gaussian), read only; its column means are removed before use,
+ *              which leaves A^T Omega unchanged
+ *   p          oversampling, p >= 0, with r + p <= min(n - 1, m, r_max)
+ *   q          power passes, 0 <= q <= q_max (0: the scheme of App. A as printed)
+ *   V          device, float[m x r], out only (no warm start).  Column signs:
+ *              the entry of largest magnitude (lowest row on ties) is positive.
+ *   delta, sigma as in wssr_step (sigma: the r largest of the sketch). */
+wssr_status wssr_step_sketch(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                             const double* g, const float* omega, int32_t p, int32_t q, float* V, double lambda,
+                             int32_t r, double* delta, double* sigma);
+
 /* Ingest of O: one pass over a block of rows of the unrounded FP32 matrix
  * that writes them in the handle's storage form and forms, from the unrounded
  * values, the gradient g = O_bar^T eps / n (Sec. 4.1 eq. barg; eps = E_L -

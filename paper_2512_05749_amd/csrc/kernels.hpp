@@ -168,6 +168,7 @@ __global__ void k_lhat(const double* eps, int64_t n, const double* l, int r, dou
                        double* lhat, const DevStatus* st);
 __global__ void k_state_l(const double* Rz, const double* Ps, int rp, int r, const double* t, const float* sgn,
                           double* sig, double wscale, double* l_out, const DevStatus* st);
+__global__ void k_transpose_rp(const double* R, int rp, int r, double* Ct, const DevStatus* st);
 
 // dynamic LDS sizes (bytes)
 constexpr size_t kCholLds = 4 * 64 * 65 * sizeof(double);

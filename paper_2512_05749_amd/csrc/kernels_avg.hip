@@ -1,7 +1,8 @@
 // Small kernels of the averaged-state step (Sec. 4.1, eqs. Ohat, Lhat, Obar,
-// Lbar, barg).  The stored matrix of the previous step, U diag(sigma), enters
-// the subspace iteration as r extra rows of the sample-side block; these
-// kernels build those rows and the r x r factors that carry them through the
+// Lbar, barg) and of the randomized-sketch step (App. A).  In the averaged
+// step the stored matrix of the previous step, U diag(sigma), enters the
+// subspace iteration as r extra rows of the sample-side block; these kernels
+// build those rows and the r x r factors that carry them through the
 // parameter-side product, the averaged gradient, and the new stored vector.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -81,6 +82,17 @@ __global__ __launch_bounds__(512) void k_state_l(const double* __restrict__ Rz, 
     l_out[j] = s > 0.0 ? (double)sgn[j] * a / s : 0.0;
     sig[j] = wscale * s;
   }
+}
+
+// Ct = R^T restricted to r x r (zero elsewhere in rp x rp); R is rp x rp
+// row-major.
+__global__ __launch_bounds__(256) void k_transpose_rp(const double* __restrict__ R, int rp, int r,
+                                                      double* __restrict__ Ct, const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rp * rp) return;
+  const int i = (int)(e / rp), j = (int)(e % rp);
+  Ct[e] = (i < r && j < r) ? R[(int64_t)j * rp + i] : 0.0;
 }
 
 }  // namespace wssr

@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_sign_partial(const float* __restrict__ 
   int64_t bestrow = -1;
   for (int64_t i = i0; i < i1; ++i) {
     const float a = vnew[i * r + j];
-    d += (double)a * (double)vin[i * r + j];
+    if (vin) d += (double)a * (double)vin[i * r + j];
     if (fabsf(a) > best) {
       best = fabsf(a);
       bestv = a;

@@ -204,15 +204,25 @@ struct wssr_ctx {
   //  * the parameter-side product gains V_in B, B = c diag(sig) Q_Y[n:n+r];
   //  * the Rayleigh-Ritz step is unchanged (C = R_Z^T), and the singular
   //    values are scaled back by sqrt(1 - avg) at the end.
+  // Continuation of another step's work (the sketch's power passes): the
+  // passes start from vstart (m x r) instead of V, keep the status word, sign
+  // by the largest entry instead of against V, and return the first r_out
+  // columns.
+  struct Cont {
+    const float* vstart;
+    int r_out;
+  };
+
   wssr_status enqueue(int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, float* V,
                       double lambda, int32_t r, int32_t q, double* delta, double* sigma,
-                      const double* g_ext = nullptr, const AvgArgs* av = nullptr) {
+                      const double* g_ext = nullptr, const AvgArgs* av = nullptr, const Cont* cont = nullptr) {
     wssr_ctx* h = this;
     const double* gv = g_ext ? g_ext : h->g;
     const int rp = (int)rup(r, 64);
+    const int r_out = cont ? cont->r_out : r;
     const DevStatus* cst = h->st;
     hipStream_t stream = h->stream;
-    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
+    if (!cont) hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
 
     const double c_hist = av ? std::sqrt(av->avg / (1.0 - av->avg)) : 0.0;
     const bool hist = av && c_hist > 0.0;          // history rows that are not all zero
@@ -222,7 +232,7 @@ struct wssr_ctx {
     // pass 1's history rows come from the Gram of V_in
     if (hist) h->gram(V, m, r, false);
 
-    const float* vcur = V;
+    const float* vcur = cont ? cont->vstart : V;
     for (int p = 1; p <= q; ++p) {
       // sample side: Y = A V (FP64), then its QR: Q_Y = Y Tq (float)
       h->gemm_sample_side(O, ld_o, n, m, vcur, r);
@@ -265,10 +275,75 @@ struct wssr_ctx {
         h->small_svd(h->Rz, r);
         // V = Q_Z P = Z (Tq P)
         h->smallgemm(h->Tq, h->Ps, rp, h->T, false, false);
-        h->apply((const float*)h->z, m, r, r, h->T, rp, r, h->vw, r, false);
+        h->apply((const float*)h->z, m, r, r, h->T, rp, r_out, h->vw, r_out, false);
       }
     }
     if (!g_ext) (void)hipStreamWaitEvent(stream, h->ev_join, 0);
+    return finish(n, m, h->vw, V, cont ? nullptr : V, r_out, lambda, delta, sigma, gv, av, ny);
+  }
+
+  // Randomized-sketch step (App. A, eq. randsvd): the rank-rs sketch of A
+  // from the random sample-side block omega (n x rs, row stride rs),
+  // truncated to rank r; no warm start.  In this orientation the paper's
+  // Y = Ohat Omega is Z = A^T Omega, its B = Q^T Ohat is the transpose of
+  // W = A Q, and the SVD of B comes from W = Q_W R_W and the SVD of R_W.
+  // With q > 0, q passes of the subspace iteration at rank rs follow from Q
+  // (the power scheme of the randomized range finder) and end in the usual
+  // Rayleigh-Ritz step.
+  wssr_status enqueue_sketch(int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                             const float* omega, int rs, int32_t q, float* V, double lambda, int32_t r,
+                             double* delta, double* sigma, const double* g_ext) {
+    wssr_ctx* h = this;
+    const double* gv = g_ext ? g_ext : h->g;
+    const int rps = (int)rup(rs, 64);
+    const DevStatus* cst = h->st;
+    hipStream_t stream = h->stream;
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
+    // Q_Omega: omega less its column means (A^T Omega does not change, since
+    // the columns of A sum to zero; the parameter-side product needs 1^T X = 0)
+    const int64_t tot = n * rs;
+    hipLaunchKernelGGL(k_ysum, dim3(cdiv(tot, 256)), dim3(256), 0, stream, omega, 1, tot, h->y64, cst);
+    h->center_y(n, rs, 1.0);
+    h->cholqr<double, double>(h->y64, n, rs, h->yq1, nullptr);
+    h->apply((const double*)h->y64, n, rs, rs, h->Tq, rps, rs, h->qy, rs, true);
+    // Z = A^T Q_Omega and its orthonormal basis Q (into vw)
+    h->gemm_param_side(O, ld_o, n, m, h->qy, rs, h->z);
+    h->cholqr<float, float>(h->z, m, rs, h->q1, nullptr);
+    h->apply((const float*)h->z, m, rs, rs, h->Tq, rps, rs, h->vw, rs, true);
+    if (q > 0) {
+      Cont cont{h->vw, r};
+      return enqueue(n, m, O, ld_o, e_l, V, lambda, rs, q, delta, sigma, g_ext, nullptr, &cont);
+    }
+    // W = A Q, W = Q_W R_W
+    h->gemm_sample_side(O, ld_o, n, m, h->vw, rs);
+    if (!g_ext) {
+      (void)hipEventRecord(h->ev_fork, stream);
+      (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+      h->gradient(O, ld_o, n, m, e_l, h->g, h->side, true);
+      (void)hipEventRecord(h->ev_join, h->side);
+    }
+    h->cholqr<double, double>(h->y64, n, rs, h->yq1, h->Rz);
+    // right singular vectors of R_W (the small SVD takes the transpose)
+    hipLaunchKernelGGL(k_transpose_rp, dim3(cdiv((int64_t)rps * rps, 256)), dim3(256), 0, stream,
+                       (const double*)h->Rz, rps, rs, h->Hc, cst);
+    h->small_svd(h->Hc, rs);
+    // V = Q P, its first r columns (into z)
+    h->apply((const float*)h->vw, m, rs, rs, h->Ps, rps, r, h->z, r, false);
+    if (!g_ext) (void)hipStreamWaitEvent(stream, h->ev_join, 0);
+    return finish(n, m, h->z, V, nullptr, r, lambda, delta, sigma, gv, nullptr, n);
+  }
+
+  // The end of a step, once vnew holds the new basis (unsigned, m x r), sig
+  // the sorted singular values and, for the averaged step, Rz and Ps the last
+  // pass's factors: output signs (against vref, or by the largest entry when
+  // vref is NULL), the averaged state, and the Woodbury direction into V and
+  // delta.
+  wssr_status finish(int64_t n, int64_t m, const float* vnew, float* V, const float* vref, int32_t r, double lambda,
+                     double* delta, double* sigma, const double* gv, const AvgArgs* av, int64_t ny) {
+    wssr_ctx* h = this;
+    const int rp = (int)rup(r, 64);
+    const DevStatus* cst = h->st;
+    hipStream_t stream = h->stream;
     if (h->coop_err != hipSuccess)
       return h->fail(WSSR_ERR_HIP, "cooperative launch of the SVD kernel failed: %s", hipGetErrorString(h->coop_err));
     // row chunks: as many as the partial buffers hold (enough blocks to cover
@@ -298,8 +373,8 @@ struct wssr_ctx {
     }
     // output signs, then V <- signed vw
     {
-      hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)h->vw,
-                         (const float*)V, m, r, rpc, h->dots, h->maxval, h->maxrow, cst);
+      hipLaunchKernelGGL(k_sign_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, vnew, vref, m, r, rpc,
+                         h->dots, h->maxval, h->maxrow, cst);
       hipLaunchKernelGGL(k_sign_final, dim3(r), dim3(256), 0, stream, (const double*)h->dots, (const float*)h->maxval,
                          (const int64_t*)h->maxrow, nch, r, h->sgn, cst);
       if (av)
@@ -309,8 +384,8 @@ struct wssr_ctx {
                            (const double*)h->tvec, (const float*)h->sgn, h->sig, std::sqrt(1.0 - av->avg),
                            av->l_state, cst);
       const int64_t tot = m * r;
-      hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)h->vw,
-                         (const float*)h->sgn, tot, r, V, cst);
+      hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, vnew, (const float*)h->sgn, tot, r,
+                         V, cst);
       // Woodbury
       hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
                          gv, m, r, rpc, h->vpart, cst);
@@ -419,13 +494,19 @@ struct wssr_ctx {
     const int64_t tot = n * r;
     hipLaunchKernelGGL(k_ysum, dim3(cdiv(tot, 256)), dim3(256), 0, stream, (const float*)ypart, s1, tot, y64,
                        (const DevStatus*)st);
+    center_y(n, r, 1.0 / std::sqrt((double)n));
+  }
+
+  // y64 (n x r) <- (y64 - column means) * scale
+  void center_y(int64_t n, int r, double scale) {
+    const int64_t tot = n * r;
     const int rows = 128, nrb = (int)cdiv(n, rows);
     hipLaunchKernelGGL(k_colsum_partial, dim3(nrb, cdiv(r, 256)), dim3(256), 0, stream, (const double*)y64, n, r,
                        rows, colpart, (const DevStatus*)st);
     hipLaunchKernelGGL(k_colreduce, dim3(r), dim3(256), 0, stream, (const double*)colpart, nrb, r, 1.0 / (double)n,
                        ymean, (const DevStatus*)st);
     hipLaunchKernelGGL(k_ycenter, dim3(cdiv(tot, 256)), dim3(256), 0, stream, y64, (const double*)ymean, tot, r,
-                       1.0 / std::sqrt((double)n), (const DevStatus*)st);
+                       scale, (const DevStatus*)st);
   }
 
   void gemm_sample_side(const void* Ov, int64_t ld, int64_t n, int64_t m, const float* V, int r) {
@@ -1172,6 +1253,22 @@ wssr_status wssr_step_avg(wssr_handle h, int64_t n, int64_t m, const void* O, in
   if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
   wssr_ctx::AvgArgs av{avg, sig_state, l_state, g_bar};
   return h->enqueue(n, m, O, ld_o, e_l, V, lambda, r, q, delta, sig_state, g, &av);
+}
+
+wssr_status wssr_step_sketch(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                             const double* g, const float* omega, int32_t p, int32_t q, float* V, double lambda,
+                             int32_t r, double* delta, double* sigma) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!e_l && !g) return h->fail(WSSR_ERR_INVALID_ARG, "e_l and g are both NULL");
+  if (!omega) return h->fail(WSSR_ERR_INVALID_ARG, "omega is NULL");
+  if (p < 0) return h->fail(WSSR_ERR_INVALID_ARG, "p < 0");
+  if (r < 1) return h->fail(WSSR_ERR_INVALID_ARG, "r < 1");
+  if (q < 0 || q > h->cfg.q_max) return h->fail(WSSR_ERR_INVALID_ARG, "q=%d outside [0, q_max]", q);
+  // the sketch's rank r + p takes the place of r in the common checks
+  wssr_status s = check_step(h, n, m, O, ld_o, e_l ? e_l : g, V, lambda, r + p, 1, delta, sigma);
+  if (s != WSSR_OK) return s;
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+  return h->enqueue_sketch(n, m, O, ld_o, e_l, omega, r + p, q, V, lambda, r, delta, sigma, g);
 }
 
 wssr_status wssr_ingest(wssr_handle h, int64_t n, int64_t m, int64_t row0, int64_t rows, const float* O32,

@@ -67,6 +67,7 @@ _SIGS = {
     "wssr_step": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
     "wssr_step_g": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
     "wssr_step_avg": ([_P, _I64, _I64, _P, _I64, _P, _P, _P, _D, _I32, _I32, _D, _P, _P, _P, _P], ctypes.c_int),
+    "wssr_step_sketch": ([_P, _I64, _I64, _P, _I64, _P, _P, _P, _I32, _I32, _P, _D, _I32, _P, _P], ctypes.c_int),
     "wssr_ingest": ([_P, _I64, _I64, _I64, _I64, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
     "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
@@ -254,6 +255,36 @@ class Wssr:
                                         _ptr(V), float(lam), r, int(q), float(avg), _ptr(sig_state),
                                         _ptr(l_state), _ptr(delta), _ptr(g_bar) if g_bar is not None else nul))
         return delta
+
+    def step_sketch(self, O, e_l, omega, V, lam, q=0, delta=None, sigma=None, g=None):
+        """SR step with the rank-r SVD from a randomized sketch (wssr_step_sketch):
+        omega (float32, n x (r + p), contiguous) is the random sample-side block,
+        q the power passes, V (m x r, float32) is written.  Returns (delta, sigma)."""
+        n, m, ld = self._o(O)
+        if V.dim() != 2 or not V.is_contiguous():
+            raise ValueError("V must be a contiguous m x r tensor")
+        r = V.shape[1]
+        _need(V, "V", torch.float32, self.device, (m, r))
+        if omega.dim() != 2 or omega.shape[0] != n or omega.shape[1] < r:
+            raise ValueError("omega must be n x (r + p)")
+        _need(omega, "omega", torch.float32, self.device, contiguous=True)
+        p = omega.shape[1] - r
+        if g is None:
+            _need(e_l, "e_l", torch.float64, self.device, (n,), contiguous=True)
+        else:
+            _need(g, "g", torch.float64, self.device, (m,), contiguous=True)
+        if delta is None:
+            delta = torch.empty(m, dtype=torch.float64, device=self.device)
+        if sigma is None:
+            sigma = torch.empty(r, dtype=torch.float64, device=self.device)
+        _need(delta, "delta", torch.float64, self.device, (m,), contiguous=True)
+        _need(sigma, "sigma", torch.float64, self.device, (r,), contiguous=True)
+        nul = ctypes.c_void_p(None)
+        self._check(lib().wssr_step_sketch(self._h, n, m, _ptr(O), ld, _ptr(e_l) if e_l is not None else nul,
+                                           _ptr(g) if g is not None else nul, _ptr(omega), p, int(q), _ptr(V),
+                                           float(lam), r,
+                                           _ptr(delta), _ptr(sigma)))
+        return delta, sigma
 
     def storage_like(self, n, m):
         """An empty O buffer in this handle's storage form: (n, m) float32 or

@@ -59,5 +59,7 @@ def test_null_handle_calls_are_rejected():
     assert lib.wssr_step(None, 10, 10, None, 10, None, None, 1.0, 1, 1, None, None) == wssr.ERR_INVALID_ARG
     assert lib.wssr_step_avg(None, 10, 10, None, 10, None, None, None, 1.0, 1, 1, 0.5, None, None, None,
                              None) == wssr.ERR_INVALID_ARG
+    assert lib.wssr_step_sketch(None, 10, 10, None, 10, None, None, None, 2, 0, None, 1.0, 1, None,
+                                None) == wssr.ERR_INVALID_ARG
     code = ctypes.c_int32()
     assert lib.wssr_status_sync(None, ctypes.byref(code), None) == wssr.ERR_INVALID_ARG
