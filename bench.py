@@ -81,6 +81,9 @@ def parse():
                     help="also time the FP32 benchmark workload f32_n8192_m100k_r256 as a secondary record")
     ap.add_argument("--averaged", type=float, default=0.95,
                     help="also time the averaged-state step with this weight on the same data (0: skip)")
+    ap.add_argument("--sketch", default="16,0;16,1",
+                    help="randomized-sketch cold steps to time on the headline data: 'p,q;p,q' (oversampling "
+                         "capped so that r + p <= 512; empty: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-cols", type=int, default=0, help="columns of the oracle sample (0: auto)")
     ap.add_argument("--plain-inputs", type=int, default=0,
@@ -142,6 +145,7 @@ def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev, avg=None
     e1.record(stream)
     code, diag = h.status()
     cold_ms = e0.elapsed_time(e1)
+    cold_delta = delta.clone() if avg is None else None
     log(f"[{tag}] cold step (q=8): {cold_ms:.2f} ms, status {code}, diag {diag}")
     if code < 0:
         raise SystemExit(f"cold step failed with status {code}")
@@ -176,7 +180,35 @@ def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev, avg=None
         raise SystemExit(f"timed steps failed with status {code}")
     return dict(ms_per_step=ms_per_step, median_ms=float(np.median(per_step)),
                 p10_ms=float(np.percentile(per_step, 10)), p90_ms=float(np.percentile(per_step, 90)),
-                cold_ms=cold_ms, prof=prof, diag=diag, v=v)
+                cold_ms=cold_ms, prof=prof, diag=diag, v=v, cold_delta=cold_delta)
+
+
+def time_sketch(h, form, o_ring, e_ring, g_ring, cfg, dev, p, q, cold_delta):
+    """One randomized-sketch step (oversampling p, q power passes) on the
+    first O, as the cold start, against the q = 8 cold step on the same O:
+    its time and the relative difference of the two directions."""
+    import torch
+
+    m, r, n = cfg.m, cfg.r, cfg.n
+    gen = torch.Generator(device=dev).manual_seed(cfg.seed + 101)
+    omega = torch.randn(n, r + p, generator=gen, device=dev, dtype=torch.float32)
+    v = torch.empty(m, r, dtype=torch.float32, device=dev)
+    delta = torch.empty(m, dtype=torch.float64, device=dev)
+    g = None if g_ring is None else g_ring[0]
+    stream = torch.cuda.current_stream(dev)
+    ms = []
+    for _ in range(2):          # the first call warms the code paths
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.step_sketch(o_ring[0], e_ring[0] if g is None else None, omega, v, cfg.lam, q=q, delta=delta, g=g)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    code, diag = h.status()
+    diff = float((delta - cold_delta).norm() / cold_delta.norm())
+    log(f"[{form}] sketch cold step (p={p}, q={q}): {ms[-1]:.2f} ms, status {code}, "
+        f"delta vs the 8-pass cold step {diff:.2e}")
+    return {"p": p, "q": q, "ms": round(ms[-1], 3), "status": code, "delta_rel_diff_vs_8_pass_cold": diff}
 
 
 def product_kernel(form, side, cfg):
@@ -508,14 +540,15 @@ def hbm_of(form, prof, cfg, res):
             "step_bytes": step_bytes, "peak_GB/s": PEAK_HBM_GBS}
 
 
-def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0):
+def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0, sketch=()):
     """Generate, time and release one workload in one form; returns the
     result record, the step-1 sample columns and V (for the accuracy leg)."""
     import torch
 
     from paper_2512_05749_amd import Wssr
     ring = ring or args.ring or (4 if cfg.n * cfg.m <= (1 << 30) else 1)
-    h = Wssr(n_max=cfg.n, m_max=cfg.m, r_max=cfg.r, q_max=8, device=dev, dtype=form)
+    p_max = max([p_ for p_, _ in sketch], default=0)
+    h = Wssr(n_max=cfg.n, m_max=cfg.m, r_max=min(512, cfg.r + p_max), q_max=8, device=dev, dtype=form)
     os_, es, gs, v, sample, ingest_ms = generate(h, cfg, form, ring, dev, args, sample_cols)
     if args.copy_calibration:
         # one elementwise kernel reading and writing exactly copy_calibration MiB
@@ -526,6 +559,9 @@ def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0):
         log(f"copy calibration: {args.copy_calibration} MiB read + written by one neg kernel")
         del src, dst
     res = time_form(h, form, os_, es, gs, v, cfg, args, dev)
+    sk = None
+    if sketch:
+        sk = [time_sketch(h, form, os_, es, gs, cfg, dev, p_, q_, res["cold_delta"]) for p_, q_ in sketch]
     res_avg = None
     if averaged > 0:
         # the averaged-state step on the same data and handle
@@ -544,6 +580,8 @@ def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0):
            "diag": res["diag"]}
     if form != "f32":
         rec["ingest_ms_per_O"] = round(ingest_ms, 3)
+    if sk:
+        rec["sketch_cold_start"] = sk
     if res_avg is not None:
         rec["averaged"] = {"weight": averaged, "value": round(1e3 / res_avg["ms_per_step"], 3),
                            "ms_per_step": round(res_avg["ms_per_step"], 4),
@@ -592,7 +630,12 @@ def main():
     torch.cuda.set_device(dev)
     cols = oracle_cols(args, cfg) if args.cpu_baseline else 0
     cols_wide = min(cfg.m, OracleSample.WIDE * cols)
-    rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols_wide, averaged=args.averaged)
+    sketch = []
+    for item in filter(None, args.sketch.split(";")):
+        p_, q_ = (int(x) for x in item.split(","))
+        sketch.append((min(p_, 512 - cfg.r), q_))
+    rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols_wide, averaged=args.averaged,
+                                        sketch=sketch)
     out = {
         "metric": METRIC,
         "value": rec["value"],
@@ -617,6 +660,8 @@ def main():
         out["ingest_ms_per_O"] = rec["ingest_ms_per_O"]
     if "averaged" in rec:
         out["averaged_state_step"] = rec["averaged"]
+    if "sketch_cold_start" in rec:
+        out["sketch_cold_start"] = rec["sketch_cold_start"]
     oracle = OracleSample(args, cfg, sample, e1, v_end[:cols_wide], form, cols) if args.cpu_baseline else None
     del sample, v_end
     torch.cuda.empty_cache()
