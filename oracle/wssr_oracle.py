@@ -467,6 +467,31 @@ def sr_pushthrough(o, e_l, lam):
     return a.T @ spd_solve(t + lam * np.eye(n), center_energies(e_l) / np.sqrt(n))
 
 
+def spring_step(o, e_l, dtheta_prev, lam, mu, eta):
+    """The comparison system of Sec. 3.2 in its damped form: MinSR (eq. mT)
+    with the SPRING momentum (eq. param:spring), solved in sample space.
+
+        Ltilde = eps/sqrt(N) - mu A dtheta_prev            (dtheta_prev = theta_k - theta_{k-1})
+        delta  = A^T (A A^T + lam I)^{-1} Ltilde            (T = A A^T, eq. mT; no factor 2, A3)
+        dtheta = -eta delta + mu dtheta_prev               (theta_{k+1} - theta_k)
+
+    mu = 0 is MinSR, whose delta is the damped full-rank SR direction
+    (S + lam I)^{-1} g.  dtheta_prev may be None when mu = 0.
+    Returns dict(delta, dtheta, t (the N x N T + lam I), rhs (Ltilde))."""
+    o = np.asarray(o, dtype=np.float64)
+    n, m = o.shape
+    if not lam > 0 or not 0.0 <= mu < 1.0:
+        raise ValueError("bad lambda or momentum")
+    a = scaled_centered(o)
+    rhs = center_energies(e_l) / np.sqrt(n)
+    prev = np.zeros(m) if dtheta_prev is None else np.asarray(dtheta_prev, dtype=np.float64)
+    if mu != 0.0:
+        rhs = rhs - mu * (a @ prev)
+    t = a @ a.T + lam * np.eye(n)
+    delta = a.T @ spd_solve(t, rhs)
+    return dict(delta=delta, dtheta=-eta * delta + mu * prev, t=t, rhs=rhs)
+
+
 def exact_topr(o, r):
     """Exact top-r right singular vectors and values of A by Jacobi SVD of A^T
     (columns of A^T are the N samples)."""

@@ -657,3 +657,53 @@ def test_sketch_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(orc, "randomized_svd", no_q)
     assert not pin_passes()
     monkeypatch.undo()
+
+
+# --------------------------------------------------------------- MinSR / SPRING (Sec. 3.2)
+
+def test_spring_momentum_zero_is_the_direct_solve():
+    """MinSR (mu = 0) in the damped form: the sample-space solve equals the
+    parameter-space (S + lam I)^{-1} g by a LAPACK solve of the M x M system."""
+    n, m = 30, 80
+    o, e = _problem(n, m, 71)
+    res = orc.spring_step(o, e, None, 0.05, 0.0, 0.1)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    g = a.T @ (e - e.mean()) / np.sqrt(n)
+    assert _rel(res["delta"], np.linalg.solve(a.T @ a + 0.05 * np.eye(m), g)) < 1e-10
+    assert _rel(res["dtheta"], -0.1 * res["delta"]) < 1e-15
+
+
+def test_spring_with_momentum_against_parameter_space_solve():
+    """SPRING: delta = (A^T A + lam I)^{-1} A^T (eps/sqrt(N) - mu A dtheta)
+    (the damped push-through identity with the modified right-hand side),
+    solved by LAPACK in parameter space; dtheta = -eta delta + mu dtheta_prev."""
+    n, m, mu, eta, lam = 25, 60, 0.9, 0.02, 0.01
+    o, e = _problem(n, m, 72)
+    prev = rng0(73).standard_normal(m)
+    res = orc.spring_step(o, e, prev, lam, mu, eta)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    b = (e - e.mean()) / np.sqrt(n) - mu * a @ prev
+    want = np.linalg.solve(a.T @ a + lam * np.eye(m), a.T @ b)
+    assert _rel(res["delta"], want) < 1e-10
+    assert _rel(res["dtheta"], -eta * want + mu * prev) < 1e-12
+
+
+def test_spring_small_damping_is_the_minimum_norm_projection():
+    """As lam -> 0 the SPRING direction is the minimum-norm solution of the
+    sample-space system A delta = Ltilde (the Kaczmarz-type projection the
+    method is built on): LAPACK's least-squares solution."""
+    n, m, mu = 20, 70, 0.5
+    o, e = _problem(n, m, 74, noise=0.3)
+    prev = rng0(75).standard_normal(m)
+    res = orc.spring_step(o, e, prev, 1e-11, mu, 1.0)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    b = (e - e.mean()) / np.sqrt(n) - mu * a @ prev
+    want = np.linalg.lstsq(a, b, rcond=None)[0]
+    assert _rel(res["delta"], want) < 1e-6
+
+
+def test_spring_rejects_bad_arguments():
+    o, e = _problem(10, 20, 76)
+    for lam, mu in ((0.0, 0.1), (0.1, 1.0), (0.1, -0.2)):
+        with pytest.raises(ValueError):
+            orc.spring_step(o, e, np.zeros(20), lam, mu, 0.1)
