@@ -91,6 +91,8 @@ typedef enum {
 /* Flags (wssr_config.flags). */
 #define WSSR_FLOOR_PRECOND 0x1u  /* eq. updated_sr_1 weights w_j = 1 - lambda/sigma_j^2 instead of
                                     the damped w_j = sigma_j^2/(sigma_j^2 + lambda) */
+#define WSSR_SAMPLE_SPACE 0x4u   /* allocate the workspace of wssr_spring: an n_max x n_max FP64
+                                    matrix (8 n_max^2 bytes) and up to 268 MB of partial tiles */
 #define WSSR_GRAPH 0x2u          /* wssr_step_batched captures a batch into a HIP graph on its first
                                     call and replays the graph while the same problem array (same
                                     sizes and pointers) is passed again.  Currently disabled:
@@ -220,6 +222,28 @@ wssr_status wssr_step_sketch(wssr_handle h, int64_t n, int64_t m, const void* O,
                              const double* g, const float* omega, int32_t p, int32_t q, float* V, double lambda,
                              int32_t r, double* delta, double* sigma);
 
+/* The comparison system of Sec. 3.2 on the same GPU: MinSR (eq. mT) with the
+ * SPRING momentum (eq. param:spring), damped and solved in sample space.
+ *   Ltilde = eps/sqrt(N) - momentum A dtheta_in
+ *   delta  = A^T (A A^T + lambda I)^{-1} Ltilde          (no factor 2, as in wssr_step)
+ *   dtheta = -eta delta + momentum dtheta_in             (the next theta_{k+1} - theta_k)
+ * momentum = 0 is MinSR, and its delta is the damped full-rank SR direction
+ * (S + lambda I)^{-1} g that wssr_step approximates at rank r.  T = A A^T is
+ * formed on the FP64 MFMA (exact products of the stored values, FP64 sums;
+ * N^2 M multiply-adds, half of them by symmetry), double-centred, and solved
+ * by a blocked FP64 Cholesky and two blocked triangular solves.
+ * Needs a handle created with WSSR_SAMPLE_SPACE (WSSR_ERR_INVALID_ARG otherwise).
+ *   O, ld_o, n, m, e_l  as in wssr_step (any storage form)
+ *   lambda     damping > 0
+ *   momentum   0 <= momentum < 1
+ *   eta        the step size of the momentum update (finite)
+ *   dtheta     device, double[m], in/out, or NULL when momentum = 0 (then not written):
+ *              in theta_k - theta_{k-1}, out -eta delta + momentum dtheta_in
+ *   delta      device, double[m], out
+ * A Cholesky pivot that is not positive raises WSSR_ERR_BREAKDOWN. */
+wssr_status wssr_spring(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                        double lambda, double momentum, double eta, double* dtheta, double* delta);
+
 /* Ingest of O: one pass over a block of rows of the unrounded FP32 matrix
  * that writes them in the handle's storage form and forms, from the unrounded
  * values, the gradient g = O_bar^T eps / n (Sec. 4.1 eq. barg; eps = E_L -
@@ -304,7 +328,9 @@ const char* wssr_last_error(wssr_handle h);
  * split-K reduction excluded, and the parameter-side product); 0 stops.
  * wssr_profile_read synchronises the stream and returns, per slot, the summed
  * milliseconds and the launch count: slot 0 = sample-side product kernel,
- * slot 1 = parameter-side product kernel.  nslots <= 2. */
+ * slot 1 = parameter-side product kernel, slot 2 = wssr_spring's product
+ * T = O O^T (with its chunk reduction), slot 3 = wssr_spring's blocked
+ * Cholesky (all its launches as one interval).  nslots <= 4. */
 wssr_status wssr_profile(wssr_handle h, int32_t enable);
 wssr_status wssr_profile_read(wssr_handle h, double* ms, int64_t* counts, int32_t nslots);
 

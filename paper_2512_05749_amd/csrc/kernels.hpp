@@ -169,6 +169,27 @@ __global__ void k_lhat(const double* eps, int64_t n, const double* l, int r, dou
 __global__ void k_state_l(const double* Rz, const double* Ps, int rp, int r, const double* t, const float* sgn,
                           double* sig, double wscale, double* l_out, const DevStatus* st);
 __global__ void k_transpose_rp(const double* R, int rp, int r, double* Ct, const DevStatus* st);
+// sample-space solver (kernels_minsr.hip)
+template <typename T, int PL>
+__global__ void k_syrk_partial(const T* O, int64_t ld, int64_t pstride, int64_t n, int64_t m, int ntile,
+                               int64_t kchunk, double* part, double* G, bool vec, const DevStatus* st);
+__global__ void k_syrk_reduce(const double* part, int nchunk, int ntile, int64_t n, double* G, const DevStatus* st);
+__global__ void k_row_mean(const double* G, int64_t n, double* rho, const DevStatus* st);
+__global__ void k_dcenter(double* G, int64_t n, const double* rho, const double* tau, double scale, double lambda,
+                          const DevStatus* st);
+__global__ void k_potrf_diag(double* G, int64_t n, int64_t k0, int nb, DevStatus* st);
+__global__ void k_trsm_panel(double* G, int64_t n, int64_t k0, int nb, const DevStatus* st);
+__global__ void k_syrk_update(double* G, int64_t n, int64_t k0, int nb, int ntile, bool vec, const DevStatus* st);
+__global__ void k_trsv_fwd_diag(const double* G, int64_t n, int64_t k0, int nb, double* y, const DevStatus* st);
+__global__ void k_trsv_fwd_update(const double* G, int64_t n, int64_t k0, int nb, double* y, const DevStatus* st);
+__global__ void k_trsv_bwd_diag(const double* G, int64_t n, int64_t k0, int nb, double* y, const DevStatus* st);
+__global__ void k_trsv_bwd_update(const double* G, int64_t n, int64_t k0, int nb, double* y, const DevStatus* st);
+template <typename T, int PL>
+__global__ void k_gemv_rows(const T* O, int64_t ld, int64_t pstride, int64_t n, int64_t m, const double* x,
+                            double* u, const DevStatus* st);
+__global__ void k_spring_rhs(const double* eps, const double* u, const double* ubar, int64_t n, double a_eps,
+                             double a_u, double* b, const DevStatus* st);
+__global__ void k_axpby(const double* delta, int64_t m, double a, double b, double* dtheta, const DevStatus* st);
 
 // dynamic LDS sizes (bytes)
 constexpr size_t kCholLds = 4 * 64 * 65 * sizeof(double);

@@ -93,6 +93,10 @@ struct wssr_ctx {
   double *y1 = nullptr, *Hc = nullptr, *Hn = nullptr, *Bm = nullptr, *gbar = nullptr, *lhat = nullptr;
   double* tvec = nullptr;
   int64_t gram_part_elems = 0;
+  // sample-space solver (wssr_spring, flag WSSR_SAMPLE_SPACE): T (n_max^2),
+  // its K-chunk partial tiles, and n-vectors
+  double *Tn = nullptr, *tpart = nullptr, *rho = nullptr, *su = nullptr, *sb = nullptr, *sscal = nullptr;
+  int64_t tpart_tiles = 0;
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
 
@@ -331,6 +335,117 @@ struct wssr_ctx {
     h->apply((const float*)h->vw, m, rs, rs, h->Ps, rps, r, h->z, r, false);
     if (!g_ext) (void)hipStreamWaitEvent(stream, h->ev_join, 0);
     return finish(n, m, h->z, V, nullptr, r, lambda, delta, sigma, gv, nullptr, n);
+  }
+
+  // MinSR with the SPRING momentum in sample space (Sec. 3.2, eqs. mT and
+  // param:spring, damped): T = A A^T + lambda I on the FP64 MFMA, its blocked
+  // Cholesky, b = eps/sqrt(N) - momentum A dtheta, x = T^{-1} b, delta = A^T x
+  // (= O^T x / sqrt(N): x sums to zero), dtheta <- -eta delta + momentum dtheta.
+  wssr_status enqueue_spring(int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l, double lambda,
+                             double mom, double eta, double* dtheta, double* delta) {
+    wssr_ctx* h = this;
+    const DevStatus* cst = h->st;
+    hipStream_t stream = h->stream;
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
+    hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, h->eps, h->st);
+    const bool b16 = bf16();
+    const int pl = o_planes();
+    // G = O O^T
+    const int nt = (int)cdiv(n, 128), npairs = nt * (nt + 1) / 2;
+    int nch = 1;
+    int64_t kchunk = rup(m, 16);
+    if (npairs < 512) {
+      nch = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, npairs), tpart_tiles / npairs),
+                                                        cdiv(m, 256)));
+      kchunk = rup(cdiv(m, nch), 16);
+      nch = (int)cdiv(m, kchunk);
+    }
+    double* part = nch > 1 ? h->tpart : nullptr;
+    const dim3 g1((unsigned)npairs, (unsigned)nch);
+    h->timed(2, [&] {
+      if (!b16) {
+        const bool vec = (ld_o % 4 == 0) && ((uintptr_t)O % 16 == 0);
+        hipLaunchKernelGGL((k_syrk_partial<float, 1>), g1, dim3(256), 0, stream, static_cast<const float*>(O), ld_o,
+                           (int64_t)0, n, m, nt, kchunk, part, h->Tn, vec, cst);
+      } else {
+        const bool vec = (ld_o % 4 == 0) && ((uintptr_t)O % 8 == 0);
+        const auto* o16 = static_cast<const unsigned short*>(O);
+        if (pl == 2)
+          hipLaunchKernelGGL((k_syrk_partial<unsigned short, 2>), g1, dim3(256), 0, stream, o16, ld_o, n * ld_o, n,
+                             m, nt, kchunk, part, h->Tn, vec, cst);
+        else
+          hipLaunchKernelGGL((k_syrk_partial<unsigned short, 1>), g1, dim3(256), 0, stream, o16, ld_o, n * ld_o, n,
+                             m, nt, kchunk, part, h->Tn, vec, cst);
+      }
+      if (part)
+        hipLaunchKernelGGL(k_syrk_reduce, dim3(npairs, 64), dim3(256), 0, stream, (const double*)part, nch, nt, n,
+                           h->Tn, cst);
+    });
+    // T = (G - rho 1^T - 1 rho^T + tau) / n + lambda I
+    hipLaunchKernelGGL(k_row_mean, dim3(cdiv(n, 4)), dim3(256), 0, stream, (const double*)h->Tn, n, h->rho, cst);
+    hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(256), 0, stream, (const double*)h->rho, (int)n, 1, 1.0 / (double)n,
+                       h->sscal + 1, cst);
+    hipLaunchKernelGGL(k_dcenter, dim3(cdiv(n * n, 256)), dim3(256), 0, stream, h->Tn, n, (const double*)h->rho,
+                       (const double*)(h->sscal + 1), 1.0 / (double)n, lambda, cst);
+    // blocked Cholesky (64-column panels)
+    const bool vecd = (n % 2 == 0);
+    h->timed(3, [&] {
+      for (int64_t k0 = 0; k0 < n; k0 += 64) {
+        const int nb = (int)std::min<int64_t>(64, n - k0);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, stream, h->Tn, n, k0, nb, h->st);
+        const int64_t rest = n - k0 - nb;
+        if (rest > 0) {
+          hipLaunchKernelGGL(k_trsm_panel, dim3(cdiv(rest, 64)), dim3(256), 0, stream, h->Tn, n, k0, nb, cst);
+          const int ntr = (int)cdiv(rest, 128);
+          hipLaunchKernelGGL(k_syrk_update, dim3(ntr * (ntr + 1) / 2), dim3(256), 0, stream, h->Tn, n, k0, nb, ntr,
+                             vecd, cst);
+        }
+      }
+    });
+    // right-hand side
+    const double isn = 1.0 / std::sqrt((double)n);
+    if (mom != 0.0) {
+      if (!b16) {
+        hipLaunchKernelGGL((k_gemv_rows<float, 1>), dim3(cdiv(n, 4)), dim3(256), 0, stream,
+                           static_cast<const float*>(O), ld_o, (int64_t)0, n, m, (const double*)dtheta, h->su, cst);
+      } else if (pl == 2) {
+        hipLaunchKernelGGL((k_gemv_rows<unsigned short, 2>), dim3(cdiv(n, 4)), dim3(256), 0, stream,
+                           static_cast<const unsigned short*>(O), ld_o, n * ld_o, n, m, (const double*)dtheta, h->su,
+                           cst);
+      } else {
+        hipLaunchKernelGGL((k_gemv_rows<unsigned short, 1>), dim3(cdiv(n, 4)), dim3(256), 0, stream,
+                           static_cast<const unsigned short*>(O), ld_o, n * ld_o, n, m, (const double*)dtheta, h->su,
+                           cst);
+      }
+      hipLaunchKernelGGL(k_colreduce, dim3(1), dim3(256), 0, stream, (const double*)h->su, (int)n, 1, 1.0 / (double)n,
+                         h->sscal, cst);
+    }
+    hipLaunchKernelGGL(k_spring_rhs, dim3(cdiv(n, 256)), dim3(256), 0, stream, (const double*)h->eps,
+                       mom != 0.0 ? (const double*)h->su : nullptr, (const double*)h->sscal, n, isn, mom * isn, h->sb,
+                       cst);
+    // x = (L L^T)^{-1} b, in place in sb
+    for (int64_t k0 = 0; k0 < n; k0 += 64) {
+      const int nb = (int)std::min<int64_t>(64, n - k0);
+      hipLaunchKernelGGL(k_trsv_fwd_diag, dim3(1), dim3(64), 0, stream, (const double*)h->Tn, n, k0, nb, h->sb, cst);
+      const int64_t rest = n - k0 - nb;
+      if (rest > 0)
+        hipLaunchKernelGGL(k_trsv_fwd_update, dim3(cdiv(rest, 4)), dim3(256), 0, stream, (const double*)h->Tn, n, k0,
+                           nb, h->sb, cst);
+    }
+    for (int64_t k0 = (n - 1) / 64 * 64; k0 >= 0; k0 -= 64) {
+      const int nb = (int)std::min<int64_t>(64, n - k0);
+      hipLaunchKernelGGL(k_trsv_bwd_diag, dim3(1), dim3(64), 0, stream, (const double*)h->Tn, n, k0, nb, h->sb, cst);
+      if (k0 > 0)
+        hipLaunchKernelGGL(k_trsv_bwd_update, dim3(cdiv(k0, 256)), dim3(256), 0, stream, (const double*)h->Tn, n, k0,
+                           nb, h->sb, cst);
+    }
+    // delta = O^T x / sqrt(n); the momentum update
+    h->otv(O, ld_o, n, m, h->sb, isn, delta, stream, false);
+    if (dtheta)
+      hipLaunchKernelGGL(k_axpby, dim3(cdiv(m, 256)), dim3(256), 0, stream, (const double*)delta, m, -eta, mom,
+                         dtheta, cst);
+    if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+    return WSSR_OK;
   }
 
   // The end of a step, once vnew holds the new basis (unsigned, m x r), sig
@@ -755,6 +870,12 @@ struct wssr_ctx {
                 hipStream_t on = nullptr, bool lean = false) {
     hipStream_t stream = on ? on : this->stream;
     hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, eps, st);
+    otv(Ov, ld, n, m, eps, 1.0 / (double)n, gout, stream, lean);
+  }
+
+  // out = scale * O^T x (x: n doubles), one HBM-bound pass over O
+  void otv(const void* Ov, int64_t ld, int64_t n, int64_t m, const double* x, double scale, double* gout,
+           hipStream_t stream, bool lean) {
     // BF16 rows that are whole 16-byte chunks: 8 columns per thread
     const bool vec8 = bf16() && (ld % 8 == 0) && ((uintptr_t)Ov % 16 == 0);
     const int64_t cb = cdiv(m, vec8 ? 2048 : 1024);
@@ -764,7 +885,7 @@ struct wssr_ctx {
     if (!bf16()) {
       const float* O = static_cast<const float*>(Ov);
       const bool vec = (ld % 4 == 0) && ((uintptr_t)O % 16 == 0);
-      hipLaunchKernelGGL(k_gradient_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n, m, (const double*)eps,
+      hipLaunchKernelGGL(k_gradient_partial, dim3(cb, gs), dim3(256), 0, stream, O, ld, n, m, x,
                          rows, gpart, vec, (const DevStatus*)st);
     } else {
       const auto* O = static_cast<const unsigned short*>(Ov);
@@ -772,13 +893,13 @@ struct wssr_ctx {
       const dim3 grid((unsigned)cb, (unsigned)gs);
       if (o_planes() == 2)
         hipLaunchKernelGGL((vec8 ? k_gradient16_partial<2, 8> : k_gradient16_partial<2, 4>), grid, dim3(256), 0,
-                           stream, O, ld, n * ld, n, m, (const double*)eps, rows, gpart, vec, (const DevStatus*)st);
+                           stream, O, ld, n * ld, n, m, x, rows, gpart, vec, (const DevStatus*)st);
       else
         hipLaunchKernelGGL((vec8 ? k_gradient16_partial<1, 8> : k_gradient16_partial<1, 4>), grid, dim3(256), 0,
-                           stream, O, ld, n * ld, n, m, (const double*)eps, rows, gpart, vec, (const DevStatus*)st);
+                           stream, O, ld, n * ld, n, m, x, rows, gpart, vec, (const DevStatus*)st);
     }
     hipLaunchKernelGGL(k_gradient_reduce, dim3(cdiv(m, 256)), dim3(256), 0, stream, (const double*)gpart, gs, m,
-                       1.0 / (double)n, gout, (const DevStatus*)st);
+                       scale, gout, (const DevStatus*)st);
   }
 
   // Ingest of a block of rows of FP32 O (see wssr_ingest).  The first block
@@ -1163,6 +1284,21 @@ wssr_status wssr_create(const wssr_config* cfg, wssr_handle* out) {
     g_create_error = why;
     return s;
   }
+  if (cfg->flags & WSSR_SAMPLE_SPACE) {
+    const int64_t n = cfg->n_max;
+    const int nt = (int)cdiv(n, 128), npairs = nt * (nt + 1) / 2;
+    // partial tiles only where the K range is split (fewer than 512 pairs)
+    h->tpart_tiles = npairs < 512 ? 2048 : 0;
+    bool ok = h->alloc(h->Tn, (size_t)n * n) && h->alloc(h->rho, n) && h->alloc(h->su, n) && h->alloc(h->sb, n) &&
+              h->alloc(h->sscal, 2) && h->alloc(h->tpart, (size_t)h->tpart_tiles * 128 * 128);
+    if (!ok) {
+      (void)hipGetLastError();
+      h->release();
+      delete h;
+      g_create_error = "sample-space workspace allocation failed";
+      return WSSR_ERR_OOM;
+    }
+  }
   for (int i = 0; i < cfg->lanes; ++i) {
     wssr_ctx* c = nullptr;
     hipEvent_t e = nullptr;
@@ -1269,6 +1405,22 @@ wssr_status wssr_step_sketch(wssr_handle h, int64_t n, int64_t m, const void* O,
   if (s != WSSR_OK) return s;
   if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
   return h->enqueue_sketch(n, m, O, ld_o, e_l, omega, r + p, q, V, lambda, r, delta, sigma, g);
+}
+
+wssr_status wssr_spring(wssr_handle h, int64_t n, int64_t m, const void* O, int64_t ld_o, const double* e_l,
+                        double lambda, double momentum, double eta, double* dtheta, double* delta) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!(h->cfg.flags & WSSR_SAMPLE_SPACE))
+    return h->fail(WSSR_ERR_INVALID_ARG, "the handle was created without WSSR_SAMPLE_SPACE");
+  wssr_status s = check_common(h, n, m, O, ld_o, 1);
+  if (s != WSSR_OK) return s;
+  if (!e_l || !delta) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return h->fail(WSSR_ERR_INVALID_ARG, "lambda must be > 0 and finite");
+  if (!(momentum >= 0.0 && momentum < 1.0)) return h->fail(WSSR_ERR_INVALID_ARG, "momentum must be in [0, 1)");
+  if (!std::isfinite(eta)) return h->fail(WSSR_ERR_INVALID_ARG, "eta must be finite");
+  if (momentum != 0.0 && !dtheta) return h->fail(WSSR_ERR_INVALID_ARG, "dtheta is NULL with nonzero momentum");
+  if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
+  return h->enqueue_spring(n, m, O, ld_o, e_l, lambda, momentum, eta, dtheta, delta);
 }
 
 wssr_status wssr_ingest(wssr_handle h, int64_t n, int64_t m, int64_t row0, int64_t rows, const float* O32,
@@ -1542,7 +1694,7 @@ wssr_status wssr_profile(wssr_handle h, int32_t enable) {
 }
 
 wssr_status wssr_profile_read(wssr_handle h, double* ms, int64_t* counts, int32_t nslots) {
-  if (!h || !ms || !counts || nslots < 1 || nslots > 2) return WSSR_ERR_INVALID_ARG;
+  if (!h || !ms || !counts || nslots < 1 || nslots > 4) return WSSR_ERR_INVALID_ARG;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipStreamSynchronize failed");
   for (int i = 0; i < nslots; ++i) {
     ms[i] = 0.0;

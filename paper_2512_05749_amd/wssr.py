@@ -35,6 +35,7 @@ BF16_SPLIT = 3
 DTYPES = {"f32": F32, "bf16": BF16, "bf16x2": BF16X2, "bf16_split": BF16_SPLIT}
 FLOOR_PRECOND = 0x1
 GRAPH = 0x2
+SAMPLE_SPACE = 0x4
 
 
 class WssrError(RuntimeError):
@@ -68,6 +69,7 @@ _SIGS = {
     "wssr_step_g": ([_P, _I64, _I64, _P, _I64, _P, _P, _D, _I32, _I32, _P, _P], ctypes.c_int),
     "wssr_step_avg": ([_P, _I64, _I64, _P, _I64, _P, _P, _P, _D, _I32, _I32, _D, _P, _P, _P, _P], ctypes.c_int),
     "wssr_step_sketch": ([_P, _I64, _I64, _P, _I64, _P, _P, _P, _I32, _I32, _P, _D, _I32, _P, _P], ctypes.c_int),
+    "wssr_spring": ([_P, _I64, _I64, _P, _I64, _P, _D, _D, _D, _P, _P], ctypes.c_int),
     "wssr_ingest": ([_P, _I64, _I64, _I64, _I64, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
     "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
@@ -129,12 +131,13 @@ class Wssr:
     """One libwssr handle bound to a device and a stream."""
 
     def __init__(self, n_max, m_max, r_max, q_max=8, floor_precond=False, device=None, stream=None, dtype="f32",
-                 lanes=0, graph=False):
+                 lanes=0, graph=False, sample_space=False):
         """dtype: storage and product precision of O -- "f32"; "bf16" (one BF16
         product); "bf16_split" (BF16 O, skinny operand split in two); "bf16x2"
         (O as BF16 hi and lo planes, shape (2, n, m), three products).
         lanes, graph: the batched form (step_batched) -- problems run on this
-        many concurrent lanes; graph captures a batch once and replays it."""
+        many concurrent lanes; graph captures a batch once and replays it.
+        sample_space: allocate the n_max x n_max workspace of spring()."""
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
         self.dtype = dtype
@@ -145,7 +148,8 @@ class Wssr:
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
-        flags = (FLOOR_PRECOND if floor_precond else 0) | (GRAPH if graph else 0)
+        flags = (FLOOR_PRECOND if floor_precond else 0) | (GRAPH if graph else 0) | \
+            (SAMPLE_SPACE if sample_space else 0)
         cfg = Config(int(n_max), int(m_max), int(r_max), int(q_max), DTYPES[dtype], flags,
                      ctypes.c_void_p(s.cuda_stream), int(lanes))
         h = ctypes.c_void_p()
@@ -286,6 +290,22 @@ class Wssr:
                                            _ptr(delta), _ptr(sigma)))
         return delta, sigma
 
+    def spring(self, O, e_l, lam, momentum=0.0, eta=0.0, dtheta=None, delta=None):
+        """MinSR / SPRING in sample space (wssr_spring; the handle needs
+        sample_space=True).  dtheta (float64 [m]) is updated in place to
+        -eta delta + momentum dtheta; returns delta."""
+        n, m, ld = self._o(O)
+        _need(e_l, "e_l", torch.float64, self.device, (n,), contiguous=True)
+        if dtheta is not None:
+            _need(dtheta, "dtheta", torch.float64, self.device, (m,), contiguous=True)
+        if delta is None:
+            delta = torch.empty(m, dtype=torch.float64, device=self.device)
+        _need(delta, "delta", torch.float64, self.device, (m,), contiguous=True)
+        nul = ctypes.c_void_p(None)
+        self._check(lib().wssr_spring(self._h, n, m, _ptr(O), ld, _ptr(e_l), float(lam), float(momentum), float(eta),
+                                      _ptr(dtheta) if dtheta is not None else nul, _ptr(delta)))
+        return delta
+
     def storage_like(self, n, m):
         """An empty O buffer in this handle's storage form: (n, m) float32 or
         bfloat16, or (2, n, m) bfloat16 planes for bf16x2."""
@@ -398,11 +418,17 @@ class Wssr:
         self._check(lib().wssr_profile(self._h, 1 if enable else 0))
 
     def profile_read(self):
-        """{'sample_side': (ms, launches), 'param_side': (ms, launches)} since profile(True)."""
-        ms = (ctypes.c_double * 2)()
-        cnt = (ctypes.c_int64 * 2)()
-        self._check(lib().wssr_profile_read(self._h, ms, cnt, 2))
-        return {"sample_side": (ms[0], cnt[0]), "param_side": (ms[1], cnt[1])}
+        """{'sample_side': (ms, launches), 'param_side': (ms, launches)} since
+        profile(True), plus 'spring_product' and 'spring_cholesky' when
+        wssr_spring ran."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        self._check(lib().wssr_profile_read(self._h, ms, cnt, 4))
+        out = {"sample_side": (ms[0], cnt[0]), "param_side": (ms[1], cnt[1])}
+        for k, name in ((2, "spring_product"), (3, "spring_cholesky")):
+            if cnt[k]:
+                out[name] = (ms[k], cnt[k])
+        return out
 
     # -------------------------------------------------------- single stages
     def sample_side(self, O, V):

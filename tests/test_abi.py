@@ -61,5 +61,6 @@ def test_null_handle_calls_are_rejected():
                              None) == wssr.ERR_INVALID_ARG
     assert lib.wssr_step_sketch(None, 10, 10, None, 10, None, None, None, 2, 0, None, 1.0, 1, None,
                                 None) == wssr.ERR_INVALID_ARG
+    assert lib.wssr_spring(None, 10, 10, None, 10, None, 1.0, 0.0, 0.0, None, None) == wssr.ERR_INVALID_ARG
     code = ctypes.c_int32()
     assert lib.wssr_status_sync(None, ctypes.byref(code), None) == wssr.ERR_INVALID_ARG
