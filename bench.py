@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--sketch", default="16,0;16,1",
                     help="randomized-sketch cold steps to time on the headline data: 'p,q;p,q' (oversampling "
                          "capped so that r + p <= 512; empty: skip)")
+    ap.add_argument("--spring", type=int, default=1,
+                    help="time MinSR/SPRING in sample space on the same data (workloads with N <= 8192)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-cols", type=int, default=0, help="columns of the oracle sample (0: auto)")
     ap.add_argument("--plain-inputs", type=int, default=0,
@@ -181,6 +183,46 @@ def time_form(h, form, o_ring, e_ring, g_ring, v_start, cfg, args, dev, avg=None
     return dict(ms_per_step=ms_per_step, median_ms=float(np.median(per_step)),
                 p10_ms=float(np.percentile(per_step, 10)), p90_ms=float(np.percentile(per_step, 90)),
                 cold_ms=cold_ms, prof=prof, diag=diag, v=v, cold_delta=cold_delta)
+
+
+def time_spring(h, form, o_ring, e_ring, cfg, dev, momentum, steps):
+    """MinSR / SPRING in sample space (the paper's comparison system) on the
+    same data: one untimed call, then `steps` timed calls with the momentum
+    state carried; the FP64 product T = O O^T and the Cholesky reported
+    against the FP64 MFMA peak."""
+    import numpy as np
+    import torch
+
+    n, m = cfg.n, cfg.m
+    dth = torch.zeros(m, dtype=torch.float64, device=dev)
+    delta = torch.empty(m, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    h.spring(o_ring[0], e_ring[0], cfg.lam, momentum=momentum, eta=0.05, dtheta=dth, delta=delta)
+    torch.cuda.synchronize()
+    h.profile(True)
+    ms = []
+    for k in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.spring(o_ring[(k + 1) % len(o_ring)], e_ring[(k + 1) % len(e_ring)], cfg.lam, momentum=momentum,
+                 eta=0.05, dtheta=dth, delta=delta)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    prof = h.profile_read()
+    h.profile(False)
+    code, diag = h.status()
+    pm, pc = prof.get("spring_product", (0.0, 0))
+    cm, cc = prof.get("spring_cholesky", (0.0, 0))
+    t_ms = pm / max(pc, 1)
+    flops = float(n) * (n + 1) * m                  # the N(N+1)/2 distinct entries of T, 2M flops each
+    rec = {"momentum": momentum, "ms_per_step": round(float(np.median(ms)), 3),
+           "value": round(1e3 / float(np.median(ms)), 3), "status": code,
+           "product_T": {"ms": round(t_ms, 3), "TFLOP/s": round(flops / (t_ms * 1e-3) / 1e12, 2),
+                         "peak_TFLOP/s": 78.6, "frac": round(flops / (t_ms * 1e-3) / 1e12 / 78.6, 4)},
+           "cholesky_ms": round(cm / max(cc, 1), 3)}
+    log(f"[{form}] SPRING (momentum {momentum}): {rec}")
+    return rec
 
 
 def time_sketch(h, form, o_ring, e_ring, g_ring, cfg, dev, p, q, cold_delta):
@@ -540,7 +582,7 @@ def hbm_of(form, prof, cfg, res):
             "step_bytes": step_bytes, "peak_GB/s": PEAK_HBM_GBS}
 
 
-def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0, sketch=()):
+def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0, sketch=(), spring=False):
     """Generate, time and release one workload in one form; returns the
     result record, the step-1 sample columns and V (for the accuracy leg)."""
     import torch
@@ -548,7 +590,8 @@ def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0, sketch
     from paper_2512_05749_amd import Wssr
     ring = ring or args.ring or (4 if cfg.n * cfg.m <= (1 << 30) else 1)
     p_max = max([p_ for p_, _ in sketch], default=0)
-    h = Wssr(n_max=cfg.n, m_max=cfg.m, r_max=min(512, cfg.r + p_max), q_max=8, device=dev, dtype=form)
+    h = Wssr(n_max=cfg.n, m_max=cfg.m, r_max=min(512, cfg.r + p_max), q_max=8, device=dev, dtype=form,
+             sample_space=spring)
     os_, es, gs, v, sample, ingest_ms = generate(h, cfg, form, ring, dev, args, sample_cols)
     if args.copy_calibration:
         # one elementwise kernel reading and writing exactly copy_calibration MiB
@@ -562,6 +605,7 @@ def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0, sketch
     sk = None
     if sketch:
         sk = [time_sketch(h, form, os_, es, gs, cfg, dev, p_, q_, res["cold_delta"]) for p_, q_ in sketch]
+    sp = time_spring(h, form, os_, es, cfg, dev, 0.9, 3) if spring else None
     res_avg = None
     if averaged > 0:
         # the averaged-state step on the same data and handle
@@ -582,6 +626,8 @@ def run_single(args, cfg, form, dev, sample_cols=0, ring=0, averaged=0.0, sketch
         rec["ingest_ms_per_O"] = round(ingest_ms, 3)
     if sk:
         rec["sketch_cold_start"] = sk
+    if sp:
+        rec["spring"] = sp
     if res_avg is not None:
         rec["averaged"] = {"weight": averaged, "value": round(1e3 / res_avg["ms_per_step"], 3),
                            "ms_per_step": round(res_avg["ms_per_step"], 4),
@@ -635,7 +681,7 @@ def main():
         p_, q_ = (int(x) for x in item.split(","))
         sketch.append((min(p_, 512 - cfg.r), q_))
     rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols_wide, averaged=args.averaged,
-                                        sketch=sketch)
+                                        sketch=sketch, spring=bool(args.spring) and cfg.n <= 8192)
     out = {
         "metric": METRIC,
         "value": rec["value"],
@@ -662,6 +708,9 @@ def main():
         out["averaged_state_step"] = rec["averaged"]
     if "sketch_cold_start" in rec:
         out["sketch_cold_start"] = rec["sketch_cold_start"]
+    if "spring" in rec:
+        out["spring_same_data"] = rec["spring"]
+        out["wssr_vs_spring_time"] = round(rec["spring"]["ms_per_step"] / rec["ms_per_step"], 3)
     oracle = OracleSample(args, cfg, sample, e1, v_end[:cols_wide], form, cols) if args.cpu_baseline else None
     del sample, v_end
     torch.cuda.empty_cache()
@@ -685,11 +734,15 @@ def main():
         c2 = CONFIGS["f32_n8192_m100k_r256"]
         steps = args.steps
         args.steps = 20
-        r2, _, _, _ = run_single(args, c2, "f32", dev)
+        r2, _, _, _ = run_single(args, c2, "f32", dev, spring=bool(args.spring))
         args.steps = steps
         out["secondary"] = {"f32_n8192_m100k_r256": {"workload": describe(c2, "f32"), "steps": 20,
                                                      **{k: r2[k] for k in ("value", "ms_per_step", "step_ms_events",
                                                                            "roofline", "hbm")}}}
+        if "spring" in r2:
+            out["secondary"]["f32_n8192_m100k_r256"]["spring_same_data"] = r2["spring"]
+            out["secondary"]["f32_n8192_m100k_r256"]["wssr_vs_spring_time"] = round(
+                r2["spring"]["ms_per_step"] / r2["ms_per_step"], 3)
     if oracle is not None:
         out["cpu_baseline"], out["accuracy_vs_oracle"] = oracle.finish()
     out["env"] = env_info(dev)
