@@ -31,6 +31,12 @@ design notes):
   * output signs: column j of V_out has a non-negative inner product with
     column j of V_in; if that product is below 1e-8 in magnitude, the entry of
     largest magnitude (lowest index on ties) is made positive.
+  * adaptive rank (Sec. 4.3): the ratio of eq. ruler is taken on the
+    eigenvalues of S (sigma^2); the truncation enters only the preconditioned
+    direction, and the stored state and the warm start keep every column;
+  * Alg. 1's own ending (diag(R) of the last sample-side block, sorted) is
+    offered beside the Rayleigh-Ritz one; its parameter-side output is the
+    orthonormal basis the last block was formed from;
   * averaged state (Sec. 4.1): the stored matrix is kept as its factors, the
     orthonormal U of the previous step and sigma (Obar = U diag(sigma)); the
     initial state is zero as the paper sets it, so the first step's Sbar is
@@ -301,11 +307,54 @@ def woodbury_apply(v, sigma, g, lam, precond="damped"):
     return (g - wmat @ spd_solve(core, wmat.T @ g)) / lam
 
 
-def wssr_step(o, e_l, v_in, lam, r, q, precond="damped"):
+def ssi_diag_extract(a, v_in, q):
+    """Alg. 1 as printed, with its closing diag(R) extraction: Q^1 = orth(V_in);
+    each iteration forms the sample-side block A Q^i and the parameter-side
+    block A^T A Q^i, whose orthonormal factor is Q^(i+1); after q iterations
+    the QR of the last sample-side block A Q^q gives sigma = |diag(R)|, sorted
+    in descending order, and the parameter-side output is Q^q with its columns
+    in the same order (the normalised form of the printed output).
+    Returns V (M x r), sigma (r,)."""
+    qm = qr_positive(v_in)[0]
+    for i in range(q):
+        y = a @ qm
+        if i == q - 1:
+            _qs, rs = qr_positive(y)
+            s = np.abs(np.diag(rs))
+            order = np.argsort(-s, kind="stable")
+            return qm[:, order], s[order].copy()
+        qm = qr_positive(a.T @ y)[0]
+    raise ValueError("q must be >= 1")
+
+
+def rank_ruler(sigma, r_reg):
+    """The adaptive rank of Sec. 4.3 (eq. ruler) on the r computed values: the
+    number of i with sigma_i^2 / sigma_1^2 >= r_reg (the ratio is taken on the
+    eigenvalues of S, the squares of sigma), and whether the largest computed
+    index is in that set, which is the paper's condition for growing r_max.
+    r_reg = 0 keeps every value.  Returns (r_eff, grow)."""
+    s2 = np.asarray(sigma, dtype=np.float64) ** 2
+    if len(s2) == 0:
+        return 0, False
+    keep = s2 >= r_reg * s2[0]
+    r_eff = int(np.sum(keep))
+    return r_eff, bool(keep[-1])
+
+
+def truncated_woodbury(v, sigma, g, lam, precond="damped", r_reg=0.0):
+    """The preconditioned direction with the rank of eq. ruler: only the first
+    r_eff columns enter (eq. updated_sr_1 with U of rank r_eff)."""
+    r_eff, _grow = rank_ruler(sigma, r_reg)
+    return woodbury_apply(np.asarray(v)[:, :r_eff], np.asarray(sigma)[:r_eff], g, lam, precond)
+
+
+def wssr_step(o, e_l, v_in, lam, r, q, precond="damped", r_reg=0.0, extract="rr"):
     """One WSSR step at averaging weight 0 (Alg. 2 with Alg. 1 for the SVD).
 
     Inputs: o (N x M) raw per-sample log-derivatives, e_l (N,) local energies,
     v_in (M x r) warm start, damping lam > 0, rank r, passes q >= 1.
+    r_reg: the truncation ratio of eq. ruler (0: none).  extract: "rr" for
+    the two-sided Rayleigh-Ritz ending, "diag" for Alg. 1's diag(R) ending.
     Returns dict(delta (M,), v (M x r), sigma (r,), g (M,), eps (N,))."""
     o = np.asarray(o, dtype=np.float64)
     n, m = o.shape
@@ -318,9 +367,15 @@ def wssr_step(o, e_l, v_in, lam, r, q, precond="damped"):
     eps = center_energies(e_l)
     a = scaled_centered(o)
     g = a.T @ eps / np.sqrt(n)
-    v, sigma, last = ssi_svd(a, np.asarray(v_in, dtype=np.float64)[:, :r], q)
-    delta = woodbury_apply(v, sigma, g, lam, precond)
-    return dict(delta=delta, v=v, sigma=sigma, g=g, eps=eps, last=last)
+    v_in = np.asarray(v_in, dtype=np.float64)[:, :r]
+    if extract == "diag":
+        v, sigma = ssi_diag_extract(a, v_in, q)
+        v, last = fix_signs(v, v_in), {}
+    else:
+        v, sigma, last = ssi_svd(a, v_in, q)
+    delta = truncated_woodbury(v, sigma, g, lam, precond, r_reg)
+    r_eff, grow = rank_ruler(sigma, r_reg)
+    return dict(delta=delta, v=v, sigma=sigma, g=g, eps=eps, last=last, r_eff=r_eff, grow=grow)
 
 
 def stack_averaged(a, lbar, state, avg):
@@ -353,7 +408,7 @@ def state_l(last, sgn, lhat):
     return sgn * (w.T @ lhat)
 
 
-def averaged_step(o, e_l, v_in, state, lam, r, q, avg, precond="damped"):
+def averaged_step(o, e_l, v_in, state, lam, r, q, avg, precond="damped", r_reg=0.0):
     """One WSSR step with the averaged state (Sec. 4.1: eqs. Ohat, Lhat,
     svd:det, Obar, Lbar, barg, barS and updated_sr_1; Alg. 2).
 
@@ -390,7 +445,7 @@ def averaged_step(o, e_l, v_in, state, lam, r, q, avg, precond="damped"):
     sgn = np.where(np.einsum("ij,ij->j", v, last["qz"] @ last["p"]) >= 0, 1.0, -1.0)
     l_new = state_l(last, sgn, lhat)
     gbar = ahat.T @ lhat                          # eq. barg
-    delta = woodbury_apply(v, sigma, gbar, lam, precond)
+    delta = truncated_woodbury(v, sigma, gbar, lam, precond, r_reg)
     g = a.T @ lbar
     return dict(delta=delta, v=v, sigma=sigma, l=l_new, gbar=gbar, g=g, eps=eps, last=last)
 

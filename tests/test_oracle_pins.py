@@ -707,3 +707,80 @@ def test_spring_rejects_bad_arguments():
     for lam, mu in ((0.0, 0.1), (0.1, 1.0), (0.1, -0.2)):
         with pytest.raises(ValueError):
             orc.spring_step(o, e, np.zeros(20), lam, mu, 0.1)
+
+
+# --------------------------------------------------------------- adaptive rank, diag(R) ending
+
+def test_rank_ruler_hand_cases():
+    """Eq. ruler on the squares of sigma: sigma = (1, 0.5, 0.3, 0.1) has
+    sigma^2 ratios (1, 0.25, 0.09, 0.01)."""
+    s = [1.0, 0.5, 0.3, 0.1]
+    assert orc.rank_ruler(s, 0.0) == (4, True)
+    assert orc.rank_ruler(s, 0.25) == (2, False)
+    assert orc.rank_ruler(s, 0.1) == (2, False)
+    assert orc.rank_ruler(s, 0.09) == (3, False)
+    assert orc.rank_ruler(s, 0.01) == (4, True)
+    assert orc.rank_ruler(s, 0.5) == (1, False)
+
+
+def test_truncated_woodbury_against_dense_inverse():
+    """Only the kept columns enter: delta = (V_k diag(s_k^2) V_k^T + lam I)^{-1} g,
+    and the floor form sends the dropped directions to 1/lam."""
+    rng = rng0(81)
+    m, r = 40, 6
+    v = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    s = np.array([2.0, 1.5, 1.0, 0.4, 0.2, 0.05])
+    g = rng.standard_normal(m)
+    lam, r_reg = 0.03, 0.02                     # keeps s^2 >= 0.08: the first four
+    assert orc.rank_ruler(s, r_reg)[0] == 4
+    d = orc.truncated_woodbury(v, s, g, lam, "damped", r_reg)
+    vk = v[:, :4]
+    want = np.linalg.solve((vk * s[:4] ** 2) @ vk.T + lam * np.eye(m), g)
+    assert _rel(d, want) < 1e-12
+    df = orc.truncated_woodbury(v, s, g, lam, "floor", r_reg)
+    pinv = (vk / s[:4] ** 2) @ vk.T + (np.eye(m) - vk @ vk.T) / lam
+    assert _rel(df, pinv @ g) < 1e-12
+
+
+def test_diag_extraction_converges_to_the_svd():
+    """Alg. 1's diag(R) ending: with many passes sigma and span(V) are the
+    exact top-r (LAPACK), column by column where the gaps are clear, and
+    sigma comes out sorted."""
+    n, m, r = 50, 80, 5
+    o, e = _problem(n, m, 82, spectrum=np.r_[np.linspace(1, 0.5, r), 0.05 * np.ones(n - r)], noise=0.0)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    _, s_ref, wt = np.linalg.svd(a)
+    # without a Rayleigh-Ritz rotation the columns separate at the rate of
+    # the gaps inside the top r, (0.875)^2 per pass here
+    v, s = orc.ssi_diag_extract(a, rng0(83).standard_normal((m, r)), 120)
+    assert np.all(np.diff(s) <= 0)
+    assert _rel(s, s_ref[:r]) < 1e-10
+    assert np.all(np.abs(np.sum(v * wt[:r].T, axis=0)) > 1 - 1e-8)
+    res = orc.wssr_step(o, e, rng0(83).standard_normal((m, r)), 1e-2, r, 120, extract="diag")
+    rr = orc.wssr_step(o, e, rng0(83).standard_normal((m, r)), 1e-2, r, 120)
+    assert _rel(res["delta"], rr["delta"]) < 1e-8
+
+
+def test_diag_extraction_one_pass_by_hand():
+    """q = 1: sigma = |diag R| of A orth(V_in), sorted, V = orth(V_in)
+    reordered (LAPACK QR written out here)."""
+    n, m, r = 30, 40, 4
+    o, e = _problem(n, m, 84)
+    a = (o - o.mean(axis=0)) / np.sqrt(n)
+    vin = rng0(85).standard_normal((m, r))
+    q0 = np.linalg.qr(vin)[0]
+    q0 = q0 * np.sign(np.diag(np.linalg.qr(vin)[1]))
+    rr = np.linalg.qr(a @ q0)[1]
+    s = np.abs(np.diag(rr))
+    order = np.argsort(-s)
+    v, sig = orc.ssi_diag_extract(a, vin, 1)
+    assert _rel(sig, s[order]) < 1e-13
+    assert np.abs(np.abs(v) - np.abs(q0[:, order])).max() < 1e-13
+
+
+def test_step_reports_the_ruler():
+    n, m, r = 40, 60, 8
+    o, e = _problem(n, m, 86)
+    res = orc.wssr_step(o, e, rng0(87).standard_normal((m, r)), 1e-3, r, 3, r_reg=0.05)
+    assert (res["r_eff"], res["grow"]) == orc.rank_ruler(res["sigma"], 0.05)
+    assert res["r_eff"] < r
