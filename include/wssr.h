@@ -91,6 +91,12 @@ typedef enum {
 /* Flags (wssr_config.flags). */
 #define WSSR_FLOOR_PRECOND 0x1u  /* eq. updated_sr_1 weights w_j = 1 - lambda/sigma_j^2 instead of
                                     the damped w_j = sigma_j^2/(sigma_j^2 + lambda) */
+#define WSSR_DIAGR_EXTRACT 0x8u  /* Alg. 1's own ending instead of the Rayleigh-Ritz step: the last
+                                    pass stops after the QR of its sample-side block A V (V
+                                    orthonormal), sigma = |diag(R)| sorted, and V is that basis in
+                                    the same order (one product fewer; sigma and V converge more
+                                    slowly inside the top r).  wssr_step, wssr_step_g and the
+                                    batched form; wssr_step_avg rejects it */
 #define WSSR_SAMPLE_SPACE 0x4u   /* allocate the workspace of wssr_spring: an n_max x n_max FP64
                                     matrix (8 n_max^2 bytes) and up to 268 MB of partial tiles */
 #define WSSR_GRAPH 0x2u          /* wssr_step_batched captures a batch into a HIP graph on its first
@@ -333,6 +339,22 @@ const char* wssr_last_error(wssr_handle h);
  * Cholesky (all its launches as one interval).  nslots <= 4. */
 wssr_status wssr_profile(wssr_handle h, int32_t enable);
 wssr_status wssr_profile_read(wssr_handle h, double* ms, int64_t* counts, int32_t nslots);
+
+/* Adaptive rank (Sec. 4.3, eq. ruler).  With r_reg > 0 the steps that follow
+ * keep in the preconditioned direction only the columns j with
+ * sigma_j^2 >= r_reg sigma_1^2 (the ratio on the eigenvalues of S): the
+ * damped weights of the others are 0, and in the floor form they take the
+ * floor 1/lambda (eq. updated_sr_1 with U of that rank).  V and sigma still
+ * return all r columns (the warm start and the averaged state keep them).
+ * 0 <= r_reg < 1; 0 (the default) keeps every column.  Applies to the
+ * handle's batch lanes too. */
+wssr_status wssr_set_rank_ratio(wssr_handle h, double r_reg);
+
+/* After a step: *r_eff = the rank eq. ruler kept, *grow = 1 when the last
+ * computed column passed the ratio (the paper's condition for growing r_max:
+ * the caller then pads V with new columns and steps at the larger rank; any
+ * full-rank basis is a valid warm start).  Synchronises the handle's stream. */
+wssr_status wssr_rank_info(wssr_handle h, int32_t* r_eff, int32_t* grow);
 
 /* Library version string, e.g. "libwssr 0.1 gfx950". */
 const char* wssr_version(void);

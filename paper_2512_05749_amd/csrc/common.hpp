@@ -25,7 +25,8 @@ struct DevStatus {
   int round2_count;       // second rounds actually run
   int rank_def;           // pivots of first-round Cholesky factorizations replaced in this step
   int repl;               // set by a first-round Cholesky that replaced a pivot; forces its second round
-  int pad;
+  int r_eff;              // rank kept by the truncation ratio (eq. ruler) in the last step's direction
+  int grow;               // the last computed value passed the ratio (the condition for growing r_max)
 };
 
 enum : int {

@@ -26,7 +26,7 @@ __global__ void k_sign_apply(const float* vnew, const float* sgn, int64_t total,
 __global__ void k_vtg_partial(const float* v, const double* g, int64_t m, int r, int64_t rows_per_chunk,
                               double* part, const DevStatus* st);
 __global__ void k_vtg_final(const double* part, int nchunk, int r, const double* sig_sorted, double lambda,
-                            int floor_form, double* cw, double* sigma_out, const DevStatus* st);
+                            int floor_form, double r_reg, double* cw, double* sigma_out, DevStatus* st);
 __global__ void k_delta(const float* v, const double* g, const double* cw, int64_t m, int r, double inv_lambda,
                         double* delta, const DevStatus* st);
 
@@ -169,6 +169,8 @@ __global__ void k_lhat(const double* eps, int64_t n, const double* l, int r, dou
 __global__ void k_state_l(const double* Rz, const double* Ps, int rp, int r, const double* t, const float* sgn,
                           double* sig, double wscale, double* l_out, const DevStatus* st);
 __global__ void k_transpose_rp(const double* R, int rp, int r, double* Ct, const DevStatus* st);
+__global__ void k_diag_sort(const double* R, int rp, int r, double* sig, int* perm, const DevStatus* st);
+__global__ void k_permute_cols(const float* src, int64_t m, int r, const int* perm, float* dst, const DevStatus* st);
 // sample-space solver (kernels_minsr.hip)
 template <typename T, int PL>
 __global__ void k_syrk_partial(const T* O, int64_t ld, int64_t pstride, int64_t n, int64_t m, int ntile,

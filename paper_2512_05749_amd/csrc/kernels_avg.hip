@@ -1,5 +1,6 @@
 // Small kernels of the averaged-state step (Sec. 4.1, eqs. Ohat, Lhat, Obar,
-// Lbar, barg) and of the randomized-sketch step (App. A).  In the averaged
+// Lbar, barg), of the randomized-sketch step (App. A) and of Alg. 1's
+// diag(R) ending.  In the averaged
 // step the stored matrix of the previous step, U diag(sigma), enters the
 // subspace iteration as r extra rows of the sample-side block; these kernels
 // build those rows and the r x r factors that carry them through the
@@ -93,6 +94,36 @@ __global__ __launch_bounds__(256) void k_transpose_rp(const double* __restrict__
   if (e >= (int64_t)rp * rp) return;
   const int i = (int)(e / rp), j = (int)(e % rp);
   Ct[e] = (i < r && j < r) ? R[(int64_t)j * rp + i] : 0.0;
+}
+
+// Alg. 1's diag(R) ending: sig = |diag(R)| (R rp x rp row-major, r used)
+// in descending order (ties by index) and perm[j] = the column that goes to
+// position j.  One workgroup; the rank of each value is counted.
+__global__ __launch_bounds__(512) void k_diag_sort(const double* __restrict__ R, int rp, int r,
+                                                   double* __restrict__ sig, int* __restrict__ perm,
+                                                   const DevStatus* st) {
+  if (failed(st)) return;
+  __shared__ double d[512];
+  for (int i = threadIdx.x; i < r; i += blockDim.x) d[i] = fabs(R[(int64_t)i * rp + i]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < r; i += blockDim.x) {
+    int pos = 0;
+    for (int k = 0; k < r; ++k) pos += d[k] > d[i] || (d[k] == d[i] && k < i);
+    sig[pos] = d[i];
+    perm[pos] = i;
+  }
+}
+
+// dst[:, j] = src[:, perm[j]] (m x r, row stride r).
+__global__ __launch_bounds__(256) void k_permute_cols(const float* __restrict__ src, int64_t m, int r,
+                                                      const int* __restrict__ perm, float* __restrict__ dst,
+                                                      const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * r) return;
+  const int64_t i = e / r;
+  const int j = (int)(e % r);
+  dst[e] = src[i * r + perm[j]];
 }
 
 }  // namespace wssr

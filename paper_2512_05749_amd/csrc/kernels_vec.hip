@@ -321,11 +321,13 @@ __global__ __launch_bounds__(256) void k_vtg_partial(const float* __restrict__ v
 }
 
 // Stage 2 (one block of 256 threads per column): cw_j = w_j * c_j; also
-// writes sigma to the caller.
+// writes sigma to the caller.  With r_reg > 0 only the columns with
+// sigma_j^2 >= r_reg sigma_0^2 enter (the rank of eq. ruler); block 0 records
+// that rank and whether the last column passed in the status word.
 __global__ __launch_bounds__(256) void k_vtg_final(const double* __restrict__ part, int nchunk, int r,
                                                    const double* __restrict__ sig_sorted, double lambda, int floor_form,
-                                                   double* __restrict__ cw, double* __restrict__ sigma_out,
-                                                   const DevStatus* st) {
+                                                   double r_reg, double* __restrict__ cw,
+                                                   double* __restrict__ sigma_out, DevStatus* st) {
   if (failed(st)) return;
   __shared__ double red[256];
   const int j = blockIdx.x, t = threadIdx.x;
@@ -340,9 +342,17 @@ __global__ __launch_bounds__(256) void k_vtg_final(const double* __restrict__ pa
   if (t == 0) {
     const double s = sig_sorted[j];
     const double s2 = s * s;
-    const double w = floor_form ? (s2 > 0.0 ? 1.0 - lambda / s2 : 0.0) : s2 / (s2 + lambda);
+    const double s0 = sig_sorted[0];
+    const bool keep = s2 >= r_reg * (s0 * s0);
+    const double w = !keep ? 0.0 : floor_form ? (s2 > 0.0 ? 1.0 - lambda / s2 : 0.0) : s2 / (s2 + lambda);
     cw[j] = w * red[0];
     sigma_out[j] = s;
+    if (j == 0) {
+      int k = 0;
+      for (int i = 0; i < r; ++i) k += sig_sorted[i] * sig_sorted[i] >= r_reg * (s0 * s0);
+      st->r_eff = k;
+      st->grow = sig_sorted[r - 1] * sig_sorted[r - 1] >= r_reg * (s0 * s0);
+    }
   }
 }
 
@@ -376,8 +386,9 @@ __global__ void k_status_init(DevStatus* st) {
     st->kappa_max = 0.0;
     st->round2_count = 0;
     st->rank_def = 0;
+    st->r_eff = 0;
+    st->grow = 0;
     st->repl = 0;
-    st->pad = 0;
   }
 }
 }  // namespace wssr

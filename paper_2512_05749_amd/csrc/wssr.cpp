@@ -97,6 +97,8 @@ struct wssr_ctx {
   // its K-chunk partial tiles, and n-vectors
   double *Tn = nullptr, *tpart = nullptr, *rho = nullptr, *su = nullptr, *sb = nullptr, *sscal = nullptr;
   int64_t tpart_tiles = 0;
+  double r_reg = 0.0;             // truncation ratio of eq. ruler (wssr_set_rank_ratio; 0: none)
+  int* perm = nullptr;            // column order of the diag(R) ending
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
 
@@ -237,9 +239,28 @@ struct wssr_ctx {
     if (hist) h->gram(V, m, r, false);
 
     const float* vcur = cont ? cont->vstart : V;
+    // Alg. 1's own ending: the last pass stops after the QR of its
+    // sample-side block, whose basis must be orthonormal (for q = 1, V_in is
+    // orthonormalised first)
+    const bool diag_end = (h->cfg.flags & WSSR_DIAGR_EXTRACT) && !cont && !av;
+    if (diag_end && q == 1) {
+      h->cholqr<float, float>(V, m, r, h->q1, nullptr);
+      h->apply((const float*)V, m, r, r, h->Tq, rp, r, h->vw, r, true);
+      vcur = h->vw;
+    }
     for (int p = 1; p <= q; ++p) {
       // sample side: Y = A V (FP64), then its QR: Q_Y = Y Tq (float)
       h->gemm_sample_side(O, ld_o, n, m, vcur, r);
+      if (diag_end && p == q) {
+        // sigma = |diag(R_Y)| sorted, V = the pass's basis in that order
+        h->cholqr<double, double>(h->y64, n, r, h->yq1, h->Rz);
+        hipLaunchKernelGGL(k_diag_sort, dim3(1), dim3(512), 0, stream, (const double*)h->Rz, rp, r, h->sig, h->perm,
+                           cst);
+        hipLaunchKernelGGL(k_permute_cols, dim3(cdiv(m * r, 256)), dim3(256), 0, stream, vcur, m, r,
+                           (const int*)h->perm, h->z, cst);
+        if (!g_ext) h->gradient(O, ld_o, n, m, e_l, h->g, stream, false);
+        return finish(n, m, h->z, V, V, r, lambda, delta, sigma, gv, nullptr, n);
+      }
       if (av) {
         hipLaunchKernelGGL(k_hist_rows, dim3(cdiv((int64_t)r * r, 256)), dim3(256), 0, stream, yh, r,
                            (const double*)av->sig_state, (const double*)(p == 1 ? h->G : h->Hn), rp, c_hist, cst);
@@ -505,7 +526,8 @@ struct wssr_ctx {
       hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
                          gv, m, r, rpc, h->vpart, cst);
       hipLaunchKernelGGL(k_vtg_final, dim3(r), dim3(256), 0, stream, (const double*)h->vpart, nch, r,
-                         (const double*)h->sig, lambda, (h->cfg.flags & WSSR_FLOOR_PRECOND) ? 1 : 0, h->cw, sigma, cst);
+                         (const double*)h->sig, lambda, (h->cfg.flags & WSSR_FLOOR_PRECOND) ? 1 : 0, h->r_reg, h->cw,
+                         sigma, h->st);
       hipLaunchKernelGGL(k_delta, dim3(cdiv(m, 4)), dim3(256), 0, stream, (const float*)V, gv,
                          (const double*)h->cw, m, r, 1.0 / lambda, delta, cst);
     }
@@ -1157,7 +1179,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->gram_part, (size_t)h->gram_part_elems) &&
             h->alloc(h->y1, (size_t)(n + r) * r) && h->alloc(h->Hc, (size_t)rp * rp) &&
             h->alloc(h->Hn, (size_t)rp * rp) && h->alloc(h->Bm, (size_t)rp * rp) && h->alloc(h->gbar, m) &&
-            h->alloc(h->lhat, (size_t)(n + r)) && h->alloc(h->tvec, rp) &&
+            h->alloc(h->lhat, (size_t)(n + r)) && h->alloc(h->tvec, rp) && h->alloc(h->perm, rp) &&
             h->alloc(h->G, (size_t)rp * rp) &&
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
             h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
@@ -1386,6 +1408,8 @@ wssr_status wssr_step_avg(wssr_handle h, int64_t n, int64_t m, const void* O, in
   if (s != WSSR_OK) return s;
   if (!l_state) return h->fail(WSSR_ERR_INVALID_ARG, "l_state is NULL");
   if (!(avg >= 0.0 && avg < 1.0)) return h->fail(WSSR_ERR_INVALID_ARG, "avg must be in [0, 1)");
+  if (h->cfg.flags & WSSR_DIAGR_EXTRACT)
+    return h->fail(WSSR_ERR_INVALID_ARG, "the averaged step needs the Rayleigh-Ritz ending (no WSSR_DIAGR_EXTRACT)");
   if (hipSetDevice(h->device) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipSetDevice failed");
   wssr_ctx::AvgArgs av{avg, sig_state, l_state, g_bar};
   return h->enqueue(n, m, O, ld_o, e_l, V, lambda, r, q, delta, sig_state, g, &av);
@@ -1681,6 +1705,25 @@ wssr_status wssr_status_sync(wssr_handle h, int32_t* numeric_status, double* dia
     diag[4] = s.kappa_max;
     diag[5] = (double)s.round2_count;
   }
+  return WSSR_OK;
+}
+
+wssr_status wssr_set_rank_ratio(wssr_handle h, double r_reg) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!(r_reg >= 0.0 && r_reg < 1.0)) return h->fail(WSSR_ERR_INVALID_ARG, "r_reg must be in [0, 1)");
+  h->r_reg = r_reg;
+  for (wssr_ctx* c : h->lanes) c->r_reg = r_reg;
+  return WSSR_OK;
+}
+
+wssr_status wssr_rank_info(wssr_handle h, int32_t* r_eff, int32_t* grow) {
+  if (!h || !r_eff || !grow) return WSSR_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(WSSR_ERR_HIP, "hipStreamSynchronize failed");
+  DevStatus s;
+  if (hipMemcpy(&s, h->st, sizeof s, hipMemcpyDeviceToHost) != hipSuccess)
+    return h->fail(WSSR_ERR_HIP, "status copy failed");
+  *r_eff = s.r_eff;
+  *grow = s.grow;
   return WSSR_OK;
 }
 

@@ -8,6 +8,7 @@ the library has not been built.
 from __future__ import annotations
 
 import ctypes
+import math
 import pathlib
 
 import torch
@@ -36,6 +37,7 @@ DTYPES = {"f32": F32, "bf16": BF16, "bf16x2": BF16X2, "bf16_split": BF16_SPLIT}
 FLOOR_PRECOND = 0x1
 GRAPH = 0x2
 SAMPLE_SPACE = 0x4
+DIAGR_EXTRACT = 0x8
 
 
 class WssrError(RuntimeError):
@@ -70,6 +72,8 @@ _SIGS = {
     "wssr_step_avg": ([_P, _I64, _I64, _P, _I64, _P, _P, _P, _D, _I32, _I32, _D, _P, _P, _P, _P], ctypes.c_int),
     "wssr_step_sketch": ([_P, _I64, _I64, _P, _I64, _P, _P, _P, _I32, _I32, _P, _D, _I32, _P, _P], ctypes.c_int),
     "wssr_spring": ([_P, _I64, _I64, _P, _I64, _P, _D, _D, _D, _P, _P], ctypes.c_int),
+    "wssr_set_rank_ratio": ([_P, _D], ctypes.c_int),
+    "wssr_rank_info": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "wssr_ingest": ([_P, _I64, _I64, _I64, _I64, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
     "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
@@ -131,13 +135,14 @@ class Wssr:
     """One libwssr handle bound to a device and a stream."""
 
     def __init__(self, n_max, m_max, r_max, q_max=8, floor_precond=False, device=None, stream=None, dtype="f32",
-                 lanes=0, graph=False, sample_space=False):
+                 lanes=0, graph=False, sample_space=False, diag_extract=False):
         """dtype: storage and product precision of O -- "f32"; "bf16" (one BF16
         product); "bf16_split" (BF16 O, skinny operand split in two); "bf16x2"
         (O as BF16 hi and lo planes, shape (2, n, m), three products).
         lanes, graph: the batched form (step_batched) -- problems run on this
         many concurrent lanes; graph captures a batch once and replays it.
-        sample_space: allocate the n_max x n_max workspace of spring()."""
+        sample_space: allocate the n_max x n_max workspace of spring().
+        diag_extract: Alg. 1's diag(R) ending instead of Rayleigh-Ritz."""
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
         self.dtype = dtype
@@ -149,7 +154,7 @@ class Wssr:
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
         flags = (FLOOR_PRECOND if floor_precond else 0) | (GRAPH if graph else 0) | \
-            (SAMPLE_SPACE if sample_space else 0)
+            (SAMPLE_SPACE if sample_space else 0) | (DIAGR_EXTRACT if diag_extract else 0)
         cfg = Config(int(n_max), int(m_max), int(r_max), int(q_max), DTYPES[dtype], flags,
                      ctypes.c_void_p(s.cuda_stream), int(lanes))
         h = ctypes.c_void_p()
@@ -305,6 +310,16 @@ class Wssr:
         self._check(lib().wssr_spring(self._h, n, m, _ptr(O), ld, _ptr(e_l), float(lam), float(momentum), float(eta),
                                       _ptr(dtheta) if dtheta is not None else nul, _ptr(delta)))
         return delta
+
+    def set_rank_ratio(self, r_reg):
+        """Truncation ratio of eq. ruler for the steps that follow (0: none)."""
+        self._check(lib().wssr_set_rank_ratio(self._h, float(r_reg)))
+
+    def rank_info(self):
+        """(r_eff, grow) of the last step (synchronises)."""
+        r_eff, grow = _I32(), _I32()
+        self._check(lib().wssr_rank_info(self._h, ctypes.byref(r_eff), ctypes.byref(grow)))
+        return r_eff.value, bool(grow.value)
 
     def storage_like(self, n, m):
         """An empty O buffer in this handle's storage form: (n, m) float32 or
@@ -498,3 +513,43 @@ def small_svd_noalloc(C, s=None, P=None, status=None, stream=None):
     if code != OK:
         raise WssrError(code, "wssr_small_svd_noalloc failed")
     return s, P, status
+
+
+class AdaptiveRank:
+    """Host side of the adaptive rank of Sec. 4.3 and Alg. 2: the handle keeps
+    only the columns that pass the ratio r_reg (eq. ruler, on the device);
+    after each step, when the last computed column passed too, r_max grows to
+    ceil((1 + eps) r_max), at most r_cap.  grow_basis() pads the warm start
+    (and the averaged state) to the new r_max: the new columns are drawn by
+    the caller's generator (any full-rank basis is a valid warm start), the
+    state's new entries are zero (its stored matrix gains zero columns)."""
+
+    def __init__(self, handle, r0, r_reg, eps, r_cap):
+        if not (0 < r0 <= r_cap) or not (0.0 <= r_reg < 1.0) or not eps > 0:
+            raise ValueError("bad adaptive-rank parameters")
+        self.h, self.r_max, self.r_reg, self.eps, self.r_cap = handle, int(r0), float(r_reg), float(eps), int(r_cap)
+        if handle is not None:
+            handle.set_rank_ratio(self.r_reg)
+
+    def next_rank(self, grow):
+        """r_max for the next step given the last step's grow flag."""
+        if grow and self.r_max < self.r_cap:
+            self.r_max = min(self.r_cap, int(math.ceil((1.0 + self.eps) * self.r_max)))
+        return self.r_max
+
+    def after_step(self):
+        """Read the last step's (r_eff, grow) and update r_max; returns r_eff."""
+        r_eff, grow = self.h.rank_info()
+        self.next_rank(grow)
+        return r_eff
+
+    def grow_basis(self, V, generator=None, state=()):
+        """V (m x r_old, float32) padded to m x r_max; state tensors ([r_old])
+        padded with zeros.  Returns (V, *state)."""
+        m, r_old = V.shape
+        if r_old >= self.r_max:
+            return (V, *state)
+        extra = torch.randn(m, self.r_max - r_old, generator=generator, device=V.device, dtype=V.dtype)
+        v = torch.cat([V, extra * (1.0 / math.sqrt(m))], dim=1).contiguous()
+        padded = [torch.cat([t, torch.zeros(self.r_max - r_old, dtype=t.dtype, device=t.device)]) for t in state]
+        return (v, *padded)

@@ -62,5 +62,32 @@ def test_null_handle_calls_are_rejected():
     assert lib.wssr_step_sketch(None, 10, 10, None, 10, None, None, None, 2, 0, None, 1.0, 1, None,
                                 None) == wssr.ERR_INVALID_ARG
     assert lib.wssr_spring(None, 10, 10, None, 10, None, 1.0, 0.0, 0.0, None, None) == wssr.ERR_INVALID_ARG
+    assert lib.wssr_set_rank_ratio(None, 0.1) == wssr.ERR_INVALID_ARG
+    assert lib.wssr_rank_info(None, None, None) == wssr.ERR_INVALID_ARG
     code = ctypes.c_int32()
     assert lib.wssr_status_sync(None, ctypes.byref(code), None) == wssr.ERR_INVALID_ARG
+
+
+def test_adaptive_rank_growth_rule():
+    """Host logic of the rank growth (Alg. 2): r_max <- ceil((1 + eps) r_max)
+    while the last column passes, capped; no growth otherwise."""
+    import torch
+
+    from paper_2512_05749_amd.wssr import AdaptiveRank
+    ar = AdaptiveRank(None, 100, 0.01, 0.2, 200)
+    assert ar.next_rank(False) == 100
+    assert ar.next_rank(True) == 120
+    assert ar.next_rank(True) == 144
+    assert ar.next_rank(True) == 173
+    assert ar.next_rank(True) == 200
+    assert ar.next_rank(True) == 200
+    ar = AdaptiveRank(None, 8, 0.01, 0.5, 64)
+    ar.next_rank(True)
+    v = torch.ones(30, 8)
+    s, l = torch.ones(8, dtype=torch.float64), torch.ones(8, dtype=torch.float64)
+    v2, s2, l2 = ar.grow_basis(v, torch.Generator().manual_seed(0), (s, l))
+    assert v2.shape == (30, 12) and torch.equal(v2[:, :8], v)
+    assert torch.equal(s2[8:], torch.zeros(4, dtype=torch.float64)) and torch.equal(l2[:8], l)
+    for bad in ((0, 0.1, 0.1, 10), (20, 0.1, 0.1, 10), (5, 1.0, 0.1, 10), (5, 0.1, 0.0, 10)):
+        with pytest.raises(ValueError):
+            AdaptiveRank(None, *bad)
