@@ -471,6 +471,10 @@ def env_info(dev):
         info["rocm"] = open("/opt/rocm/.info/version").read().strip()
     except OSError:
         info["rocm"] = None
+    if any(k.startswith("ROCPROF") for k in os.environ):
+        # under the profiler the query's own interpreter start is refused
+        info["clocks"] = None
+        return info
     try:
         res = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
         js = json.loads(res.stdout) if res.returncode == 0 else {}

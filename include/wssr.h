@@ -390,6 +390,19 @@ wssr_status wssr_dbg_gradient(wssr_handle h, int64_t n, int64_t m, const void* O
 wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_t r,
                              float* Q, double* R);
 
+/* Gram matrix G = X^T X (X float[rows x r] row-major, G double[r x r]): with
+ * f32 = 0 on the FP64 MFMA (exact products, FP64 sums); with f32 != 0 on the
+ * FP32 MFMA, FP32 sums flushed into FP64 every 256 rows (entries to about
+ * 1e-6 relative), the Gram used where only a span is carried on.
+ * rows <= max(n_max, m_max). */
+wssr_status wssr_dbg_gram(wssr_handle h, int64_t rows, const float* X, int32_t r, int32_t f32, double* G);
+
+/* The basis an intermediate pass carries on from Z = X (float[rows x r]): V
+ * (float[rows x r]) spans the columns of X, and *mode (device int32) says how
+ * it was made: 0 the columns scaled to unit norm (they were orthogonal), 1
+ * X R^{-1} from the FP32-MFMA Gram, 2 the FP64 CholeskyQR2.  rows <= m_max. */
+wssr_status wssr_dbg_span_basis(wssr_handle h, int64_t rows, const float* X, int32_t r, float* V, int32_t* mode);
+
 /* SVD of a small square matrix C (r x r, double, row-major): C = G diag(s) P^T
  * by block one-sided Jacobi.  s double[r] descending; P double[r x r] row-major. */
 wssr_status wssr_dbg_small_svd(wssr_handle h, const double* C, int32_t r, double* s, double* P);

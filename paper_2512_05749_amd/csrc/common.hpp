@@ -35,7 +35,8 @@ enum : int {
   ST_WARN_NOT_CONVERGED = 2,
   ST_NONFINITE = -5,
   ST_BREAKDOWN = -6,
-  ST_TIMEOUT = -7
+  ST_TIMEOUT = -7,
+  ST_SKIP = -1000          // a shadow status word whose kernels are not to run
 };
 
 __device__ __forceinline__ void raise_error(DevStatus* st, int code) {

@@ -111,12 +111,12 @@ __global__ void k_gemm16_sample_side_rs(const unsigned short* O, int64_t ld, int
                                         int64_t kchunk, const unsigned short* zeros, const DevStatus* st, int tn,
                                         int tj, bool xcd_groups);
 
-template <typename T>
-__global__ void k_gram_partial(const T* X, int64_t rows, int r, int ntile, int64_t rows_per_chunk, double* part,
-                               bool vec, const DevStatus* st, bool gated);
+template <typename T, bool F32>
+__global__ void k_gram_partial(const T* X, int64_t rows, int r, int64_t ldx, int ntile, int64_t rows_per_chunk,
+                               double* part, bool vec, const DevStatus* st, bool gated);
 __global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, int rp, double* G,
                               const DevStatus* st, bool gated);
-template <typename Tin, typename Tout>
+template <typename Tin, typename Tout, bool F32>
 __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
                         Tout* Out, int ldo, bool upper, bool vec, bool acc, const DevStatus* st, bool gated);
 template <typename TX, typename TW>
@@ -171,6 +171,10 @@ __global__ void k_state_l(const double* Rz, const double* Ps, int rp, int r, con
 __global__ void k_transpose_rp(const double* R, int rp, int r, double* Ct, const DevStatus* st);
 __global__ void k_diag_sort(const double* R, int rp, int r, double* sig, int* perm, const DevStatus* st);
 __global__ void k_permute_cols(const float* src, int64_t m, int r, const int* perm, float* dst, const DevStatus* st);
+__global__ void k_fast_decide(const DevStatus* probe, double kappa_orth, const DevStatus* main, DevStatus* st_f32,
+                              DevStatus* st_f64, int* mode);
+__global__ void k_colscale(const float* z, const double* gdiag, int64_t m, int r, float* v, const int* mode);
+__global__ void k_status_merge(const DevStatus* from, DevStatus* to);
 // sample-space solver (kernels_minsr.hip)
 template <typename T, int PL>
 __global__ void k_syrk_partial(const T* O, int64_t ld, int64_t pstride, int64_t n, int64_t m, int ntile,

@@ -126,4 +126,63 @@ __global__ __launch_bounds__(256) void k_permute_cols(const float* __restrict__ 
   dst[e] = src[i * r + perm[j]];
 }
 
+// fast_orth's choice from its probe (the FP32 Gram's Cholesky): mode 0 when
+// the columns are already orthogonal, 1 when the FP32 apply of R^{-1} is
+// well conditioned, 2 otherwise (and on any breakdown or replaced pivot).
+// The alternatives' status words start clean, or skipped (code ST_SKIP) when
+// not chosen; nothing is chosen when the step has already failed.
+__global__ void k_fast_decide(const DevStatus* __restrict__ probe, double kappa_orth, const DevStatus* main,
+                              DevStatus* __restrict__ st_f32, DevStatus* __restrict__ st_f64, int* __restrict__ mode) {
+  if (threadIdx.x != 0) return;
+  int md = 2;
+  if (!failed(probe) && probe->rank_def == 0 && probe->repl == 0) {
+    const double piv = probe->min_rel_pivot;
+    if (probe->kappa_max <= kappa_orth && piv >= 0.99)
+      md = 0;
+    else if (piv >= 0.03)
+      md = 1;
+  }
+  if (failed(main)) md = -1;
+  *mode = md;
+  DevStatus* sts[2] = {st_f32, st_f64};
+  for (int k = 0; k < 2; ++k) {
+    DevStatus* s = sts[k];
+    s->code = (md == k + 1) ? 0 : ST_SKIP;
+    s->chol_count = 0;
+    s->min_rel_pivot = 1.0;
+    s->jacobi_sweeps = 0.0;
+    s->jacobi_cosine = 0.0;
+    s->jacobi_done = 0;
+    s->round2 = 0;
+    s->kappa_max = 0.0;
+    s->round2_count = 0;
+    s->rank_def = 0;
+    s->repl = 0;
+    s->r_eff = 0;
+    s->grow = 0;
+  }
+}
+
+// V = Z diag(gdiag)^{-1/2} (columns scaled to unit norm) when mode == 0.
+__global__ __launch_bounds__(256) void k_colscale(const float* __restrict__ z, const double* __restrict__ gdiag,
+                                                  int64_t m, int r, float* __restrict__ v, const int* __restrict__ mode) {
+  if (*mode != 0) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * r) return;
+  const double d = gdiag[e % r];
+  v[e] = d > 0.0 ? (float)((double)z[e] / sqrt(d)) : 0.0f;
+}
+
+// Fold the FP64 alternative's outcome into the step's status: its error (if
+// it ran and failed) and its diagnostics.
+__global__ void k_status_merge(const DevStatus* __restrict__ from, DevStatus* __restrict__ to) {
+  if (threadIdx.x != 0 || from->code == ST_SKIP) return;
+  if (from->code < 0) raise_error(to, from->code);
+  to->chol_count += from->chol_count;
+  to->round2_count += from->round2_count;
+  to->rank_def += from->rank_def;
+  if (from->min_rel_pivot < to->min_rel_pivot) to->min_rel_pivot = from->min_rel_pivot;
+  if (from->kappa_max > to->kappa_max) to->kappa_max = from->kappa_max;
+}
+
 }  // namespace wssr

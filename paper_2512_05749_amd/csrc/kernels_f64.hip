@@ -1,6 +1,10 @@
-// FP64 kernels on the 16x16x4 FP64 MFMA for the orthonormalisation of the
-// tall blocks (CholeskyQR): the Gram matrix X^T X and the apply X T with a
-// small square T.  Inputs may be float or double; products and sums are FP64.
+// Kernels on the 16x16x4 MFMA for the orthonormalisation of the tall blocks
+// (CholeskyQR): the Gram matrix X^T X and the apply X T with a small square T.
+// Inputs may be float or double.  The FP64 instantiations multiply and sum in
+// FP64.  The F32 ones run the FP32 MFMA at twice the rate, for blocks whose
+// span is all that is used: the Gram's FP32 sums are flushed into FP64 every
+// 256 rows, so its entries carry about 1e-6 relative error; the apply's sums
+// run over at most r terms.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -13,6 +17,31 @@ constexpr int GS = GT + 16;     // LDS row stride in doubles: the four K-rows of
                                 // MFMA operand read fall into two halves of the banks
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// element type, accumulator and MFMA of the two precisions
+template <bool F32>
+struct Acc;
+// The two 16x16x4 MFMAs take A[i][k] from lane i + 16 k and B[k][j] from lane
+// j + 16 k alike, but place D differently: the FP64 one holds D[4 v + l/16][l%16]
+// in register v of lane l, the FP32 one D[4 (l/16) + v][l%16] (checked on the
+// device).  row() gives the D row of register v.
+template <>
+struct Acc<false> {
+  typedef double e;
+  typedef f64x4 v;
+  static __device__ __forceinline__ v mma(double a, double b, v c) { return mfma16x16x4d(a, b, c); }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * v + lk; }
+};
+template <>
+struct Acc<true> {
+  typedef float e;
+  typedef f32x4 v;
+  static __device__ __forceinline__ v mma(float a, float b, v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
+constexpr int kFlushSteps = 16;   // K-steps between FP64 flushes of the FP32 Gram accumulators
 
 // four consecutive elements p[0..3] as doubles; n of them valid (the rest 0)
 __device__ __forceinline__ f64x4 load4d(const float* __restrict__ p, int n, bool vec) {
@@ -60,13 +89,15 @@ __device__ __forceinline__ void tile_pair(int pair, int ntile, int& I, int& J) {
 // FP64 while the next 16 rows are being loaded into registers.
 // part[(chunk * npairs + pair) * 16384 + i * 128 + j].
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X, int64_t rows, int r, int ntile,
-                                                         int64_t rows_per_chunk, double* __restrict__ part, bool vec,
-                                                         const DevStatus* st, bool gated) {
+template <typename T, bool F32>
+__global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X, int64_t rows, int r, int64_t ldx,
+                                                         int ntile, int64_t rows_per_chunk, double* __restrict__ part,
+                                                         bool vec, const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
-  __shared__ double XI[GK][GS];
-  __shared__ double XJ[GK][GS];
+  typedef typename Acc<F32>::e E;
+  typedef typename Acc<F32>::v Vt;
+  __shared__ E XI[GK][GS];
+  __shared__ E XJ[GK][GS];
   int I, J;
   tile_pair(blockIdx.x, ntile, I, J);
   const bool diag = I == J;
@@ -77,11 +108,15 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
   const int64_t rbeg = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t rend = min(rows, rbeg + rows_per_chunk);
 
-  f64x4 acc[4][4];
+  Vt acc[4][4];
+  f64x4 acc64[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0};
+    for (int b = 0; b < 4; ++b) {
+      acc[a][b] = Vt{0, 0, 0, 0};
+      acc64[a][b] = f64x4{0, 0, 0, 0};
+    }
 
   // thread -> (K-row, 4 columns) of a 16 x 128 block, two units per thread
   f64x4 pi[2], pj[2];
@@ -93,8 +128,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
       const int c4 = (idx & 31) * 4;
       const int ci = I * GT + c4, cj = J * GT + c4;
       const bool row_ok = gr < rend;
-      pi[e] = load4d(X + gr * r + ci, row_ok ? min(4, r - ci) : 0, vec);
-      if (!diag) pj[e] = load4d(X + gr * r + cj, row_ok ? min(4, r - cj) : 0, vec);
+      pi[e] = load4d(X + gr * ldx + ci, row_ok ? min(4, r - ci) : 0, vec);
+      if (!diag) pj[e] = load4d(X + gr * ldx + cj, row_ok ? min(4, r - cj) : 0, vec);
     }
   };
   auto store = [&]() __attribute__((always_inline)) {
@@ -102,24 +137,25 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
     for (int e = 0; e < 2; ++e) {
       const int idx = t + 256 * e;
       const int kr = idx >> 5, c4 = (idx & 31) * 4;
-      *reinterpret_cast<f64x2*>(&XI[kr][c4]) = f64x2{pi[e][0], pi[e][1]};
-      *reinterpret_cast<f64x2*>(&XI[kr][c4 + 2]) = f64x2{pi[e][2], pi[e][3]};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) XI[kr][c4 + q] = (E)pi[e][q];
       if (!diag) {
-        *reinterpret_cast<f64x2*>(&XJ[kr][c4]) = f64x2{pj[e][0], pj[e][1]};
-        *reinterpret_cast<f64x2*>(&XJ[kr][c4 + 2]) = f64x2{pj[e][2], pj[e][3]};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) XJ[kr][c4 + q] = (E)pj[e][q];
       }
     }
   };
+  int since = 0;
   if (rbeg < rend) load(rbeg);
   for (int64_t k0 = rbeg; k0 < rend; k0 += GK) {
     store();
     __syncthreads();
     if (k0 + GK < rend) load(k0 + GK);
-    const double(*B)[GS] = diag ? XI : XJ;
+    const E(*B)[GS] = diag ? XI : XJ;
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int k = kk * 4 + lk;
-      double av[4], bv[4];
+      E av[4], bv[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = XI[k][qi * 64 + a * 16 + li];
 #pragma unroll
@@ -127,7 +163,20 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = Acc<F32>::mma(av[a], bv[b], acc[a][b]);
+    }
+    if constexpr (F32) {
+      if (++since == kFlushSteps) {
+        since = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
+            acc[a][b] = Vt{0, 0, 0, 0};
+          }
+      }
     }
     __syncthreads();
   }
@@ -138,9 +187,12 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = qi * 64 + a * 16 + 4 * v + lk;
+        const int i = qi * 64 + a * 16 + Acc<F32>::row(v, lk);
         const int j = qj * 64 + b * 16 + li;
-        out[i * GT + j] = acc[a][b][v];
+        if constexpr (F32)
+          out[i * GT + j] = acc64[a][b][v] + (double)acc[a][b][v];
+        else
+          out[i * GT + j] = (double)acc[a][b][v];
       }
 }
 
@@ -189,14 +241,16 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 // skipped.  The next K-step's tiles are loaded into registers while the
 // current ones are multiplied.
 // ---------------------------------------------------------------------------
-template <typename Tin, typename Tout>
+template <typename Tin, typename Tout, bool F32>
 __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int64_t rows, int ldx, int kdim,
                                                   const double* __restrict__ Tm, int rp, int ncol,
                                                   Tout* __restrict__ Out, int ldo, bool upper, bool vec,
                                                   bool acc, const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
-  __shared__ double Xs[GK][GS];   // [k][row]
-  __shared__ double Ts[GK][GS];   // [k][col]
+  typedef typename Acc<F32>::e E;
+  typedef typename Acc<F32>::v Vt;
+  __shared__ E Xs[GK][GS];   // [k][row]
+  __shared__ E Ts[GK][GS];   // [k][col]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int qi = w >> 1, qj = w & 1;
   const int li = lane & 15, lk = lane >> 4;
@@ -204,11 +258,11 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
   const int col0 = blockIdx.y * GT;
   const int kend = upper ? min(kdim, col0 + GT) : kdim;
 
-  f64x4 acc_v[4][4];
+  Vt acc_v[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc_v[a][b] = f64x4{0};
+    for (int b = 0; b < 4; ++b) acc_v[a][b] = Vt{0, 0, 0, 0};
 
   // X: thread -> (row, 4 K-values), two units; T: thread -> (K-row, 2 columns), four units
   f64x4 px[2];
@@ -242,12 +296,13 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
       const int idx = t + 256 * e;
       const int rr = idx >> 2, kq = (idx & 3) * 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Xs[kq + q][rr] = px[e][q];
+      for (int q = 0; q < 4; ++q) Xs[kq + q][rr] = (E)px[e][q];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = t + 256 * e;
-      *reinterpret_cast<f64x2*>(&Ts[idx >> 6][(idx & 63) * 2]) = pt[e];
+      Ts[idx >> 6][(idx & 63) * 2] = (E)pt[e][0];
+      Ts[idx >> 6][(idx & 63) * 2 + 1] = (E)pt[e][1];
     }
   };
   if (kend > 0) load(0);
@@ -258,7 +313,7 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int k = kk * 4 + lk;
-      double av[4], bv[4];
+      E av[4], bv[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = Xs[k][qi * 64 + a * 16 + li];
 #pragma unroll
@@ -266,7 +321,7 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc_v[a][b] = mfma16x16x4d(av[a], bv[b], acc_v[a][b]);
+        for (int b = 0; b < 4; ++b) acc_v[a][b] = Acc<F32>::mma(av[a], bv[b], acc_v[a][b]);
     }
     __syncthreads();
   }
@@ -276,10 +331,11 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t i = row0 + qi * 64 + a * 16 + 4 * v + lk;
+        const int64_t i = row0 + qi * 64 + a * 16 + Acc<F32>::row(v, lk);
         const int j = col0 + qj * 64 + b * 16 + li;
         if (i < rows && j < ncol)
-          Out[i * ldo + j] = acc ? (Tout)(acc_v[a][b][v] + (double)Out[i * ldo + j]) : (Tout)acc_v[a][b][v];
+          Out[i * ldo + j] = acc ? (Tout)((double)acc_v[a][b][v] + (double)Out[i * ldo + j])
+                                 : (Tout)acc_v[a][b][v];
       }
 }
 
@@ -394,17 +450,21 @@ __global__ __launch_bounds__(256) void k_cross_reduce(const double* __restrict__
 }
 
 // explicit instantiations used by the host runtime
-template __global__ void k_gram_partial<float>(const float*, int64_t, int, int, int64_t, double*, bool,
-                                               const DevStatus*, bool);
-template __global__ void k_gram_partial<double>(const double*, int64_t, int, int, int64_t, double*, bool,
-                                                const DevStatus*, bool);
+template __global__ void k_gram_partial<float, false>(const float*, int64_t, int, int64_t, int, int64_t, double*,
+                                                      bool, const DevStatus*, bool);
+template __global__ void k_gram_partial<float, true>(const float*, int64_t, int, int64_t, int, int64_t, double*, bool,
+                                                     const DevStatus*, bool);
+template __global__ void k_gram_partial<double, false>(const double*, int64_t, int, int64_t, int, int64_t, double*,
+                                                       bool, const DevStatus*, bool);
 template __global__ void k_cross_partial<double, float>(const double*, const float*, int64_t, int, int, int64_t,
                                                         double*, bool, const DevStatus*);
-template __global__ void k_apply<float, float>(const float*, int64_t, int, int, const double*, int, int, float*, int,
-                                               bool, bool, bool, const DevStatus*, bool);
-template __global__ void k_apply<double, float>(const double*, int64_t, int, int, const double*, int, int, float*,
-                                                int, bool, bool, bool, const DevStatus*, bool);
-template __global__ void k_apply<double, double>(const double*, int64_t, int, int, const double*, int, int, double*,
-                                                 int, bool, bool, bool, const DevStatus*, bool);
+template __global__ void k_apply<float, float, false>(const float*, int64_t, int, int, const double*, int, int, float*,
+                                                      int, bool, bool, bool, const DevStatus*, bool);
+template __global__ void k_apply<float, float, true>(const float*, int64_t, int, int, const double*, int, int, float*,
+                                                     int, bool, bool, bool, const DevStatus*, bool);
+template __global__ void k_apply<double, float, false>(const double*, int64_t, int, int, const double*, int, int,
+                                                       float*, int, bool, bool, bool, const DevStatus*, bool);
+template __global__ void k_apply<double, double, false>(const double*, int64_t, int, int, const double*, int, int,
+                                                        double*, int, bool, bool, bool, const DevStatus*, bool);
 
 }  // namespace wssr

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -26,6 +27,11 @@ constexpr int kJacobiSweeps = 30;
 constexpr int kJacobiInner = 1;     // inner sweeps per block step
 constexpr double kJacobiTol = 1e-8;
 constexpr double kKappaRound2 = 1e4;
+#ifdef WSSR_FAST_MID_OFF
+constexpr bool kFastMid = false;   // intermediate passes always take the FP64 CholeskyQR2
+#else
+constexpr bool kFastMid = true;
+#endif
 constexpr int kBatchMax = 1024;     // problems per batched step
 constexpr int kLanesMax = 16;       // concurrent batch lanes
 #ifndef WSSR_RS_ROUNDS
@@ -98,6 +104,8 @@ struct wssr_ctx {
   double *Tn = nullptr, *tpart = nullptr, *rho = nullptr, *su = nullptr, *sb = nullptr, *sscal = nullptr;
   int64_t tpart_tiles = 0;
   double r_reg = 0.0;             // truncation ratio of eq. ruler (wssr_set_rank_ratio; 0: none)
+  DevStatus* shadow = nullptr;    // status words of fast_orth's probe and alternatives (3)
+  int* fmode = nullptr;           // fast_orth's choice (0 scale, 1 FP32 apply, 2 FP64 CholeskyQR)
   int* perm = nullptr;            // column order of the diag(R) ending
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
@@ -275,6 +283,12 @@ struct wssr_ctx {
         hipLaunchKernelGGL(k_hist_b, dim3(cdiv((int64_t)rp * rp, 256)), dim3(256), 0, stream,
                            (const float*)(h->qy + n * r), r, (const double*)av->sig_state, c_hist, h->Bm, rp, cst);
         h->apply((const float*)V, m, r, r, h->Bm, rp, r, h->z, r, false, false, true);
+      }
+      if (kFastMid && !av && p < q) {
+        // an intermediate pass: only the span of Z is carried on
+        h->fast_orth(h->z, m, r);
+        vcur = h->vw;
+        continue;
       }
       h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
       if (p < q) {
@@ -970,15 +984,26 @@ struct wssr_ctx {
     return (int)std::max<int64_t>(1, std::min(std::min(cdiv(512, npairs), cdiv(rows, 256)), cap));
   }
 
+  // f32: the FP32-MFMA Gram (float X only), for blocks whose span is all that is used
   template <typename T>
-  void gram(const T* X, int64_t rows, int r, bool gated) {
+  void gram(const T* X, int64_t rows, int r, bool gated, bool f32 = false) {
     const int rp = (int)rup(r, 64), nt = (int)cdiv(r, kF64Tile), npairs = nt * (nt + 1) / 2;
     int nch = gram_chunks(rows, npairs);
     const int64_t rpc = std::max<int64_t>(16, rup(cdiv(rows, nch), 16));
     nch = (int)std::max<int64_t>(1, cdiv(rows, rpc));
     const bool vec = (r % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    hipLaunchKernelGGL(k_gram_partial<T>, dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, nt, rpc, gram_part,
-                       vec, (const DevStatus*)st, gated);
+    const int64_t ldx = r;
+    if constexpr (std::is_same<T, float>::value) {
+      if (f32)
+        hipLaunchKernelGGL((k_gram_partial<float, true>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx,
+                           nt, rpc, gram_part, vec, (const DevStatus*)st, gated);
+      else
+        hipLaunchKernelGGL((k_gram_partial<float, false>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx,
+                           nt, rpc, gram_part, vec, (const DevStatus*)st, gated);
+    } else {
+      hipLaunchKernelGGL((k_gram_partial<T, false>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx, nt,
+                         rpc, gram_part, vec, (const DevStatus*)st, gated);
+    }
     hipLaunchKernelGGL(k_gram_reduce, dim3(npairs, kF64Tile * kF64Tile / 256), dim3(256), 0, stream,
                        (const double*)gram_part, nch, nt, r, rp, G, (const DevStatus*)st, gated);
   }
@@ -1010,10 +1035,51 @@ struct wssr_ctx {
 
   template <typename Tin, typename Tout>
   void apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol, Tout* out, int ldo,
-             bool upper, bool gated = false, bool acc = false) {
+             bool upper, bool gated = false, bool acc = false, bool f32 = false) {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    hipLaunchKernelGGL((k_apply<Tin, Tout>), dim3(cdiv(rows, kF64Tile), cdiv(ncol, kF64Tile)), dim3(256), 0, stream,
-                       X, rows, ldx, kdim, Tm, rp, ncol, out, ldo, upper, vec, acc, (const DevStatus*)st, gated);
+    const dim3 grid(cdiv(rows, kF64Tile), cdiv(ncol, kF64Tile));
+    if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
+      if (f32) {
+        hipLaunchKernelGGL((k_apply<float, float, true>), grid, dim3(256), 0, stream, X, rows, ldx, kdim, Tm, rp, ncol,
+                           out, ldo, upper, vec, acc, (const DevStatus*)st, gated);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_apply<Tin, Tout, false>), grid, dim3(256), 0, stream, X, rows, ldx, kdim, Tm, rp, ncol, out,
+                       ldo, upper, vec, acc, (const DevStatus*)st, gated);
+  }
+
+  // An intermediate pass's parameter-side basis: any V = Z T with the span of
+  // Z serves the next pass, so the exact FP64 CholeskyQR is not needed where
+  // Z is well conditioned.  An FP32-MFMA Gram and its Cholesky decide on the
+  // device: columns already orthogonal (condition bound within
+  // sqrt(r (r + 8)), every relative pivot >= 0.99) -> V = Z diag(G)^{-1/2};
+  // relative pivots >= 0.03 -> V = Z R^{-1} by the FP32-MFMA apply; otherwise
+  // (or on a breakdown) the FP64 CholeskyQR2 and apply.  The alternatives not
+  // taken skip through shadow status words; the FP64 path's errors and
+  // diagnostics are merged into the step's status.  Leaves V in vw.
+  void fast_orth(float* Z, int64_t m, int r) {
+    const int rp = (int)rup(r, 64);
+    DevStatus* main = st;
+    DevStatus* probe = shadow;
+    DevStatus* st_f32 = shadow + 1;
+    DevStatus* st_f64 = shadow + 2;
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, probe);
+    st = probe;
+    gram((const float*)Z, m, r, false, true);
+    chol(rp, r, R1, R1i, false);
+    st = main;
+    hipLaunchKernelGGL(k_fast_decide, dim3(1), dim3(64), 0, stream, (const DevStatus*)probe,
+                       std::sqrt((double)r * (r + 8.0)), (const DevStatus*)main, st_f32, st_f64, fmode);
+    hipLaunchKernelGGL(k_colscale, dim3(cdiv(m * r, 256)), dim3(256), 0, stream, (const float*)Z,
+                       (const double*)gdiag, m, r, vw, (const int*)fmode);
+    st = st_f32;
+    apply((const float*)Z, m, r, r, R1i, rp, r, vw, r, true, false, false, true);
+    st = st_f64;
+    cholqr<float, float>(Z, m, r, q1, nullptr);
+    apply((const float*)Z, m, r, r, Tq, rp, r, vw, r, true);
+    st = main;
+    hipLaunchKernelGGL(k_status_merge, dim3(1), dim3(64), 0, stream, (const DevStatus*)st_f64, main);
   }
 
   // H = X^T W (rp x rp, zero outside r x r) for two rows x r blocks
@@ -1180,6 +1246,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->y1, (size_t)(n + r) * r) && h->alloc(h->Hc, (size_t)rp * rp) &&
             h->alloc(h->Hn, (size_t)rp * rp) && h->alloc(h->Bm, (size_t)rp * rp) && h->alloc(h->gbar, m) &&
             h->alloc(h->lhat, (size_t)(n + r)) && h->alloc(h->tvec, rp) && h->alloc(h->perm, rp) &&
+            h->alloc(h->shadow, 3) && h->alloc(h->fmode, 1) &&
             h->alloc(h->G, (size_t)rp * rp) &&
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
             h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
@@ -1806,6 +1873,34 @@ wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_
   h->apply((const float*)xc, rows, r, r, h->Tq, rp, r, Q, r, true);
   (void)hipMemcpy2DAsync(R, sizeof(double) * r, h->Rz, sizeof(double) * rp, sizeof(double) * r, r,
                          hipMemcpyDeviceToDevice, h->stream);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_dbg_gram(wssr_handle h, int64_t rows, const float* X, int32_t r, int32_t f32, double* G) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!X || !G) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (r < 1 || r > h->cfg.r_max) return h->fail(WSSR_ERR_INVALID_ARG, "r outside [1, r_max]");
+  if (rows < 1 || rows > h->rows_max) return h->fail(WSSR_ERR_INVALID_ARG, "rows outside [1, max(n_max, m_max)]");
+  const int rp = (int)rup(r, 64);
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  h->gram(X, rows, r, false, f32 != 0);
+  (void)hipMemcpy2DAsync(G, sizeof(double) * r, h->G, sizeof(double) * rp, sizeof(double) * r, r,
+                         hipMemcpyDeviceToDevice, h->stream);
+  if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
+  return WSSR_OK;
+}
+
+wssr_status wssr_dbg_span_basis(wssr_handle h, int64_t rows, const float* X, int32_t r, float* V, int32_t* mode) {
+  if (!h) return WSSR_ERR_INVALID_ARG;
+  if (!X || !V || !mode) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (r < 1 || r > h->cfg.r_max) return h->fail(WSSR_ERR_INVALID_ARG, "r outside [1, r_max]");
+  if (rows < r || rows > h->cfg.m_max) return h->fail(WSSR_ERR_INVALID_ARG, "rows outside [r, m_max]");
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
+  (void)hipMemcpyAsync(h->z, X, sizeof(float) * rows * r, hipMemcpyDeviceToDevice, h->stream);
+  h->fast_orth(h->z, rows, r);
+  (void)hipMemcpyAsync(V, h->vw, sizeof(float) * rows * r, hipMemcpyDeviceToDevice, h->stream);
+  (void)hipMemcpyAsync(mode, h->fmode, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
   return WSSR_OK;
 }

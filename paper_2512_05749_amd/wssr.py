@@ -74,6 +74,8 @@ _SIGS = {
     "wssr_spring": ([_P, _I64, _I64, _P, _I64, _P, _D, _D, _D, _P, _P], ctypes.c_int),
     "wssr_set_rank_ratio": ([_P, _D], ctypes.c_int),
     "wssr_rank_info": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
+    "wssr_dbg_gram": ([_P, _I64, _P, _I32, _I32, _P], ctypes.c_int),
+    "wssr_dbg_span_basis": ([_P, _I64, _P, _I32, _P, _P], ctypes.c_int),
     "wssr_ingest": ([_P, _I64, _I64, _I64, _I64, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "wssr_status_sync": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_D)], ctypes.c_int),
     "wssr_step_batched": ([_P, _P, _I32], ctypes.c_int),
@@ -477,6 +479,22 @@ class Wssr:
         R = torch.empty(r, r, dtype=torch.float64, device=self.device)
         self._check(lib().wssr_dbg_cholqr2(self._h, rows, _ptr(X), r, _ptr(Q), _ptr(R)))
         return Q, R
+
+    def gram(self, X, f32=False):
+        rows, r = X.shape
+        _need(X, "X", torch.float32, self.device, contiguous=True)
+        G = torch.empty(r, r, dtype=torch.float64, device=self.device)
+        self._check(lib().wssr_dbg_gram(self._h, rows, _ptr(X), r, int(bool(f32)), _ptr(G)))
+        return G
+
+    def span_basis(self, X):
+        """(V, mode) of an intermediate pass's basis from Z = X."""
+        rows, r = X.shape
+        _need(X, "X", torch.float32, self.device, contiguous=True)
+        V = torch.empty_like(X)
+        mode = torch.empty(1, dtype=torch.int32, device=self.device)
+        self._check(lib().wssr_dbg_span_basis(self._h, rows, _ptr(X), r, _ptr(V), _ptr(mode)))
+        return V, int(mode.item())
 
     def small_svd(self, C):
         r = C.shape[0]
