@@ -171,8 +171,9 @@ __global__ void k_state_l(const double* Rz, const double* Ps, int rp, int r, con
 __global__ void k_transpose_rp(const double* R, int rp, int r, double* Ct, const DevStatus* st);
 __global__ void k_diag_sort(const double* R, int rp, int r, double* sig, int* perm, const DevStatus* st);
 __global__ void k_permute_cols(const float* src, int64_t m, int r, const int* perm, float* dst, const DevStatus* st);
-__global__ void k_fast_decide(const DevStatus* probe, double kappa_orth, const DevStatus* main, DevStatus* st_f32,
-                              DevStatus* st_f64, int* mode);
+__global__ void k_fast_decide(const DevStatus* probe, double kappa_orth, double piv_fast, DevStatus* main,
+                              DevStatus* st_m1, DevStatus* st_m2, DevStatus* st_m01, int* mode);
+__global__ void k_copy_st(const double* src, int64_t count, double* dst, const DevStatus* st);
 __global__ void k_colscale(const float* z, const double* gdiag, int64_t m, int r, float* v, const int* mode);
 __global__ void k_status_merge(const DevStatus* from, DevStatus* to);
 // sample-space solver (kernels_minsr.hip)

@@ -126,28 +126,39 @@ __global__ __launch_bounds__(256) void k_permute_cols(const float* __restrict__ 
   dst[e] = src[i * r + perm[j]];
 }
 
-// fast_orth's choice from its probe (the FP32 Gram's Cholesky): mode 0 when
-// the columns are already orthogonal, 1 when the FP32 apply of R^{-1} is
-// well conditioned, 2 otherwise (and on any breakdown or replaced pivot).
-// The alternatives' status words start clean, or skipped (code ST_SKIP) when
-// not chosen; nothing is chosen when the step has already failed.
-__global__ void k_fast_decide(const DevStatus* __restrict__ probe, double kappa_orth, const DevStatus* main,
-                              DevStatus* __restrict__ st_f32, DevStatus* __restrict__ st_f64, int* __restrict__ mode) {
+// The choice between the FP32 probe's factorisation and the FP64
+// CholeskyQR2, from the probe (the FP32 Gram's Cholesky): mode 0 when the
+// columns are already orthogonal (condition bound <= kappa_orth, every
+// relative pivot >= 0.99), 1 when every relative pivot is >= piv_fast, 2
+// otherwise (and on any breakdown or replaced pivot); -1 when the step has
+// already failed.  The alternatives' status words start clean, or skipped
+// (code ST_SKIP) when not chosen: st_m1 runs in mode 1, st_m2 in mode 2,
+// st_m01 in modes 0 and 1.  When the probe's factor is used its diagnostics
+// are folded into the step's status.
+__global__ void k_fast_decide(const DevStatus* __restrict__ probe, double kappa_orth, double piv_fast,
+                              DevStatus* __restrict__ main, DevStatus* __restrict__ st_m1, DevStatus* __restrict__ st_m2,
+                              DevStatus* __restrict__ st_m01, int* __restrict__ mode) {
   if (threadIdx.x != 0) return;
   int md = 2;
   if (!failed(probe) && probe->rank_def == 0 && probe->repl == 0) {
     const double piv = probe->min_rel_pivot;
     if (probe->kappa_max <= kappa_orth && piv >= 0.99)
       md = 0;
-    else if (piv >= 0.03)
+    else if (piv >= piv_fast)
       md = 1;
   }
   if (failed(main)) md = -1;
   *mode = md;
-  DevStatus* sts[2] = {st_f32, st_f64};
-  for (int k = 0; k < 2; ++k) {
+  if (md == 0 || md == 1) {
+    main->chol_count += probe->chol_count;
+    if (probe->min_rel_pivot < main->min_rel_pivot) main->min_rel_pivot = probe->min_rel_pivot;
+    if (probe->kappa_max > main->kappa_max) main->kappa_max = probe->kappa_max;
+  }
+  DevStatus* sts[3] = {st_m1, st_m2, st_m01};
+  const bool run[3] = {md == 1, md == 2, md == 0 || md == 1};
+  for (int k = 0; k < 3; ++k) {
     DevStatus* s = sts[k];
-    s->code = (md == k + 1) ? 0 : ST_SKIP;
+    s->code = run[k] ? 0 : ST_SKIP;
     s->chol_count = 0;
     s->min_rel_pivot = 1.0;
     s->jacobi_sweeps = 0.0;
@@ -161,6 +172,14 @@ __global__ void k_fast_decide(const DevStatus* __restrict__ probe, double kappa_
     s->r_eff = 0;
     s->grow = 0;
   }
+}
+
+// dst = src (count doubles) unless the status word says skip.
+__global__ __launch_bounds__(256) void k_copy_st(const double* __restrict__ src, int64_t count,
+                                                 double* __restrict__ dst, const DevStatus* st) {
+  if (failed(st)) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < count) dst[e] = src[e];
 }
 
 // V = Z diag(gdiag)^{-1/2} (columns scaled to unit norm) when mode == 0.

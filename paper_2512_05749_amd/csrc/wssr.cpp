@@ -104,7 +104,7 @@ struct wssr_ctx {
   double *Tn = nullptr, *tpart = nullptr, *rho = nullptr, *su = nullptr, *sb = nullptr, *sscal = nullptr;
   int64_t tpart_tiles = 0;
   double r_reg = 0.0;             // truncation ratio of eq. ruler (wssr_set_rank_ratio; 0: none)
-  DevStatus* shadow = nullptr;    // status words of fast_orth's probe and alternatives (3)
+  DevStatus* shadow = nullptr;    // status words of the factorisation probe and its alternatives (4)
   int* fmode = nullptr;           // fast_orth's choice (0 scale, 1 FP32 apply, 2 FP64 CholeskyQR)
   int* perm = nullptr;            // column order of the diag(R) ending
   float *maxval = nullptr, *sgn = nullptr;
@@ -284,13 +284,17 @@ struct wssr_ctx {
                            (const float*)(h->qy + n * r), r, (const double*)av->sig_state, c_hist, h->Bm, rp, cst);
         h->apply((const float*)V, m, r, r, h->Bm, rp, r, h->z, r, false, false, true);
       }
-      if (kFastMid && !av && p < q) {
+      const bool fast = kFastMid && !av;
+      if (fast && p < q) {
         // an intermediate pass: only the span of Z is carried on
         h->fast_orth(h->z, m, r);
         vcur = h->vw;
         continue;
       }
-      h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
+      if (fast)
+        h->fast_factor(h->z, m, r);
+      else
+        h->cholqr<float, float>(h->z, m, r, h->q1, p == q ? h->Rz : nullptr);
       if (p < q) {
         if (av) {
           // V_in^T V_{p+1} = (Y_1^T Q_Y) Tq for the next pass's history rows
@@ -314,7 +318,10 @@ struct wssr_ctx {
         h->small_svd(h->Rz, r);
         // V = Q_Z P = Z (Tq P)
         h->smallgemm(h->Tq, h->Ps, rp, h->T, false, false);
-        h->apply((const float*)h->z, m, r, r, h->T, rp, r_out, h->vw, r_out, false);
+        if (fast && r_out == r)
+          h->final_apply(h->z, m, r, h->T, h->vw);
+        else
+          h->apply((const float*)h->z, m, r, r, h->T, rp, r_out, h->vw, r_out, false);
       }
     }
     if (!g_ext) (void)hipStreamWaitEvent(stream, h->ev_join, 0);
@@ -1049,37 +1056,74 @@ struct wssr_ctx {
                        ldo, upper, vec, acc, (const DevStatus*)st, gated);
   }
 
-  // An intermediate pass's parameter-side basis: any V = Z T with the span of
-  // Z serves the next pass, so the exact FP64 CholeskyQR is not needed where
-  // Z is well conditioned.  An FP32-MFMA Gram and its Cholesky decide on the
-  // device: columns already orthogonal (condition bound within
-  // sqrt(r (r + 8)), every relative pivot >= 0.99) -> V = Z diag(G)^{-1/2};
-  // relative pivots >= 0.03 -> V = Z R^{-1} by the FP32-MFMA apply; otherwise
-  // (or on a breakdown) the FP64 CholeskyQR2 and apply.  The alternatives not
-  // taken skip through shadow status words; the FP64 path's errors and
-  // diagnostics are merged into the step's status.  Leaves V in vw.
-  void fast_orth(float* Z, int64_t m, int r) {
+  // Probe for the orthonormalisation of the parameter-side block Z: an
+  // FP32-MFMA Gram and its FP64 Cholesky (into G, R1, R1i, gdiag), then the
+  // device's choice of mode (k_fast_decide) and clean shadow status words for
+  // the alternatives.
+  void probe_factor(float* Z, int64_t m, int r, double piv_fast) {
     const int rp = (int)rup(r, 64);
     DevStatus* main = st;
-    DevStatus* probe = shadow;
-    DevStatus* st_f32 = shadow + 1;
-    DevStatus* st_f64 = shadow + 2;
-    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, probe);
-    st = probe;
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, shadow);
+    st = shadow;
     gram((const float*)Z, m, r, false, true);
     chol(rp, r, R1, R1i, false);
     st = main;
-    hipLaunchKernelGGL(k_fast_decide, dim3(1), dim3(64), 0, stream, (const DevStatus*)probe,
-                       std::sqrt((double)r * (r + 8.0)), (const DevStatus*)main, st_f32, st_f64, fmode);
+    hipLaunchKernelGGL(k_fast_decide, dim3(1), dim3(64), 0, stream, (const DevStatus*)shadow,
+                       std::sqrt((double)r * (r + 8.0)), piv_fast, main, shadow + 1, shadow + 2, shadow + 3, fmode);
+  }
+
+  // An intermediate pass's parameter-side basis: any V = Z T with the span of
+  // Z serves the next pass, so the exact FP64 CholeskyQR is not needed where
+  // Z is well conditioned.  Mode 0 (columns already orthogonal): V = Z
+  // diag(G)^{-1/2}; mode 1 (relative pivots >= 0.03): V = Z R^{-1} by the
+  // FP32-MFMA apply; mode 2: the FP64 CholeskyQR2 and apply.  The
+  // alternatives not taken skip through their status words; the FP64 path's
+  // errors and diagnostics are merged into the step's status.  Leaves V in vw.
+  void fast_orth(float* Z, int64_t m, int r) {
+    const int rp = (int)rup(r, 64);
+    DevStatus* main = st;
+    probe_factor(Z, m, r, 0.03);
     hipLaunchKernelGGL(k_colscale, dim3(cdiv(m * r, 256)), dim3(256), 0, stream, (const float*)Z,
                        (const double*)gdiag, m, r, vw, (const int*)fmode);
-    st = st_f32;
+    st = shadow + 1;
     apply((const float*)Z, m, r, r, R1i, rp, r, vw, r, true, false, false, true);
-    st = st_f64;
+    st = shadow + 2;
     cholqr<float, float>(Z, m, r, q1, nullptr);
     apply((const float*)Z, m, r, r, Tq, rp, r, vw, r, true);
     st = main;
-    hipLaunchKernelGGL(k_status_merge, dim3(1), dim3(64), 0, stream, (const DevStatus*)st_f64, main);
+    hipLaunchKernelGGL(k_status_merge, dim3(1), dim3(64), 0, stream, (const DevStatus*)(shadow + 2), main);
+  }
+
+  // The last pass's factorisation Z = Q_Z R_Z (Q_Z = Z Tq): the probe's R
+  // where every relative pivot is >= 0.3 (its FP32-accurate Gram then gives R
+  // and R^{-1} to about 1e-6 relative), else the FP64 CholeskyQR2.  Leaves R_Z
+  // in Rz and Tq; the final apply of the same step chooses its precision the
+  // same way (final_apply).
+  void fast_factor(float* Z, int64_t m, int r) {
+    const int rp = (int)rup(r, 64);
+    DevStatus* main = st;
+    probe_factor(Z, m, r, 0.3);
+    const int64_t cnt = (int64_t)rp * rp;
+    hipLaunchKernelGGL(k_copy_st, dim3(cdiv(cnt, 256)), dim3(256), 0, stream, (const double*)R1, cnt, Rz,
+                       (const DevStatus*)(shadow + 3));
+    hipLaunchKernelGGL(k_copy_st, dim3(cdiv(cnt, 256)), dim3(256), 0, stream, (const double*)R1i, cnt, Tq,
+                       (const DevStatus*)(shadow + 3));
+    st = shadow + 2;
+    cholqr<float, float>(Z, m, r, q1, Rz);
+    st = main;
+    hipLaunchKernelGGL(k_status_merge, dim3(1), dim3(64), 0, stream, (const DevStatus*)(shadow + 2), main);
+  }
+
+  // V = Z T after fast_factor: the FP32-MFMA apply where the probe's factor
+  // was taken, the FP64 apply otherwise.
+  void final_apply(const float* Z, int64_t m, int r, const double* T, float* out) {
+    const int rp = (int)rup(r, 64);
+    DevStatus* main = st;
+    st = shadow + 3;
+    apply(Z, m, r, r, T, rp, r, out, r, false, false, false, true);
+    st = shadow + 2;
+    apply(Z, m, r, r, T, rp, r, out, r, false);
+    st = main;
   }
 
   // H = X^T W (rp x rp, zero outside r x r) for two rows x r blocks
@@ -1246,7 +1290,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->y1, (size_t)(n + r) * r) && h->alloc(h->Hc, (size_t)rp * rp) &&
             h->alloc(h->Hn, (size_t)rp * rp) && h->alloc(h->Bm, (size_t)rp * rp) && h->alloc(h->gbar, m) &&
             h->alloc(h->lhat, (size_t)(n + r)) && h->alloc(h->tvec, rp) && h->alloc(h->perm, rp) &&
-            h->alloc(h->shadow, 3) && h->alloc(h->fmode, 1) &&
+            h->alloc(h->shadow, 4) && h->alloc(h->fmode, 1) &&
             h->alloc(h->G, (size_t)rp * rp) &&
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
             h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
