@@ -37,17 +37,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SR steps/s at N×M×r vs plain FP32; HBM GB/s; rel err of δ vs FP64 oracle"
 PEAK_FP32_TFLOPS = 157.3
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_wssr_step_f32_n8192_m100k_r256.md")
+# committed counter summaries per (workload, M, form)
+TRAFFIC_RECORDS = {
+    ("f32_n8192_m100k_r256", 100_000, "f32"): "hbm_traffic_wssr_step_f32_n8192_m100k_r256.md",
+    ("bf16_n16384_m4m_r512_q3", 4_000_000, "bf16_split"): "hbm_traffic_wssr_step_bf16split_n16384_m4m_r512_q3.md",
+}
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
+def recorded_traffic(kernel, record):
+    """Bytes per launch of `kernel` moved between the L2 and the memory side
+    (FETCH_SIZE + WRITE_SIZE) from the committed counter summary `record`, or
     None when there is none or the kernel source changed since it was taken
     (the summary records the SHA-256 of the source file it measured)."""
     import hashlib
     import re
     try:
-        text = open(TRAFFIC_RECORD).read()
+        text = open(os.path.join(ROOT, "profiles", record)).read()
     except OSError:
         return None
     for mt in re.finditer(r"traffic-record: kernel=(\S+) bytes_per_launch=(\d+) source=(\S+) sha256=([0-9a-f]+)", text):
@@ -297,8 +302,8 @@ def roofline_of(form, prof, cfg):
     achieved = kern[dom]["tflops"]
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": (recorded_traffic(product_kernel(form, dom, cfg))
-                        if form == "f32" and (cfg.name, cfg.m) == ("f32_n8192_m100k_r256", 100_000) else None),
+            "traffic": (recorded_traffic(product_kernel(form, dom, cfg), TRAFFIC_RECORDS[(cfg.name, cfg.m, form)])
+                        if (cfg.name, cfg.m, form) in TRAFFIC_RECORDS else None),
             "kernel": product_kernel(form, dom, cfg), "avg_ms": round(kern[dom]["avg_ms"], 4),
             "flops_per_launch": flops_gemm, "products": PRODUCTS[form],
             "other": {k: {"avg_ms": round(v_["avg_ms"], 4), "tflops": round(v_["tflops"], 2)}
