@@ -183,13 +183,31 @@ __global__ __launch_bounds__(256) void k_copy_st(const double* __restrict__ src,
 }
 
 // V = Z diag(gdiag)^{-1/2} (columns scaled to unit norm) when mode == 0.
+// Grid-stride, four consecutive elements per thread and step (16-byte
+// accesses when r % 4 == 0 and the rows are 16-byte aligned).
 __global__ __launch_bounds__(256) void k_colscale(const float* __restrict__ z, const double* __restrict__ gdiag,
                                                   int64_t m, int r, float* __restrict__ v, const int* __restrict__ mode) {
   if (*mode != 0) return;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= m * r) return;
-  const double d = gdiag[e % r];
-  v[e] = d > 0.0 ? (float)((double)z[e] / sqrt(d)) : 0.0f;
+  const int64_t total = m * r;
+  const bool vec = (r % 4 == 0) && ((uintptr_t)z % 16 == 0) && ((uintptr_t)v % 16 == 0);
+  const int64_t stride = (int64_t)gridDim.x * 256 * 4;
+  for (int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4; e < total; e += stride) {
+    if (vec) {
+      const int c = (int)(e % r);
+      f32x4 x = *reinterpret_cast<const f32x4*>(z + e);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double d = gdiag[c + q];
+        x[q] = d > 0.0 ? (float)((double)x[q] / sqrt(d)) : 0.0f;
+      }
+      *reinterpret_cast<f32x4*>(v + e) = x;
+    } else {
+      for (int q = 0; q < 4 && e + q < total; ++q) {
+        const double d = gdiag[(e + q) % r];
+        v[e + q] = d > 0.0 ? (float)((double)z[e + q] / sqrt(d)) : 0.0f;
+      }
+    }
+  }
 }
 
 // Fold the FP64 alternative's outcome into the step's status: its error (if

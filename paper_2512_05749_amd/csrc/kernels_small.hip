@@ -617,29 +617,33 @@ __global__ __launch_bounds__(NTH) void k_jacobi_final(const double* __restrict__
 // xi_k plus the rounding residual, which the second round orthonormalises
 // against the others.  R stays the factor of the modified X (X = Q1 R by
 // construction), so X Tq is orthonormal and R the triangular factor of the
-// modified X, whose column k moved by R_kk = sqrt(rp eps) max_j |x_j|.  The zero sum keeps the columns of a centred basis centred.
-// grid: ceil(rows * r / 256) workgroups of 256 threads.
+// modified X, whose column k moved by R_kk = sqrt(rp eps) max_j |x_j|.  The
+// zero sum keeps the columns of a centred basis centred.
+// grid: (kCompleteBlocks, r) workgroups of 256 threads: blockIdx.y is the
+// column, and a column that was not replaced leaves at once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_complete(T* __restrict__ X, int64_t rows, int r, const double* __restrict__ R,
                                                   int rp, const int* __restrict__ repcol, const DevStatus* st) {
   if (failed(st)) return;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= rows * r) return;
-  const int k = (int)(e % r);
+  const int k = blockIdx.y;
   if (!repcol[k]) return;
-  const int64_t i = e / r;
-  const int64_t pair = i >> 1;
-  if ((rows & 1) && i == rows - 1) return;
-  // integer hash of (pair, k) (a 32-bit finaliser of multiply-xorshift steps)
-  uint32_t hsh = (uint32_t)pair * 0x9E3779B1u ^ (uint32_t)(pair >> 32) * 0x85EBCA77u ^ (uint32_t)k * 0xC2B2AE3Du;
-  hsh ^= hsh >> 16;
-  hsh *= 0x7FEB352Du;
-  hsh ^= hsh >> 15;
-  hsh *= 0x846CA68Bu;
-  hsh ^= hsh >> 16;
-  const double h = ((double)hsh * (1.0 / 4294967296.0)) * 2.0 - 1.0;
-  const double xi = ((i & 1) ? -h : h) * sqrt(3.0 / (double)rows);
-  X[e] = (T)((double)X[e] + R[(int64_t)k * rp + k] * xi);
+  const double rkk = R[(int64_t)k * rp + k];
+  const double amp = sqrt(3.0 / (double)rows);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256) {
+    const int64_t e = i * r + k;
+    const int64_t pair = i >> 1;
+    if ((rows & 1) && i == rows - 1) continue;
+    // integer hash of (pair, k) (a 32-bit finaliser of multiply-xorshift steps)
+    uint32_t hsh = (uint32_t)pair * 0x9E3779B1u ^ (uint32_t)(pair >> 32) * 0x85EBCA77u ^ (uint32_t)k * 0xC2B2AE3Du;
+    hsh ^= hsh >> 16;
+    hsh *= 0x7FEB352Du;
+    hsh ^= hsh >> 15;
+    hsh *= 0x846CA68Bu;
+    hsh ^= hsh >> 16;
+    const double h = ((double)hsh * (1.0 / 4294967296.0)) * 2.0 - 1.0;
+    const double xi = ((i & 1) ? -h : h) * amp;
+    X[e] = (T)((double)X[e] + rkk * xi);
+  }
 }
 template __global__ void k_complete<float>(float*, int64_t, int, const double*, int, const int*, const DevStatus*);
 template __global__ void k_complete<double>(double*, int64_t, int, const double*, int, const int*,

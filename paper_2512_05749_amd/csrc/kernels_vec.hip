@@ -292,13 +292,27 @@ __global__ __launch_bounds__(256) void k_sign_final(const double* __restrict__ d
 }
 
 // Stage 3: v[i][j] = sgn[j] * vnew[i][j] (elementwise over m x r).
+// grid-stride, four consecutive elements per thread and step (one 16-byte
+// access each way when r % 4 == 0 and the rows are 16-byte aligned)
 __global__ __launch_bounds__(256) void k_sign_apply(const float* __restrict__ vnew, const float* __restrict__ sgn,
                                                     int64_t total, int r, float* __restrict__ v,
                                                     const DevStatus* st) {
   if (failed(st)) return;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total) return;
-  v[e] = sgn[e % r] * vnew[e];
+  const bool vec = (r % 4 == 0) && ((uintptr_t)vnew % 16 == 0) && ((uintptr_t)v % 16 == 0);
+  const int64_t stride = (int64_t)gridDim.x * 256 * 4;
+  for (int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4; e < total; e += stride) {
+    const int c = (int)(e % r);
+    if (vec) {
+      f32x4 x = *reinterpret_cast<const f32x4*>(vnew + e);
+      x[0] *= sgn[c];
+      x[1] *= sgn[c + 1];
+      x[2] *= sgn[c + 2];
+      x[3] *= sgn[c + 3];
+      *reinterpret_cast<f32x4*>(v + e) = x;
+    } else {
+      for (int q = 0; q < 4 && e + q < total; ++q) v[e + q] = sgn[(e + q) % r] * vnew[e + q];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -541,8 +541,8 @@ struct wssr_ctx {
                            (const double*)h->tvec, (const float*)h->sgn, h->sig, std::sqrt(1.0 - av->avg),
                            av->l_state, cst);
       const int64_t tot = m * r;
-      hipLaunchKernelGGL(k_sign_apply, dim3(cdiv(tot, 256)), dim3(256), 0, stream, vnew, (const float*)h->sgn, tot, r,
-                         V, cst);
+      hipLaunchKernelGGL(k_sign_apply, dim3((unsigned)std::min<int64_t>(8192, cdiv(tot, 1024))), dim3(256), 0, stream,
+                         vnew, (const float*)h->sgn, tot, r, V, cst);
       // Woodbury
       hipLaunchKernelGGL(k_vtg_partial, dim3(nch, cdiv(r, 256)), dim3(256), 0, stream, (const float*)V,
                          gv, m, r, rpc, h->vpart, cst);
@@ -1083,8 +1083,8 @@ struct wssr_ctx {
     const int rp = (int)rup(r, 64);
     DevStatus* main = st;
     probe_factor(Z, m, r, 0.03);
-    hipLaunchKernelGGL(k_colscale, dim3(cdiv(m * r, 256)), dim3(256), 0, stream, (const float*)Z,
-                       (const double*)gdiag, m, r, vw, (const int*)fmode);
+    hipLaunchKernelGGL(k_colscale, dim3((unsigned)std::min<int64_t>(8192, cdiv(m * r, 1024))), dim3(256), 0, stream,
+                       (const float*)Z, (const double*)gdiag, m, r, vw, (const int*)fmode);
     st = shadow + 1;
     apply((const float*)Z, m, r, r, R1i, rp, r, vw, r, true, false, false, true);
     st = shadow + 2;
@@ -1154,8 +1154,9 @@ struct wssr_ctx {
     // a rank-deficient X: its dependent columns get directions of their own
     // (X is modified in place; X Tq and the factor R then refer to the
     // modified X)
-    hipLaunchKernelGGL((k_complete<Tin>), dim3(cdiv(rows * r, 256)), dim3(256), 0, stream, const_cast<Tin*>(X), rows,
-                       r, (const double*)R1, rp, (const int*)repcol, (const DevStatus*)st);
+    hipLaunchKernelGGL((k_complete<Tin>), dim3((unsigned)std::min<int64_t>(64, cdiv(rows, 256)), r), dim3(256), 0,
+                       stream, const_cast<Tin*>(X), rows, r, (const double*)R1, rp, (const int*)repcol,
+                       (const DevStatus*)st);
     apply(X, rows, r, r, R1i, rp, r, mid, r, true, true);
     gram((const Tmid*)mid, rows, r, true);
     chol(rp, r, R2, R2i, true);

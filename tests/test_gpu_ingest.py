@@ -176,7 +176,8 @@ def test_large_column_means_f32_implicit(shift):
     from paper_2512_05749_amd import Wssr
     n, m, r = 1024, 3000, 32
     o, e, v = random_problem(n, m, r, seed=91, device="cuda", alpha=1.2)
-    c = o.double().std(dim=0) * shift * torch.sign(torch.randn(m, device="cuda", dtype=torch.float64))
+    gen = torch.Generator(device="cuda").manual_seed(93)
+    c = o.double().std(dim=0) * shift * torch.sign(torch.randn(m, generator=gen, device="cuda", dtype=torch.float64))
     o = (o.double() + c[None, :]).float().contiguous()
     h = Wssr(n_max=n, m_max=m, r_max=r, q_max=2)
     try:
@@ -184,8 +185,10 @@ def test_large_column_means_f32_implicit(shift):
         delta, sigma = h.step(o, e, v, 1e-3, q=2)
         assert h.status()[0] == 0
         ref = orc.wssr_step(_np(o), _np(e), _np(v_in), 1e-3, r, 2)
-        assert rel(_np(delta), ref["delta"]) <= 1e-4
-        assert _max_rel(_np(delta), ref["delta"]) <= 1e-4
+        d_err, d_max = rel(_np(delta), ref["delta"]), _max_rel(_np(delta), ref["delta"])
+        print(f"shift {shift}: delta {d_err:.2e} (element-wise {d_max:.2e})")
+        assert d_err <= 1e-4
+        assert d_max <= 1e-4
         assert sigma_rel_gated(_np(sigma), ref["sigma"], 1e-3) <= 1e-4
     finally:
         h.close()
@@ -199,7 +202,8 @@ def test_large_column_means_bf16_explicit_centring(shift):
     from paper_2512_05749_amd import Wssr
     n, m, r = 1024, 3000, 32
     o, e, v = random_problem(n, m, r, seed=92, device="cuda", alpha=1.2)
-    c = o.double().std(dim=0) * shift * torch.sign(torch.randn(m, device="cuda", dtype=torch.float64))
+    gen = torch.Generator(device="cuda").manual_seed(94)
+    c = o.double().std(dim=0) * shift * torch.sign(torch.randn(m, generator=gen, device="cuda", dtype=torch.float64))
     o = (o.double() + c[None, :]).float().contiguous()
     h = Wssr(n_max=n, m_max=m, r_max=r, q_max=2, dtype="bf16_split")
     try:
