@@ -66,7 +66,7 @@ __global__ void k_gradient16_partial(const unsigned short* O, int64_t ld, int64_
 // split into BF16 planes laid out [k / 16][column][k % 16] (plane stride in
 // elements).
 __global__ void k_split_skinny(const float* S, int64_t K, int r, int sw, unsigned short* out, int64_t pstride,
-                               int planes, const DevStatus* st);
+                               int planes, const DevStatus* st, const float* alt, const double* gd, const int* mode);
 template <int BN, int BK, int PA, int PB>
 __global__ void k_gemm16_sample_side(const unsigned short* O, int64_t ld, int64_t pstride, int64_t n, int64_t m,
                                      const unsigned short* Vs, int64_t vstride, int r, float* ypart, int64_t kchunk,
@@ -111,14 +111,19 @@ __global__ void k_gemm16_sample_side_rs(const unsigned short* O, int64_t ld, int
                                         int64_t kchunk, const unsigned short* zeros, const DevStatus* st, int tn,
                                         int tj, bool xcd_groups);
 
-template <typename T, bool F32>
+template <typename T>
 __global__ void k_gram_partial(const T* X, int64_t rows, int r, int64_t ldx, int ntile, int64_t rows_per_chunk,
                                double* part, bool vec, const DevStatus* st, bool gated);
+__global__ void k_gram32_partial(const float* X, int64_t rows, int r, int64_t ldx, int ntile, int nchunk,
+                                 int64_t rows_per_chunk, double* part, bool vec, const DevStatus* st, bool gated);
 __global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, int rp, double* G,
                               const DevStatus* st, bool gated);
-template <typename Tin, typename Tout, bool F32>
+template <typename Tin, typename Tout>
 __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
                         Tout* Out, int ldo, bool upper, bool vec, bool acc, const DevStatus* st, bool gated);
+__global__ void k_apply32(const float* X, int64_t rows, int ldx, int kdim, const float* Tf, int rp, int ncol,
+                          float* Out, int ldo, bool upper, bool vec, const DevStatus* st, bool gated);
+__global__ void k_round_f32(const double* src, int64_t n, float* dst, const DevStatus* st, bool gated);
 template <typename TX, typename TW>
 __global__ void k_cross_partial(const TX* X, const TW* W, int64_t rows, int r, int ntile, int64_t rows_per_chunk,
                                 double* part, bool vec, const DevStatus* st);

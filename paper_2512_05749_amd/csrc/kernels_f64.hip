@@ -1,10 +1,10 @@
 // Kernels on the 16x16x4 MFMA for the orthonormalisation of the tall blocks
 // (CholeskyQR): the Gram matrix X^T X and the apply X T with a small square T.
-// Inputs may be float or double.  The FP64 instantiations multiply and sum in
-// FP64.  The F32 ones run the FP32 MFMA at twice the rate, for blocks whose
-// span is all that is used: the Gram's FP32 sums are flushed into FP64 every
-// 256 rows, so its entries carry about 1e-6 relative error; the apply's sums
-// run over at most r terms.
+// Inputs may be float or double.  The FP64 kernels multiply and sum in FP64.
+// The FP32 ones (k_gram32_partial, k_apply32) run the FP32 MFMA at
+// twice the rate, for blocks whose span is all that is used: the Gram's FP32
+// sums are flushed into FP64 every 256 rows, so its entries carry about 1e-6
+// relative error; the apply's sums run over at most r terms.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,30 +18,13 @@ constexpr int GS = GT + 16;     // LDS row stride in doubles: the four K-rows of
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-// element type, accumulator and MFMA of the two precisions
-template <bool F32>
-struct Acc;
-// The two 16x16x4 MFMAs take A[i][k] from lane i + 16 k and B[k][j] from lane
-// j + 16 k alike, but place D differently: the FP64 one holds D[4 v + l/16][l%16]
-// in register v of lane l, the FP32 one D[4 (l/16) + v][l%16] (checked on the
-// device).  row() gives the D row of register v.
-template <>
-struct Acc<false> {
-  typedef double e;
-  typedef f64x4 v;
-  static __device__ __forceinline__ v mma(double a, double b, v c) { return mfma16x16x4d(a, b, c); }
-  static __device__ __forceinline__ int row(int v, int lk) { return 4 * v + lk; }
-};
-template <>
-struct Acc<true> {
-  typedef float e;
-  typedef f32x4 v;
-  static __device__ __forceinline__ v mma(float a, float b, v c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
-};
-constexpr int kFlushSteps = 16;   // K-steps between FP64 flushes of the FP32 Gram accumulators
+// The FP64 and FP32 16x16x4 MFMAs take A[i][k] from lane i + 16 k and
+// B[k][j] from lane j + 16 k alike, but place D differently: the FP64 one
+// holds D[4 v + l/16][l%16] in register v of lane l, the FP32 one
+// D[4 (l/16) + v][l%16] (checked on the device).  These give the D row of
+// register v for lk = l/16.
+__device__ __forceinline__ int drow_f64(int v, int lk) { return 4 * v + lk; }
+__device__ __forceinline__ int drow_f32(int v, int lk) { return 4 * lk + v; }
 
 // four consecutive elements p[0..3] as doubles; n of them valid (the rest 0)
 __device__ __forceinline__ f64x4 load4d(const float* __restrict__ p, int n, bool vec) {
@@ -81,7 +64,7 @@ __device__ __forceinline__ void tile_pair(int pair, int ntile, int& I, int& J) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Gram partials.  X is rows x r row-major (row stride r).  grid.x enumerates
+// FP64 Gram partials.  X is rows x r row-major (row stride r).  grid.x enumerates
 // the tile pairs (I <= J) of 128 x 128 tiles of the Gram matrix, grid.y the
 // row chunks.  4 waves in a 2 x 2 arrangement, each a 64 x 64 quadrant =
 // 4 x 4 MFMA tiles of 16 x 16; a diagonal pair (I = J) stages its one column
@@ -89,15 +72,13 @@ __device__ __forceinline__ void tile_pair(int pair, int ntile, int& I, int& J) {
 // FP64 while the next 16 rows are being loaded into registers.
 // part[(chunk * npairs + pair) * 16384 + i * 128 + j].
 // ---------------------------------------------------------------------------
-template <typename T, bool F32>
+template <typename T>
 __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X, int64_t rows, int r, int64_t ldx,
                                                          int ntile, int64_t rows_per_chunk, double* __restrict__ part,
                                                          bool vec, const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
-  typedef typename Acc<F32>::e E;
-  typedef typename Acc<F32>::v Vt;
-  __shared__ E XI[GK][GS];
-  __shared__ E XJ[GK][GS];
+  __shared__ double XI[GK][GS];
+  __shared__ double XJ[GK][GS];
   int I, J;
   tile_pair(blockIdx.x, ntile, I, J);
   const bool diag = I == J;
@@ -108,15 +89,11 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
   const int64_t rbeg = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t rend = min(rows, rbeg + rows_per_chunk);
 
-  Vt acc[4][4];
-  f64x4 acc64[4][4];
+  f64x4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      acc[a][b] = Vt{0, 0, 0, 0};
-      acc64[a][b] = f64x4{0, 0, 0, 0};
-    }
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
 
   // thread -> (K-row, 4 columns) of a 16 x 128 block, two units per thread
   f64x4 pi[2], pj[2];
@@ -138,24 +115,23 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
       const int idx = t + 256 * e;
       const int kr = idx >> 5, c4 = (idx & 31) * 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) XI[kr][c4 + q] = (E)pi[e][q];
+      for (int q = 0; q < 4; ++q) XI[kr][c4 + q] = pi[e][q];
       if (!diag) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) XJ[kr][c4 + q] = (E)pj[e][q];
+        for (int q = 0; q < 4; ++q) XJ[kr][c4 + q] = pj[e][q];
       }
     }
   };
-  int since = 0;
   if (rbeg < rend) load(rbeg);
   for (int64_t k0 = rbeg; k0 < rend; k0 += GK) {
     store();
     __syncthreads();
     if (k0 + GK < rend) load(k0 + GK);
-    const E(*B)[GS] = diag ? XI : XJ;
+    const double(*B)[GS] = diag ? XI : XJ;
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int k = kk * 4 + lk;
-      E av[4], bv[4];
+      double av[4], bv[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = XI[k][qi * 64 + a * 16 + li];
 #pragma unroll
@@ -163,20 +139,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = Acc<F32>::mma(av[a], bv[b], acc[a][b]);
-    }
-    if constexpr (F32) {
-      if (++since == kFlushSteps) {
-        since = 0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
-            acc[a][b] = Vt{0, 0, 0, 0};
-          }
-      }
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4d(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
@@ -187,12 +150,143 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = qi * 64 + a * 16 + Acc<F32>::row(v, lk);
+        const int i = qi * 64 + a * 16 + drow_f64(v, lk);
         const int j = qj * 64 + b * 16 + li;
-        if constexpr (F32)
-          out[i * GT + j] = acc64[a][b][v] + (double)acc[a][b][v];
-        else
-          out[i * GT + j] = (double)acc[a][b][v];
+        out[i * GT + j] = acc[a][b][v];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// FP32-MFMA Gram partials of a float block, tuned for tall blocks: the same
+// 128 x 128 tile pairs, wave layout, FP64 flush every 256 rows and partial
+// layout as k_gram_partial<float, true> (k_gram_reduce sums them), with
+// - 16-row K-steps staged through float registers into a double-buffered LDS
+//   tile (one barrier per step; the loads of step s + 1 are in flight during
+//   the MFMAs of step s);
+// - a one-dimensional grid of npairs x nchunk workgroups in which, when the
+//   total is a multiple of 8, the tile pairs of one row chunk are consecutive
+//   workgroups of one XCD (workgroups are dealt to the 8 XCDs in turn), so
+//   the column blocks of a chunk that several pairs read are fetched into
+//   that XCD's L2 once.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int G32K = 16;                      // K step (rows)
+constexpr int G32Flush = 256 / G32K;          // steps between FP64 flushes
+}  // namespace
+
+__global__ __launch_bounds__(256, 2) void k_gram32_partial(const float* __restrict__ X, int64_t rows, int r,
+                                                           int64_t ldx, int ntile, int nchunk,
+                                                           int64_t rows_per_chunk, double* __restrict__ part,
+                                                           bool vec, const DevStatus* st, bool gated) {
+  if (skipped(st, gated)) return;
+  __shared__ float XI[2][G32K][GS];
+  __shared__ float XJ[2][G32K][GS];
+  const int npairs = ntile * (ntile + 1) / 2;
+  const int total = npairs * nchunk;
+  int w = blockIdx.x;
+  if (total % 8 == 0) w = (w % 8) * (total / 8) + w / 8;
+  const int pair = w % npairs, chunk = w / npairs;
+  int I, J;
+  tile_pair(pair, ntile, I, J);
+  const bool diag = I == J;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int qi = wv >> 1, qj = wv & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t rbeg = (int64_t)chunk * rows_per_chunk;
+  const int64_t rend = min(rows, rbeg + rows_per_chunk);
+
+  f32x4 acc[4][4];
+  f64x4 acc64[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      acc[a][b] = f32x4{0, 0, 0, 0};
+      acc64[a][b] = f64x4{0, 0, 0, 0};
+    }
+
+  // thread -> (K-row, 4 columns) of a G32K x 128 block, G32K / 8 units per thread;
+  // 32 consecutive threads read one 512-byte row piece
+  f32x4 pi[G32K / 8], pj[G32K / 8];
+  auto ld4 = [&](const float* p, int n) __attribute__((always_inline)) {
+    if (vec && n >= 4) return *reinterpret_cast<const f32x4*>(p);
+    f32x4 v = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (e < n) v[e] = p[e];
+    return v;
+  };
+  auto load = [&](int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < G32K / 8; ++e) {
+      const int idx = t + 256 * e;
+      const int64_t gr = k0 + (idx >> 5);
+      const int c4 = (idx & 31) * 4;
+      const int ci = I * GT + c4, cj = J * GT + c4;
+      const bool row_ok = gr < rend;
+      pi[e] = ld4(X + gr * ldx + ci, row_ok ? min(4, r - ci) : 0);
+      if (!diag) pj[e] = ld4(X + gr * ldx + cj, row_ok ? min(4, r - cj) : 0);
+    }
+  };
+  auto store = [&](int b) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < G32K / 8; ++e) {
+      const int idx = t + 256 * e;
+      const int kr = idx >> 5, c4 = (idx & 31) * 4;
+      *reinterpret_cast<f32x4*>(&XI[b][kr][c4]) = pi[e];
+      if (!diag) *reinterpret_cast<f32x4*>(&XJ[b][kr][c4]) = pj[e];
+    }
+  };
+
+  if (rbeg < rend) {
+    load(rbeg);
+    store(0);
+  }
+  __syncthreads();
+  int since = 0, cur = 0;
+  for (int64_t k0 = rbeg; k0 < rend; k0 += G32K) {
+    const bool more = k0 + G32K < rend;
+    if (more) load(k0 + G32K);
+    const float(*A)[GS] = XI[cur];
+    const float(*B)[GS] = diag ? XI[cur] : XJ[cur];
+#pragma unroll
+    for (int kk = 0; kk < G32K / 4; ++kk) {
+      const int k = kk * 4 + lk;
+      float av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = A[k][qi * 64 + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = B[k][qj * 64 + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (++since == G32Flush) {
+      since = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc[a][b][v];
+          acc[a][b] = f32x4{0, 0, 0, 0};
+        }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  double* out = part + ((int64_t)chunk * npairs + pair) * (GT * GT);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = qi * 64 + a * 16 + drow_f32(v, lk);
+        const int j = qj * 64 + b * 16 + li;
+        out[i * GT + j] = acc64[a][b][v] + (double)acc[a][b][v];
       }
 }
 
@@ -241,16 +335,14 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 // skipped.  The next K-step's tiles are loaded into registers while the
 // current ones are multiplied.
 // ---------------------------------------------------------------------------
-template <typename Tin, typename Tout, bool F32>
+template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int64_t rows, int ldx, int kdim,
                                                   const double* __restrict__ Tm, int rp, int ncol,
                                                   Tout* __restrict__ Out, int ldo, bool upper, bool vec,
                                                   bool acc, const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
-  typedef typename Acc<F32>::e E;
-  typedef typename Acc<F32>::v Vt;
-  __shared__ E Xs[GK][GS];   // [k][row]
-  __shared__ E Ts[GK][GS];   // [k][col]
+  __shared__ double Xs[GK][GS];   // [k][row]
+  __shared__ double Ts[GK][GS];   // [k][col]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int qi = w >> 1, qj = w & 1;
   const int li = lane & 15, lk = lane >> 4;
@@ -258,11 +350,11 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
   const int col0 = blockIdx.y * GT;
   const int kend = upper ? min(kdim, col0 + GT) : kdim;
 
-  Vt acc_v[4][4];
+  f64x4 acc_v[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc_v[a][b] = Vt{0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) acc_v[a][b] = f64x4{0, 0, 0, 0};
 
   // X: thread -> (row, 4 K-values), two units; T: thread -> (K-row, 2 columns), four units
   f64x4 px[2];
@@ -296,13 +388,13 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
       const int idx = t + 256 * e;
       const int rr = idx >> 2, kq = (idx & 3) * 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Xs[kq + q][rr] = (E)px[e][q];
+      for (int q = 0; q < 4; ++q) Xs[kq + q][rr] = px[e][q];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = t + 256 * e;
-      Ts[idx >> 6][(idx & 63) * 2] = (E)pt[e][0];
-      Ts[idx >> 6][(idx & 63) * 2 + 1] = (E)pt[e][1];
+      Ts[idx >> 6][(idx & 63) * 2] = pt[e][0];
+      Ts[idx >> 6][(idx & 63) * 2 + 1] = pt[e][1];
     }
   };
   if (kend > 0) load(0);
@@ -313,7 +405,7 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int k = kk * 4 + lk;
-      E av[4], bv[4];
+      double av[4], bv[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = Xs[k][qi * 64 + a * 16 + li];
 #pragma unroll
@@ -321,7 +413,7 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc_v[a][b] = Acc<F32>::mma(av[a], bv[b], acc_v[a][b]);
+        for (int b = 0; b < 4; ++b) acc_v[a][b] = mfma16x16x4d(av[a], bv[b], acc_v[a][b]);
     }
     __syncthreads();
   }
@@ -331,12 +423,130 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t i = row0 + qi * 64 + a * 16 + Acc<F32>::row(v, lk);
+        const int64_t i = row0 + qi * 64 + a * 16 + drow_f64(v, lk);
         const int j = col0 + qj * 64 + b * 16 + li;
         if (i < rows && j < ncol)
           Out[i * ldo + j] = acc ? (Tout)((double)acc_v[a][b][v] + (double)Out[i * ldo + j])
                                  : (Tout)acc_v[a][b][v];
       }
+}
+
+// ---------------------------------------------------------------------------
+// FP32-MFMA apply Out = X Tf (X rows x kdim float, row stride ldx; Tf the
+// FP64 factor rounded to float, rp x rp row-major, columns 0 .. ncol-1),
+// for the blocks whose FP32 apply is taken (sums over at most kdim terms).
+// 128 x 128 output tiles, 4 waves of 64 x 64 on the 16x16x4 FP32 MFMA as in
+// k_apply.  16-row K-steps staged through registers into a double-buffered
+// LDS tile (one barrier per step); X stays [row][k] in LDS with a row stride
+// of 20 floats (the 16 rows x 4 K-values of an MFMA operand read fall into
+// distinct banks) and is stored with 16-byte writes.  One-dimensional grid:
+// the column tiles of one row tile are consecutive workgroups of one XCD
+// when the total is a multiple of 8, so each row slab of X is fetched into
+// that XCD's L2 once.  When `upper`, K-steps below the column tile are
+// skipped (Tf upper triangular).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int A32S = 20;   // LDS row stride (floats) of the X tile
+}  // namespace
+
+__global__ __launch_bounds__(256, 4) void k_apply32(const float* __restrict__ X, int64_t rows, int ldx, int kdim,
+                                                    const float* __restrict__ Tf, int rp, int ncol,
+                                                    float* __restrict__ Out, int ldo, bool upper, bool vec,
+                                                    const DevStatus* st, bool gated) {
+  if (skipped(st, gated)) return;
+  __shared__ float Xs[2][GT][A32S];   // [row][k]
+  __shared__ float Ts[2][GK][GS];     // [k][col]
+  const int ctiles = (ncol + GT - 1) / GT;
+  const int total = (int)((rows + GT - 1) / GT) * ctiles;
+  int w = blockIdx.x;
+  if (total % 8 == 0) w = (w % 8) * (total / 8) + w / 8;
+  const int64_t row0 = (int64_t)(w / ctiles) * GT;
+  const int col0 = (w % ctiles) * GT;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int qi = wv >> 1, qj = wv & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int kend = upper ? min(kdim, col0 + GT) : kdim;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+
+  // X: thread -> (row, 4 K-values), two units; Tf: thread -> (K-row, 4 columns), two units
+  f32x4 px[2], pt[2];
+  auto ld4 = [&](const float* p, int n, bool v4) __attribute__((always_inline)) {
+    if (v4 && n >= 4) return *reinterpret_cast<const f32x4*>(p);
+    f32x4 v = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (e < n) v[e] = p[e];
+    return v;
+  };
+  auto load = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = t + 256 * e;
+      const int64_t gr = row0 + (idx >> 2);
+      const int gk = k0 + (idx & 3) * 4;
+      px[e] = ld4(X + gr * ldx + gk, gr < rows ? min(4, kdim - gk) : 0, vec);
+      const int tk = k0 + (idx >> 5), tc = col0 + (idx & 31) * 4;
+      pt[e] = ld4(Tf + (int64_t)tk * rp + tc, tk < kdim ? min(4, ncol - tc) : 0, true);
+    }
+  };
+  auto store = [&](int b) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = t + 256 * e;
+      *reinterpret_cast<f32x4*>(&Xs[b][idx >> 2][(idx & 3) * 4]) = px[e];
+      *reinterpret_cast<f32x4*>(&Ts[b][idx >> 5][(idx & 31) * 4]) = pt[e];
+    }
+  };
+
+  if (kend > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = 0; k0 < kend; k0 += GK) {
+    const bool more = k0 + GK < kend;
+    if (more) load(k0 + GK);
+#pragma unroll
+    for (int kk = 0; kk < GK / 4; ++kk) {
+      const int k = kk * 4 + lk;
+      float av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = Xs[cur][qi * 64 + a * 16 + li][k];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Ts[cur][k][qj * 64 + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = row0 + qi * 64 + a * 16 + drow_f32(v, lk);
+        const int j = col0 + qj * 64 + b * 16 + li;
+        if (i < rows && j < ncol) Out[i * ldo + j] = acc[a][b][v];
+      }
+}
+
+// Round an FP64 array to float (the factor of k_apply32); skipped with the apply.
+__global__ __launch_bounds__(256) void k_round_f32(const double* __restrict__ src, int64_t n, float* __restrict__ dst,
+                                                   const DevStatus* st, bool gated) {
+  if (skipped(st, gated)) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -450,21 +660,17 @@ __global__ __launch_bounds__(256) void k_cross_reduce(const double* __restrict__
 }
 
 // explicit instantiations used by the host runtime
-template __global__ void k_gram_partial<float, false>(const float*, int64_t, int, int64_t, int, int64_t, double*,
-                                                      bool, const DevStatus*, bool);
-template __global__ void k_gram_partial<float, true>(const float*, int64_t, int, int64_t, int, int64_t, double*, bool,
-                                                     const DevStatus*, bool);
-template __global__ void k_gram_partial<double, false>(const double*, int64_t, int, int64_t, int, int64_t, double*,
-                                                       bool, const DevStatus*, bool);
+template __global__ void k_gram_partial<float>(const float*, int64_t, int, int64_t, int, int64_t, double*, bool,
+                                               const DevStatus*, bool);
+template __global__ void k_gram_partial<double>(const double*, int64_t, int, int64_t, int, int64_t, double*, bool,
+                                                const DevStatus*, bool);
 template __global__ void k_cross_partial<double, float>(const double*, const float*, int64_t, int, int, int64_t,
                                                         double*, bool, const DevStatus*);
-template __global__ void k_apply<float, float, false>(const float*, int64_t, int, int, const double*, int, int, float*,
-                                                      int, bool, bool, bool, const DevStatus*, bool);
-template __global__ void k_apply<float, float, true>(const float*, int64_t, int, int, const double*, int, int, float*,
-                                                     int, bool, bool, bool, const DevStatus*, bool);
-template __global__ void k_apply<double, float, false>(const double*, int64_t, int, int, const double*, int, int,
-                                                       float*, int, bool, bool, bool, const DevStatus*, bool);
-template __global__ void k_apply<double, double, false>(const double*, int64_t, int, int, const double*, int, int,
-                                                        double*, int, bool, bool, bool, const DevStatus*, bool);
+template __global__ void k_apply<float, float>(const float*, int64_t, int, int, const double*, int, int, float*, int,
+                                               bool, bool, bool, const DevStatus*, bool);
+template __global__ void k_apply<double, float>(const double*, int64_t, int, int, const double*, int, int, float*,
+                                                int, bool, bool, bool, const DevStatus*, bool);
+template __global__ void k_apply<double, double>(const double*, int64_t, int, int, const double*, int, int, double*,
+                                                 int, bool, bool, bool, const DevStatus*, bool);
 
 }  // namespace wssr

@@ -159,21 +159,31 @@ __device__ __forceinline__ void s_store(const u32x4 (&rs)[PB][PT], u16* __restri
 // kernels read whole tiles of S unguarded.  One thread per (kb, j):
 // 16 loads that are coalesced across threads (consecutive j), two 32-byte
 // stores per plane.
+// With mode given and *mode == 0, S is taken as Z diag(gd)^{-1/2} (column j
+// of alt times 1/sqrt(gd[j]) in FP64, 0 where gd[j] <= 0): the column scaling
+// of k_colscale, without storing the scaled block.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_split_skinny(const float* __restrict__ S, int64_t K, int r, int sw,
                                                       u16* __restrict__ out, int64_t pstride, int planes,
-                                                      const DevStatus* st) {
+                                                      const DevStatus* st, const float* __restrict__ alt,
+                                                      const double* __restrict__ gd, const int* __restrict__ mode) {
   if (failed(st)) return;
   const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t kblocks = (K + 15) / 16;
   if (id >= kblocks * sw) return;
   const int64_t kb = id / sw;
   const int j = (int)(id % sw);
+  const bool scaled = mode != nullptr && *mode == 0;
+  const float* src = scaled ? alt : S;
+  double d = 1.0;
+  if (scaled && j < r) d = gd[j];
+  const double inv = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   u16 hi[16], lo[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int64_t k = kb * 16 + e;
-    const float x = (k < K && j < r) ? S[k * r + j] : 0.0f;
+    float x = (k < K && j < r) ? src[k * r + j] : 0.0f;
+    if (scaled) x = (float)((double)x * inv);
     split_bf16(x, hi[e], lo[e]);
   }
   u16* dst = out + id * 16;

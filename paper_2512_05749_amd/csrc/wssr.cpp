@@ -106,6 +106,8 @@ struct wssr_ctx {
   double r_reg = 0.0;             // truncation ratio of eq. ruler (wssr_set_rank_ratio; 0: none)
   DevStatus* shadow = nullptr;    // status words of the factorisation probe and its alternatives (4)
   int* fmode = nullptr;           // fast_orth's choice (0 scale, 1 FP32 apply, 2 FP64 CholeskyQR)
+  const float* split_alt = nullptr;  // Z for the next split_skinny to scale itself (fast_orth, mode 0)
+  float* tf32 = nullptr;          // the factor of an FP32 apply, rounded to float (rp x rp)
   int* perm = nullptr;            // column order of the diag(R) ending
   float *maxval = nullptr, *sgn = nullptr;
   int64_t* maxrow = nullptr;
@@ -236,6 +238,7 @@ struct wssr_ctx {
     const int r_out = cont ? cont->r_out : r;
     const DevStatus* cst = h->st;
     hipStream_t stream = h->stream;
+    h->split_alt = nullptr;
     if (!cont) hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, h->st);
 
     const double c_hist = av ? std::sqrt(av->avg / (1.0 - av->avg)) : 0.0;
@@ -287,7 +290,9 @@ struct wssr_ctx {
       const bool fast = kFastMid && !av;
       if (fast && p < q) {
         // an intermediate pass: only the span of Z is carried on
-        h->fast_orth(h->z, m, r);
+        // (in the BF16 forms the next sample side reads V only through its
+        // split, which can scale Z itself; Alg. 1's ending reads V too)
+        h->fast_orth(h->z, m, r, h->bf16() && !diag_end);
         vcur = h->vw;
         continue;
       }
@@ -637,12 +642,17 @@ struct wssr_ctx {
 
   // BF16 forms: round the K x r FP32 skinny operand S into s16 (hi, and lo
   // when pb = 2), K-blocked, r padded with zero columns to the product's
-  // column tiles (bn); returns the plane stride in elements
+  // column tiles (bn); returns the plane stride in elements.  With split_alt
+  // set (by fast_orth), the device's mode decides whether S or the column-scaled
+  // split_alt is rounded; split_alt is cleared.
   int64_t split_skinny(const float* S, int64_t K, int r, int pb, int bn) {
     const int sw = (int)rup(r, bn);
     const int64_t kblocks = cdiv(K, 16), ps = kblocks * 16 * sw;
+    const float* alt = split_alt;
+    split_alt = nullptr;
     hipLaunchKernelGGL(k_split_skinny, dim3(cdiv(kblocks * sw, 256)), dim3(256), 0, stream, S, K, r, sw, s16, ps, pb,
-                       (const DevStatus*)st);
+                       (const DevStatus*)st, alt, (const double*)(alt ? gdiag : nullptr),
+                       (const int*)(alt ? fmode : nullptr));
     return ps;
   }
 
@@ -1001,14 +1011,19 @@ struct wssr_ctx {
     const bool vec = (r % 4 == 0) && ((uintptr_t)X % 16 == 0);
     const int64_t ldx = r;
     if constexpr (std::is_same<T, float>::value) {
-      if (f32)
-        hipLaunchKernelGGL((k_gram_partial<float, true>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx,
-                           nt, rpc, gram_part, vec, (const DevStatus*)st, gated);
-      else
-        hipLaunchKernelGGL((k_gram_partial<float, false>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx,
+      if (f32) {
+        // whole groups of 8 chunks, so that every XCD holds whole chunks
+        int nc = gram_chunks(rows, npairs);
+        if (nc >= 8) nc -= nc % 8;
+        const int64_t rpc32 = std::max<int64_t>(16, rup(cdiv(rows, nc), 16));
+        nch = (int)std::max<int64_t>(1, cdiv(rows, rpc32));
+        hipLaunchKernelGGL(k_gram32_partial, dim3(npairs * nch), dim3(256), 0, stream, X, rows, r, ldx, nt, nch,
+                           rpc32, gram_part, vec, (const DevStatus*)st, gated);
+      } else
+        hipLaunchKernelGGL((k_gram_partial<float>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx,
                            nt, rpc, gram_part, vec, (const DevStatus*)st, gated);
     } else {
-      hipLaunchKernelGGL((k_gram_partial<T, false>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx, nt,
+      hipLaunchKernelGGL((k_gram_partial<T>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx, nt,
                          rpc, gram_part, vec, (const DevStatus*)st, gated);
     }
     hipLaunchKernelGGL(k_gram_reduce, dim3(npairs, kF64Tile * kF64Tile / 256), dim3(256), 0, stream,
@@ -1046,13 +1061,16 @@ struct wssr_ctx {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
     const dim3 grid(cdiv(rows, kF64Tile), cdiv(ncol, kF64Tile));
     if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
-      if (f32) {
-        hipLaunchKernelGGL((k_apply<float, float, true>), grid, dim3(256), 0, stream, X, rows, ldx, kdim, Tm, rp, ncol,
-                           out, ldo, upper, vec, acc, (const DevStatus*)st, gated);
+      if (f32 && !acc) {
+        const int64_t cnt = (int64_t)rp * rp;
+        hipLaunchKernelGGL(k_round_f32, dim3(cdiv(cnt, 256)), dim3(256), 0, stream, Tm, cnt, tf32,
+                           (const DevStatus*)st, gated);
+        hipLaunchKernelGGL(k_apply32, dim3((unsigned)(grid.x * grid.y)), dim3(256), 0, stream, X, rows, ldx, kdim,
+                           (const float*)tf32, rp, ncol, out, ldo, upper, vec, (const DevStatus*)st, gated);
         return;
       }
     }
-    hipLaunchKernelGGL((k_apply<Tin, Tout, false>), grid, dim3(256), 0, stream, X, rows, ldx, kdim, Tm, rp, ncol, out,
+    hipLaunchKernelGGL((k_apply<Tin, Tout>), grid, dim3(256), 0, stream, X, rows, ldx, kdim, Tm, rp, ncol, out,
                        ldo, upper, vec, acc, (const DevStatus*)st, gated);
   }
 
@@ -1078,13 +1096,18 @@ struct wssr_ctx {
   // diag(G)^{-1/2}; mode 1 (relative pivots >= 0.03): V = Z R^{-1} by the
   // FP32-MFMA apply; mode 2: the FP64 CholeskyQR2 and apply.  The
   // alternatives not taken skip through their status words; the FP64 path's
-  // errors and diagnostics are merged into the step's status.  Leaves V in vw.
-  void fast_orth(float* Z, int64_t m, int r) {
+  // errors and diagnostics are merged into the step's status.  Leaves V in vw;
+  // with defer_scale, mode 0 leaves vw as it is and the next split_skinny
+  // (the BF16 sample side, the only reader of this V) scales Z itself.
+  void fast_orth(float* Z, int64_t m, int r, bool defer_scale) {
     const int rp = (int)rup(r, 64);
     DevStatus* main = st;
     probe_factor(Z, m, r, 0.03);
-    hipLaunchKernelGGL(k_colscale, dim3((unsigned)std::min<int64_t>(8192, cdiv(m * r, 1024))), dim3(256), 0, stream,
-                       (const float*)Z, (const double*)gdiag, m, r, vw, (const int*)fmode);
+    if (defer_scale)
+      split_alt = Z;
+    else
+      hipLaunchKernelGGL(k_colscale, dim3((unsigned)std::min<int64_t>(8192, cdiv(m * r, 1024))), dim3(256), 0,
+                         stream, (const float*)Z, (const double*)gdiag, m, r, vw, (const int*)fmode);
     st = shadow + 1;
     apply((const float*)Z, m, r, r, R1i, rp, r, vw, r, true, false, false, true);
     st = shadow + 2;
@@ -1291,7 +1314,7 @@ wssr_status build_ctx(const wssr_config* cfg, int dev, hipStream_t stream, bool 
             h->alloc(h->y1, (size_t)(n + r) * r) && h->alloc(h->Hc, (size_t)rp * rp) &&
             h->alloc(h->Hn, (size_t)rp * rp) && h->alloc(h->Bm, (size_t)rp * rp) && h->alloc(h->gbar, m) &&
             h->alloc(h->lhat, (size_t)(n + r)) && h->alloc(h->tvec, rp) && h->alloc(h->perm, rp) &&
-            h->alloc(h->shadow, 4) && h->alloc(h->fmode, 1) &&
+            h->alloc(h->shadow, 4) && h->alloc(h->fmode, 1) && h->alloc(h->tf32, (size_t)rp * rp) &&
             h->alloc(h->G, (size_t)rp * rp) &&
             h->alloc(h->R1, (size_t)rp * rp) && h->alloc(h->R1i, (size_t)rp * rp) && h->alloc(h->R2, (size_t)rp * rp) &&
             h->alloc(h->R2i, (size_t)rp * rp) && h->alloc(h->Rz, (size_t)rp * rp) && h->alloc(h->Bc, (size_t)rp * rp) &&
@@ -1943,7 +1966,7 @@ wssr_status wssr_dbg_span_basis(wssr_handle h, int64_t rows, const float* X, int
   if (rows < r || rows > h->cfg.m_max) return h->fail(WSSR_ERR_INVALID_ARG, "rows outside [r, m_max]");
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
   (void)hipMemcpyAsync(h->z, X, sizeof(float) * rows * r, hipMemcpyDeviceToDevice, h->stream);
-  h->fast_orth(h->z, rows, r);
+  h->fast_orth(h->z, rows, r, false);
   (void)hipMemcpyAsync(V, h->vw, sizeof(float) * rows * r, hipMemcpyDeviceToDevice, h->stream);
   (void)hipMemcpyAsync(mode, h->fmode, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");
