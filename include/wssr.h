@@ -390,12 +390,16 @@ wssr_status wssr_dbg_gradient(wssr_handle h, int64_t n, int64_t m, const void* O
 wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_t r,
                              float* Q, double* R);
 
-/* Gram matrix G = X^T X (X float[rows x r] row-major, G double[r x r]): with
- * f32 = 0 on the FP64 MFMA (exact products, FP64 sums); with f32 != 0 on the
- * FP32 MFMA, FP32 sums flushed into FP64 every 256 rows (entries to about
- * 1e-6 relative), the Gram used where only a span is carried on.
- * rows <= max(n_max, m_max). */
-wssr_status wssr_dbg_gram(wssr_handle h, int64_t rows, const float* X, int32_t r, int32_t f32, double* G);
+/* Gram matrix G = X^T X (X float[rows x r] row-major, G double[r x r]) as
+ * the step forms it for a parameter-side block Z: kind 0 on the FP64 MFMA
+ * (exact products, FP64 sums; the CholeskyQR2); kind 1 on the FP32 MFMA,
+ * FP32 sums flushed into FP64 every 256 rows (entries to about 1e-7 relative
+ * to sqrt(G_ii G_jj); the last pass's probe); kind 2 on the BF16 MFMA, each
+ * element split into two BF16 planes and the four products summed in FP32,
+ * flushed into FP64 every 256 rows (about 3e-7; the intermediate passes'
+ * probe, where only a span is carried on).  WSSR_ERR_INVALID_ARG for another
+ * kind.  rows <= max(n_max, m_max). */
+wssr_status wssr_dbg_gram(wssr_handle h, int64_t rows, const float* X, int32_t r, int32_t kind, double* G);
 
 /* The basis an intermediate pass carries on from Z = X (float[rows x r]): V
  * (float[rows x r]) spans the columns of X, and *mode (device int32) says how

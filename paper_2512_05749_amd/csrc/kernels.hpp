@@ -116,6 +116,8 @@ __global__ void k_gram_partial(const T* X, int64_t rows, int r, int64_t ldx, int
                                double* part, bool vec, const DevStatus* st, bool gated);
 __global__ void k_gram32_partial(const float* X, int64_t rows, int r, int64_t ldx, int ntile, int nchunk,
                                  int64_t rows_per_chunk, double* part, bool vec, const DevStatus* st, bool gated);
+__global__ void k_gram16_partial(const float* X, int64_t rows, int r, int64_t ldx, int ntile, int nchunk,
+                                 int64_t rows_per_chunk, double* part, const DevStatus* st, bool gated);
 __global__ void k_gram_reduce(const double* part, int nchunk, int ntile, int r, int rp, double* G,
                               const DevStatus* st, bool gated);
 template <typename Tin, typename Tout>
@@ -176,6 +178,8 @@ __global__ void k_state_l(const double* Rz, const double* Ps, int rp, int r, con
 __global__ void k_transpose_rp(const double* R, int rp, int r, double* Ct, const DevStatus* st);
 __global__ void k_diag_sort(const double* R, int rp, int r, double* sig, int* perm, const DevStatus* st);
 __global__ void k_permute_cols(const float* src, int64_t m, int r, const int* perm, float* dst, const DevStatus* st);
+__global__ void k_select_t(const int* mode, const double* gdiag, const double* r1i, const double* tq, int rp, int r,
+                           double* out);
 __global__ void k_fast_decide(const DevStatus* probe, double kappa_orth, double piv_fast, DevStatus* main,
                               DevStatus* st_m1, DevStatus* st_m2, DevStatus* st_m01, int* mode);
 __global__ void k_copy_st(const double* src, int64_t count, double* dst, const DevStatus* st);

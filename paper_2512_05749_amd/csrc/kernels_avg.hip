@@ -174,6 +174,26 @@ __global__ void k_fast_decide(const DevStatus* __restrict__ probe, double kappa_
   }
 }
 
+// The factor T of an intermediate pass's basis V = Z T (fast_orth's mode):
+// 0: diag(G)^{-1/2} (0 where G_jj <= 0), 1: the probe's R^{-1}, 2: the FP64
+// CholeskyQR2's Tq; rp x rp, zero outside the r x r block in mode 0 (the
+// others carry the factors' identity padding).  Nothing in mode -1.
+__global__ __launch_bounds__(256) void k_select_t(const int* __restrict__ mode, const double* __restrict__ gdiag,
+                                                  const double* __restrict__ r1i, const double* __restrict__ tq,
+                                                  int rp, int r, double* __restrict__ out) {
+  const int md = *mode;
+  if (md < 0) return;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)rp * rp) return;
+  if (md == 0) {
+    const int i = (int)(idx / rp), j = (int)(idx % rp);
+    const double d = (i == j && i < r) ? gdiag[i] : 0.0;
+    out[idx] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  } else {
+    out[idx] = (md == 1 ? r1i : tq)[idx];
+  }
+}
+
 // dst = src (count doubles) unless the status word says skip.
 __global__ __launch_bounds__(256) void k_copy_st(const double* __restrict__ src, int64_t count,
                                                  double* __restrict__ dst, const DevStatus* st) {

@@ -1,10 +1,12 @@
-// Kernels on the 16x16x4 MFMA for the orthonormalisation of the tall blocks
-// (CholeskyQR): the Gram matrix X^T X and the apply X T with a small square T.
-// Inputs may be float or double.  The FP64 kernels multiply and sum in FP64.
-// The FP32 ones (k_gram32_partial, k_apply32) run the FP32 MFMA at
-// twice the rate, for blocks whose span is all that is used: the Gram's FP32
-// sums are flushed into FP64 every 256 rows, so its entries carry about 1e-6
-// relative error; the apply's sums run over at most r terms.
+// Kernels for the orthonormalisation of the tall blocks (CholeskyQR): the
+// Gram matrix X^T X and the apply X T with a small square T.  Inputs may be
+// float or double.  The FP64 kernels multiply and sum in FP64 on the 16x16x4
+// FP64 MFMA.  The fast ones serve the parameter-side block, whose FP32 values
+// are all there is: k_gram32_partial and k_apply32 on the FP32 MFMA at twice
+// the FP64 rate, k_gram16_partial on the BF16 MFMA (two-plane split, four
+// products).  The fast Grams' FP32 sums are flushed into FP64 every 256 rows,
+// so their entries carry about 1e-7 (FP32) and 3e-7 (BF16 split) relative
+// error; the apply's sums run over at most r terms.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -288,6 +290,148 @@ __global__ __launch_bounds__(256, 2) void k_gram32_partial(const float* __restri
         const int j = qj * 64 + b * 16 + li;
         out[i * GT + j] = acc64[a][b][v] + (double)acc[a][b][v];
       }
+}
+
+// ---------------------------------------------------------------------------
+// Gram partials of a float block on the BF16 MFMA.  Each element is split on
+// load into two RNE BF16 planes, z = h + l + e with |e| <= 2^-16 |z|, and
+// the four products (h + l)^T (h + l) run on v_mfma_f32_32x32x16_bf16, whose
+// BF16 products are exact in FP32.  The FP32 sums are flushed into FP64 every
+// 256 rows, as in k_gram32_partial, so the entries carry the same FP32
+// accumulation error; the split residual adds at most 2^-15 relative to
+// sqrt(G_ii G_jj) (about 2^-16 / sqrt(rows) for rounding errors of random
+// sign).  Tile pairs, row chunks, the one-dimensional XCD-grouped grid and
+// the partial layout are those of k_gram32_partial.
+// 512 threads = 8 waves in a 4 x 2 arrangement, each a 32 x 64 part of the
+// 128 x 128 tile pair (two MFMA tiles of 32 x 32), one workgroup per compute
+// unit and two waves per SIMD.  K-steps of 16 rows: each thread loads 4 rows
+// of one column of each column block (coalesced across the 128 threads of a
+// row quarter), splits them and writes the 4 K-values of each plane as one
+// 8-byte LDS store into a [plane][column][k] tile with a column stride of 24
+// elements (48 bytes, an odd multiple of 16, so the 16-byte fragment reads
+// are conflict-free); double-buffered, one barrier per step, the next step's
+// loads in flight during the MFMAs.
+// ---------------------------------------------------------------------------
+namespace {
+typedef __bf16 g16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned g16u4 __attribute__((ext_vector_type(4)));
+typedef unsigned g16u2 __attribute__((ext_vector_type(2)));
+constexpr int G16S = 24;       // LDS column stride (BF16 elements)
+constexpr int G16Flush = 16;   // 16-row steps between FP64 flushes
+
+__device__ __forceinline__ unsigned short g16_bits(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+__device__ __forceinline__ float g16_val(unsigned short b) { return (float)__builtin_bit_cast(__bf16, b); }
+}  // namespace
+
+__global__ __launch_bounds__(512, 1) void k_gram16_partial(const float* __restrict__ X, int64_t rows, int r,
+                                                           int64_t ldx, int ntile, int nchunk,
+                                                           int64_t rows_per_chunk, double* __restrict__ part,
+                                                           const DevStatus* st, bool gated) {
+  if (skipped(st, gated)) return;
+  // [buffer][block I, J][plane hi, lo][column][k]
+  __shared__ __attribute__((aligned(16))) unsigned short S[2][2][2][GT][G16S];
+  const int npairs = ntile * (ntile + 1) / 2;
+  const int total = npairs * nchunk;
+  int w = blockIdx.x;
+  if (total % 8 == 0) w = (w % 8) * (total / 8) + w / 8;
+  const int pair = w % npairs, chunk = w / npairs;
+  int I, J;
+  tile_pair(pair, ntile, I, J);
+  const bool diag = I == J;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int qi = wv >> 1, qj = wv & 1;
+  const int x = lane & 31, hh = lane >> 5;
+  const int64_t rbeg = (int64_t)chunk * rows_per_chunk;
+  const int64_t rend = min(rows, rbeg + rows_per_chunk);
+
+  f32x16 acc[2];
+  f64x4 acc64[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    acc[b] = f32x16{0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc64[b][q] = f64x4{0, 0, 0, 0};
+  }
+
+  // thread -> rows 4 h .. 4 h + 3 of the step, column c of each block
+  const int h4 = t >> 7, c = t & 127;
+  const int ci = I * GT + c, cj = J * GT + c;
+  float pi[4], pj[4];
+  auto load = [&](int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t gr = k0 + 4 * h4 + e;
+      const bool ok = gr < rend;
+      pi[e] = ok && ci < r ? X[gr * ldx + ci] : 0.0f;
+      if (!diag) pj[e] = ok && cj < r ? X[gr * ldx + cj] : 0.0f;
+    }
+  };
+  auto put = [&](int b, int blk, const float* v) __attribute__((always_inline)) {
+    unsigned short hi[4], lo[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      hi[e] = g16_bits(v[e]);
+      lo[e] = g16_bits(v[e] - g16_val(hi[e]));
+    }
+    const g16u2 vh = {(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
+    const g16u2 vl = {(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
+    *reinterpret_cast<g16u2*>(&S[b][blk][0][c][4 * h4]) = vh;
+    *reinterpret_cast<g16u2*>(&S[b][blk][1][c][4 * h4]) = vl;
+  };
+  auto store = [&](int b) __attribute__((always_inline)) {
+    put(b, 0, pi);
+    if (!diag) put(b, 1, pj);
+  };
+
+  if (rbeg < rend) {
+    load(rbeg);
+    store(0);
+  }
+  __syncthreads();
+  int since = 0, cur = 0;
+  const int bj = diag ? 0 : 1;
+  for (int64_t k0 = rbeg; k0 < rend; k0 += 16) {
+    const bool more = k0 + 16 < rend;
+    if (more) load(k0 + 16);
+    g16u4 af[2], bf[2][2];   // [plane], [tile][plane]
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      af[p] = *reinterpret_cast<const g16u4*>(&S[cur][0][p][qi * 32 + x][8 * hh]);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        bf[b][p] = *reinterpret_cast<const g16u4*>(&S[cur][bj][p][qj * 64 + b * 32 + x][8 * hh]);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(g16x8, af[p]),
+                                                           __builtin_bit_cast(g16x8, bf[b][q]), acc[b], 0, 0, 0);
+    if (++since == G16Flush) {
+      since = 0;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc64[b][v >> 2][v & 3] += (double)acc[b][v];
+        acc[b] = f32x16{0};
+      }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // D of the 32 x 32 MFMA: register v of lane l holds row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+  double* out = part + ((int64_t)chunk * npairs + pair) * (GT * GT);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = qi * 32 + 8 * (v >> 2) + 4 * hh + (v & 3);
+      const int j = qj * 64 + b * 32 + x;
+      out[i * GT + j] = acc64[b][v >> 2][v & 3] + (double)acc[b][v];
+    }
 }
 
 // Sum the partials in chunk order and write the symmetric rp x rp Gram matrix

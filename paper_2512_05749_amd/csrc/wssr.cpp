@@ -33,6 +33,9 @@ constexpr bool kFastMid = false;   // intermediate passes always take the FP64 C
 constexpr bool kFastMid = true;
 #endif
 constexpr int kBatchMax = 1024;     // problems per batched step
+// Gram of a float block: FP64 MFMA; FP32 MFMA with FP64 flushes (entries to
+// about 1e-7 relative); the BF16 MFMA on the two-plane split (about 3e-7)
+enum { kGram64 = 0, kGram32 = 1, kGram16 = 2 };
 constexpr int kLanesMax = 16;       // concurrent batch lanes
 #ifndef WSSR_RS_ROUNDS
 #define WSSR_RS_ROUNDS 4
@@ -287,12 +290,20 @@ struct wssr_ctx {
                            (const float*)(h->qy + n * r), r, (const double*)av->sig_state, c_hist, h->Bm, rp, cst);
         h->apply((const float*)V, m, r, r, h->Bm, rp, r, h->z, r, false, false, true);
       }
-      const bool fast = kFastMid && !av;
+      const bool fast = kFastMid;
       if (fast && p < q) {
         // an intermediate pass: only the span of Z is carried on
         // (in the BF16 forms the next sample side reads V only through its
         // split, which can scale Z itself; Alg. 1's ending reads V too)
         h->fast_orth(h->z, m, r, h->bf16() && !diag_end);
+        if (hist) {
+          // V_in^T V_{p+1} = (Y_1^T Q_Y) T with the factor T the pass took
+          h->cross(h->y1, h->qy, ny, r, h->Hc);
+          hipLaunchKernelGGL(k_select_t, dim3(cdiv((int64_t)rp * rp, 256)), dim3(256), 0, stream,
+                             (const int*)h->fmode, (const double*)h->gdiag, (const double*)h->R1i,
+                             (const double*)h->Tq, rp, r, h->T);
+          h->smallgemm(h->Hc, h->T, rp, h->Hn, false, false);
+        }
         vcur = h->vw;
         continue;
       }
@@ -1001,9 +1012,10 @@ struct wssr_ctx {
     return (int)std::max<int64_t>(1, std::min(std::min(cdiv(512, npairs), cdiv(rows, 256)), cap));
   }
 
-  // f32: the FP32-MFMA Gram (float X only), for blocks whose span is all that is used
+  // kind (float X only): kGram32 the FP32-MFMA Gram, kGram16 the Gram of the
+  // two-plane BF16 split on the BF16 MFMA; otherwise the FP64 one
   template <typename T>
-  void gram(const T* X, int64_t rows, int r, bool gated, bool f32 = false) {
+  void gram(const T* X, int64_t rows, int r, bool gated, int kind = kGram64) {
     const int rp = (int)rup(r, 64), nt = (int)cdiv(r, kF64Tile), npairs = nt * (nt + 1) / 2;
     int nch = gram_chunks(rows, npairs);
     const int64_t rpc = std::max<int64_t>(16, rup(cdiv(rows, nch), 16));
@@ -1011,14 +1023,18 @@ struct wssr_ctx {
     const bool vec = (r % 4 == 0) && ((uintptr_t)X % 16 == 0);
     const int64_t ldx = r;
     if constexpr (std::is_same<T, float>::value) {
-      if (f32) {
+      if (kind != kGram64) {
         // whole groups of 8 chunks, so that every XCD holds whole chunks
         int nc = gram_chunks(rows, npairs);
         if (nc >= 8) nc -= nc % 8;
         const int64_t rpc32 = std::max<int64_t>(16, rup(cdiv(rows, nc), 16));
         nch = (int)std::max<int64_t>(1, cdiv(rows, rpc32));
-        hipLaunchKernelGGL(k_gram32_partial, dim3(npairs * nch), dim3(256), 0, stream, X, rows, r, ldx, nt, nch,
-                           rpc32, gram_part, vec, (const DevStatus*)st, gated);
+        if (kind == kGram16)
+          hipLaunchKernelGGL(k_gram16_partial, dim3(npairs * nch), dim3(512), 0, stream, X, rows, r, ldx, nt, nch,
+                             rpc32, gram_part, (const DevStatus*)st, gated);
+        else
+          hipLaunchKernelGGL(k_gram32_partial, dim3(npairs * nch), dim3(256), 0, stream, X, rows, r, ldx, nt, nch,
+                             rpc32, gram_part, vec, (const DevStatus*)st, gated);
       } else
         hipLaunchKernelGGL((k_gram_partial<float>), dim3(npairs, nch), dim3(256), 0, stream, X, rows, r, ldx,
                            nt, rpc, gram_part, vec, (const DevStatus*)st, gated);
@@ -1078,12 +1094,12 @@ struct wssr_ctx {
   // FP32-MFMA Gram and its FP64 Cholesky (into G, R1, R1i, gdiag), then the
   // device's choice of mode (k_fast_decide) and clean shadow status words for
   // the alternatives.
-  void probe_factor(float* Z, int64_t m, int r, double piv_fast) {
+  void probe_factor(float* Z, int64_t m, int r, double piv_fast, int kind) {
     const int rp = (int)rup(r, 64);
     DevStatus* main = st;
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, stream, shadow);
     st = shadow;
-    gram((const float*)Z, m, r, false, true);
+    gram((const float*)Z, m, r, false, kind);
     chol(rp, r, R1, R1i, false);
     st = main;
     hipLaunchKernelGGL(k_fast_decide, dim3(1), dim3(64), 0, stream, (const DevStatus*)shadow,
@@ -1102,7 +1118,7 @@ struct wssr_ctx {
   void fast_orth(float* Z, int64_t m, int r, bool defer_scale) {
     const int rp = (int)rup(r, 64);
     DevStatus* main = st;
-    probe_factor(Z, m, r, 0.03);
+    probe_factor(Z, m, r, 0.03, kGram16);
     if (defer_scale)
       split_alt = Z;
     else
@@ -1125,7 +1141,7 @@ struct wssr_ctx {
   void fast_factor(float* Z, int64_t m, int r) {
     const int rp = (int)rup(r, 64);
     DevStatus* main = st;
-    probe_factor(Z, m, r, 0.3);
+    probe_factor(Z, m, r, 0.3, kGram32);
     const int64_t cnt = (int64_t)rp * rp;
     hipLaunchKernelGGL(k_copy_st, dim3(cdiv(cnt, 256)), dim3(256), 0, stream, (const double*)R1, cnt, Rz,
                        (const DevStatus*)(shadow + 3));
@@ -1945,14 +1961,15 @@ wssr_status wssr_dbg_cholqr2(wssr_handle h, int64_t rows, const float* X, int32_
   return WSSR_OK;
 }
 
-wssr_status wssr_dbg_gram(wssr_handle h, int64_t rows, const float* X, int32_t r, int32_t f32, double* G) {
+wssr_status wssr_dbg_gram(wssr_handle h, int64_t rows, const float* X, int32_t r, int32_t kind, double* G) {
   if (!h) return WSSR_ERR_INVALID_ARG;
   if (!X || !G) return h->fail(WSSR_ERR_INVALID_ARG, "NULL pointer argument");
+  if (kind < 0 || kind > 2) return h->fail(WSSR_ERR_INVALID_ARG, "kind outside 0..2");
   if (r < 1 || r > h->cfg.r_max) return h->fail(WSSR_ERR_INVALID_ARG, "r outside [1, r_max]");
   if (rows < 1 || rows > h->rows_max) return h->fail(WSSR_ERR_INVALID_ARG, "rows outside [1, max(n_max, m_max)]");
   const int rp = (int)rup(r, 64);
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, h->stream, h->st);
-  h->gram(X, rows, r, false, f32 != 0);
+  h->gram(X, rows, r, false, (int)kind);
   (void)hipMemcpy2DAsync(G, sizeof(double) * r, h->G, sizeof(double) * rp, sizeof(double) * r, r,
                          hipMemcpyDeviceToDevice, h->stream);
   if (hipGetLastError() != hipSuccess) return h->fail(WSSR_ERR_HIP, "kernel launch failed");

@@ -480,11 +480,18 @@ class Wssr:
         self._check(lib().wssr_dbg_cholqr2(self._h, rows, _ptr(X), r, _ptr(Q), _ptr(R)))
         return Q, R
 
-    def gram(self, X, f32=False):
+    GRAM_KINDS = {"fp64": 0, "fp32": 1, "bf16_split": 2}
+
+    def gram(self, X, kind="fp64"):
+        """G = X^T X as the step forms it: "fp64" (the CholeskyQR2's),
+        "fp32" (the last pass's probe) or "bf16_split" (the intermediate
+        passes' probe)."""
         rows, r = X.shape
         _need(X, "X", torch.float32, self.device, contiguous=True)
+        if kind not in self.GRAM_KINDS:
+            raise WssrError(f"gram kind {kind!r} is not one of {sorted(self.GRAM_KINDS)}")
         G = torch.empty(r, r, dtype=torch.float64, device=self.device)
-        self._check(lib().wssr_dbg_gram(self._h, rows, _ptr(X), r, int(bool(f32)), _ptr(G)))
+        self._check(lib().wssr_dbg_gram(self._h, rows, _ptr(X), r, self.GRAM_KINDS[kind], _ptr(G)))
         return G
 
     def span_basis(self, X):

@@ -85,10 +85,9 @@ def test_averaged_chain_against_oracle(n, m, r, q, avg):
 
 def test_averaged_weight_zero_is_the_plain_step():
     """avg = 0: the history rows are zero and the step is wssr_step's, to
-    rounding: the sample-side block has r more rows, all zero, and the plain
-    step factors its well-conditioned parameter-side blocks from an
-    FP32-accurate Gram where the averaged step keeps the FP64 one (both are
-    within the FP32 bars of the oracle; here they agree to 1e-5)."""
+    rounding: the sample-side block has r more rows, all zero, which change
+    the row chunking of its Gram sums (both are within the FP32 bars of the
+    oracle; here they agree to 1e-5)."""
     from paper_2512_05749_amd import Wssr
     n, m, r = 900, 3000, 40
     cfg, wl = _workload(n, m, r, seed=5)
