@@ -124,7 +124,7 @@ template <typename Tin, typename Tout>
 __global__ void k_apply(const Tin* X, int64_t rows, int ldx, int kdim, const double* Tm, int rp, int ncol,
                         Tout* Out, int ldo, bool upper, bool vec, bool acc, const DevStatus* st, bool gated);
 __global__ void k_apply32(const float* X, int64_t rows, int ldx, int kdim, const float* Tf, int rp, int ncol,
-                          float* Out, int ldo, bool upper, bool vec, const DevStatus* st, bool gated);
+                          float* Out, int ldo, bool upper, bool vec, bool acc_out, const DevStatus* st, bool gated);
 __global__ void k_round_f32(const double* src, int64_t n, float* dst, const DevStatus* st, bool gated);
 template <typename TX, typename TW>
 __global__ void k_cross_partial(const TX* X, const TW* W, int64_t rows, int r, int ntile, int64_t rows_per_chunk,

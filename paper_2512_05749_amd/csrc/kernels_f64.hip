@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256, 2) void k_apply(const Tin* __restrict__ X, int
 // the column tiles of one row tile are consecutive workgroups of one XCD
 // when the total is a multiple of 8, so each row slab of X is fetched into
 // that XCD's L2 once.  When `upper`, K-steps below the column tile are
-// skipped (Tf upper triangular).
+// skipped (Tf upper triangular); with acc_out, Out += X Tf (in FP32).
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int A32S = 20;   // LDS row stride (floats) of the X tile
@@ -596,7 +596,7 @@ constexpr int A32S = 20;   // LDS row stride (floats) of the X tile
 __global__ __launch_bounds__(256, 4) void k_apply32(const float* __restrict__ X, int64_t rows, int ldx, int kdim,
                                                     const float* __restrict__ Tf, int rp, int ncol,
                                                     float* __restrict__ Out, int ldo, bool upper, bool vec,
-                                                    const DevStatus* st, bool gated) {
+                                                    bool acc_out, const DevStatus* st, bool gated) {
   if (skipped(st, gated)) return;
   __shared__ float Xs[2][GT][A32S];   // [row][k]
   __shared__ float Ts[2][GK][GS];     // [k][col]
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256, 4) void k_apply32(const float* __restrict__ X,
       for (int v = 0; v < 4; ++v) {
         const int64_t i = row0 + qi * 64 + a * 16 + drow_f32(v, lk);
         const int j = col0 + qj * 64 + b * 16 + li;
-        if (i < rows && j < ncol) Out[i * ldo + j] = acc[a][b][v];
+        if (i < rows && j < ncol) Out[i * ldo + j] = acc_out ? Out[i * ldo + j] + acc[a][b][v] : acc[a][b][v];
       }
 }
 

@@ -250,7 +250,7 @@ struct wssr_ctx {
     double* yh = h->y64 + n * r;                   // its history rows
     if (av && g_ext) hipLaunchKernelGGL(k_center_energies, dim3(1), dim3(1024), 0, stream, e_l, n, h->eps, h->st);
     // pass 1's history rows come from the Gram of V_in
-    if (hist) h->gram(V, m, r, false);
+    if (hist) h->gram(V, m, r, false, kGram32);
 
     const float* vcur = cont ? cont->vstart : V;
     // Alg. 1's own ending: the last pass stops after the QR of its
@@ -288,7 +288,7 @@ struct wssr_ctx {
       if (hist) {
         hipLaunchKernelGGL(k_hist_b, dim3(cdiv((int64_t)rp * rp, 256)), dim3(256), 0, stream,
                            (const float*)(h->qy + n * r), r, (const double*)av->sig_state, c_hist, h->Bm, rp, cst);
-        h->apply((const float*)V, m, r, r, h->Bm, rp, r, h->z, r, false, false, true);
+        h->apply((const float*)V, m, r, r, h->Bm, rp, r, h->z, r, false, false, true, true);
       }
       const bool fast = kFastMid;
       if (fast && p < q) {
@@ -1077,12 +1077,12 @@ struct wssr_ctx {
     const bool vec = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
     const dim3 grid(cdiv(rows, kF64Tile), cdiv(ncol, kF64Tile));
     if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
-      if (f32 && !acc) {
+      if (f32) {
         const int64_t cnt = (int64_t)rp * rp;
         hipLaunchKernelGGL(k_round_f32, dim3(cdiv(cnt, 256)), dim3(256), 0, stream, Tm, cnt, tf32,
                            (const DevStatus*)st, gated);
         hipLaunchKernelGGL(k_apply32, dim3((unsigned)(grid.x * grid.y)), dim3(256), 0, stream, X, rows, ldx, kdim,
-                           (const float*)tf32, rp, ncol, out, ldo, upper, vec, (const DevStatus*)st, gated);
+                           (const float*)tf32, rp, ncol, out, ldo, upper, vec, acc, (const DevStatus*)st, gated);
         return;
       }
     }
