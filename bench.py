@@ -283,8 +283,6 @@ def column_tile(form, r, side):
     BF16 with one plane of each operand)."""
     if form == "f32":
         return 32 if r <= 32 else 64 if r <= 64 else 128 if r <= 128 else 256
-    if side == "param_side" and r > 256:
-        return 256              # two 256-column tiles per row block
     return 64 if r <= 64 else 128 if r <= 128 else 256 if r <= 256 else 512
 
 
