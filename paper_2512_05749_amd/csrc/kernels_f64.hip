@@ -304,20 +304,20 @@ __global__ __launch_bounds__(256, 2) void k_gram32_partial(const float* __restri
 // the partial layout are those of k_gram32_partial.
 // 512 threads = 8 waves in a 4 x 2 arrangement, each a 32 x 64 part of the
 // 128 x 128 tile pair (two MFMA tiles of 32 x 32), one workgroup per compute
-// unit and two waves per SIMD.  K-steps of 16 rows: each thread loads 4 rows
-// of one column of each column block (coalesced across the 128 threads of a
-// row quarter), splits them and writes the 4 K-values of each plane as one
-// 8-byte LDS store into a [plane][column][k] tile with a column stride of 24
-// elements (48 bytes, an odd multiple of 16, so the 16-byte fragment reads
-// are conflict-free); double-buffered, one barrier per step, the next step's
-// loads in flight during the MFMAs.
+// unit and two waves per SIMD.  K-steps of G16K = 32 rows: each thread loads
+// 8 rows of one column of each column block (coalesced across the 128
+// threads of a row quarter), splits them and writes the 8 K-values of each
+// plane as one 16-byte LDS store into a [plane][column][k] tile with a column
+// stride of 40 elements (80 bytes, an odd multiple of 16, so the 16-byte
+// fragment reads are conflict-free); double-buffered (80 KB), one barrier per
+// step, the next step's loads in flight during the step's 16 MFMAs per wave.
 // ---------------------------------------------------------------------------
 namespace {
 typedef __bf16 g16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned g16u4 __attribute__((ext_vector_type(4)));
-typedef unsigned g16u2 __attribute__((ext_vector_type(2)));
-constexpr int G16S = 24;       // LDS column stride (BF16 elements)
-constexpr int G16Flush = 16;   // 16-row steps between FP64 flushes
+constexpr int G16K = 32;             // rows per K-step
+constexpr int G16S = G16K + 8;       // LDS column stride (BF16 elements)
+constexpr int G16Flush = 256 / G16K; // steps between FP64 flushes
 
 __device__ __forceinline__ unsigned short g16_bits(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
 __device__ __forceinline__ float g16_val(unsigned short b) { return (float)__builtin_bit_cast(__bf16, b); }
@@ -353,30 +353,35 @@ __global__ __launch_bounds__(512, 1) void k_gram16_partial(const float* __restri
     for (int q = 0; q < 4; ++q) acc64[b][q] = f64x4{0, 0, 0, 0};
   }
 
-  // thread -> rows 4 h .. 4 h + 3 of the step, column c of each block
+  // thread -> rows RT h .. RT h + RT - 1 of the step, column c of each block
+  constexpr int RT = G16K / 4;
   const int h4 = t >> 7, c = t & 127;
   const int ci = I * GT + c, cj = J * GT + c;
-  float pi[4], pj[4];
+  float pi[RT], pj[RT];
   auto load = [&](int64_t k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t gr = k0 + 4 * h4 + e;
+    for (int e = 0; e < RT; ++e) {
+      const int64_t gr = k0 + RT * h4 + e;
       const bool ok = gr < rend;
       pi[e] = ok && ci < r ? X[gr * ldx + ci] : 0.0f;
       if (!diag) pj[e] = ok && cj < r ? X[gr * ldx + cj] : 0.0f;
     }
   };
   auto put = [&](int b, int blk, const float* v) __attribute__((always_inline)) {
-    unsigned short hi[4], lo[4];
+    unsigned short hi[RT], lo[RT];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < RT; ++e) {
       hi[e] = g16_bits(v[e]);
       lo[e] = g16_bits(v[e] - g16_val(hi[e]));
     }
-    const g16u2 vh = {(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
-    const g16u2 vl = {(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
-    *reinterpret_cast<g16u2*>(&S[b][blk][0][c][4 * h4]) = vh;
-    *reinterpret_cast<g16u2*>(&S[b][blk][1][c][4 * h4]) = vl;
+    g16u4 vh, vl;
+#pragma unroll
+    for (int q = 0; q < RT / 2; ++q) {
+      vh[q] = (unsigned)hi[2 * q] | ((unsigned)hi[2 * q + 1] << 16);
+      vl[q] = (unsigned)lo[2 * q] | ((unsigned)lo[2 * q + 1] << 16);
+    }
+    *reinterpret_cast<g16u4*>(&S[b][blk][0][c][RT * h4]) = vh;
+    *reinterpret_cast<g16u4*>(&S[b][blk][1][c][RT * h4]) = vl;
   };
   auto store = [&](int b) __attribute__((always_inline)) {
     put(b, 0, pi);
@@ -390,25 +395,28 @@ __global__ __launch_bounds__(512, 1) void k_gram16_partial(const float* __restri
   __syncthreads();
   int since = 0, cur = 0;
   const int bj = diag ? 0 : 1;
-  for (int64_t k0 = rbeg; k0 < rend; k0 += 16) {
-    const bool more = k0 + 16 < rend;
-    if (more) load(k0 + 16);
-    g16u4 af[2], bf[2][2];   // [plane], [tile][plane]
+  for (int64_t k0 = rbeg; k0 < rend; k0 += G16K) {
+    const bool more = k0 + G16K < rend;
+    if (more) load(k0 + G16K);
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      af[p] = *reinterpret_cast<const g16u4*>(&S[cur][0][p][qi * 32 + x][8 * hh]);
+    for (int kb = 0; kb < G16K / 16; ++kb) {
+      g16u4 af[2], bf[2][2];   // [plane], [tile][plane]
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        bf[b][p] = *reinterpret_cast<const g16u4*>(&S[cur][bj][p][qj * 64 + b * 32 + x][8 * hh]);
-    }
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int p = 0; p < 2; ++p) {
+        af[p] = *reinterpret_cast<const g16u4*>(&S[cur][0][p][qi * 32 + x][16 * kb + 8 * hh]);
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(g16x8, af[p]),
-                                                           __builtin_bit_cast(g16x8, bf[b][q]), acc[b], 0, 0, 0);
+          bf[b][p] = *reinterpret_cast<const g16u4*>(&S[cur][bj][p][qj * 64 + b * 32 + x][16 * kb + 8 * hh]);
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(g16x8, af[p]),
+                                                             __builtin_bit_cast(g16x8, bf[b][q]), acc[b], 0, 0, 0);
+    }
     if (++since == G16Flush) {
       since = 0;
 #pragma unroll
