@@ -159,9 +159,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_partial(const T* __restrict__ X
 }
 
 // ---------------------------------------------------------------------------
-// FP32-MFMA Gram partials of a float block, tuned for tall blocks: the same
-// 128 x 128 tile pairs, wave layout, FP64 flush every 256 rows and partial
-// layout as k_gram_partial<float, true> (k_gram_reduce sums them), with
+// FP32-MFMA Gram partials of a float block, tuned for tall blocks: the
+// 128 x 128 tile pairs, 2 x 2 wave layout and partial layout of
+// k_gram_partial (k_gram_reduce sums them), on the FP32 16x16x4 MFMA with
+// the FP32 sums flushed into FP64 every 256 rows, and
 // - 16-row K-steps staged through float registers into a double-buffered LDS
 //   tile (one barrier per step; the loads of step s + 1 are in flight during
 //   the MFMAs of step s);
