@@ -329,9 +329,19 @@ __global__ __launch_bounds__(256) void k_vtg_partial(const float* __restrict__ v
   if (j >= r) return;
   const int64_t i0 = (int64_t)blockIdx.x * rows_per_chunk;
   const int64_t i1 = min(m, i0 + rows_per_chunk);
-  double d = 0.0;
-  for (int64_t i = i0; i < i1; ++i) d += (double)v[i * r + j] * g[i];
-  part[(int64_t)blockIdx.x * r + j] = d;
+  // four rows per trip, their loads issued together; four partial sums
+  // added in a fixed order at the end
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  int64_t i = i0;
+  for (; i + 3 < i1; i += 4) {
+    const float x0 = v[i * r + j], x1 = v[(i + 1) * r + j], x2 = v[(i + 2) * r + j], x3 = v[(i + 3) * r + j];
+    d0 += (double)x0 * g[i];
+    d1 += (double)x1 * g[i + 1];
+    d2 += (double)x2 * g[i + 2];
+    d3 += (double)x3 * g[i + 3];
+  }
+  for (; i < i1; ++i) d0 += (double)v[i * r + j] * g[i];
+  part[(int64_t)blockIdx.x * r + j] = (d0 + d1) + (d2 + d3);
 }
 
 // Stage 2 (one block of 256 threads per column): cw_j = w_j * c_j; also
@@ -379,7 +389,26 @@ __global__ __launch_bounds__(256) void k_delta(const float* __restrict__ v, cons
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= m) return;
   double d = 0.0;
-  for (int j = lane; j < r; j += 64) d += (double)v[i * r + j] * cw[j];
+  const float* row = v + i * r;
+  if ((r % 4) == 0 && ((uintptr_t)v % 16) == 0) {
+    // 16-byte loads, two in flight per lane before their sums
+    int j = 4 * lane;
+    for (; j + 256 < r; j += 512) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(row + j);
+      const f32x4 b = *reinterpret_cast<const f32x4*>(row + j + 256);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d += (double)a[q] * cw[j + q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d += (double)b[q] * cw[j + 256 + q];
+    }
+    if (j < r) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(row + j);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d += (double)a[q] * cw[j + q];
+    }
+  } else {
+    for (int j = lane; j < r; j += 64) d += (double)row[j] * cw[j];
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
   if (lane == 0) delta[i] = (g[i] - d) * inv_lambda;
