@@ -681,12 +681,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cols = oracle_cols(args, cfg) if args.cpu_baseline else 0
-    cols_wide = min(cfg.m, OracleSample.WIDE * cols)
     sketch = []
     for item in filter(None, args.sketch.split(";")):
         p_, q_ = (int(x) for x in item.split(","))
         sketch.append((min(p_, 512 - cfg.r), q_))
-    rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols_wide, averaged=args.averaged,
+    rec, sample, e1, v_end = run_single(args, cfg, form, dev, sample_cols=cols, averaged=args.averaged,
                                         sketch=sketch, spring=bool(args.spring) and cfg.n <= 8192)
     out = {
         "metric": METRIC,
@@ -717,7 +716,7 @@ def main():
     if "spring" in rec:
         out["spring_same_data"] = rec["spring"]
         out["wssr_vs_spring_time"] = round(rec["spring"]["ms_per_step"] / rec["ms_per_step"], 3)
-    oracle = OracleSample(args, cfg, sample, e1, v_end[:cols_wide], form, cols) if args.cpu_baseline else None
+    oracle = OracleSample(args, cfg, sample, e1, v_end[:cols], form, cols) if args.cpu_baseline else None
     del sample, v_end
     torch.cuda.empty_cache()
     # the FP32 form beside it: the same instance, or the same recipe at the M
@@ -755,12 +754,15 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _oracle_job(o32, e_np, v32, cols, lam, r, q, threads, queue):
+def _oracle_job(o32, e_np, v32, cols, lam, r, q, threads, queue, wide=1):
     """Child process (spawned, so that it shares nothing with the parent's
     GPU runtime): the FP64 oracle step on the first `cols` columns of the
-    sample (the accuracy reference), timed, and when the sample is wider, the
-    same step on all of its columns, timed: a second point of time against
-    columns."""
+    sample (the accuracy reference), timed, and when wide > 1 the same step on
+    those columns tiled `wide` times (V's rows tiled and scaled by
+    1/sqrt(wide), so that every r x r matrix of the step is the sample's up to
+    a scale and the Rayleigh-Ritz SVD takes the same sweeps), timed: a second
+    point of time against columns that differs from the first only in the
+    work that grows with the column count."""
     sys.path.insert(0, ROOT)
     try:
         from threadpoolctl import threadpool_limits
@@ -783,9 +785,9 @@ def _oracle_job(o32, e_np, v32, cols, lam, r, q, threads, queue):
     res = {"delta": ref["delta"], "sigma": ref["sigma"], "v": ref["v"], "g": ref["g"],
            "seconds": time.perf_counter() - t0}
     del o_np, v_np, ref
-    if o32.shape[1] > cols:
-        o2 = np.asarray(o32, dtype=np.float64)
-        v2 = np.asarray(v32, dtype=np.float64)
+    if wide > 1:
+        o2 = np.tile(np.asarray(o32[:, :cols], dtype=np.float64), (1, wide))
+        v2 = np.tile(np.asarray(v32[:cols], dtype=np.float64), (wide, 1)) / np.sqrt(wide)
         t0 = time.perf_counter()
         orc.wssr_step(o2, e_np, v2, lam, r, q)
         res["seconds_wide"] = time.perf_counter() - t0
@@ -805,10 +807,12 @@ class OracleSample:
     on the unrounded O (the end-to-end error of the form, where the BF16 bar
     applies) and, for the BF16 forms, on the values O holds in storage (the
     implementation error).  The CPU baseline times the oracle on the sample
-    and on a sample `wide` times wider (the first wide * cols columns): the
-    step's time is linear in the column count (every stage but the N x r and
-    r x r ones grows with M, those do not), so the two points give the time
-    of a full step, a + b M."""
+    and on the sample tiled WIDE times along the columns: the step's time is
+    linear in the column count (every stage but the N x r and r x r ones
+    grows with M, those do not), and the tiled copy keeps the r x r work the
+    same up to scale (the same Rayleigh-Ritz sweeps, whose count varies with
+    the data and would otherwise swamp the difference), so the two points
+    give the time of a full step, a + b M."""
 
     WIDE = 5
 
@@ -821,7 +825,7 @@ class OracleSample:
         self.cfg, self.form = cfg, form
         n, r, q, lam = cfg.n, cfg.r, cfg.q, cfg.lam
         self.cols = cols
-        self.cols_wide = o_sample.shape[1]
+        self.cols_wide = self.WIDE * cols
         o32 = o_sample.cpu().numpy()
         e_np = e_dev.cpu().numpy()
         v32 = v_sample.cpu().numpy()
@@ -847,7 +851,7 @@ class OracleSample:
         ctx = mp.get_context("spawn")
         self.q_main, self.q_stored = ctx.Queue(), ctx.Queue()
         self.p_main = ctx.Process(target=_oracle_job,
-                                  args=(o32, e_np, v32, cols, lam, r, q, self.threads, self.q_main))
+                                  args=(o32, e_np, v32, cols, lam, r, q, self.threads, self.q_main, self.WIDE))
         self.p_main.start()
         self.p_stored = None
         if stored is not None:
@@ -914,7 +918,8 @@ class OracleSample:
         log(f"accuracy on the sample: {acc}")
         base = {"value": round(1.0 / full_s, 6), "unit": "SR steps/s", "cores": self.threads, "kind": "oracle",
                 "sample": (f"one step of the FP64 oracle (r={cfg.r}, q={cfg.q}) on N={cfg.n} x {self.cols} columns "
-                           f"of M={cfg.m}: {dt:.2f}s, and on {self.cols_wide} columns: {dt2:.2f}s; "
+                           f"of M={cfg.m}: {dt:.2f}s, and on those columns tiled {self.WIDE} times "
+                           f"({self.cols_wide} columns): {dt2:.2f}s; "
                            + (f"a full step from the line through the two points, {a:.1f}s + {b * 1e3:.3f}ms "
                               f"per column" if fit else "the two points do not separate the per-column part from "
                               "the noise; the longer sample time is reported, a lower bound on a full step"))}
