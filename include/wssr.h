@@ -20,6 +20,15 @@
  * sigma are the singular values of A (descending); sigma^2 are the
  * eigenvalues of S = A^T A.  The caller applies theta <- theta - eta * delta.
  *
+ * Precision.  The products run on the MFMA in the configured dtype with FP32
+ * accumulation; the sample-side block Y is kept and orthonormalised in FP64
+ * (CholeskyQR2).  The parameter-side block Z (FP32) is orthonormalised from a
+ * fast Gram (an FP32-MFMA one, or the BF16 MFMA on a two-plane split of Z,
+ * with FP64 sums every 256 rows; entries to 1e-7 / 3e-7 of sqrt(G_ii G_jj))
+ * and an FP64 Cholesky where Z is well conditioned, else by the FP64
+ * CholeskyQR2; an intermediate pass carries on only the span of Z, which
+ * leaves the iteration's subspace that of Alg. 1 in exact arithmetic.
+ *
  * Memory.  Every data pointer passed to wssr_step and the wssr_dbg_* calls is
  * DEVICE memory on the handle's device; the caller owns it.  The library owns
  * only the workspace it allocates in wssr_create.  wssr_step never allocates.
