@@ -251,9 +251,9 @@ def ssi_svd(a, v_in, q):
     """q passes of warm-started subspace iteration on A^T A, each ending in a
     two-sided Rayleigh-Ritz step.
 
-    Alg. 1 orthonormalises the parameter-side block, multiplies by the data
-    matrix twice per pass (lines "V = O^T Q", "U = O V" in the paper's
-    orientation).  Per pass here, with A = O_bar/sqrt(N):
+    Alg. 1 orthonormalises the parameter-side block and multiplies by the
+    data matrix twice per pass (in the paper's orientation).  Per pass here,
+    with A = O_bar/sqrt(N):
         Y = A V            (sample side, N x r)
         Z = A^T Y          (parameter side, M x r)
         Q_Y R_Y = Y,  Q_Z R_Z = Z   (QR, positive diagonal)
