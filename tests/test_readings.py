@@ -2,7 +2,8 @@
 FP64 oracle on the CPU (no GPU): an intermediate pass of the subspace
 iteration may carry any well-conditioned basis Z T of the parameter-side
 block in place of its orthonormal factor Q_Z, because the next pass depends
-on Z only through its span (Alg. 1 in exact arithmetic)."""
+on Z only through its span (Alg. 1 in exact arithmetic); and the
+Rayleigh-Ritz SVD is needed on the last pass only."""
 import numpy as np
 import pytest
 
@@ -73,3 +74,15 @@ def test_a_rank_losing_basis_would_not_do():
 
     _, s = _span_carrying(a, v_in, 2, drop_last)
     assert np.max(np.abs(s - s_ref) / s_ref) > 1e-2
+
+
+@pytest.mark.parametrize("q", [1, 3])
+def test_rayleigh_ritz_on_the_last_pass_only(q):
+    """Reading A8: the GPU closes only the last pass with the Rayleigh-Ritz
+    SVD; the oracle closes every pass.  An intermediate Rayleigh-Ritz step
+    rotates Q_Z within its span, so the last pass sees the same subspace."""
+    a, v_in = _problem(seed=10 + q)
+    v_ref, s_ref, _ = orc.ssi_svd(a, v_in, q)
+    v, s = _span_carrying(a, v_in, q, lambda z: orc.qr_positive(z)[0])
+    assert np.max(np.abs(s - s_ref) / s_ref) < 1e-10
+    assert np.abs(v @ v.T - v_ref @ v_ref.T).max() < 1e-10
