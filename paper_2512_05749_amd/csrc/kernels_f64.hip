@@ -305,18 +305,19 @@ __global__ __launch_bounds__(256, 2) void k_gram32_partial(const float* __restri
 // the partial layout are those of k_gram32_partial.
 // 512 threads = 8 waves in a 4 x 2 arrangement, each a 32 x 64 part of the
 // 128 x 128 tile pair (two MFMA tiles of 32 x 32), one workgroup per compute
-// unit and two waves per SIMD.  K-steps of G16K = 32 rows: each thread loads
-// 8 rows of one column of each column block (coalesced across the 128
-// threads of a row quarter), splits them and writes the 8 K-values of each
-// plane as one 16-byte LDS store into a [plane][column][k] tile with a column
-// stride of 40 elements (80 bytes, an odd multiple of 16, so the 16-byte
-// fragment reads are conflict-free); double-buffered (80 KB), one barrier per
-// step, the next step's loads in flight during the step's 16 MFMAs per wave.
+// unit and two waves per SIMD.  K-steps of G16K = 64 rows: each thread loads
+// 16 rows of one column of each column block (coalesced across the 128
+// threads of a row quarter), splits them and writes them as 16-byte LDS
+// stores of 8 K-values per plane into a [plane][column][k] tile with a
+// column stride of 72 elements (144 bytes, an odd multiple of 16, so the
+// 16-byte fragment reads are conflict-free); double-buffered (144 KB), one
+// barrier per step, the next step's loads in flight during the step's 32
+// MFMAs per wave.
 // ---------------------------------------------------------------------------
 namespace {
 typedef __bf16 g16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned g16u4 __attribute__((ext_vector_type(4)));
-constexpr int G16K = 32;             // rows per K-step
+constexpr int G16K = 64;             // rows per K-step
 constexpr int G16S = G16K + 8;       // LDS column stride (BF16 elements)
 constexpr int G16Flush = 256 / G16K; // steps between FP64 flushes
 
@@ -369,20 +370,23 @@ __global__ __launch_bounds__(512, 1) void k_gram16_partial(const float* __restri
     }
   };
   auto put = [&](int b, int blk, const float* v) __attribute__((always_inline)) {
-    unsigned short hi[RT], lo[RT];
 #pragma unroll
-    for (int e = 0; e < RT; ++e) {
-      hi[e] = g16_bits(v[e]);
-      lo[e] = g16_bits(v[e] - g16_val(hi[e]));
-    }
-    g16u4 vh, vl;
+    for (int h = 0; h < RT / 8; ++h) {
+      unsigned short hi[8], lo[8];
 #pragma unroll
-    for (int q = 0; q < RT / 2; ++q) {
-      vh[q] = (unsigned)hi[2 * q] | ((unsigned)hi[2 * q + 1] << 16);
-      vl[q] = (unsigned)lo[2 * q] | ((unsigned)lo[2 * q + 1] << 16);
+      for (int e = 0; e < 8; ++e) {
+        hi[e] = g16_bits(v[8 * h + e]);
+        lo[e] = g16_bits(v[8 * h + e] - g16_val(hi[e]));
+      }
+      g16u4 vh, vl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        vh[q] = (unsigned)hi[2 * q] | ((unsigned)hi[2 * q + 1] << 16);
+        vl[q] = (unsigned)lo[2 * q] | ((unsigned)lo[2 * q + 1] << 16);
+      }
+      *reinterpret_cast<g16u4*>(&S[b][blk][0][c][RT * h4 + 8 * h]) = vh;
+      *reinterpret_cast<g16u4*>(&S[b][blk][1][c][RT * h4 + 8 * h]) = vl;
     }
-    *reinterpret_cast<g16u4*>(&S[b][blk][0][c][RT * h4]) = vh;
-    *reinterpret_cast<g16u4*>(&S[b][blk][1][c][RT * h4]) = vl;
   };
   auto store = [&](int b) __attribute__((always_inline)) {
     put(b, 0, pi);
