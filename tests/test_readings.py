@@ -86,3 +86,15 @@ def test_rayleigh_ritz_on_the_last_pass_only(q):
     v, s = _span_carrying(a, v_in, q, lambda z: orc.qr_positive(z)[0])
     assert np.max(np.abs(s - s_ref) / s_ref) < 1e-10
     assert np.abs(v @ v.T - v_ref @ v_ref.T).max() < 1e-10
+
+
+def test_warm_start_needs_only_its_span():
+    """Reading A13: the GPU feeds V_in to the first product as it is, the
+    oracle takes its QR first; V_in and V_in T (T well conditioned) span the
+    same space and give the same step."""
+    a, v_in = _problem(seed=21)
+    t = np.eye(v_in.shape[1]) + 0.3 * np.random.default_rng(22).standard_normal((v_in.shape[1],) * 2)
+    v_ref, s_ref, _ = orc.ssi_svd(a, v_in, 2)
+    v, s = _span_carrying(a, v_in @ t, 2, _scale_columns)
+    assert np.max(np.abs(s - s_ref) / s_ref) < 1e-10
+    assert np.abs(v @ v.T - v_ref @ v_ref.T).max() < 1e-10
