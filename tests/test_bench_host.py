@@ -49,3 +49,17 @@ def test_recorded_traffic_of_the_largest_instance():
         b = bench.recorded_traffic(kernel, rec)
         assert b is not None and b > 1e11, (kernel, b)
     assert bench.recorded_traffic("k_no_such_kernel", rec) is None
+
+
+def test_product_kernel_names_follow_the_dispatch():
+    """The kernel the benchmark names in its roofline object is the one the
+    library launches for the form, side and shape."""
+    from workloads import CONFIGS
+    big = CONFIGS["bf16_n16384_m4m_r512_q3"]
+    assert bench.product_kernel("bf16_split", "sample_side", big) == "k_gemm16_sample_side_rs"
+    assert bench.product_kernel("bf16_split", "param_side", big) == "k_gemm16_param_side_rs"
+    assert bench.product_kernel("bf16x2", "param_side", big) == "k_gemm16_param_side_dma"
+    c2 = CONFIGS["f32_n8192_m100k_r256"]
+    assert bench.product_kernel("f32", "param_side", c2) == "k_gemm_param_side_dma"
+    assert bench.column_tile("bf16", 512, "param_side") == 512
+    assert bench.column_tile("f32", 16, "sample_side") == 32
